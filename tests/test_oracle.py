@@ -1,0 +1,384 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's formula in the same arithmetic: each
+compares it with exact rational arithmetic, a closed form, a different
+approximation from the paper (Eq. 4), a library routine, brute force, or an
+invariant of Eq. 3.
+"""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+KDM_EXACT = Fraction("4148.808")
+
+
+def _plan(cfg, n_dm=None):
+    return oracle.shift_table(cfg["n_chan"], cfg["f_high"], cfg["chan_bw"], cfg["t_samp"],
+                              cfg["dm_start"], cfg["dm_step"], n_dm or cfg["n_dm"])
+
+
+# --------------------------------------------------------------------------------------
+# Shift table: Eq. 1 with channel c at f_high - c*df (Sec. 4.1), rounded half up.
+# --------------------------------------------------------------------------------------
+
+def _golden_rows(name):
+    rows = []
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                rows.append(line.split())
+    return rows
+
+
+def test_shift_hand_derived_delays():
+    """Textbook delays worked out by hand from Eq. 1 (tests/golden/dispersion_delays.txt)."""
+    for fh, f, dm, ts, want in _golden_rows("dispersion_delays.txt"):
+        fh, f, dm, ts, want = float(fh), float(f), float(dm), float(ts), int(want)
+        s = oracle.shift_table(1, fh, 0.0, ts, dm, 1.0, 1, freqs=np.array([f]))
+        assert int(s[0, 0]) == want, (fh, f, dm, ts)
+        # the same delay through the uniform-band form: channel 1 of a band with df = fh - f
+        s2 = oracle.shift_table(2, fh, fh - f, ts, dm, 1.0, 1)
+        assert int(s2[0, 1]) == want and int(s2[0, 0]) == 0
+
+
+@pytest.mark.parametrize("name", ["small", "headline", "lowfreq_u4", "grad_f32"])
+def test_shift_plan_max(name):
+    """Largest shift of each workload, computed by hand (tests/golden/plan_facts.txt)."""
+    facts = {r[0]: int(r[1]) for r in _golden_rows("plan_facts.txt")}
+    s = _plan(synth.CONFIGS[name])
+    assert int(s.max()) == facts[name]
+    assert int(s[-1, -1]) == facts[name]  # lowest channel, largest DM
+
+
+@pytest.mark.parametrize("name", ["small", "headline", "lowfreq_u4", "grad_f32"])
+def test_shift_special_cases_and_monotone(name):
+    """DM = 0 and the top channel have no delay; lower frequencies and larger DMs arrive later (Sec. 1)."""
+    s = _plan(synth.CONFIGS[name])
+    assert (s[0] == 0).all()
+    assert (s[:, 0] == 0).all()
+    assert (np.diff(s, axis=0) >= 0).all()
+    assert (np.diff(s, axis=1) >= 0).all()
+    assert s.dtype == np.int32
+
+
+def _exact_delay(dm, f, f_high, t_samp):
+    return dm * KDM_EXACT * (1 / (f * f) - 1 / (f_high * f_high)) / t_samp
+
+
+@pytest.mark.parametrize("name", ["small", "headline", "lowfreq_u4", "grad_f32"])
+def test_shift_matches_exact_rational(name):
+    """Every FP64 entry equals round-half-up of the exact rational delay, away from ties."""
+    cfg = synth.CONFIGS[name]
+    s = _plan(cfg)
+    fh = Fraction(repr(cfg["f_high"]))
+    df = Fraction(cfg["chan_bw"])  # the band splits exactly in binary for all workloads
+    ts = Fraction(repr(cfg["t_samp"]))
+    step = Fraction(repr(cfg["dm_step"]))
+    rng = np.random.default_rng(7)
+    n = s.size if s.size <= 40000 else 20000
+    idx = np.arange(s.size) if n == s.size else rng.choice(s.size, n, replace=False)
+    checked = 0
+    for i in idx:
+        d, c = divmod(int(i), cfg["n_chan"])
+        v = _exact_delay(Fraction(cfg["dm_start"]) + d * step, fh - c * df, fh, ts)
+        frac = v - math.floor(v)
+        if abs(frac - Fraction(1, 2)) < Fraction(1, 10**6):
+            continue  # too near a tie for FP64 to be held to the exact result
+        assert int(s[d, c]) == math.floor(v + Fraction(1, 2)), (d, c, float(v))
+        checked += 1
+    assert checked >= 0.99 * n
+
+
+@pytest.mark.parametrize("name", ["headline", "lowfreq_u4", "grad_f32"])
+def test_shift_against_narrow_band_form(name):
+    """Across m channels the delay slope agrees with the narrow-band form of Eq. 4.
+
+    Eq. 4 gives the delay across a channel of width df at centre f_c as
+    2 * K * DM * df / f_c^3 (K = 4.148808e3), an independent statement of the
+    f^-2 law's slope.  Over m adjacent channels the rounded table differs from
+    it only by rounding (<= 1 sample) and the curvature of the law.
+    """
+    cfg = synth.CONFIGS[name]
+    s = _plan(cfg)
+    m = 64
+    df = cfg["chan_bw"]
+    for d in [cfg["n_dm"] // 3, cfg["n_dm"] - 1]:
+        dm = cfg["dm_start"] + d * cfg["dm_step"]
+        for c in [0, cfg["n_chan"] // 2, cfg["n_chan"] - 1 - m]:
+            fc = cfg["f_high"] - (c + m / 2) * df
+            pred = 2 * 4.148808e3 * dm * (m * df) / fc**3 / cfg["t_samp"]
+            got = int(s[d, c + m]) - int(s[d, c])
+            curv = pred * 1.5 * (m * df / fc) ** 2 + 1e-9
+            assert abs(got - pred) <= 1.0 + curv, (d, c, got, pred)
+
+
+def test_shift_rejects_bad_band():
+    with pytest.raises(ValueError):
+        oracle.shift_table(4, 100.0, 40.0, 1e-3, 0.0, 1.0, 2)  # channel 3 at -20 MHz
+
+
+# --------------------------------------------------------------------------------------
+# Forward transform: Eq. 3 / Algorithm 1.
+# --------------------------------------------------------------------------------------
+
+def _tiny_case(rng, dtype):
+    n_chan = int(rng.integers(1, 9))
+    n_samp = int(rng.integers(40, 97)) & ~1
+    f_high = float(rng.uniform(300, 1600))
+    bw = float(rng.uniform(0.05, 0.4)) * f_high / max(n_chan, 1)
+    t_samp = float(rng.choice([64e-6, 128e-6, 1e-3]))
+    # pick a DM range whose largest delay fits comfortably in the window
+    k_max = 1 / (f_high - (n_chan - 1) * bw) ** 2 - 1 / f_high**2
+    dm_max = 0.6 * n_samp * t_samp / (4.148808e3 * k_max) if k_max > 0 else 10.0
+    n_dm = int(rng.integers(1, 6))
+    step = dm_max / max(n_dm - 1, 1)
+    start = float(rng.uniform(0, 0.2)) * dm_max if n_dm > 1 else dm_max * 0.5
+    step = (dm_max - start) / max(n_dm - 1, 1)
+    if dtype == "u8":
+        x = rng.integers(0, 256, (n_chan, n_samp)).astype(np.uint8)
+        x[:, ::7] = 0
+        x[:, 3::11] = 255
+    elif dtype == "u4":
+        x = rng.integers(0, 16, (n_chan, n_samp)).astype(np.uint8)
+    else:
+        x = rng.standard_normal((n_chan, n_samp)).astype(np.float32)
+        x[:, ::5] = 0.0
+    return dict(n_chan=n_chan, n_samp=n_samp, f_high=f_high, bw=bw, t_samp=t_samp,
+                start=start, step=step, n_dm=n_dm, x=x)
+
+
+def _pack_u4(v):
+    return (v[:, 0::2] | (v[:, 1::2] << 4)).astype(np.uint8)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u4", "f32"])
+def test_forward_equals_literal_eq3(dtype):
+    """Brute-force Eq. 3 (oracle/eq3_literal.py, independent code) on tiny random inputs."""
+    rng = np.random.default_rng({"u8": 11, "u4": 12, "f32": 13}[dtype])
+    for _ in range(12):
+        k = _tiny_case(rng, dtype)
+        dms = [k["start"] + d * k["step"] for d in range(k["n_dm"])]
+        ref, table, n_out = oracle.eq3_literal(
+            [list(map(float, r)) if dtype == "f32" else list(map(int, r)) for r in k["x"]],
+            k["n_samp"], k["f_high"], k["bw"], k["t_samp"], dms)
+        s = oracle.shift_table(k["n_chan"], k["f_high"], k["bw"], k["t_samp"], k["start"],
+                               k["step"], k["n_dm"])
+        assert s.tolist() == table
+        if n_out <= 0:
+            continue
+        if dtype == "u8":
+            got = oracle.forward(k["x"], "u8", k["n_samp"], s)
+            assert got.tolist() == ref
+        elif dtype == "u4":
+            got = oracle.forward(_pack_u4(k["x"]), "u4", k["n_samp"], s)
+            assert got.tolist() == ref
+        else:
+            got, _ = oracle.forward_f32(k["x"], k["n_samp"], s)
+            np.testing.assert_allclose(got, np.array(ref), rtol=0, atol=1e-12)
+
+
+def _small():
+    cfg = synth.CONFIGS["small"]
+    s = _plan(cfg)
+    x = synth.gaussian_u8(cfg["n_chan"], cfg["n_samp"], cfg["seed"])
+    return cfg, s, x
+
+
+def test_forward_dm0_is_channel_sum():
+    """At DM = 0 every delay is 0, so the output is the plain channel sum."""
+    cfg, s, x = _small()
+    n_out = oracle.n_out_for(s, cfg["n_samp"])
+    out = oracle.forward(x, "u8", cfg["n_samp"], s, rows=[0])
+    assert np.array_equal(out[0], x[:, :n_out].sum(axis=0, dtype=np.int64).astype(np.float32))
+
+
+def test_forward_injected_pulse():
+    """A pulse injected along the plan's own delays adds exactly its amplitude at its DM
+    and peaks there (the paper's injected-signal comparison, Sec. 5.3)."""
+    cfg, s, x = _small()
+    (dp, width, t0), = cfg["pulses"]
+    xp = x.copy()
+    applied = synth.inject_boxcar_u8(xp, s[dp], t0, width, cfg["amp"])
+    rows = list(range(256))
+    base = oracle.forward(x, "u8", cfg["n_samp"], s, rows=rows)
+    withp = oracle.forward(xp, "u8", cfg["n_samp"], s, rows=rows)
+    gain = (withp[dp, t0:t0 + width].astype(np.int64) - base[dp, t0:t0 + width].astype(np.int64))
+    assert np.array_equal(gain, applied.sum(axis=0))
+    assert gain.min() > 0.9 * cfg["amp"] * cfg["n_chan"]
+    for k in range(width):
+        assert int(np.argmax(withp[:, t0 + k])) == dp
+
+
+def test_forward_linear():
+    """A(x1 + x2) = A x1 + A x2 exactly for integer input without overflow."""
+    rng = np.random.default_rng(3)
+    n_chan, n_samp = 24, 4096
+    s = oracle.shift_table(n_chan, 1500.0, 300.0 / n_chan, 64e-6, 0.0, 2.0, 40)
+    x1 = rng.integers(0, 128, (n_chan, n_samp)).astype(np.uint8)
+    x2 = rng.integers(0, 128, (n_chan, n_samp)).astype(np.uint8)
+    a = oracle.forward(x1, "u8", n_samp, s)
+    b = oracle.forward(x2, "u8", n_samp, s)
+    ab = oracle.forward((x1 + x2).astype(np.uint8), "u8", n_samp, s)
+    assert np.array_equal(ab.astype(np.int64), a.astype(np.int64) + b.astype(np.int64))
+
+
+def test_forward_time_shift_and_chunking():
+    """Delaying the input delays the output; chunks with a max-delay overlap reassemble the whole."""
+    cfg, s, x = _small()
+    n_samp = cfg["n_samp"]
+    full = oracle.forward(x, "u8", n_samp, s)
+    tau = 777
+    shifted = oracle.forward(np.ascontiguousarray(x[:, tau:]), "u8", n_samp - tau, s)
+    assert np.array_equal(shifted, full[:, tau:])
+    max_shift = int(s.max())
+    n_out = n_samp - max_shift
+    parts, t = [], 0
+    for chunk in [5000, 9999, 4096, n_out]:
+        m = min(chunk, n_out - t)
+        if m <= 0:
+            break
+        xs = np.ascontiguousarray(x[:, t:t + m + max_shift])
+        parts.append(oracle.forward(xs, "u8", m + max_shift, s))
+        t += m
+    assert np.array_equal(np.concatenate(parts, axis=1), full)
+
+
+def test_forward_row_sum_identity():
+    """Sum over t of S(d,t) equals sum over c of (P_c[s + N_out] - P_c[s]) with P_c the prefix sums."""
+    cfg, s, x = _small()
+    n_out = oracle.n_out_for(s, cfg["n_samp"])
+    out = oracle.forward(x, "u8", cfg["n_samp"], s)
+    p = np.zeros((x.shape[0], x.shape[1] + 1), dtype=np.int64)
+    np.cumsum(x, axis=1, out=p[:, 1:])
+    c = np.arange(x.shape[0])
+    want = (p[c[None, :], s + n_out] - p[c[None, :], s]).sum(axis=1)
+    assert np.array_equal(out.astype(np.int64).sum(axis=1), want)
+
+
+def test_forward_u4_equals_u8_equals_f32():
+    """Packed 4-bit input equals its unpacked 8-bit and float forms."""
+    cfg = synth.CONFIGS["lowfreq_u4"]
+    n_chan, n_samp = 64, 8192
+    s = oracle.shift_table(n_chan, cfg["f_high"], 70.0 / n_chan, cfg["t_samp"], 0.0, 0.5, 30)
+    packed = synth.uniform_u4_packed(n_chan, n_samp, 3)
+    unpacked = synth.unpack_u4(packed, n_samp)
+    a = oracle.forward(packed, "u4", n_samp, s)
+    b = oracle.forward(unpacked, "u8", n_samp, s)
+    c, _ = oracle.forward_f32(unpacked.astype(np.float32), n_samp, s)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a.astype(np.float64), c)
+
+
+def _dense_matrix(s, n_samp):
+    n_dm, n_chan = s.shape
+    n_out = n_samp - int(s.max())
+    a = np.zeros((n_dm * n_out, n_chan * n_samp))
+    for d in range(n_dm):
+        for c in range(n_chan):
+            for t in range(n_out):
+                a[d * n_out + t, c * n_samp + t + s[d, c]] += 1.0
+    return a, n_out
+
+
+def test_forward_and_adjoint_against_dense_matrix():
+    """Both directions agree with an explicit 0/1 matrix built term by term."""
+    rng = np.random.default_rng(5)
+    n_chan, n_samp = 6, 80
+    s = oracle.shift_table(n_chan, 400.0, 20.0, 1e-3, 0.5, 0.5, 5)
+    a, n_out = _dense_matrix(s, n_samp)
+    x = rng.integers(0, 256, (n_chan, n_samp)).astype(np.uint8)
+    got = oracle.forward(x, "u8", n_samp, s)
+    assert np.array_equal(got.reshape(-1), a @ x.reshape(-1).astype(np.float64))
+    y = rng.standard_normal((s.shape[0], n_out)).astype(np.float32)
+    g = oracle.adjoint(y, n_chan, n_samp, s)
+    np.testing.assert_allclose(g.reshape(-1), a.T @ y.reshape(-1).astype(np.float64), rtol=0, atol=1e-12)
+
+
+# --------------------------------------------------------------------------------------
+# Adjoint: transpose of Eq. 3 (scatter form).
+# --------------------------------------------------------------------------------------
+
+def _grad_case(n_chan=96, n_samp=6000, n_dm=48):
+    cfg = synth.CONFIGS["grad_f32"]
+    s = oracle.shift_table(n_chan, cfg["f_high"], 300.0 / n_chan, cfg["t_samp"], 0.0, 4.0, n_dm)
+    return s, n_samp
+
+
+def test_adjoint_exact_dot_test_small_integers():
+    """<Ax, y> = <x, A^T y> exactly: small integers make every sum exact in FP64."""
+    s, n_samp = _grad_case()
+    rng = np.random.default_rng(9)
+    n_dm, n_chan = s.shape
+    n_out = oracle.n_out_for(s, n_samp)
+    x = rng.integers(-15, 16, (n_chan, n_samp)).astype(np.float32)
+    y = rng.integers(-3, 4, (n_dm, n_out)).astype(np.float32)
+    ax, _ = oracle.forward_f32(x, n_samp, s)
+    aty = oracle.adjoint(y, n_chan, n_samp, s)
+    lhs = float((ax * y.astype(np.float64)).sum())
+    rhs = float((x.astype(np.float64) * aty).sum())
+    assert lhs == rhs
+
+
+def test_adjoint_dot_test_gaussian():
+    s, n_samp = _grad_case()
+    rng = np.random.default_rng(10)
+    n_dm, n_chan = s.shape
+    n_out = oracle.n_out_for(s, n_samp)
+    x = rng.standard_normal((n_chan, n_samp)).astype(np.float32)
+    y = rng.standard_normal((n_dm, n_out)).astype(np.float32)
+    ax, _ = oracle.forward_f32(x, n_samp, s)
+    aty = oracle.adjoint(y, n_chan, n_samp, s)
+    lhs = float((ax * y.astype(np.float64)).sum())
+    rhs = float((x.astype(np.float64) * aty).sum())
+    assert abs(lhs - rhs) <= 1e-10 * max(abs(lhs), abs(rhs))
+
+
+def test_adjoint_unread_entries_are_zero():
+    """Input samples that no output reads get exactly zero gradient."""
+    s, n_samp = _grad_case()
+    n_dm, n_chan = s.shape
+    n_out = oracle.n_out_for(s, n_samp)
+    y = np.ones((n_dm, n_out), dtype=np.float32)
+    g = oracle.adjoint(y, n_chan, n_samp, s)
+    read = np.zeros((n_chan, n_samp), dtype=bool)
+    for c in range(n_chan):
+        for d in range(n_dm):
+            read[c, s[d, c]:s[d, c] + n_out] = True
+    assert (g[~read] == 0).all()
+    assert (g[read] > 0).all()
+
+
+def test_gradient_by_central_differences():
+    """loss = sum (A x - target)^2 is exactly quadratic, so central differences with
+    h = 0.5 have no truncation error; they must match 2 A^T (A x - target)."""
+    s, n_samp = _grad_case(n_chan=32, n_samp=3000, n_dm=20)
+    rng = np.random.default_rng(41)
+    n_dm, n_chan = s.shape
+    n_out = oracle.n_out_for(s, n_samp)
+    x = rng.standard_normal((n_chan, n_samp)).astype(np.float32)
+    target = rng.standard_normal((n_dm, n_out))
+
+    def loss(xx):
+        ax, _ = oracle.forward_f32(xx, n_samp, s)
+        return float(((ax - target) ** 2).sum())
+
+    ax, _ = oracle.forward_f32(x, n_samp, s)
+    grad = 2.0 * oracle.adjoint((ax - target).astype(np.float32), n_chan, n_samp, s)
+    picks = [(int(c), int(t)) for c, t in zip(rng.integers(0, n_chan, 24), rng.integers(0, n_samp, 24))]
+    picks += [(0, n_samp - 1), (0, n_out), (n_chan - 1, n_samp - 1)]  # the first two feed no output
+    h = 0.5
+    for c, t in picks:
+        xp, xm = x.copy(), x.copy()
+        xp[c, t] += h
+        xm[c, t] -= h
+        fd = (loss(xp) - loss(xm)) / (2 * h)
+        assert abs(fd - grad[c, t]) <= 1e-6 * max(1.0, abs(fd)), (c, t, fd, grad[c, t])
+    assert grad[0, n_samp - 1] == 0.0 and grad[0, n_out] == 0.0  # channel 0 never delays

@@ -1,0 +1,76 @@
+"""Plant plausible mistakes in copies of the oracle and check that the pins catch each.
+
+Each mutant is the oracle's C source with one edit (a dropped term, a wrong
+sign, index, rounding, constant or transposed operand).  The pins of
+``test_oracle.py`` run against the mutant build; at least one must fail.
+"""
+import os
+import tempfile
+
+import pytest
+
+import oracle
+import oracle.oracle as oracle_front
+import test_oracle as pins
+
+MUTANTS = {
+    "read index off by one": ("acc[t] += x_u8(x, pitch, c, t + s);", "acc[t] += x_u8(x, pitch, c, t + s + 1);"),
+    "round down instead of half up": ("floor(delay_samples + 0.5)", "floor(delay_samples)"),
+    "dropped reference-frequency term": ("1.0 / (f * f) - 1.0 / (f_high * f_high)", "1.0 / (f * f)"),
+    "inverse instead of inverse square": ("1.0 / (f * f) - 1.0 / (f_high * f_high)", "1.0 / f - 1.0 / f_high"),
+    "channel frequencies ascending": ("f_high - (double)c * chan_bw", "f_high - (double)(c + 1) * chan_bw"),
+    "first channel dropped": ("for (int c = 0; c < n_chan; ++c) {\n        int64_t s", "for (int c = 1; c < n_chan; ++c) {\n        int64_t s"),
+    "DM index off by one": ("dm_start + (double)d * dm_step", "dm_start + (double)(d + 1) * dm_step"),
+    "time sampling multiplied": ("((dm * ORACLE_KDM) * k) / t_samp", "((dm * ORACLE_KDM) * k) * (1e-4 / t_samp) / t_samp"),
+    "constant as printed with Eq. 1 in MHz ms": ("#define ORACLE_KDM 4.148808e3", "#define ORACLE_KDM 4.1488e3"),
+    "nibbles swapped": ("return (t & 1) ? (b >> 4) : (b & 15);", "return (t & 1) ? (b & 15) : (b >> 4);"),
+    "adjoint reads transposed table": ("int64_t s = shift[(int64_t)d * n_chan + c];\n      const float *yr", "int64_t s = shift[(int64_t)c * n_dm + d];\n      const float *yr"),
+    "adjoint delays the wrong way": ("gr[t + s] += (double)yr[t];", "gr[t + (n_samp - n_out - s)] += (double)yr[t];"),
+    "f32 forward drops last channel": ("for (int c = 0; c < n_chan; ++c) {\n      const float *row", "for (int c = 0; c < n_chan - 1; ++c) {\n      const float *row"),
+    "normalised by channel count": ("out[(int64_t)r * n_out + t] = (float)acc[t];", "out[(int64_t)r * n_out + t] = (float)(acc[t] / n_chan);"),
+}
+
+PIN_CALLS = [
+    ("hand delays", pins.test_shift_hand_derived_delays, ()),
+    ("plan max small", pins.test_shift_plan_max, ("small",)),
+    ("plan max lowfreq", pins.test_shift_plan_max, ("lowfreq_u4",)),
+    ("monotone", pins.test_shift_special_cases_and_monotone, ("small",)),
+    ("exact rational", pins.test_shift_matches_exact_rational, ("small",)),
+    ("eq4 slope", pins.test_shift_against_narrow_band_form, ("grad_f32",)),
+    ("literal u8", pins.test_forward_equals_literal_eq3, ("u8",)),
+    ("literal u4", pins.test_forward_equals_literal_eq3, ("u4",)),
+    ("literal f32", pins.test_forward_equals_literal_eq3, ("f32",)),
+    ("dm0", pins.test_forward_dm0_is_channel_sum, ()),
+    ("pulse", pins.test_forward_injected_pulse, ()),
+    ("u4 == u8 == f32", pins.test_forward_u4_equals_u8_equals_f32, ()),
+    ("dense", pins.test_forward_and_adjoint_against_dense_matrix, ()),
+    ("dot exact", pins.test_adjoint_exact_dot_test_small_integers, ()),
+    ("unread zero", pins.test_adjoint_unread_entries_are_zero, ()),
+]
+
+
+@pytest.fixture(scope="module")
+def workdir():
+    with tempfile.TemporaryDirectory() as d:
+        yield d
+    oracle_front.use_library(None)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_pins_catch_mutant(name, workdir):
+    old, new = MUTANTS[name]
+    src = oracle_front.source()
+    assert src.count(old) == 1, "mutation site not unique: " + name
+    lib = oracle_front.compile_source(src.replace(old, new), os.path.join(workdir, "m%d.so" % abs(hash(name))))
+    oracle_front.use_library(lib)
+    caught = []
+    try:
+        for label, fn, args in PIN_CALLS:
+            try:
+                fn(*args)
+            except (AssertionError, ValueError):
+                caught.append(label)
+                break
+    finally:
+        oracle_front.use_library(None)
+    assert caught, "no pin caught the mutant: " + name
