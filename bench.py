@@ -1,0 +1,186 @@
+"""Benchmark: brute-force dedispersion throughput on one MI355X.
+
+Default workload (the paper-shaped headline case): 8192 channels of 8-bit
+input, 2^20 samples at 64 us, 1500 MHz top of a 300 MHz band, 4000 trial DMs
+0..1999.5 in steps of 0.5, five injected pulses.  A step is one full forward
+transform of that filterbank, input already resident in HBM.
+
+Prints one JSON line with Tadds/s (adds = N_dm * N_out * N_ch), the
+x-real-time factor (N_t * t_samp / t_step), the VALU roofline fraction of the
+forward kernel, and the CPU oracle timed on a bounded sample of the same
+workload.
+
+  python bench.py [--steps K] [--warmup W] [--workload headline|lowfreq_u4|grad_f32|small]
+                  [--adjoint] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz = 39.32e12 32-bit VALU lane-operations per second.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_input(dd, torch, synth, cfg, plan):
+    """Seeded synthetic filterbank generated directly in device memory (pulses included)."""
+    n_chan, n_samp = cfg["n_chan"], cfg["n_samp"]
+    stream = torch.cuda.current_stream().cuda_stream
+    if cfg["dtype"] == "u8":
+        x = torch.empty((n_chan, plan.in_pitch_bytes), dtype=torch.uint8, device="cuda")
+        table = torch.from_numpy(synth.gaussian_table()).cuda()
+        synth.gaussian_u8_device(x.data_ptr(), n_chan, n_samp, plan.in_pitch_bytes, cfg["seed"],
+                                 table.data_ptr(), stream)
+        shift = plan.shift
+        for dp, width, t0 in cfg.get("pulses", []):
+            def at(r, c):
+                v = x[torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda()]
+                return v.cpu().numpy()
+            rows, cols, vals, _ = synth.boxcar_updates(at, shift[dp], t0, width, cfg["amp"])
+            x[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()] = torch.from_numpy(vals).cuda()
+    elif cfg["dtype"] == "u4":
+        x = torch.empty((n_chan, plan.in_pitch_bytes), dtype=torch.uint8, device="cuda")
+        synth.uniform_u4_device(x.data_ptr(), n_chan, n_samp, plan.in_pitch_bytes, cfg["seed"], stream)
+    else:
+        x = torch.from_numpy(synth.normal_f32(cfg["n_chan"], n_samp, cfg["seed"])).cuda()
+    torch.cuda.synchronize()
+    return x
+
+
+def cpu_baseline(cfg, seconds_target=15.0):
+    """Time the CPU oracle on a bounded sample: whole DM rows (all channels, all samples)."""
+    import oracle
+    import synth
+
+    s = oracle.shift_table(cfg["n_chan"], cfg["f_high"], cfg["chan_bw"], cfg["t_samp"], cfg["dm_start"],
+                           cfg["dm_step"], cfg["n_dm"])
+    n_out = oracle.n_out_for(s, cfg["n_samp"])
+    if cfg["dtype"] == "u8":
+        x = synth.gaussian_u8(cfg["n_chan"], cfg["n_samp"], cfg["seed"])
+        run = lambda rows: oracle.forward(x, "u8", cfg["n_samp"], s, rows=rows)  # noqa: E731
+    elif cfg["dtype"] == "u4":
+        x = synth.uniform_u4_packed(cfg["n_chan"], cfg["n_samp"], cfg["seed"])
+        run = lambda rows: oracle.forward(x, "u4", cfg["n_samp"], s, rows=rows)  # noqa: E731
+    else:
+        x = synth.normal_f32(cfg["n_chan"], cfg["n_samp"], cfg["seed"])
+        run = lambda rows: oracle.forward_f32(x, cfg["n_samp"], s, rows=rows, with_abs=False)  # noqa: E731
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # calibrate with a few rows, then size the sample to the time target
+    probe = list(range(0, cfg["n_dm"], max(1, cfg["n_dm"] // max(1, threads))))[:threads]
+    t = time.perf_counter()
+    run(probe)
+    dt = time.perf_counter() - t
+    per_row = dt / len(probe)
+    n_rows = int(max(len(probe), min(cfg["n_dm"], seconds_target / per_row)))
+    rows = np.linspace(0, cfg["n_dm"] - 1, n_rows).round().astype(int).tolist()
+    t = time.perf_counter()
+    run(rows)
+    dt = time.perf_counter() - t
+    adds = float(len(rows)) * n_out * cfg["n_chan"]
+    return {"value": adds / dt / 1e12, "unit": "Tadds/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of %d DM rows, all %d channels x %d output samples (%.2e adds, %.1f s)"
+                      % (len(rows), cfg["n_dm"], cfg["n_chan"], n_out, adds, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="headline")
+    ap.add_argument("--adjoint", action="store_true", help="time the adjoint instead of the forward")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2311_05341_amd as dd
+    import synth
+
+    cfg = synth.CONFIGS[args.workload]
+    log("workload %s: %s" % (args.workload, {k: v for k, v in cfg.items() if k != "pulses"}))
+    t = time.perf_counter()
+    plan = dd.Plan(cfg["n_chan"], cfg["n_samp"], cfg["dtype"], cfg["f_high"], cfg["chan_bw"], cfg["t_samp"],
+                   cfg["dm_start"], cfg["dm_step"], cfg["n_dm"])
+    log("plan %.2f s: n_out=%d max_shift=%d tile ns=%d dm/wave=%d waves=%d chan_block=%d" % (
+        time.perf_counter() - t, plan.n_out, plan.max_shift, plan.info.kernel_ns, plan.info.kernel_dm_per_wave,
+        plan.info.kernel_waves, plan.info.kernel_chan_block))
+    x = make_input(dd, torch, synth, cfg, plan)
+    out = torch.empty((plan.n_dm, plan.out_pitch), dtype=torch.float32, device="cuda")
+    if args.adjoint:
+        y = torch.randn((plan.n_dm, plan.out_pitch), device="cuda")
+        g = torch.empty((plan.n_chan, plan.in_row_elems), dtype=torch.float32, device="cuda")
+        step = lambda: plan.adjoint(y, out=g)  # noqa: E731
+    else:
+        step = lambda: plan.forward(x, out=out)  # noqa: E731
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+    stream = torch.cuda.current_stream()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in events:
+        e0.record(stream)
+        step()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [e0.elapsed_time(e1) for e0, e1 in events]
+    ms_step = wall * 1e3 / args.steps
+    adds = float(plan.n_dm) * plan.n_out * plan.n_chan
+    value = adds / (ms_step * 1e-3) / 1e12
+    k_avg = float(np.mean(kernel_ms))
+    achieved = adds / (k_avg * 1e-3) / 1e12
+    log("steps: kernel ms %s, wall ms/step %.3f" % (["%.3f" % v for v in kernel_ms], ms_step))
+    rec = {
+        "metric": "Tadds/s" + (" (adjoint)" if args.adjoint else ""),
+        "value": value,
+        "unit": "Tadds/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"u8": "u8", "u4": "u4", "f32": "f32"}[cfg["dtype"]],
+        "data": "synthetic",
+        "config": {"workload": args.workload, "n_chan": cfg["n_chan"], "n_samp": cfg["n_samp"],
+                   "n_dm": cfg["n_dm"], "dm_step": cfg["dm_step"], "t_samp_s": cfg["t_samp"],
+                   "f_high_mhz": cfg["f_high"], "band_mhz": cfg["chan_bw"] * cfg["n_chan"],
+                   "n_out": plan.n_out, "adds_per_step": adds, "input": cfg["dtype"],
+                   "direction": "adjoint" if args.adjoint else "forward"},
+        "x_realtime": cfg["n_samp"] * cfg["t_samp"] / (ms_step * 1e-3),
+        "x_realtime_streaming": plan.n_out * cfg["t_samp"] / (ms_step * 1e-3),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tadds/s",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "fwd_int_kernel" if cfg["dtype"] != "f32" else (
+                         "adj_f32_kernel" if args.adjoint else "fwd_f32_kernel"),
+                     "kernel_ms": k_avg},
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        rec["cpu_baseline"] = cpu_baseline(cfg)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,17 @@
+"""MI355X (gfx950) brute-force incoherent dedispersion.
+
+The transform, its adjoint and a batched multi-beam form run in hand-written
+HIP kernels behind the C ABI of include/dd.h; this package is the Python
+binding (ctypes + torch device memory and streams).
+"""
+from .binding import (  # noqa: F401
+    DD_F32,
+    DD_U4,
+    DD_U8,
+    LIB_PATH,
+    Batch,
+    DDError,
+    DedisperseFn,
+    Plan,
+    dedisperse,
+)

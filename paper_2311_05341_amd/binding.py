@@ -1,0 +1,263 @@
+"""Python binding of the dedispersion C ABI (include/dd.h).
+
+Argument marshalling only: every step of the transform runs in the HIP library
+``libdd.so``.  PyTorch supplies device memory and streams.  If the library is
+missing the import fails; there is no other execution path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdd.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libdd.so is not built: run `python -m paper_2311_05341_amd._build` "
+                      "(or __graft_entry__.build()) first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+DD_U8, DD_U4, DD_F32 = 1, 2, 3
+_DTYPES = {"u8": DD_U8, "u4": DD_U4, "f32": DD_F32}
+STATUS = {0: "DD_OK", -1: "DD_ERR_ARG", -2: "DD_ERR_TOO_SHORT", -3: "DD_ERR_RANGE", -4: "DD_ERR_ALIGN",
+          -5: "DD_ERR_DTYPE", -6: "DD_ERR_NOT_BOUND", -7: "DD_ERR_HIP", -8: "DD_ERR_NOMEM"}
+
+
+class PlanDesc(ctypes.Structure):
+    _fields_ = [("n_chan", ctypes.c_int32), ("n_samp", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("f_high_mhz", ctypes.c_double), ("chan_bw_mhz", ctypes.c_double),
+                ("chan_freq_mhz", ctypes.POINTER(ctypes.c_double)), ("t_samp_s", ctypes.c_double),
+                ("dm_start", ctypes.c_double), ("dm_step", ctypes.c_double), ("n_dm", ctypes.c_int32),
+                ("in_pitch_bytes", ctypes.c_int64)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n_out", ctypes.c_int64), ("max_shift", ctypes.c_int32), ("n_dm", ctypes.c_int32),
+                ("n_chan", ctypes.c_int32), ("in_pitch_bytes", ctypes.c_int64),
+                ("dev_table_bytes", ctypes.c_size_t), ("host_shift", ctypes.POINTER(ctypes.c_int32)),
+                ("kernel_ns", ctypes.c_int32), ("kernel_dm_per_wave", ctypes.c_int32),
+                ("kernel_waves", ctypes.c_int32), ("kernel_chan_block", ctypes.c_int32)]
+
+
+_vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+_lib.dd_plan_create.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(_vp)]
+_lib.dd_plan_create.restype = _i32
+_lib.dd_plan_destroy.argtypes = [_vp]
+_lib.dd_plan_destroy.restype = None
+_lib.dd_plan_query.argtypes = [_vp, ctypes.POINTER(PlanInfo)]
+_lib.dd_plan_query.restype = _i32
+_lib.dd_plan_bind.argtypes = [_vp, _vp, _sz, _vp]
+_lib.dd_plan_bind.restype = _i32
+_lib.dd_execute.argtypes = [_vp, _vp, _vp, _i64, _vp]
+_lib.dd_execute.restype = _i32
+_lib.dd_execute_adjoint.argtypes = [_vp, _vp, _i64, _vp, _vp]
+_lib.dd_execute_adjoint.restype = _i32
+_lib.dd_batch_create.argtypes = [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp)]
+_lib.dd_batch_create.restype = _i32
+_lib.dd_batch_workspace_bytes.argtypes = [_vp, ctypes.POINTER(_sz)]
+_lib.dd_batch_workspace_bytes.restype = _i32
+_lib.dd_batch_bind.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i64), _vp, _sz, _vp]
+_lib.dd_batch_bind.restype = _i32
+_lib.dd_execute_batched.argtypes = [_vp, _vp]
+_lib.dd_execute_batched.restype = _i32
+_lib.dd_batch_destroy.argtypes = [_vp]
+_lib.dd_batch_destroy.restype = None
+_lib.dd_status_string.argtypes = [_i32]
+_lib.dd_status_string.restype = ctypes.c_char_p
+_lib.dd_last_error.argtypes = []
+_lib.dd_last_error.restype = ctypes.c_char_p
+
+
+class DDError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+        detail = (_lib.dd_last_error() or b"").decode()
+        super().__init__("%s: %s (%s)" % (where, self.name, detail))
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != 0:
+        raise DDError(rc, where)
+
+
+def _stream_handle(stream=None) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return int(s.cuda_stream)
+
+
+def _round_up(v: int, a: int) -> int:
+    return (v + a - 1) // a * a
+
+
+class Plan:
+    """A dedispersion plan bound to the current device.
+
+    Mirrors dd_plan_desc.  ``in_pitch_bytes`` of 0 means tightly packed rows.
+    The FP64 shift table is built on the host by dd_plan_create; its device
+    copy lives in a torch uint8 tensor owned by the plan.
+    """
+
+    def __init__(self, n_chan, n_samp, dtype, f_high, chan_bw, t_samp, dm_start, dm_step, n_dm,
+                 chan_freq=None, in_pitch_bytes=0, device=None, bind=True):
+        self.dtype = dtype
+        self._freqs = None
+        d = PlanDesc()
+        d.n_chan, d.n_samp, d.dtype = int(n_chan), int(n_samp), _DTYPES[dtype]
+        d.f_high_mhz, d.chan_bw_mhz, d.t_samp_s = float(f_high), float(chan_bw), float(t_samp)
+        d.dm_start, d.dm_step, d.n_dm = float(dm_start), float(dm_step), int(n_dm)
+        d.in_pitch_bytes = int(in_pitch_bytes)
+        if chan_freq is not None:
+            self._freqs = np.ascontiguousarray(chan_freq, dtype=np.float64)
+            d.chan_freq_mhz = self._freqs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        h = _vp()
+        _check(_lib.dd_plan_create(ctypes.byref(d), ctypes.byref(h)), "dd_plan_create")
+        self._h = h
+        info = PlanInfo()
+        _check(_lib.dd_plan_query(h, ctypes.byref(info)), "dd_plan_query")
+        self.info = info
+        self.n_chan, self.n_samp, self.n_dm = int(n_chan), int(n_samp), int(n_dm)
+        self.n_out = int(info.n_out)
+        self.max_shift = int(info.max_shift)
+        self.in_pitch_bytes = int(info.in_pitch_bytes)
+        self.out_pitch = _round_up(self.n_out, 4)
+        self.workspace = None
+        self.device = None
+        if bind:
+            self.bind(device)
+
+    @property
+    def shift(self) -> np.ndarray:
+        """Copy of the host shift table, int32 [n_dm][n_chan]."""
+        a = np.ctypeslib.as_array(self.info.host_shift, shape=(self.n_dm * self.n_chan,))
+        return a.reshape(self.n_dm, self.n_chan).copy()
+
+    def bind(self, device=None, stream=None):
+        dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        with torch.cuda.device(dev):
+            ws = torch.empty(int(self.info.dev_table_bytes), dtype=torch.uint8, device=dev)
+            _check(_lib.dd_plan_bind(self._h, ws.data_ptr(), ws.numel(), _stream_handle(stream)), "dd_plan_bind")
+        self.workspace, self.device = ws, dev
+
+    @property
+    def in_row_elems(self) -> int:
+        return self.in_pitch_bytes // (4 if self.dtype == "f32" else 1)
+
+    def empty_input(self):
+        dt = torch.float32 if self.dtype == "f32" else torch.uint8
+        return torch.empty((self.n_chan, self.in_row_elems), dtype=dt, device=self.device)
+
+    def _check_input(self, x):
+        dt = torch.float32 if self.dtype == "f32" else torch.uint8
+        if x.dtype != dt or x.device != self.device or x.dim() != 2 or x.shape[0] != self.n_chan:
+            raise ValueError("input must be %s [n_chan][...] on %s" % (dt, self.device))
+        if x.stride(1) != 1 or x.stride(0) * x.element_size() != self.in_pitch_bytes:
+            raise ValueError("input rows must be contiguous with pitch %d bytes" % self.in_pitch_bytes)
+        need = self.n_samp // 2 if self.dtype == "u4" else self.n_samp
+        if x.shape[1] < need:
+            raise ValueError("input rows are shorter than n_samp")
+
+    def forward(self, x, out=None, stream=None):
+        """S = dedisperse(x): float32 [n_dm][n_out] (a view of an [n_dm][out_pitch] buffer)."""
+        self._check_input(x)
+        if out is None:
+            out = torch.empty((self.n_dm, self.out_pitch), dtype=torch.float32, device=self.device)
+        if out.dtype != torch.float32 or out.dim() != 2 or out.shape[0] != self.n_dm or out.stride(1) != 1:
+            raise ValueError("out must be float32 [n_dm][>= n_out]")
+        _check(_lib.dd_execute(self._h, x.data_ptr(), out.data_ptr(), out.stride(0), _stream_handle(stream)),
+               "dd_execute")
+        return out[:, : self.n_out]
+
+    def adjoint(self, y, out=None, stream=None):
+        """g = A^T y for float32 plans: float32 [n_chan][n_samp] (view of a pitched buffer)."""
+        if y.dtype != torch.float32 or y.dim() != 2 or y.shape[0] != self.n_dm or y.stride(1) != 1:
+            raise ValueError("y must be float32 [n_dm][>= n_out] with contiguous rows")
+        if y.shape[1] < self.n_out:
+            raise ValueError("y rows shorter than n_out")
+        if y.stride(0) % 4 or y.data_ptr() % 16:
+            y = _pad_rows(y, self.n_out)
+        if out is None:
+            out = torch.empty((self.n_chan, self.in_row_elems), dtype=torch.float32, device=self.device)
+        _check(_lib.dd_execute_adjoint(self._h, y.data_ptr(), y.stride(0), out.data_ptr(), _stream_handle(stream)),
+               "dd_execute_adjoint")
+        return out[:, : self.n_samp]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.dd_plan_destroy(h)
+            self._h = None
+
+
+def _pad_rows(y, n):
+    p = torch.zeros((y.shape[0], _round_up(n, 4)), dtype=y.dtype, device=y.device)
+    p[:, :n] = y[:, :n]
+    return p
+
+
+def dedisperse(x, plan: Plan, out=None):
+    """Forward transform of ``x`` with ``plan`` on the current stream."""
+    return plan.forward(x, out=out)
+
+
+class DedisperseFn(torch.autograd.Function):
+    """Differentiable forward transform for float32 plans; backward is dd_execute_adjoint."""
+
+    @staticmethod
+    def forward(ctx, x, plan):
+        if plan.dtype != "f32":
+            raise TypeError("autograd needs a float32 plan")
+        ctx.plan = plan
+        return plan.forward(x.contiguous() if x.stride(1) != 1 else x)
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        plan = ctx.plan
+        g = grad_out
+        if g.stride(1) != 1 or g.stride(0) % 4 or g.data_ptr() % 16:
+            g = _pad_rows(g, plan.n_out)
+        gx = plan.adjoint(g)
+        full = torch.zeros((plan.n_chan, plan.in_row_elems), dtype=torch.float32, device=plan.device)
+        full[:, : plan.n_samp] = gx
+        return full, None
+
+
+class Batch:
+    """Many beams (one plan each) in one persistent, graph-replayed launch."""
+
+    def __init__(self, plans, inputs, outputs=None, stream=None):
+        n = len(plans)
+        self.plans = list(plans)
+        arr = (_vp * n)(*[p._h for p in plans])
+        h = _vp()
+        _check(_lib.dd_batch_create(arr, n, ctypes.byref(h)), "dd_batch_create")
+        self._h = h
+        nbytes = _sz()
+        _check(_lib.dd_batch_workspace_bytes(h, ctypes.byref(nbytes)), "dd_batch_workspace_bytes")
+        dev = plans[0].device
+        self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)
+        for p, x in zip(plans, inputs):
+            p._check_input(x)
+        self.inputs = list(inputs)
+        if outputs is None:
+            outputs = [torch.empty((p.n_dm, p.out_pitch), dtype=torch.float32, device=dev) for p in plans]
+        self.outputs = list(outputs)
+        ins = (_vp * n)(*[x.data_ptr() for x in self.inputs])
+        outs = (_vp * n)(*[o.data_ptr() for o in self.outputs])
+        pitches = (_i64 * n)(*[o.stride(0) for o in self.outputs])
+        _check(_lib.dd_batch_bind(h, ins, outs, pitches, self.workspace.data_ptr(), self.workspace.numel(),
+                                  _stream_handle(stream)), "dd_batch_bind")
+
+    def run(self, stream=None):
+        _check(_lib.dd_execute_batched(self._h, _stream_handle(stream)), "dd_execute_batched")
+        return [o[:, : p.n_out] for o, p in zip(self.outputs, self.plans)]
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.dd_batch_destroy(h)
+            self._h = None

@@ -1,0 +1,93 @@
+// Internal declarations shared by the host plan code, the C ABI and the kernels.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dd.h"
+
+namespace dd {
+
+// Thread-local error detail; returns the status for chaining.
+dd_status fail(dd_status st, const std::string &msg);
+
+// Tile shape of the forward kernels.  A workgroup covers `waves * dm_per_wave`
+// DM rows and `64 * ns` output samples; each lane owns `ns` consecutive samples
+// of `dm_per_wave` rows.  Channels are staged `chan_block` at a time into LDS
+// rows of `row_bytes` bytes (unpacked samples).
+struct TileCfg {
+  int ns = 32;           // samples per lane (16 or 32)
+  int dm_per_wave = 4;   // DM rows per wave
+  int waves = 4;         // waves per workgroup
+  int chan_block = 16;   // channels per LDS stage
+  int row_bytes = 0;     // LDS bytes per staged channel row
+  int lds_bytes = 0;     // total dynamic LDS
+};
+
+// Everything the device needs about one plan, in device-visible form.
+struct DevPlan {
+  const int32_t *shift;  // [n_dm][n_chan]
+  int32_t n_chan, n_dm;
+  int64_t n_samp, n_out, in_pitch_bytes;
+  int32_t dtype;
+};
+
+}  // namespace dd
+
+struct dd_plan {
+  dd_plan_desc desc{};
+  std::vector<double> freqs;   // explicit frequencies (empty = uniform)
+  std::vector<int32_t> shift;  // [n_dm][n_chan]
+  std::vector<int32_t> shift_t;  // [n_chan][n_dm] (float plans, adjoint)
+  std::vector<int32_t> smax;     // [adjoint channel blocks][n_dm] (float plans)
+  int64_t n_out = 0;
+  int32_t max_shift = 0;
+  int64_t in_pitch_bytes = 0;
+  dd::TileCfg fwd;             // forward tile shape
+  dd::TileCfg adj;             // adjoint tile shape (f32 plans)
+  int32_t span_fwd = 0;        // largest delay spread inside a forward DM block
+  int32_t span_adj = 0;        // largest delay spread inside an adjoint channel block
+  // binding
+  const int32_t *d_shift = nullptr;
+  int device = -1;
+  bool bound = false;
+};
+
+namespace dd {
+
+// Host plan helpers (plan.cpp).
+dd_status build_shift_table(dd_plan &p);
+int32_t max_dm_block_span(const dd_plan &p, int dm_block);
+int row_bytes_for(int dtype, int ns, int span);
+int32_t max_chan_block_span(const dd_plan &p, int chan_block);
+dd_status choose_forward_tiles(dd_plan &p);
+dd_status choose_adjoint_tiles(dd_plan &p);
+void build_adjoint_tables(dd_plan &p);
+size_t table_bytes(const dd_plan &p);
+
+// One beam of a batch, as the persistent kernel sees it.
+struct BeamDesc {
+  const uint8_t *x;
+  const int32_t *shift;
+  float *out;
+  int64_t pitch, n_samp, n_out, out_pitch;
+  int64_t item_begin;  // first work item of this beam
+  int32_t n_chan, n_dm, row_bytes, chan_block, tiles_t, tiles_d;
+};
+
+// Kernel launchers (kernels.hip).  Return hipError_t as int.
+int launch_forward(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream);
+int launch_adjoint(const dd_plan &p, const float *d_y, int64_t y_pitch, float *d_grad, void *stream);
+
+// Persistent batched forward: kernel entry, its launch geometry and the
+// counter-reset kernel, for recording into a graph.
+struct BatchLaunch {
+  const void *reset_fn;
+  const void *main_fn;
+  int grid, block, lds_bytes;
+};
+int batch_kernels(int ns, int dm_per_wave, int waves, bool u4, int lds_bytes, BatchLaunch *out);
+
+}  // namespace dd

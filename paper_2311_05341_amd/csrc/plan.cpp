@@ -1,0 +1,207 @@
+// Host side of a plan: validation, the FP64 integer shift table, delay spans
+// and the tile shape.  No device code here.
+//
+// The shift table follows Sec. 1, Eq. 1 (cold-plasma delay relative to the top
+// of the band) with channel c at f_high - c*df as in Sec. 4.1, the constant
+// 4.148808e3 s MHz^2 cm^3/pc, divided by the sampling time and rounded half up.
+// It is evaluated in IEEE FP64 with no contraction, in one fixed order, so the
+// table is bit-for-bit reproducible; the device only receives the integers.
+#pragma clang fp contract(off)
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <thread>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+static const double kDispersionConstant = 4.148808e3;  // s MHz^2 cm^3 / pc
+
+static double channel_freq(const dd_plan &p, int c) {
+  if (!p.freqs.empty()) return p.freqs[c];
+  return p.desc.f_high_mhz - (double)c * p.desc.chan_bw_mhz;
+}
+
+dd_status build_shift_table(dd_plan &p) {
+  const int nc = p.desc.n_chan, nd = p.desc.n_dm;
+  const double fh = p.desc.f_high_mhz;
+  std::vector<double> k(nc);
+  for (int c = 0; c < nc; ++c) {
+    double f = channel_freq(p, c);
+    if (!(f > 0.0) || !(f <= fh) || !isfinite(f))
+      return fail(DD_ERR_RANGE, "channel " + std::to_string(c) + " frequency " + std::to_string(f) +
+                                    " MHz is not in (0, f_high]");
+    k[c] = 1.0 / (f * f) - 1.0 / (fh * fh);
+  }
+  try {
+    p.shift.assign((size_t)nd * nc, 0);
+  } catch (const std::bad_alloc &) {
+    return fail(DD_ERR_NOMEM, "shift table allocation failed");
+  }
+  const double t = p.desc.t_samp_s, d0 = p.desc.dm_start, step = p.desc.dm_step;
+  int bad = 0;
+  auto rows = [&](int lo, int hi, int *flag) {
+    for (int d = lo; d < hi; ++d) {
+      const double dm = d0 + (double)d * step;
+      int32_t *row = p.shift.data() + (size_t)d * nc;
+      for (int c = 0; c < nc; ++c) {
+        const double v = ((dm * kDispersionConstant) * k[c]) / t;
+        const double s = floor(v + 0.5);
+        if (!(s >= 0.0 && s <= 2147483647.0)) { *flag = 1; return; }
+        row[c] = (int32_t)s;
+      }
+    }
+  };
+  const size_t work = (size_t)nd * nc;
+  int nthr = work < (1u << 20) ? 1 : (int)std::min<unsigned>(16, std::max(1u, std::thread::hardware_concurrency()));
+  if (nthr == 1) {
+    rows(0, nd, &bad);
+  } else {
+    std::vector<std::thread> th;
+    std::vector<int> flags(nthr, 0);
+    for (int i = 0; i < nthr; ++i) {
+      int lo = (int)((int64_t)nd * i / nthr), hi = (int)((int64_t)nd * (i + 1) / nthr);
+      th.emplace_back(rows, lo, hi, &flags[i]);
+    }
+    for (auto &x : th) x.join();
+    for (int f : flags) bad |= f;
+  }
+  if (bad) return fail(DD_ERR_RANGE, "a shift does not fit in int32");
+  // The kernels rely on delays never decreasing with d (each DM block is
+  // staged from its first row's delays); Eq. 1 with dm_step >= 0 and
+  // f_c <= f_high guarantees it, and so does monotone FP64 rounding.  Check.
+  for (int d = 1; d < nd; ++d) {
+    const int32_t *a = p.shift.data() + (size_t)(d - 1) * nc, *b = a + nc;
+    for (int c = 0; c < nc; ++c)
+      if (b[c] < a[c]) return fail(DD_ERR_RANGE, "shift table decreases with DM");
+  }
+  int32_t mx = 0;
+  for (int32_t v : p.shift) mx = std::max(mx, v);
+  p.max_shift = mx;
+  p.n_out = p.desc.n_samp - (int64_t)mx;
+  if (p.n_out <= 0)
+    return fail(DD_ERR_TOO_SHORT, "n_samp " + std::to_string(p.desc.n_samp) + " <= largest shift " +
+                                      std::to_string(mx));
+  return DD_OK;
+}
+
+// Largest delay spread max_c(shift[d_hi][c] - shift[d_lo][c]) over the DM blocks
+// [b*dm_block, b*dm_block + dm_block) (the last block clipped).  Shifts never
+// decrease with d, so the spread inside a block is last row minus first row.
+int32_t max_dm_block_span(const dd_plan &p, int dm_block) {
+  const int nc = p.desc.n_chan, nd = p.desc.n_dm;
+  int32_t span = 0;
+  for (int lo = 0; lo < nd; lo += dm_block) {
+    const int hi = std::min(lo + dm_block, nd) - 1;
+    const int32_t *a = p.shift.data() + (size_t)lo * nc, *b = p.shift.data() + (size_t)hi * nc;
+    for (int c = 0; c < nc; ++c) span = std::max(span, b[c] - a[c]);
+  }
+  return span;
+}
+
+// Largest spread max_c shift - min_c shift over channel blocks [b*cb, b*cb+cb), any DM.
+int32_t max_chan_block_span(const dd_plan &p, int chan_block) {
+  const int nc = p.desc.n_chan, nd = p.desc.n_dm;
+  int32_t span = 0;
+  for (int d = 0; d < nd; ++d) {
+    const int32_t *row = p.shift.data() + (size_t)d * nc;
+    for (int lo = 0; lo < nc; lo += chan_block) {
+      const int hi = std::min(lo + chan_block, nc);
+      int32_t mn = row[lo], mx = row[lo];
+      for (int c = lo + 1; c < hi; ++c) { mn = std::min(mn, row[c]); mx = std::max(mx, row[c]); }
+      span = std::max(span, mx - mn);
+    }
+  }
+  return span;
+}
+
+static const int kLdsLimit = 160 * 1024;
+
+static int round_up(int64_t v, int a) { return (int)((v + a - 1) / a * a); }
+
+// LDS bytes of one staged row for a tile of `ns` samples per lane and a delay
+// spread `span`.  Integer rows hold unpacked uint8 samples starting at the
+// block's first-DM delay rounded down to the staging unit (16 samples for u8,
+// 32 for u4: one 16-byte global chunk); a lane reads ns/16 + 1 aligned 16-byte
+// chunks at offset up to span + unit - 1, so the row needs
+// 64*ns + span + unit + 15 bytes.  Float rows hold samples from the delay
+// rounded down to 4 and a lane reads ns/4 + 1 chunks of 4 floats.
+int row_bytes_for(int dtype, int ns, int span) {
+  if (dtype == DD_F32) return 4 * round_up((int64_t)64 * ns + span + 8, 4);
+  const int unit = dtype == DD_U4 ? 32 : 16;
+  return round_up((int64_t)64 * ns + span + unit + 16, unit);
+}
+
+dd_status choose_forward_tiles(dd_plan &p) {
+  TileCfg t;
+  t.ns = p.desc.dtype == DD_F32 ? 16 : 32;
+  t.dm_per_wave = 4;
+  t.waves = 4;
+  for (;;) {
+    const int span = max_dm_block_span(p, t.waves * t.dm_per_wave);
+    t.row_bytes = row_bytes_for(p.desc.dtype, t.ns, span);
+    for (t.chan_block = 16; t.chan_block >= 1; t.chan_block /= 2) {
+      t.lds_bytes = t.chan_block * t.row_bytes;
+      if (t.lds_bytes <= kLdsLimit) break;
+    }
+    if (t.chan_block >= 1) {
+      p.span_fwd = span;
+      p.fwd = t;
+      return DD_OK;
+    }
+    if (t.dm_per_wave > 1) { t.dm_per_wave /= 2; continue; }
+    if (t.waves > 1) { t.waves /= 2; continue; }
+    return fail(DD_ERR_RANGE, "delay spread of one DM block exceeds the LDS staging capacity");
+  }
+}
+
+dd_status choose_adjoint_tiles(dd_plan &p) {
+  TileCfg t;
+  t.ns = 16; t.dm_per_wave = 4; t.waves = 4; t.chan_block = 16;  // dm_per_wave = channels per wave here
+  for (;;) {
+    const int span = max_chan_block_span(p, t.waves * t.dm_per_wave);
+    t.row_bytes = round_up((int64_t)(64 * t.ns + span + 4 + 4 + 4) * 4, 16);
+    for (t.chan_block = 16; t.chan_block >= 1; t.chan_block /= 2) {  // DM rows per stage
+      t.lds_bytes = t.chan_block * t.row_bytes;
+      if (t.lds_bytes <= kLdsLimit) break;
+    }
+    if (t.chan_block >= 1) {
+      p.span_adj = span;
+      p.adj = t;
+      return DD_OK;
+    }
+    if (t.dm_per_wave > 1) { t.dm_per_wave /= 2; continue; }
+    if (t.waves > 1) { t.waves /= 2; continue; }
+    return fail(DD_ERR_RANGE, "channel delay spread exceeds LDS staging capacity");
+  }
+}
+
+// Adjoint tables: the shift table transposed to [n_chan][n_dm] (a workgroup
+// walks DMs for fixed channels) and, per adjoint channel block and DM, the
+// largest delay of the block's channels (the base of the staged y rows).
+void build_adjoint_tables(dd_plan &p) {
+  const int nc = p.desc.n_chan, nd = p.desc.n_dm;
+  const int cpb = p.adj.waves * p.adj.dm_per_wave;
+  const int nblk = (nc + cpb - 1) / cpb;
+  p.shift_t.assign((size_t)nc * nd, 0);
+  for (int d = 0; d < nd; ++d)
+    for (int c = 0; c < nc; ++c) p.shift_t[(size_t)c * nd + d] = p.shift[(size_t)d * nc + c];
+  p.smax.assign((size_t)nblk * nd, 0);
+  for (int b = 0; b < nblk; ++b)
+    for (int d = 0; d < nd; ++d) {
+      int32_t m = 0;
+      for (int c = b * cpb; c < std::min(nc, (b + 1) * cpb); ++c) m = std::max(m, p.shift[(size_t)d * nc + c]);
+      p.smax[(size_t)b * nd + d] = m;
+    }
+}
+
+size_t table_bytes(const dd_plan &p) {
+  size_t b = (p.shift.size() + p.shift_t.size() + p.smax.size()) * sizeof(int32_t);
+  return (b + 255) / 256 * 256;
+}
+
+}  // namespace dd

@@ -1,79 +1,134 @@
 """Seeded synthetic filterbanks shaped like the paper's workloads.
 
-Shared by the tests, the benchmark and the smoke check as the only common
-input source for the CPU oracle and the GPU library.  It holds none of the
+The only input source shared by the CPU oracle (through the tests and the
+benchmark's CPU-baseline leg) and the GPU library.  It holds none of the
 transform's arithmetic: pulse injection takes the per-channel delays of the
-pulse's DM as an argument from the caller.
+pulse's DM from the caller.  These stand in for the SIGPROC ``fake`` files the
+paper generated its test signals with (Sec. 5), which are not available.
 
-Recipe (stands in for the SIGPROC ``fake`` files the paper generated its test
-signals with, Sec. 5):
+Recipe:
 
-* Every channel row c draws from its own stream ``PCG64(SeedSequence([seed, c]))``,
-  so a row's values do not depend on how many rows are generated or in which
-  order, and rows can be generated in parallel.
-* 8-bit noise: ``normal(mean, sigma)``, rounded to nearest (``np.rint``),
-  clipped to 0..255.
-* 4-bit noise: uniform integers 0..15, packed two per byte, the even sample in
-  the low nibble.
-* float noise: standard normal, float32.
-* Pulses: a boxcar of amplitude A and width W starting at arrival time t0 at the
-  top of the band, added at ``x[c][t0 + k + delay[c]]`` for k < W and clipped
-  at 255 (8-bit) after the noise is clipped.
+* 8-bit and 4-bit samples come from a counter-based generator (``gen_common.h``):
+  SplitMix64's output function over a per-row counter, 16 bits per sample, so
+  any time slice of any row can be produced on its own, on the CPU (``gen.c``)
+  or directly in GPU memory (``gen.hip``), with identical bytes.
+* 8-bit Gaussian noise N(mean, sigma), rounded to nearest and clipped to
+  0..255, is the 16-bit draw looked up in a quantile table:
+  ``clip(rint(mean + sigma * Phi^-1((i + 0.5) / 65536)), 0, 255)``.
+* 4-bit noise: uniform 0..15 (the low 4 bits of the draw), two samples per
+  byte, the even sample in the low nibble.
+* float noise: standard normal float32, one ``PCG64(SeedSequence([seed, c]))``
+  stream per channel row.
+* Pulses: a boxcar of amplitude A and width W starting at arrival time t0 at
+  the top of the band, added at ``x[c][t0 + k + delay[c]]`` for k < W and
+  clipped at 255, after the noise.
 """
 from __future__ import annotations
 
+import ctypes
 import os
-from concurrent.futures import ThreadPoolExecutor
+import subprocess
+from functools import lru_cache
 
 import numpy as np
 
-_WORKERS = max(1, min(16, os.cpu_count() or 1))
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_CPU_LIB = os.path.join(_HERE, "libsynth_cpu.so")
+_GPU_LIB = os.path.join(_HERE, "libsynth_gpu.so")
+_cpu = None
+_gpu = None
 
 
-def _rng(seed: int, row: int) -> np.random.Generator:
-    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), int(row)])))
+def build(gpu: bool = True) -> None:
+    """Compile the CPU generator (gcc) and, if asked, the GPU generator (hipcc, gfx950)."""
+    tmp = _CPU_LIB + ".tmp%d" % os.getpid()
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall",
+                    os.path.join(_HERE, "gen.c"), "-o", tmp], check=True)
+    os.replace(tmp, _CPU_LIB)
+    if gpu:
+        tmp = _GPU_LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["hipcc", "--offload-arch=gfx950", "-O3", "-fPIC", "-shared", "-std=c++17",
+                        "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                        os.path.join(_HERE, "gen.hip"), "-o", tmp],
+                       check=True, stderr=subprocess.DEVNULL)
+        os.replace(tmp, _GPU_LIB)
 
 
-def _fill_rows(out: np.ndarray, fn, workers: int | None = None) -> np.ndarray:
-    n = out.shape[0]
-    w = workers or _WORKERS
-    if n * out.shape[1] < (1 << 22) or w == 1:
-        for c in range(n):
-            fn(c, out[c])
-    else:
-        with ThreadPoolExecutor(max_workers=w) as ex:
-            list(ex.map(lambda c: fn(c, out[c]), range(n)))
-    return out
+def _cpu_lib():
+    global _cpu
+    if _cpu is None:
+        src = os.path.join(_HERE, "gen.c")
+        if not os.path.exists(_CPU_LIB) or os.path.getmtime(_CPU_LIB) < os.path.getmtime(src):
+            build(gpu=False)
+        lib = ctypes.CDLL(_CPU_LIB)
+        vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
+        lib.synth_u8_table.argtypes = [vp, i32, i64, i64, u64, i64, vp]
+        lib.synth_u8_table.restype = None
+        lib.synth_u4_packed.argtypes = [vp, i32, i64, i64, u64, i64]
+        lib.synth_u4_packed.restype = None
+        _cpu = lib
+    return _cpu
+
+
+def _gpu_lib():
+    global _gpu
+    if _gpu is None:
+        if not os.path.exists(_GPU_LIB):
+            raise RuntimeError("synthetic GPU generator not built: run synth.build()")
+        lib = ctypes.CDLL(_GPU_LIB)
+        vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
+        lib.synth_u8_table_gpu.argtypes = [vp, i32, i64, i64, u64, i64, vp, vp]
+        lib.synth_u8_table_gpu.restype = i32
+        lib.synth_u4_packed_gpu.argtypes = [vp, i32, i64, i64, u64, i64, vp]
+        lib.synth_u4_packed_gpu.restype = i32
+        _gpu = lib
+    return _gpu
+
+
+@lru_cache(maxsize=8)
+def gaussian_table(mean: float = 128.0, sigma: float = 16.0) -> np.ndarray:
+    """uint8[65536] quantile table of N(mean, sigma), rounded to nearest, clipped to 0..255."""
+    from scipy.special import ndtri
+    p = (np.arange(65536, dtype=np.float64) + 0.5) / 65536.0
+    v = np.clip(np.rint(mean + sigma * ndtri(p)), 0.0, 255.0)
+    return v.astype(np.uint8)
 
 
 def gaussian_u8(n_chan: int, n_samp: int, seed: int, mean: float = 128.0, sigma: float = 16.0,
-                pitch: int | None = None) -> np.ndarray:
-    """uint8 [n_chan][pitch] of rounded, clipped Gaussian noise; columns >= n_samp are 0."""
+                pitch: int | None = None, t_start: int = 0) -> np.ndarray:
+    """uint8 [n_chan][pitch]: samples t_start .. t_start + n_samp - 1 of every row; padding is 0."""
     pitch = n_samp if pitch is None else pitch
-    assert pitch >= n_samp
+    assert pitch >= n_samp and n_chan > 0 and n_samp > 0
     out = np.zeros((n_chan, pitch), dtype=np.uint8)
-
-    def row(c, dst):
-        v = _rng(seed, c).normal(mean, sigma, n_samp)
-        np.rint(v, out=v)
-        np.clip(v, 0.0, 255.0, out=v)
-        dst[:n_samp] = v.astype(np.uint8)
-
-    return _fill_rows(out, row)
+    table = gaussian_table(mean, sigma)
+    _cpu_lib().synth_u8_table(out.ctypes.data, n_chan, n_samp, pitch, seed, t_start, table.ctypes.data)
+    return out
 
 
-def uniform_u4_packed(n_chan: int, n_samp: int, seed: int, pitch_bytes: int | None = None) -> np.ndarray:
+def uniform_u4_packed(n_chan: int, n_samp: int, seed: int, pitch_bytes: int | None = None,
+                      t_start: int = 0) -> np.ndarray:
     """uint8 [n_chan][pitch_bytes]: uniform 0..15 samples, two per byte, even sample low."""
-    assert n_samp % 2 == 0
+    assert n_samp % 2 == 0 and t_start % 2 == 0
     pb = n_samp // 2 if pitch_bytes is None else pitch_bytes
     assert pb >= n_samp // 2
     out = np.zeros((n_chan, pb), dtype=np.uint8)
+    _cpu_lib().synth_u4_packed(out.ctypes.data, n_chan, n_samp, pb, seed, t_start)
+    return out
 
-    def row(c, dst):
-        v = _rng(seed, c).integers(0, 16, n_samp, dtype=np.uint8)
-        dst[: n_samp // 2] = v[0::2] | (v[1::2] << 4)
 
-    return _fill_rows(out, row)
+def gaussian_u8_device(ptr: int, n_chan: int, n_samp: int, pitch: int, seed: int, table_ptr: int,
+                       stream: int = 0, t_start: int = 0) -> None:
+    """Fill device memory at ``ptr`` exactly as :func:`gaussian_u8` would (table on the device)."""
+    rc = _gpu_lib().synth_u8_table_gpu(ptr, n_chan, n_samp, pitch, seed, t_start, table_ptr, stream)
+    if rc != 0:
+        raise RuntimeError("synth_u8_table_gpu failed (%d)" % rc)
+
+
+def uniform_u4_device(ptr: int, n_chan: int, n_samp: int, pitch_bytes: int, seed: int,
+                      stream: int = 0, t_start: int = 0) -> None:
+    rc = _gpu_lib().synth_u4_packed_gpu(ptr, n_chan, n_samp, pitch_bytes, seed, t_start, stream)
+    if rc != 0:
+        raise RuntimeError("synth_u4_packed_gpu failed (%d)" % rc)
 
 
 def unpack_u4(packed: np.ndarray, n_samp: int) -> np.ndarray:
@@ -85,39 +140,42 @@ def unpack_u4(packed: np.ndarray, n_samp: int) -> np.ndarray:
 
 
 def normal_f32(n_chan: int, n_samp: int, seed: int, pitch: int | None = None) -> np.ndarray:
-    """float32 [n_chan][pitch] standard-normal noise; columns >= n_samp are 0."""
+    """float32 [n_chan][pitch] standard-normal noise, one PCG64 stream per row; padding 0."""
     pitch = n_samp if pitch is None else pitch
     out = np.zeros((n_chan, pitch), dtype=np.float32)
+    for c in range(n_chan):
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(seed), c])))
+        out[c, :n_samp] = rng.standard_normal(n_samp, dtype=np.float32)
+    return out
 
-    def row(c, dst):
-        dst[:n_samp] = _rng(seed, c).standard_normal(n_samp, dtype=np.float32)
 
-    return _fill_rows(out, row)
+def boxcar_updates(x_at, delay: np.ndarray, t0: int, width: int, amp: int):
+    """Positions and new values of a dispersed boxcar pulse, clipped at 255.
+
+    ``x_at(rows, cols)`` returns the current uint8 values at those positions
+    (from a host array, or regenerated from the counter generator).  Returns
+    (rows, cols, new_values, applied) where applied[c][k] is the increment that
+    survived clipping; its column sums are the exact gain of the dedispersed
+    pulse at its DM.
+    """
+    n_chan = delay.shape[0]
+    rows = np.repeat(np.arange(n_chan, dtype=np.int64), width)
+    cols = (t0 + delay.astype(np.int64)[:, None] + np.arange(width, dtype=np.int64)[None, :]).reshape(-1)
+    before = np.asarray(x_at(rows, cols), dtype=np.int64)
+    after = np.minimum(before + amp, 255)
+    applied = (after - before).reshape(n_chan, width)
+    return rows, cols, after.astype(np.uint8), applied
 
 
 def inject_boxcar_u8(x: np.ndarray, delay: np.ndarray, t0: int, width: int, amp: int) -> np.ndarray:
-    """Add a dispersed boxcar in place: x[c][t0 + k + delay[c]] += amp, clipped at 255.
-
-    ``delay`` is the integer per-channel delay of the pulse's DM, supplied by
-    the caller.  Returns the int64 [n_chan][width] array of increments actually
-    applied (after clipping), whose column sums are the exact amplitude the
-    dedispersed pulse gains at its DM.
-    """
-    n_chan = x.shape[0]
-    assert delay.shape == (n_chan,)
-    applied = np.zeros((n_chan, width), dtype=np.int64)
-    for k in range(width):
-        cols = t0 + k + delay.astype(np.int64)
-        rows = np.arange(n_chan)
-        before = x[rows, cols].astype(np.int64)
-        after = np.minimum(before + amp, 255)
-        x[rows, cols] = after.astype(np.uint8)
-        applied[:, k] = after - before
+    """Add a dispersed boxcar to a host array in place; returns the applied increments."""
+    rows, cols, vals, applied = boxcar_updates(lambda r, c: x[r, c], delay, t0, width, amp)
+    x[rows, cols] = vals
     return applied
 
 
-#: The five workloads: shapes, bands, DM plans and seeds.  Channel c sits at
-#: f_high - c * chan_bw_mhz.  Pulses are (dm_index, width, t0).
+#: The workloads: shapes, bands, DM plans and seeds.  Channel c sits at
+#: f_high - c * chan_bw.  Pulses are (dm_index, width, t0).
 CONFIGS = {
     "small": dict(dtype="u8", n_chan=128, n_samp=32768, f_high=1500.0, chan_bw=1.5625,
                   t_samp=64e-6, dm_start=0.0, dm_step=1.0, n_dm=256, seed=1,
@@ -141,7 +199,7 @@ def batch_beams(n_beams: int = 48, seed: int = 5):
     Channel counts from {1024, 2048, 4096, 8192}, lengths uniform in
     [2^16, 2^20], 500..4000 DM trials with a step from {0.25, 0.5, 0.75, 1.0};
     1500 MHz top of band, 300 MHz band, 64 us sampling.  Beam b's data seed is
-    500 + b.
+    500 + b; rows are padded to a pitch that is a multiple of 64 samples.
     """
     rng = np.random.Generator(np.random.PCG64(seed))
     beams = []
@@ -152,5 +210,5 @@ def batch_beams(n_beams: int = 48, seed: int = 5):
         step = float(rng.choice([0.25, 0.5, 0.75, 1.0]))
         beams.append(dict(dtype="u8", n_chan=n_chan, n_samp=n_samp, f_high=1500.0,
                           chan_bw=300.0 / n_chan, t_samp=64e-6, dm_start=0.0, dm_step=step,
-                          n_dm=n_dm, seed=500 + b))
+                          n_dm=n_dm, seed=500 + b, pitch=(n_samp + 63) // 64 * 64))
     return beams

@@ -1,0 +1,110 @@
+"""Host-side checks of the C-ABI library (no GPU needed).
+
+The plan's FP64 table must equal the oracle's entry for entry; every symbol the
+header declares must be exported; argument checks must return the documented
+status codes before touching a device.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import paper_2311_05341_amd as dd
+    return dd
+
+
+def _plan(dd, cfg, **kw):
+    args = dict(n_chan=cfg["n_chan"], n_samp=cfg["n_samp"], dtype=cfg["dtype"], f_high=cfg["f_high"],
+                chan_bw=cfg["chan_bw"], t_samp=cfg["t_samp"], dm_start=cfg["dm_start"],
+                dm_step=cfg["dm_step"], n_dm=cfg["n_dm"], bind=False)
+    args.update(kw)
+    return dd.Plan(**args)
+
+
+def test_header_symbols_exported(dd):
+    with open(os.path.join(ROOT, "include", "dd.h")) as fh:
+        text = fh.read()
+    names = sorted(set(re.findall(r"\b(dd_[a-z_]+)\s*\(", text)))
+    assert len(names) >= 12
+    lib = ctypes.CDLL(dd.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), "missing export " + n
+
+
+@pytest.mark.parametrize("name", ["small", "headline", "lowfreq_u4", "grad_f32"])
+def test_library_table_equals_oracle(dd, name):
+    cfg = synth.CONFIGS[name]
+    p = _plan(dd, cfg)
+    s = oracle.shift_table(cfg["n_chan"], cfg["f_high"], cfg["chan_bw"], cfg["t_samp"], cfg["dm_start"],
+                           cfg["dm_step"], cfg["n_dm"])
+    assert np.array_equal(p.shift, s)
+    assert p.n_out == oracle.n_out_for(s, cfg["n_samp"])
+    assert p.max_shift == int(s.max())
+
+
+def test_library_table_random_plans(dd):
+    rng = np.random.default_rng(21)
+    for _ in range(20):
+        n_chan = int(rng.integers(1, 300))
+        f_high = float(rng.uniform(100, 3000))
+        bw = float(rng.uniform(0.01, 0.5)) * f_high / n_chan
+        t_samp = float(rng.choice([10.24e-6, 64e-6, 327.68e-6, 1e-3]))
+        n_dm = int(rng.integers(1, 200))
+        start, step = float(rng.uniform(0, 50)), float(rng.choice([0.01, 0.1, 0.25, 1.0, 3.7]))
+        s = oracle.shift_table(n_chan, f_high, bw, t_samp, start, step, n_dm)
+        n_samp = int(s.max()) + int(rng.integers(1, 5000))
+        p = dd.Plan(n_chan, n_samp, "u8", f_high, bw, t_samp, start, step, n_dm,
+                    in_pitch_bytes=(n_samp + 15) // 16 * 16, bind=False)
+        assert np.array_equal(p.shift, s)
+        freqs = np.sort(rng.uniform(0.3 * f_high, f_high, n_chan))[::-1].copy()
+        freqs[0] = f_high
+        s2 = oracle.shift_table(n_chan, f_high, 0.0, t_samp, start, step, n_dm, freqs=freqs)
+        n2 = int(s2.max()) + 7
+        p2 = dd.Plan(n_chan, n2, "f32", f_high, 0.0, t_samp, start, step, n_dm,
+                     chan_freq=freqs, in_pitch_bytes=(n2 + 3) // 4 * 16, bind=False)
+        assert np.array_equal(p2.shift, s2)
+
+
+def _status(dd, fn):
+    with pytest.raises(dd.DDError) as e:
+        fn()
+    return e.value.name
+
+
+def test_error_codes(dd):
+    cfg = dict(synth.CONFIGS["small"])
+    assert _status(dd, lambda: _plan(dd, cfg, n_chan=0)) == "DD_ERR_ARG"
+    assert _status(dd, lambda: _plan(dd, cfg, n_samp=2400)) == "DD_ERR_TOO_SHORT"
+    assert _status(dd, lambda: _plan(dd, cfg, chan_bw=20.0)) == "DD_ERR_RANGE"   # band below 0 MHz
+    assert _status(dd, lambda: _plan(dd, cfg, dm_start=-1.0)) == "DD_ERR_RANGE"
+    assert _status(dd, lambda: _plan(dd, cfg, dtype="u4", n_samp=32767)) == "DD_ERR_ARG"
+    assert _status(dd, lambda: _plan(dd, cfg, in_pitch_bytes=32770)) == "DD_ERR_ALIGN"
+    assert _status(dd, lambda: _plan(dd, cfg, in_pitch_bytes=1000)) == "DD_ERR_ARG"
+    assert _status(dd, lambda: _plan(dd, cfg, n_chan=70000, chan_bw=0.001)) == "DD_ERR_RANGE"
+    assert _status(dd, lambda: _plan(dd, cfg, chan_freq=np.full(128, 1600.0))) == "DD_ERR_RANGE"  # above f_high
+    p = _plan(dd, cfg)
+    lib = ctypes.CDLL(dd.LIB_PATH)
+    lib.dd_execute.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_void_p]
+    lib.dd_execute_adjoint.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                       ctypes.c_void_p]
+    assert lib.dd_execute(p._h, 16, 16, p.out_pitch, None) == -6          # not bound
+    assert lib.dd_execute_adjoint(p._h, 16, p.out_pitch, 16, None) == -5  # integer plan
+    assert lib.dd_execute(None, 16, 16, 4, None) == -1
+
+
+def test_plan_tile_shapes(dd):
+    for name in ["small", "headline", "lowfreq_u4", "grad_f32"]:
+        p = _plan(dd, synth.CONFIGS[name])
+        i = p.info
+        assert i.kernel_ns in (16, 32) and i.kernel_waves >= 1 and i.kernel_dm_per_wave >= 1
+        assert 256 % i.kernel_chan_block == 0
