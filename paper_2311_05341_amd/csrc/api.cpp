@@ -113,15 +113,29 @@ dd_status dd_plan_bind(dd_plan *p, void *ws, size_t bytes, void *stream) {
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   hipStream_t st = (hipStream_t)stream;
-  int32_t *dst = (int32_t *)ws;
-  e = hipMemcpyAsync(dst, p->shift.data(), p->shift.size() * 4, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && !p->shift_t.empty())
-    e = hipMemcpyAsync(dst + p->shift.size(), p->shift_t.data(), p->shift_t.size() * 4, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && !p->smax.empty())
-    e = hipMemcpyAsync(dst + p->shift.size() + p->shift_t.size(), p->smax.data(), p->smax.size() * 4,
-                       hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return hip_fail(e, "table upload");
-  p->d_shift = dst;
+  uint8_t *base = (uint8_t *)ws;
+  if (p->desc.dtype != DD_F32) {
+    const size_t ob = p->itab.offs.size() * sizeof(uint16_t);
+    p->int_offs_off = 0;
+    p->int_sbase_off = (ob + 255) / 256 * 256;
+    e = hipMemcpyAsync(base, p->itab.offs.data(), ob, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(base + p->int_sbase_off, p->itab.sbase.data(), p->itab.sbase.size() * 4,
+                         hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "table upload");
+    p->d_shift = nullptr;
+  } else {
+    int32_t *dst = (int32_t *)ws;
+    e = hipMemcpyAsync(dst, p->shift.data(), p->shift.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !p->shift_t.empty())
+      e = hipMemcpyAsync(dst + p->shift.size(), p->shift_t.data(), p->shift_t.size() * 4, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !p->smax.empty())
+      e = hipMemcpyAsync(dst + p->shift.size() + p->shift_t.size(), p->smax.data(), p->smax.size() * 4,
+                         hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "table upload");
+    p->d_shift = dst;
+  }
+  p->d_tables = ws;
   p->device = dev;
   p->bound = true;
   return DD_OK;

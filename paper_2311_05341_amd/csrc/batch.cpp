@@ -18,20 +18,20 @@ struct dd_batch {
   std::vector<const dd_plan *> plans;
   int dtype = 0;
   TileCfg tile;                 // shared tile shape (ns, dm_per_wave, waves)
-  std::vector<int> row_bytes, chan_block;
+  std::vector<IntTables> tables;  // per beam (original index), for the shared shape
   int lds_bytes = 0;
   std::vector<int> order;       // beams in decreasing per-item cost
   std::vector<BeamDesc> descs;  // in `order`
   long long n_items = 0;
   size_t table_off = 0, ws_bytes = 0;
-  std::vector<size_t> table_offs;  // per beam (original index)
+  std::vector<size_t> table_offs, sbase_offs;  // per beam (original index)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   bool bound = false;
   int device = -1;
 };
 
-static const int kBatchLdsLimit = 160 * 1024;
+static const int kBatchLdsLimit = 160 * 1024 - 64;  // leaves room for the claimed-item slot
 
 static size_t up256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -59,28 +59,29 @@ dd_status dd_batch_create(const dd_plan *const *plans, int32_t n, dd_batch **out
     if (plans[i]->desc.dtype != b->dtype) { delete b; return fail(DD_ERR_DTYPE, "all beams of a batch share one dtype"); }
     b->plans.push_back(plans[i]);
   }
-  // One tile shape for all beams: the largest DM block every beam can stage.
-  b->tile.ns = 32;
-  b->tile.waves = 4;
-  for (int r = 4; r >= 1; r /= 2) {
-    b->tile.dm_per_wave = r;
-    b->row_bytes.assign(n, 0);
-    b->chan_block.assign(n, 0);
-    int lds = 0;
+  // One tile shape for all beams: the first compiled shape every beam can stage
+  // (two workgroups' worth of LDS is not required: the kernel runs one per CU).
+  bool found = false;
+  for (int s = 0; s < kNumIntShapes && !found; ++s) {
+    b->tables.assign(n, IntTables());
     bool ok = true;
+    int lds = 0;
     for (int i = 0; i < n && ok; ++i) {
-      const int span = max_dm_block_span(*b->plans[i], b->tile.waves * r);
-      const int rb = row_bytes_for(b->dtype, b->tile.ns, span);
-      int cb = 16;
-      while (cb >= 1 && cb * rb > kBatchLdsLimit / 2) cb /= 2;  // keep two workgroups per CU
-      if (cb < 1) { ok = false; break; }
-      b->row_bytes[i] = rb;
-      b->chan_block[i] = cb;
-      lds = std::max(lds, cb * rb);
+      dd_status st = build_int_tables(*b->plans[i], kIntShapes[s][0], kIntShapes[s][1], kIntShapes[s][2],
+                                      kBatchLdsLimit, &b->tables[i]);
+      if (st == DD_ERR_NOMEM) { delete b; return st; }
+      ok = st == DD_OK;
+      if (ok) lds = std::max(lds, b->tables[i].lds_bytes);
     }
-    if (ok) { b->lds_bytes = lds; break; }
-    if (r == 1) { delete b; return fail(DD_ERR_RANGE, "a beam's delay spread exceeds the LDS staging capacity"); }
+    if (ok) {
+      b->tile.ns = kIntShapes[s][0];
+      b->tile.dm_per_wave = kIntShapes[s][1];
+      b->tile.waves = kIntShapes[s][2];
+      b->lds_bytes = lds;
+      found = true;
+    }
   }
+  if (!found) { delete b; return fail(DD_ERR_RANGE, "a beam's delay spread exceeds the LDS staging capacity"); }
   // Work items: beams ordered by per-item cost (channels x DM rows per tile), largest first.
   b->order.resize(n);
   std::iota(b->order.begin(), b->order.end(), 0);
@@ -91,9 +92,12 @@ dd_status dd_batch_create(const dd_plan *const *plans, int32_t n, dd_batch **out
   size_t off = up256(sizeof(unsigned long long)) + up256(sizeof(BeamDesc) * (size_t)n);
   b->table_off = off;
   b->table_offs.assign(n, 0);
+  b->sbase_offs.assign(n, 0);
   for (int i = 0; i < n; ++i) {
     b->table_offs[i] = off;
-    off += up256(b->plans[i]->shift.size() * sizeof(int32_t));
+    off += up256(b->tables[i].offs.size() * sizeof(uint16_t));
+    b->sbase_offs[i] = off;
+    off += up256(b->tables[i].sbase.size() * sizeof(int32_t));
   }
   b->ws_bytes = off;
   b->descs.resize(n);
@@ -108,8 +112,8 @@ dd_status dd_batch_create(const dd_plan *const *plans, int32_t n, dd_batch **out
     d.n_samp = p.desc.n_samp;
     d.n_out = p.n_out;
     d.pitch = p.in_pitch_bytes;
-    d.row_bytes = b->row_bytes[i];
-    d.chan_block = b->chan_block[i];
+    d.row_bytes = b->tables[i].row_bytes;
+    d.chan_block = b->tables[i].chan_block;
     d.tiles_t = (int)((p.n_out + t_tile - 1) / t_tile);
     d.tiles_d = (p.desc.n_dm + dm_tile - 1) / dm_tile;
     d.item_begin = items;
@@ -147,14 +151,19 @@ dd_status dd_batch_bind(dd_batch *b, const void *const *d_in, float *const *d_ou
     d.x = (const uint8_t *)d_in[i];
     d.out = d_out[i];
     d.out_pitch = out_pitch[i];
-    d.shift = (const int32_t *)(base + b->table_offs[i]);
+    d.offs = (const uint32_t *)(base + b->table_offs[i]);
+    d.sbase = (const int32_t *)(base + b->sbase_offs[i]);
   }
   hipStream_t st = (hipStream_t)stream;
   e = hipMemcpyAsync(base + up256(sizeof(unsigned long long)), b->descs.data(), sizeof(BeamDesc) * n,
                      hipMemcpyHostToDevice, st);
-  for (int i = 0; i < n && e == hipSuccess; ++i)
-    e = hipMemcpyAsync(base + b->table_offs[i], b->plans[i]->shift.data(), b->plans[i]->shift.size() * 4,
+  for (int i = 0; i < n && e == hipSuccess; ++i) {
+    e = hipMemcpyAsync(base + b->table_offs[i], b->tables[i].offs.data(), b->tables[i].offs.size() * 2,
                        hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(base + b->sbase_offs[i], b->tables[i].sbase.data(), b->tables[i].sbase.size() * 4,
+                         hipMemcpyHostToDevice, st);
+  }
   if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("batch upload: ") + hipGetErrorString(e));
 
   BatchLaunch L;

@@ -26,6 +26,15 @@ struct TileCfg {
   int lds_bytes = 0;     // total dynamic LDS
 };
 
+// Device tables of the integer forward kernel for one tile shape: per DM
+// block the staging base of every channel (its first-DM delay rounded down to
+// the staging unit) and, per (block, wave, channel, row), the delay minus that
+// base as uint16.
+struct IntTables {
+  std::vector<uint16_t> offs;  // [n_dblk][waves][n_chan][max(dm_per_wave, 2)]
+  std::vector<int32_t> sbase;  // [n_dblk][n_chan]
+  int row_bytes = 0, chan_block = 0, lds_bytes = 0;
+};
 // Everything the device needs about one plan, in device-visible form.
 struct DevPlan {
   const int32_t *shift;  // [n_dm][n_chan]
@@ -49,7 +58,10 @@ struct dd_plan {
   dd::TileCfg adj;             // adjoint tile shape (f32 plans)
   int32_t span_fwd = 0;        // largest delay spread inside a forward DM block
   int32_t span_adj = 0;        // largest delay spread inside an adjoint channel block
+  dd::IntTables itab;          // integer plans: forward kernel tables
   // binding
+  const void *d_tables = nullptr;
+  size_t int_offs_off = 0, int_sbase_off = 0;
   const int32_t *d_shift = nullptr;
   int device = -1;
   bool bound = false;
@@ -70,15 +82,22 @@ size_t table_bytes(const dd_plan &p);
 // One beam of a batch, as the persistent kernel sees it.
 struct BeamDesc {
   const uint8_t *x;
-  const int32_t *shift;
+  const uint32_t *offs;
+  const int32_t *sbase;
   float *out;
   int64_t pitch, n_samp, n_out, out_pitch;
   int64_t item_begin;  // first work item of this beam
   int32_t n_chan, n_dm, row_bytes, chan_block, tiles_t, tiles_d;
 };
 
+dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves, int lds_limit, IntTables *t);
+
 // Kernel launchers (kernels.hip).  Return hipError_t as int.
 int launch_forward(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream);
+int launch_forward_int(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream);
+// Integer tile shapes compiled into the library: (ns, dm_per_wave, waves), best first.
+extern const int kIntShapes[][3];
+extern const int kNumIntShapes;
 int launch_adjoint(const dd_plan &p, const float *d_y, int64_t y_pitch, float *d_grad, void *stream);
 
 // Persistent batched forward: kernel entry, its launch geometry and the

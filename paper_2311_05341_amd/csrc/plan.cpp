@@ -9,6 +9,7 @@
 #pragma clang fp contract(off)
 
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -136,27 +137,99 @@ int row_bytes_for(int dtype, int ns, int span) {
   return round_up((int64_t)64 * ns + span + unit + 16, unit);
 }
 
+// Tables of the integer forward kernel for tile shape (ns, dm_per_wave, waves).
+// Fails with DD_ERR_RANGE if even one channel per LDS stage does not fit.
+dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves, int lds_limit, IntTables *t) {
+  const int nc = p.desc.n_chan, nd = p.desc.n_dm;
+  const int dblk = waves * dm_per_wave;
+  const int unit = p.desc.dtype == DD_U4 ? 32 : 16;
+  const int span = max_dm_block_span(p, dblk);
+  const int64_t rb = (int64_t)64 * ns + span + unit + 16;
+  if (rb > (1 << 24)) return fail(DD_ERR_RANGE, "delay spread too large");
+  t->row_bytes = round_up(rb, unit);
+  t->chan_block = 0;
+  const int row_chunks = t->row_bytes / 16;
+  for (int cb = 16; cb >= 1; cb /= 2) {
+    const int64_t lds = (int64_t)2 * cb * 4 * t->row_bytes;  // two buffers of 4 byte-phase copies
+    const bool tasks_ok = cb * row_chunks <= 1024;  // staging tasks per block (the kernel's kStageTasks)
+    if (lds <= lds_limit && tasks_ok) {
+      t->chan_block = cb;
+      t->lds_bytes = (int)lds;
+      break;
+    }
+  }
+  if (!t->chan_block) return fail(DD_ERR_RANGE, "delay spread of a DM block exceeds the LDS staging capacity");
+  if ((int64_t)span + unit - 1 > 65535) return fail(DD_ERR_RANGE, "delay spread exceeds 16-bit offsets");
+  const int n_dblk = (nd + dblk - 1) / dblk;
+  const int rp = dm_per_wave < 2 ? 2 : dm_per_wave;  // uint16 slots per channel (whole 32-bit words)
+  try {
+    t->offs.assign((size_t)n_dblk * waves * nc * rp, 0);
+    t->sbase.assign((size_t)n_dblk * nc, 0);
+  } catch (const std::bad_alloc &) {
+    return fail(DD_ERR_NOMEM, "table allocation failed");
+  }
+  for (int b = 0; b < n_dblk; ++b) {
+    const int32_t *s0 = p.shift.data() + (size_t)(b * dblk) * nc;
+    int32_t *sb = t->sbase.data() + (size_t)b * nc;
+    for (int c = 0; c < nc; ++c) sb[c] = s0[c] & ~(unit - 1);
+    for (int w = 0; w < waves; ++w)
+      for (int r = 0; r < dm_per_wave; ++r) {
+        const int d = std::min(b * dblk + w * dm_per_wave + r, nd - 1);
+        const int32_t *sd = p.shift.data() + (size_t)d * nc;
+        uint16_t *o = t->offs.data() + (((size_t)b * waves + w) * nc) * rp + r;
+        for (int c = 0; c < nc; ++c) o[(size_t)c * rp] = (uint16_t)(sd[c] - sb[c]);
+      }
+  }
+  return DD_OK;
+}
+
 dd_status choose_forward_tiles(dd_plan &p) {
   TileCfg t;
-  t.ns = p.desc.dtype == DD_F32 ? 16 : 32;
-  t.dm_per_wave = 4;
-  t.waves = 4;
-  for (;;) {
-    const int span = max_dm_block_span(p, t.waves * t.dm_per_wave);
-    t.row_bytes = row_bytes_for(p.desc.dtype, t.ns, span);
-    for (t.chan_block = 16; t.chan_block >= 1; t.chan_block /= 2) {
-      t.lds_bytes = t.chan_block * t.row_bytes;
-      if (t.lds_bytes <= kLdsLimit) break;
+  if (p.desc.dtype == DD_F32) {
+    t.ns = 16;
+    t.dm_per_wave = 4;
+    t.waves = 4;
+    for (;;) {
+      const int span = max_dm_block_span(p, t.waves * t.dm_per_wave);
+      t.row_bytes = row_bytes_for(p.desc.dtype, t.ns, span);
+      for (t.chan_block = 16; t.chan_block >= 1; t.chan_block /= 2) {
+        t.lds_bytes = t.chan_block * t.row_bytes;
+        if (t.lds_bytes <= kLdsLimit) break;
+      }
+      if (t.chan_block >= 1) {
+        p.span_fwd = span;
+        p.fwd = t;
+        return DD_OK;
+      }
+      if (t.dm_per_wave > 1) { t.dm_per_wave /= 2; continue; }
+      if (t.waves > 1) { t.waves /= 2; continue; }
+      return fail(DD_ERR_RANGE, "delay spread of one DM block exceeds the LDS staging capacity");
     }
-    if (t.chan_block >= 1) {
-      p.span_fwd = span;
+  }
+  dd_status last = DD_ERR_RANGE;
+  int first = 0;
+  if (const char *env = getenv("DD_INT_SHAPE")) {  // force a compiled shape by index (tuning experiments)
+    first = atoi(env);
+    if (first < 0 || first >= kNumIntShapes) first = 0;
+  }
+  for (int i = first; i < kNumIntShapes; ++i) {
+    IntTables tab;
+    last = build_int_tables(p, kIntShapes[i][0], kIntShapes[i][1], kIntShapes[i][2], kLdsLimit, &tab);
+    if (last == DD_OK) {
+      t.ns = kIntShapes[i][0];
+      t.dm_per_wave = kIntShapes[i][1];
+      t.waves = kIntShapes[i][2];
+      t.row_bytes = tab.row_bytes;
+      t.chan_block = tab.chan_block;
+      t.lds_bytes = tab.lds_bytes;
       p.fwd = t;
+      p.span_fwd = max_dm_block_span(p, t.waves * t.dm_per_wave);
+      p.itab = std::move(tab);
       return DD_OK;
     }
-    if (t.dm_per_wave > 1) { t.dm_per_wave /= 2; continue; }
-    if (t.waves > 1) { t.waves /= 2; continue; }
-    return fail(DD_ERR_RANGE, "delay spread of one DM block exceeds the LDS staging capacity");
+    if (last == DD_ERR_NOMEM) return last;
   }
+  return last;
 }
 
 dd_status choose_adjoint_tiles(dd_plan &p) {
@@ -199,9 +272,14 @@ void build_adjoint_tables(dd_plan &p) {
     }
 }
 
+static size_t up256(size_t v) { return (v + 255) / 256 * 256; }
+
+// Device workspace layout.  Integer plans: [offs uint16][sbase int32].
+// Float plans: [shift int32][shift transposed int32][adjoint block maxima int32].
 size_t table_bytes(const dd_plan &p) {
-  size_t b = (p.shift.size() + p.shift_t.size() + p.smax.size()) * sizeof(int32_t);
-  return (b + 255) / 256 * 256;
+  if (p.desc.dtype != DD_F32)
+    return up256(p.itab.offs.size() * sizeof(uint16_t)) + up256(p.itab.sbase.size() * sizeof(int32_t));
+  return up256((p.shift.size() + p.shift_t.size() + p.smax.size()) * sizeof(int32_t));
 }
 
 }  // namespace dd
