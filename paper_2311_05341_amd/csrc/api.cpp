@@ -56,6 +56,7 @@ dd_status dd_plan_create(const dd_plan_desc *desc, dd_plan **out) {
   const int64_t pitch = d.in_pitch_bytes ? d.in_pitch_bytes : row;
   if (pitch < row) return fail(DD_ERR_ARG, "in_pitch_bytes smaller than one row");
   if (pitch % 16) return fail(DD_ERR_ALIGN, "input row pitch must be a multiple of 16 bytes");
+  if (d.dtype != DD_F32 && pitch >= ((int64_t)1 << 31)) return fail(DD_ERR_RANGE, "integer input rows must be shorter than 2^31 bytes");
   if ((double)d.n_dm * (double)d.n_chan * 12.0 > 9.0e18) return fail(DD_ERR_RANGE, "table size overflow");
 
   dd_plan *p = new (std::nothrow) dd_plan();

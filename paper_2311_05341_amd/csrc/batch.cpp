@@ -68,7 +68,7 @@ dd_status dd_batch_create(const dd_plan *const *plans, int32_t n, dd_batch **out
     int lds = 0;
     for (int i = 0; i < n && ok; ++i) {
       dd_status st = build_int_tables(*b->plans[i], kIntShapes[s][0], kIntShapes[s][1], kIntShapes[s][2],
-                                      kBatchLdsLimit, &b->tables[i]);
+                                      kIntShapes[s][3], kBatchLdsLimit, &b->tables[i]);
       if (st == DD_ERR_NOMEM) { delete b; return st; }
       ok = st == DD_OK;
       if (ok) lds = std::max(lds, b->tables[i].lds_bytes);
@@ -77,6 +77,7 @@ dd_status dd_batch_create(const dd_plan *const *plans, int32_t n, dd_batch **out
       b->tile.ns = kIntShapes[s][0];
       b->tile.dm_per_wave = kIntShapes[s][1];
       b->tile.waves = kIntShapes[s][2];
+      b->tile.chan_block = kIntShapes[s][3];
       b->lds_bytes = lds;
       found = true;
     }
@@ -167,7 +168,8 @@ dd_status dd_batch_bind(dd_batch *b, const void *const *d_in, float *const *d_ou
   if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("batch upload: ") + hipGetErrorString(e));
 
   BatchLaunch L;
-  int le = batch_kernels(b->tile.ns, b->tile.dm_per_wave, b->tile.waves, b->dtype == DD_U4, b->lds_bytes, &L);
+  int le = batch_kernels(b->tile.ns, b->tile.dm_per_wave, b->tile.waves, b->tile.chan_block, b->dtype == DD_U4,
+                         b->lds_bytes, &L);
   if (le) return fail(DD_ERR_HIP, std::string("batch kernel setup: ") + hipGetErrorString((hipError_t)le));
   release_graph(b);
   unsigned long long *counter = (unsigned long long *)base;

@@ -31,7 +31,7 @@ struct TileCfg {
 // the staging unit) and, per (block, wave, channel, row), the delay minus that
 // base as uint16.
 struct IntTables {
-  std::vector<uint16_t> offs;  // [n_dblk][waves][n_chan][max(dm_per_wave, 2)]
+  std::vector<uint16_t> offs;  // [n_dblk][waves][n_chan rounded up to chan_block][max(dm_per_wave, 2)]
   std::vector<int32_t> sbase;  // [n_dblk][n_chan]
   int row_bytes = 0, chan_block = 0, lds_bytes = 0;
 };
@@ -90,13 +90,15 @@ struct BeamDesc {
   int32_t n_chan, n_dm, row_bytes, chan_block, tiles_t, tiles_d;
 };
 
-dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves, int lds_limit, IntTables *t);
+dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves, int chan_block, int lds_limit,
+                           IntTables *t);
 
 // Kernel launchers (kernels.hip).  Return hipError_t as int.
 int launch_forward(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream);
 int launch_forward_int(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream);
-// Integer tile shapes compiled into the library: (ns, dm_per_wave, waves), best first.
-extern const int kIntShapes[][3];
+// Integer tile shapes compiled into the library: (ns, dm_per_wave, waves,
+// chan_block), in the order plans try them.
+extern const int kIntShapes[][4];
 extern const int kNumIntShapes;
 int launch_adjoint(const dd_plan &p, const float *d_y, int64_t y_pitch, float *d_grad, void *stream);
 
@@ -107,6 +109,6 @@ struct BatchLaunch {
   const void *main_fn;
   int grid, block, lds_bytes;
 };
-int batch_kernels(int ns, int dm_per_wave, int waves, bool u4, int lds_bytes, BatchLaunch *out);
+int batch_kernels(int ns, int dm_per_wave, int waves, int chan_block, bool u4, int lds_bytes, BatchLaunch *out);
 
 }  // namespace dd

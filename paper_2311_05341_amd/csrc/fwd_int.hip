@@ -4,7 +4,8 @@
 //
 // Tiling.  A workgroup of NW waves owns NW*R consecutive DM rows (a "DM block")
 // and 64*NS consecutive output samples (a "time tile"); wave w owns R of the
-// rows and each lane NS consecutive samples of them, accumulated in registers.
+// rows and each lane NS of their samples (NS/4 words of 4 samples, strided by
+// 64 words so that the wave's LDS accesses are contiguous), in registers.
 // Channels are visited in blocks of `chan_block`: the rows of a channel block
 // are staged in LDS once, starting at the block's first-DM delay rounded down
 // to 16 bytes, and each staged sample then serves all NW*R DM rows of the
@@ -26,10 +27,6 @@
 // recovers the even samples exactly.  Every 256 channels both are flushed into
 // per-sample int32 totals, which stay below 2^24 and convert to float exactly.
 //
-// Staging runs two blocks ahead: global reads for block b+2 are issued into
-// registers before block b is summed, and block b+1's phase copies are written
-// after it, so one barrier per block suffices.
-//
 // Grid order: blockIdx.x runs over DM blocks, so the workgroups resident at any
 // time share a few time tiles and read the same input rows through L2/MALL.
 #include <hip/hip_runtime.h>
@@ -40,7 +37,16 @@
 namespace dd {
 namespace {
 
-constexpr uint32_t kOddSel = 0x0C030C01u;  // v_perm: bytes 1 and 3 into bytes 0 and 2, zeros elsewhere
+constexpr uint32_t kOddSel = 0x0C030C01u;
+constexpr int kBufferRsrcFlags = 0x00020000;  // raw (untyped) buffer access, word 3 of the descriptor
+
+// Read-only tables read with wave-uniform addresses go through the constant
+// address space, which the compiler always serves with scalar loads; a vector
+// load here would make the wave wait for every global read in flight.
+template <typename T>
+__device__ __forceinline__ T scalar_load(const T *p, int64_t i) {
+  return ((const __attribute__((address_space(4))) T *)p)[i];
+}  // v_perm: bytes 1 and 3 into bytes 0 and 2, zeros elsewhere
 
 // Unpack 8 bytes of 4-bit samples (even sample in the low nibble) into 16 bytes.
 __device__ __forceinline__ uint4 unpack_u4(uint2 p) {
@@ -89,103 +95,165 @@ __device__ __forceinline__ void flush(uint32_t (&mix)[R][NS / 4], uint32_t (&odd
 // Kernel arguments shared by the plain and the batched kernels.
 struct IntArgs {
   const uint8_t *x;       // [n_chan][pitch] bytes
-  const uint32_t *offs;   // [n_dblk][NW][n_chan][max(R,2)/2]: pairs of uint16 (shift - stage base)
+  const uint32_t *offs;   // [n_dblk][NW][n_chan][max(R,2)/2]: pairs of uint16 LDS offsets (see build_int_tables)
   const int32_t *sbase;   // [n_dblk][n_chan]: stage base (first-DM shift rounded down to the unit)
   float *out;             // [n_dm][out_pitch]
   int64_t pitch, n_samp, n_out, out_pitch;
-  int32_t n_chan, n_dm, row_bytes, chan_block;
+  int32_t n_chan, n_dm, row_bytes;
 };
 
-// Staging of one channel block, in two halves: `load` issues the global reads
-// into registers (one task = one 16-byte LDS chunk of a row, i.e. 16 samples,
-// plus the first 4 samples of the next chunk), and `write` later stores the
-// four byte-phase copies of every chunk.  Between the two the workgroup sums
-// the previous block, which hides the global-memory latency.
-template <int MAXT>
-struct Held {
-  uint32_t w[MAXT][5];
+// Workgroup barrier for LDS hand-offs.  __syncthreads() also waits for every
+// outstanding global load (vmcnt(0)), which would stall on the staging reads
+// kept in flight across blocks; only this wave's LDS operations must have
+// completed before the barrier.  The asm is a compiler memory barrier too.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Staging.  Channel blocks stream through a ring of kRing LDS slots with
+// direct global->LDS buffer loads (no registers involved), kRing-1 blocks
+// ahead of the block being summed.  A slot holds the raw input bytes of the
+// block's rows (packed nibbles for 4-bit input); from it the workgroup builds
+// the four byte-phase copies the sum reads, one block ahead.  A block always
+// has CB channels: channels past the last one are staged as zero rows.
+//
+// The loads of a block are cut in segments of 64 lanes x 16 bytes of one row;
+// segment s goes to wave s % NW, so the channel and its staging base are
+// wave-uniform (scalar loads).  Every wave issues exactly MAXT loads per block
+// (out-of-range rows, segments and blocks read zeros into a scratch area), so
+// a fixed s_waitcnt vmcnt count waits for exactly one block.
+constexpr int kStageSegs = 16;  // host keeps CB * ceil(ring row bytes / 1024) <= kStageSegs
+constexpr int kRing = 3;
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef int v4i_t __attribute__((ext_vector_type(4)));
+
+// Raw buffer descriptor over [base, base + bytes): reads past the end return 0.
+__device__ __forceinline__ v4i_t make_rsrc(const void *base, int bytes) {
+  const uint64_t a = (uint64_t)base;
+  v4i_t r;
+  r.x = (int)(uint32_t)a;
+  r.y = (int)(uint32_t)(a >> 32);  // stride 0
+  r.z = bytes;
+  r.w = kBufferRsrcFlags;
+  return r;
+}
+
+// 16 bytes per lane from buffer offset `voff` straight into LDS at
+// lds_addr + 16 * lane.  Written as asm so that the compiler does not insert
+// its own conservative wait for these LDS writes before every later LDS read:
+// the kernel waits for them explicitly (wait_vmcnt) and orders them with
+// lds_barrier().
+__device__ __forceinline__ void dma16(const v4i_t &rs, uint32_t voff, uint32_t lds_addr) {
+  asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tbuffer_load_dwordx4 %0, %2, 0 offen lds"
+               :
+               : "v"(voff), "s"(lds_addr), "s"(rs)
+               : "memory", "m0");
+}
+
+// LDS layout of a tile: two phase buffers, the ring, a 1 KB scratch area.
+struct TileLds {
+  int row_bytes;    // one byte-phase copy of a row
+  int phase_buf;    // CB * 4 * row_bytes
+  int ring_row;     // stride of a raw row in a ring slot (multiple of 16, >= raw bytes + 16)
+  int ring_slot;    // CB * ring_row
+  int ring_base;    // 2 * phase_buf
+  int scratch;      // ring_base + kRing * ring_slot
 };
 
-template <int NT, int MAXT, bool U4>
-__device__ __forceinline__ void stage_load(const IntArgs &a, const int32_t *sb, int64_t t0, int cb, int nch,
-                                           Held<MAXT> &h) {
-  const int row_chunks = a.row_bytes >> 4;
+template <int CB, bool U4>
+__device__ __forceinline__ TileLds tile_lds(int row_bytes) {
+  TileLds L;
+  L.row_bytes = row_bytes;
+  L.phase_buf = CB * 4 * row_bytes;
+  L.ring_row = (U4 ? row_bytes / 2 : row_bytes) + 16;
+  L.ring_slot = CB * L.ring_row;
+  L.ring_base = 2 * L.phase_buf;
+  L.scratch = L.ring_base + kRing * L.ring_slot;
+  return L;
+}
+
+// Issue the direct loads of block `cb` (first channel) into ring slot `slot`.
+template <int NW, int CB, int MAXT, bool U4>
+__device__ __forceinline__ void stage_dma(const IntArgs &a, const int32_t *sb, int64_t t0, int cb, uint8_t *lds,
+                                          const TileLds &L, int slot, int wave, int lane) {
+  const int raw_bytes = U4 ? L.row_bytes / 2 : L.row_bytes;  // bytes of one row to stage
+  const int segs = (raw_bytes + 1023) >> 10;
+  // Bounds are checked per 32-bit word, so the limit is the row length rounded
+  // up to 16 bytes (still inside the row pitch).
+  const int row_valid_bytes = (int)(((U4 ? a.n_samp / 2 : a.n_samp) + 15) & ~(int64_t)15);
 #pragma unroll
-  for (int k = 0; k < MAXT; ++k) {
-    const int i = threadIdx.x + k * NT;
-#pragma unroll
-    for (int q = 0; q < 5; ++q) h.w[k][q] = 0;
-    if (i < nch * row_chunks) {
-      const int cc = i / row_chunks, j = i - cc * row_chunks;
-      const int c = cb + cc;
-      const int64_t g = t0 + sb[c] + 16 * (int64_t)j;  // first sample of the chunk (multiple of 16)
-      const uint8_t *row = a.x + (int64_t)c * a.pitch;
-      if (!U4) {
-        if (g < a.n_samp) {
-          const uint4 v = *(const uint4 *)(row + g);
-          h.w[k][0] = v.x;
-          h.w[k][1] = v.y;
-          h.w[k][2] = v.z;
-          h.w[k][3] = v.w;
-        }
-        if (g + 16 < a.n_samp) h.w[k][4] = *(const uint32_t *)(row + g + 16);
-      } else {
-        if (g < a.n_samp) {
-          const uint2 v = *(const uint2 *)(row + (g >> 1));
-          h.w[k][0] = v.x;
-          h.w[k][1] = v.y;
-        }
-        if (g + 16 < a.n_samp) h.w[k][4] = *(const uint32_t *)(row + ((g + 16) >> 1));
-      }
-    }
+  for (int m = 0; m < MAXT; ++m) {
+    const int s = wave + m * NW;
+    const bool seg_ok = s < CB * segs;  // wave-uniform
+    const int cc = seg_ok ? s / segs : 0;
+    const int j0 = seg_ok ? (s - cc * segs) << 6 : 0;  // first 16-byte chunk of the segment
+    const bool chan_ok = seg_ok && cb + cc < a.n_chan;
+    const int c = __builtin_amdgcn_readfirstlane(min(cb + cc, a.n_chan - 1));
+    const int32_t base = chan_ok ? scalar_load(sb, c) : 0;
+    const v4i_t rs = make_rsrc(a.x + (int64_t)c * a.pitch, chan_ok ? row_valid_bytes : 0);
+    // first staged byte of the row: sample t0 + base (a multiple of 32 for 4-bit input)
+    const uint32_t row0 = U4 ? (uint32_t)((t0 + base) >> 1) : (uint32_t)(t0 + base);
+    const int j = j0 + lane;
+    uint8_t *dst = seg_ok ? lds + L.ring_base + slot * L.ring_slot + cc * L.ring_row + 16 * j0 : lds + L.scratch;
+    const uint32_t lds_addr = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void_t *)dst);
+    if (!seg_ok || 16 * j < raw_bytes) dma16(rs, seg_ok ? row0 + 16u * (uint32_t)j : 0u, lds_addr);
   }
 }
 
-template <int NT, int MAXT, bool U4>
-__device__ __forceinline__ void stage_write(const IntArgs &a, int nch, uint8_t *buf, const Held<MAXT> &h) {
-  const int row_chunks = a.row_bytes >> 4;
-#pragma unroll
-  for (int k = 0; k < MAXT; ++k) {
-    const int i = threadIdx.x + k * NT;
-    if (i < nch * row_chunks) {
-      const int cc = i / row_chunks, j = i - cc * row_chunks;
-      uint8_t *p0 = buf + cc * 4 * a.row_bytes + 16 * j;
-      uint32_t w[5];
-      if (!U4) {
-#pragma unroll
-        for (int q = 0; q < 5; ++q) w[q] = h.w[k][q];
-      } else {
-        const uint4 v = unpack_u4(make_uint2(h.w[k][0], h.w[k][1]));
-        const uint4 n = unpack_u4(make_uint2(h.w[k][4], 0u));
-        w[0] = v.x;
-        w[1] = v.y;
-        w[2] = v.z;
-        w[3] = v.w;
-        w[4] = n.x;
-      }
-      *(uint4 *)p0 = make_uint4(w[0], w[1], w[2], w[3]);
-      write_phases(p0, a.row_bytes, w);
+// Build the byte-phase copies of block (ring slot `slot`) into phase buffer `pb`.
+template <int NT, int CB, bool U4>
+__device__ __forceinline__ void build_phases(uint8_t *lds, const TileLds &L, int slot, int pb) {
+  const int row_chunks = L.row_bytes >> 4;
+  const uint8_t *ring = lds + L.ring_base + slot * L.ring_slot;
+  uint8_t *dst = lds + pb * L.phase_buf;
+  for (int i = threadIdx.x; i < CB * row_chunks; i += NT) {
+    const int cc = i / row_chunks, j = i - cc * row_chunks;
+    uint32_t w[5];
+    if (!U4) {
+      const uint8_t *src = ring + cc * L.ring_row + 16 * j;
+      const uint4 v = *(const uint4 *)src;
+      w[0] = v.x;
+      w[1] = v.y;
+      w[2] = v.z;
+      w[3] = v.w;
+      w[4] = *(const uint32_t *)(src + 16);  // past the row: only feeds samples beyond every window
+    } else {
+      const uint8_t *src = ring + cc * L.ring_row + 8 * j;
+      const uint2 pv = *(const uint2 *)src;
+      const uint4 v = unpack_u4(pv);
+      const uint4 n = unpack_u4(make_uint2(*(const uint32_t *)(src + 8), 0u));
+      w[0] = v.x;
+      w[1] = v.y;
+      w[2] = v.z;
+      w[3] = v.w;
+      w[4] = n.x;
     }
+    uint8_t *p0 = dst + cc * 4 * L.row_bytes + 16 * j;
+    *(uint4 *)p0 = make_uint4(w[0], w[1], w[2], w[3]);
+    write_phases(p0, L.row_bytes, w);
   }
 }
 
-// Staging tasks per block are at most kStageTasks (host keeps
-// chan_block * row_bytes / 16 <= kStageTasks), i.e. kStageTasks / threads per thread.
-constexpr int kStageTasks = 1024;
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  // s_waitcnt encoding on gfx9: vmcnt[3:0] | expcnt[6:4] | lgkmcnt[11:8] | vmcnt[5:4] << 14
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+}
 
-// One tile: DM block `dblk`, time tile `tblk`.  `lds` holds two buffers of
-// chan_block * 4 * row_bytes bytes.
-template <int NS, int R, int NW, bool U4>
+// One tile: DM block `dblk`, time tile `tblk`.
+template <int NS, int R, int NW, int CB, bool U4>
 __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int dblk, int tblk) {
   constexpr int NT = NW * 64;
   constexpr int RP = R < 2 ? 2 : R;  // uint16 slots per channel in the offset table
   constexpr int NOW = RP / 2;        // uint32 words per channel
+  constexpr int MAXT = (kStageSegs + NW - 1) / NW;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t t0 = (int64_t)tblk * (64 * NS);
-  const uint32_t *woffs = a.offs + ((int64_t)dblk * NW + wave) * a.n_chan * NOW;
+  const int chan_pad = (a.n_chan + CB - 1) / CB * CB;
+  const uint32_t *woffs = a.offs + ((int64_t)dblk * NW + wave) * chan_pad * NOW;
   const int32_t *sb = a.sbase + (int64_t)dblk * a.n_chan;
-  const int buf_bytes = a.chan_block * 4 * a.row_bytes;
+  const TileLds L = tile_lds<CB, U4>(a.row_bytes);
 
   uint32_t tot[R][NS], mix[R][NS / 4], odd[R][NS / 4];
 #pragma unroll
@@ -196,59 +264,61 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
     for (int k = 0; k < NS / 4; ++k) mix[r][k] = odd[r][k] = 0;
   }
 
-  const int nblk = (a.n_chan + a.chan_block - 1) / a.chan_block;
-  constexpr int MAXT = kStageTasks / NT;
-  Held<MAXT> next, after;  // stages b+1 and b+2
-  stage_load<NT, MAXT, U4>(a, sb, t0, 0, min(a.chan_block, a.n_chan), next);
-  if (nblk > 1) stage_load<NT, MAXT, U4>(a, sb, t0, a.chan_block, min(a.chan_block, a.n_chan - a.chan_block), after);
-  stage_write<NT, MAXT, U4>(a, min(a.chan_block, a.n_chan), lds, next);
-  next = after;
-  __syncthreads();
+  const int nblk = chan_pad / CB;
+#pragma unroll
+  for (int k = 0; k < kRing; ++k) stage_dma<NW, CB, MAXT, U4>(a, sb, t0, k * CB, lds, L, k, wave, lane);
+  wait_vmcnt<(kRing - 1) * MAXT>();
+  lds_barrier();
+  build_phases<NT, CB, U4>(lds, L, 0, 0);
 
-  const uint8_t *lane_base = lds + NS * lane;
+  const uint8_t *lane_base = lds + 4 * lane;
   int since_flush = 0;
   for (int b = 0; b < nblk; ++b) {
-    const int cb = b * a.chan_block;
-    const int nch = min(a.chan_block, a.n_chan - cb);
-    const int cur_off = (b & 1) * buf_bytes;
-    if (b + 2 < nblk) {
-      const int c2 = cb + 2 * a.chan_block;
-      stage_load<NT, MAXT, U4>(a, sb, t0, c2, min(a.chan_block, a.n_chan - c2), after);
-    }
-    // Sum this block: every (channel, DM row) pair reads NS/4 aligned words of
-    // the byte phase that puts its window on a word boundary.
-    for (int cc = 0; cc < nch; ++cc) {
-      uint32_t ow[NOW];
+    // Block b+1's loads have landed (this wave's); after the barrier, every
+    // wave's have, block b's phase copies are complete, and nobody reads ring
+    // slot b % kRing or phase buffer (b+1) % 2 any more.
+    wait_vmcnt<(kRing - 2) * MAXT>();
+    lds_barrier();
+    stage_dma<NW, CB, MAXT, U4>(a, sb, t0, (b + kRing) * CB, lds, L, b % kRing, wave, lane);  // zeros past the end
+    if (b + 1 < nblk) build_phases<NT, CB, U4>(lds, L, (b + 1) % kRing, (b + 1) & 1);
+    // Sum block b.  Each (channel, DM row) pair reads NS/4 aligned words of
+    // the byte phase that puts its window on a word boundary; the table entry
+    // is that word's byte offset inside the channel's four copies.  Lane i
+    // owns words i, i+64, i+128, ... of the window, so every read is one
+    // contiguous, bank-conflict-free 256-byte access per wave.  All offsets of
+    // the block come in one scalar load and the channel loop is unrolled, so
+    // the reads of several pairs are in flight together.
+    uint32_t ow[CB * NOW];
+    const int oi = __builtin_amdgcn_readfirstlane(b * CB * NOW);
 #pragma unroll
-      for (int q = 0; q < NOW; ++q) ow[q] = woffs[(int64_t)(cb + cc) * NOW + q];
+    for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, oi + q);
+    const uint8_t *blk = lane_base + (b & 1) * L.phase_buf;
+#pragma unroll
+    for (int cc = 0; cc < CB; ++cc) {
+      const uint8_t *chan = blk + cc * 4 * L.row_bytes;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const uint32_t o = (ow[r >> 1] >> (16 * (r & 1))) & 0xFFFFu;
-        const uint32_t *p = (const uint32_t *)(lane_base + cur_off + (cc * 4 + (int)(o & 3u)) * a.row_bytes +
-                                               (o & ~3u));
+        const uint32_t e = (ow[cc * NOW + (r >> 1)] >> (16 * (r & 1))) & 0xFFFFu;
+        const uint32_t *p = (const uint32_t *)(chan + e);
 #pragma unroll
         for (int k = 0; k < NS / 4; ++k) {
-          const uint32_t w = p[k];
+          const uint32_t w = p[64 * k];
           mix[r][k] += w;
           odd[r][k] += __builtin_amdgcn_perm(w, w, kOddSel);
         }
       }
     }
-    since_flush += nch;
-    const bool more = b + 1 < nblk;
-    if (since_flush >= 256 || !more) {
+    since_flush += CB;
+    if (since_flush >= 256 || b + 1 == nblk) {
       flush<NS, R>(mix, odd, tot);
       since_flush = 0;
     }
-    if (more) {
-      const int c1 = cb + a.chan_block;
-      stage_write<NT, MAXT, U4>(a, min(a.chan_block, a.n_chan - c1), lds + ((b + 1) & 1) * buf_bytes, next);
-      next = after;
-    }
-    __syncthreads();
   }
+  wait_vmcnt<0>();  // the trailing all-zero loads must land before the LDS is reused
+  lds_barrier();
 
-  const int64_t tl = t0 + (int64_t)NS * lane;
+  // Word k of lane i holds samples t0 + 4*(i + 64k) + 0..3: stores are
+  // contiguous across the wave.
   const int d0 = dblk * (NW * R) + wave * R;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -256,25 +326,25 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
     if (d >= a.n_dm) break;
     float *orow = a.out + (int64_t)d * a.out_pitch;
 #pragma unroll
-    for (int j = 0; j < NS; j += 4) {
-      const int64_t t = tl + j;
+    for (int k = 0; k < NS / 4; ++k) {
+      const int64_t t = t0 + 4 * (int64_t)(lane + 64 * k);
       if (t + 3 < a.n_out) {
-        *(float4 *)(orow + t) = make_float4((float)tot[r][j], (float)tot[r][j + 1], (float)tot[r][j + 2],
-                                            (float)tot[r][j + 3]);
+        *(float4 *)(orow + t) = make_float4((float)tot[r][4 * k], (float)tot[r][4 * k + 1], (float)tot[r][4 * k + 2],
+                                            (float)tot[r][4 * k + 3]);
       } else {
 #pragma unroll
         for (int i = 0; i < 4; ++i)
-          if (t + i < a.n_out) orow[t + i] = (float)tot[r][j + i];
+          if (t + i < a.n_out) orow[t + i] = (float)tot[r][4 * k + i];
       }
     }
   }
 }
 
 // One workgroup per tile; grid = (DM blocks, time tiles).
-template <int NS, int R, int NW, bool U4>
+template <int NS, int R, int NW, int CB, bool U4>
 __global__ __launch_bounds__(NW * 64) void fwd_int_kernel(IntArgs a) {
   extern __shared__ __align__(16) uint8_t lds[];
-  fwd_int_tile<NS, R, NW, U4>(lds, a, blockIdx.x, blockIdx.y);
+  fwd_int_tile<NS, R, NW, CB, U4>(lds, a, blockIdx.x, blockIdx.y);
 }
 
 __global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0ull; }
@@ -284,7 +354,7 @@ __global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0
 // beam by beam with the beams in decreasing cost order and, inside a beam,
 // DM block fastest.  A workgroup returns at its first claim past the last
 // item, so every wave reaches the exit.
-template <int NS, int R, int NW, bool U4>
+template <int NS, int R, int NW, int CB, bool U4>
 __global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc *__restrict__ beams, int n_beams,
                                                                    long long n_items,
                                                                    unsigned long long *__restrict__ counter) {
@@ -318,14 +388,18 @@ __global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc
     a.n_chan = b.n_chan;
     a.n_dm = b.n_dm;
     a.row_bytes = b.row_bytes;
-    a.chan_block = b.chan_block;
-    fwd_int_tile<NS, R, NW, U4>(lds, a, dblk, tblk);
+
+    fwd_int_tile<NS, R, NW, CB, U4>(lds, a, dblk, tblk);
   }
 }
 
-#define DD_INT_SHAPES(X) X(16, 2, 16) X(16, 4, 8) X(32, 2, 8) X(16, 1, 16) X(32, 1, 8)
+// Compiled tile shapes (samples per lane, DM rows per wave, waves, channels
+// per LDS stage), in the order the plan tries them.
+#define DD_INT_SHAPES(X)                                                                                    \
+  X(16, 2, 16, 8) X(16, 4, 8, 8) X(16, 2, 16, 4) X(16, 4, 8, 4) X(16, 1, 16, 8) X(16, 1, 16, 4) X(16, 1, 16, 2) \
+  X(16, 1, 16, 1)
 
-template <int NS, int R, int NW>
+template <int NS, int R, int NW, int CB>
 int launch_int_shape(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, hipStream_t st) {
   const TileCfg &t = p.fwd;
   IntArgs a;
@@ -340,41 +414,43 @@ int launch_int_shape(const dd_plan &p, const void *d_in, float *d_out, int64_t o
   a.n_chan = p.desc.n_chan;
   a.n_dm = p.desc.n_dm;
   a.row_bytes = t.row_bytes;
-  a.chan_block = t.chan_block;
   const int64_t tiles_t = (p.n_out + 64 * NS - 1) / (64 * NS);
   if (tiles_t > 65535) return (int)hipErrorInvalidConfiguration;
   dim3 grid((unsigned)((p.desc.n_dm + NW * R - 1) / (NW * R)), (unsigned)tiles_t);
-  const void *fn = p.desc.dtype == DD_U4 ? (const void *)fwd_int_kernel<NS, R, NW, true>
-                                         : (const void *)fwd_int_kernel<NS, R, NW, false>;
+  const void *fn = p.desc.dtype == DD_U4 ? (const void *)fwd_int_kernel<NS, R, NW, CB, true>
+                                         : (const void *)fwd_int_kernel<NS, R, NW, CB, false>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, t.lds_bytes);
   if (e != hipSuccess) return (int)e;
   if (p.desc.dtype == DD_U4)
-    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, true>), grid, dim3(NW * 64), t.lds_bytes, st, a);
+    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, true>), grid, dim3(NW * 64), t.lds_bytes, st, a);
   else
-    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, false>), grid, dim3(NW * 64), t.lds_bytes, st, a);
+    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, false>), grid, dim3(NW * 64), t.lds_bytes, st, a);
   return (int)hipGetLastError();
 }
 
 }  // namespace
 
-const int kIntShapes[][3] = {{16, 2, 16}, {16, 4, 8}, {32, 2, 8}, {16, 1, 16}, {32, 1, 8}};
-const int kNumIntShapes = 5;
+#define DD_ROW(NS, R, NW, CB) {NS, R, NW, CB},
+const int kIntShapes[][4] = {DD_INT_SHAPES(DD_ROW)};
+#undef DD_ROW
+const int kNumIntShapes = (int)(sizeof(kIntShapes) / sizeof(kIntShapes[0]));
 
 int launch_forward_int(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream) {
   const TileCfg &t = p.fwd;
-#define DD_TRY(NS, R, NW) \
-  if (t.ns == NS && t.dm_per_wave == R && t.waves == NW) return launch_int_shape<NS, R, NW>(p, d_in, d_out, out_pitch, (hipStream_t)stream);
+#define DD_TRY(NS, R, NW, CB)                                                       \
+  if (t.ns == NS && t.dm_per_wave == R && t.waves == NW && t.chan_block == CB)     \
+    return launch_int_shape<NS, R, NW, CB>(p, d_in, d_out, out_pitch, (hipStream_t)stream);
   DD_INT_SHAPES(DD_TRY)
 #undef DD_TRY
   return (int)hipErrorInvalidValue;
 }
 
-int batch_kernels(int ns, int dm_per_wave, int waves, bool u4, int lds_bytes, BatchLaunch *out) {
+int batch_kernels(int ns, int dm_per_wave, int waves, int chan_block, bool u4, int lds_bytes, BatchLaunch *out) {
   const void *fn = nullptr;
-#define DD_TRY(NS, R, NW)                                                              \
-  if (ns == NS && dm_per_wave == R && waves == NW)                                     \
-    fn = u4 ? (const void *)fwd_int_batched_kernel<NS, R, NW, true>                     \
-            : (const void *)fwd_int_batched_kernel<NS, R, NW, false>;
+#define DD_TRY(NS, R, NW, CB)                                                               \
+  if (ns == NS && dm_per_wave == R && waves == NW && chan_block == CB)                      \
+    fn = u4 ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, true>                      \
+            : (const void *)fwd_int_batched_kernel<NS, R, NW, CB, false>;
   DD_INT_SHAPES(DD_TRY)
 #undef DD_TRY
   if (!fn) return (int)hipErrorInvalidValue;

@@ -138,8 +138,14 @@ int row_bytes_for(int dtype, int ns, int span) {
 }
 
 // Tables of the integer forward kernel for tile shape (ns, dm_per_wave, waves).
+// For DM block b, channel c: sbase = shift(c, first DM of b) rounded down to
+// the staging unit; for each DM d of the block, with v = shift(c, d) - sbase
+// the window's offset in the staged row, the entry is the LDS byte offset of
+// its first word inside the channel's four byte-phase copies (each row_bytes
+// long): (v % 4) * row_bytes + (v - v % 4).
 // Fails with DD_ERR_RANGE if even one channel per LDS stage does not fit.
-dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves, int lds_limit, IntTables *t) {
+dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves, int chan_block, int lds_limit,
+                           IntTables *t) {
   const int nc = p.desc.n_chan, nd = p.desc.n_dm;
   const int dblk = waves * dm_per_wave;
   const int unit = p.desc.dtype == DD_U4 ? 32 : 16;
@@ -147,23 +153,20 @@ dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves,
   const int64_t rb = (int64_t)64 * ns + span + unit + 16;
   if (rb > (1 << 24)) return fail(DD_ERR_RANGE, "delay spread too large");
   t->row_bytes = round_up(rb, unit);
-  t->chan_block = 0;
-  const int row_chunks = t->row_bytes / 16;
-  for (int cb = 16; cb >= 1; cb /= 2) {
-    const int64_t lds = (int64_t)2 * cb * 4 * t->row_bytes;  // two buffers of 4 byte-phase copies
-    const bool tasks_ok = cb * row_chunks <= 1024;  // staging tasks per block (the kernel's kStageTasks)
-    if (lds <= lds_limit && tasks_ok) {
-      t->chan_block = cb;
-      t->lds_bytes = (int)lds;
-      break;
-    }
-  }
-  if (!t->chan_block) return fail(DD_ERR_RANGE, "delay spread of a DM block exceeds the LDS staging capacity");
-  if ((int64_t)span + unit - 1 > 65535) return fail(DD_ERR_RANGE, "delay spread exceeds 16-bit offsets");
+  // LDS: two buffers of 4 byte-phase copies, a ring of 3 raw slots (rows of
+  // raw bytes + 16), 1 KB of scratch.  Loads per block: 1 KB segments of raw rows.
+  const int raw = p.desc.dtype == DD_U4 ? t->row_bytes / 2 : t->row_bytes;
+  const int64_t lds = (int64_t)2 * chan_block * 4 * t->row_bytes + (int64_t)3 * chan_block * (raw + 16) + 1024;
+  if (lds > lds_limit) return fail(DD_ERR_RANGE, "staged channel block exceeds LDS");
+  if (chan_block * ((raw + 1023) / 1024) > 16) return fail(DD_ERR_RANGE, "too many staging segments");  // kStageSegs
+  if ((int64_t)4 * t->row_bytes > 65536) return fail(DD_ERR_RANGE, "staged rows too long for 16-bit LDS offsets");
+  t->chan_block = chan_block;
+  t->lds_bytes = (int)lds;
   const int n_dblk = (nd + dblk - 1) / dblk;
   const int rp = dm_per_wave < 2 ? 2 : dm_per_wave;  // uint16 slots per channel (whole 32-bit words)
+  const int ncp = (nc + chan_block - 1) / chan_block * chan_block;  // padding channels read offset 0
   try {
-    t->offs.assign((size_t)n_dblk * waves * nc * rp, 0);
+    t->offs.assign((size_t)n_dblk * waves * ncp * rp, 0);
     t->sbase.assign((size_t)n_dblk * nc, 0);
   } catch (const std::bad_alloc &) {
     return fail(DD_ERR_NOMEM, "table allocation failed");
@@ -176,8 +179,13 @@ dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves,
       for (int r = 0; r < dm_per_wave; ++r) {
         const int d = std::min(b * dblk + w * dm_per_wave + r, nd - 1);
         const int32_t *sd = p.shift.data() + (size_t)d * nc;
-        uint16_t *o = t->offs.data() + (((size_t)b * waves + w) * nc) * rp + r;
-        for (int c = 0; c < nc; ++c) o[(size_t)c * rp] = (uint16_t)(sd[c] - sb[c]);
+        uint16_t *o = t->offs.data() + (((size_t)b * waves + w) * ncp) * rp + r;
+        for (int c = 0; c < nc; ++c) {
+          // window offset v inside the staged row -> byte offset of its first
+          // word inside the channel's four byte-phase copies
+          const int32_t v = sd[c] - sb[c];
+          o[(size_t)c * rp] = (uint16_t)((v & 3) * t->row_bytes + (v & ~3));
+        }
       }
   }
   return DD_OK;
@@ -214,13 +222,14 @@ dd_status choose_forward_tiles(dd_plan &p) {
   }
   for (int i = first; i < kNumIntShapes; ++i) {
     IntTables tab;
-    last = build_int_tables(p, kIntShapes[i][0], kIntShapes[i][1], kIntShapes[i][2], kLdsLimit, &tab);
+    const int *k = kIntShapes[i];
+    last = build_int_tables(p, k[0], k[1], k[2], k[3], kLdsLimit, &tab);
     if (last == DD_OK) {
-      t.ns = kIntShapes[i][0];
-      t.dm_per_wave = kIntShapes[i][1];
-      t.waves = kIntShapes[i][2];
+      t.ns = k[0];
+      t.dm_per_wave = k[1];
+      t.waves = k[2];
+      t.chan_block = k[3];
       t.row_bytes = tab.row_bytes;
-      t.chan_block = tab.chan_block;
       t.lds_bytes = tab.lds_bytes;
       p.fwd = t;
       p.span_fwd = max_dm_block_span(p, t.waves * t.dm_per_wave);
@@ -229,7 +238,7 @@ dd_status choose_forward_tiles(dd_plan &p) {
     }
     if (last == DD_ERR_NOMEM) return last;
   }
-  return last;
+  return fail(DD_ERR_RANGE, "delay spread of a DM block exceeds every compiled staging shape");
 }
 
 dd_status choose_adjoint_tiles(dd_plan &p) {
