@@ -102,6 +102,8 @@ def main():
     ap.add_argument("--workload", default="headline")
     ap.add_argument("--adjoint", action="store_true", help="time the adjoint instead of the forward")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy first, as a known-size reference for memory counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -121,6 +123,13 @@ def main():
     log("plan %.2f s: n_out=%d max_shift=%d tile ns=%d dm/wave=%d waves=%d chan_block=%d" % (
         time.perf_counter() - t, plan.n_out, plan.max_shift, plan.info.kernel_ns, plan.info.kernel_dm_per_wave,
         plan.info.kernel_waves, plan.info.kernel_chan_block))
+    if args.copy_calibration:
+        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 1 GiB read + 1 GiB written")
     x = make_input(dd, torch, synth, cfg, plan)
     out = torch.empty((plan.n_dm, plan.out_pitch), dtype=torch.float32, device="cuda")
     if args.adjoint:
