@@ -48,7 +48,7 @@ dd_status dd_plan_create(const dd_plan_desc *desc, dd_plan **out) {
   if (!(d.chan_bw_mhz >= 0.0) || !isfinite(d.chan_bw_mhz)) return fail(DD_ERR_ARG, "chan_bw must be >= 0");
   if (!(d.dm_start >= 0.0) || !isfinite(d.dm_start)) return fail(DD_ERR_RANGE, "dm_start must be >= 0");
   if (!(d.dm_step >= 0.0) || !isfinite(d.dm_step)) return fail(DD_ERR_RANGE, "dm_step must be >= 0");
-  if (d.n_samp > ((int64_t)1 << 40)) return fail(DD_ERR_RANGE, "n_samp too large");
+  if (d.n_samp >= ((int64_t)1 << 29)) return fail(DD_ERR_RANGE, "n_samp must be below 2^29");
   // Exactness of int32 accumulation and float output: every sum below 2^24.
   if (d.dtype == DD_U8 && d.n_chan > 65793) return fail(DD_ERR_RANGE, "more than 65793 8-bit channels cannot be summed exactly in float32");
   if (d.dtype == DD_U4 && d.n_chan > 1118481) return fail(DD_ERR_RANGE, "too many 4-bit channels for exact float32 output");
@@ -56,7 +56,7 @@ dd_status dd_plan_create(const dd_plan_desc *desc, dd_plan **out) {
   const int64_t pitch = d.in_pitch_bytes ? d.in_pitch_bytes : row;
   if (pitch < row) return fail(DD_ERR_ARG, "in_pitch_bytes smaller than one row");
   if (pitch % 16) return fail(DD_ERR_ALIGN, "input row pitch must be a multiple of 16 bytes");
-  if (d.dtype != DD_F32 && pitch >= ((int64_t)1 << 31)) return fail(DD_ERR_RANGE, "integer input rows must be shorter than 2^31 bytes");
+  if (pitch >= ((int64_t)1 << 31)) return fail(DD_ERR_RANGE, "input rows must be shorter than 2^31 bytes");
   if ((double)d.n_dm * (double)d.n_chan * 12.0 > 9.0e18) return fail(DD_ERR_RANGE, "table size overflow");
 
   dd_plan *p = new (std::nothrow) dd_plan();
@@ -75,10 +75,6 @@ dd_status dd_plan_create(const dd_plan_desc *desc, dd_plan **out) {
   p->desc.in_pitch_bytes = pitch;
   dd_status st = build_shift_table(*p);
   if (st == DD_OK) st = choose_forward_tiles(*p);
-  if (st == DD_OK && d.dtype == DD_F32) {
-    st = choose_adjoint_tiles(*p);
-    if (st == DD_OK) build_adjoint_tables(*p);
-  }
   if (st != DD_OK) {
     delete p;
     return st;
@@ -124,17 +120,18 @@ dd_status dd_plan_bind(dd_plan *p, void *ws, size_t bytes, void *stream) {
       e = hipMemcpyAsync(base + p->int_sbase_off, p->itab.sbase.data(), p->itab.sbase.size() * 4,
                          hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "table upload");
-    p->d_shift = nullptr;
   } else {
-    int32_t *dst = (int32_t *)ws;
-    e = hipMemcpyAsync(dst, p->shift.data(), p->shift.size() * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && !p->shift_t.empty())
-      e = hipMemcpyAsync(dst + p->shift.size(), p->shift_t.data(), p->shift_t.size() * 4, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && !p->smax.empty())
-      e = hipMemcpyAsync(dst + p->shift.size() + p->shift_t.size(), p->smax.data(), p->smax.size() * 4,
-                         hipMemcpyHostToDevice, st);
+    size_t off = 0;
+    FloatTables *tabs[2] = {&p->ftab_fwd, &p->ftab_adj};
+    for (FloatTables *t : tabs) {
+      t->offs_off = off;
+      if (e == hipSuccess) e = hipMemcpyAsync(base + off, t->offs.data(), t->offs.size() * 2, hipMemcpyHostToDevice, st);
+      off += (t->offs.size() * 2 + 255) / 256 * 256;
+      t->sbase_off = off;
+      if (e == hipSuccess) e = hipMemcpyAsync(base + off, t->sbase.data(), t->sbase.size() * 4, hipMemcpyHostToDevice, st);
+      off += (t->sbase.size() * 4 + 255) / 256 * 256;
+    }
     if (e != hipSuccess) return hip_fail(e, "table upload");
-    p->d_shift = dst;
   }
   p->d_tables = ws;
   p->device = dev;
@@ -158,7 +155,8 @@ dd_status dd_execute(const dd_plan *p, const void *d_in, float *d_out, int64_t o
   if (!aligned16(d_in) || !aligned16(d_out)) return fail(DD_ERR_ALIGN, "buffers must be 16-byte aligned");
   if (out_pitch < p->n_out) return fail(DD_ERR_ARG, "out_pitch < n_out");
   if (out_pitch % 4) return fail(DD_ERR_ALIGN, "out_pitch must be a multiple of 4 elements");
-  int e = launch_forward(*p, d_in, d_out, out_pitch, stream);
+  int e = p->desc.dtype == DD_F32 ? launch_forward_f32(*p, d_in, d_out, out_pitch, stream)
+                                  : launch_forward_int(*p, d_in, d_out, out_pitch, stream);
   if (e) return hip_fail(e, "forward launch");
   return DD_OK;
 }

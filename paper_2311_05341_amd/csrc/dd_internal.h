@@ -35,12 +35,18 @@ struct IntTables {
   std::vector<int32_t> sbase;  // [n_dblk][n_chan]
   int row_bytes = 0, chan_block = 0, lds_bytes = 0;
 };
-// Everything the device needs about one plan, in device-visible form.
-struct DevPlan {
-  const int32_t *shift;  // [n_dm][n_chan]
-  int32_t n_chan, n_dm;
-  int64_t n_samp, n_out, in_pitch_bytes;
-  int32_t dtype;
+// Tables of the float kernel (forward or adjoint) for one tile shape.  The
+// kernel sums staged rows k (channels forward, DM rows adjoint) into outputs o
+// (DM rows forward, channels adjoint) at delay sh(o, k) = +shift (forward) or
+// -shift (adjoint).  Per output block: sbase = the block's smallest sh of row
+// k rounded down to 4 floats; per (block, wave, row, output of the wave): the
+// LDS byte offset 4 * (sh - sbase) of the window in the staged row.
+struct FloatTables {
+  int ns = 0, per_wave = 0, waves = 0, row_block = 0;
+  int row_bytes = 0, lds_bytes = 0;
+  std::vector<uint16_t> offs;  // [n_oblk][waves][n_rows rounded up to row_block][max(per_wave, 2)]
+  std::vector<int32_t> sbase;  // [n_oblk][n_rows]
+  size_t offs_off = 0, sbase_off = 0;  // device offsets inside the plan workspace
 };
 
 }  // namespace dd
@@ -49,20 +55,17 @@ struct dd_plan {
   dd_plan_desc desc{};
   std::vector<double> freqs;   // explicit frequencies (empty = uniform)
   std::vector<int32_t> shift;  // [n_dm][n_chan]
-  std::vector<int32_t> shift_t;  // [n_chan][n_dm] (float plans, adjoint)
-  std::vector<int32_t> smax;     // [adjoint channel blocks][n_dm] (float plans)
   int64_t n_out = 0;
   int32_t max_shift = 0;
   int64_t in_pitch_bytes = 0;
   dd::TileCfg fwd;             // forward tile shape
-  dd::TileCfg adj;             // adjoint tile shape (f32 plans)
   int32_t span_fwd = 0;        // largest delay spread inside a forward DM block
-  int32_t span_adj = 0;        // largest delay spread inside an adjoint channel block
   dd::IntTables itab;          // integer plans: forward kernel tables
+  dd::FloatTables ftab_fwd;    // float plans: forward kernel tables
+  dd::FloatTables ftab_adj;    // float plans: adjoint kernel tables
   // binding
   const void *d_tables = nullptr;
   size_t int_offs_off = 0, int_sbase_off = 0;
-  const int32_t *d_shift = nullptr;
   int device = -1;
   bool bound = false;
 };
@@ -73,10 +76,8 @@ namespace dd {
 dd_status build_shift_table(dd_plan &p);
 int32_t max_dm_block_span(const dd_plan &p, int dm_block);
 int row_bytes_for(int dtype, int ns, int span);
-int32_t max_chan_block_span(const dd_plan &p, int chan_block);
 dd_status choose_forward_tiles(dd_plan &p);
-dd_status choose_adjoint_tiles(dd_plan &p);
-void build_adjoint_tables(dd_plan &p);
+dd_status choose_float_tiles(dd_plan &p);
 size_t table_bytes(const dd_plan &p);
 
 // One beam of a batch, as the persistent kernel sees it.
@@ -94,8 +95,11 @@ dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves,
                            IntTables *t);
 
 // Kernel launchers (kernels.hip).  Return hipError_t as int.
-int launch_forward(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream);
 int launch_forward_int(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream);
+int launch_forward_f32(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream);
+// Float tile shapes compiled into the library: (ns, per_wave, waves, row_block).
+extern const int kF32Shapes[][4];
+extern const int kNumF32Shapes;
 // Integer tile shapes compiled into the library: (ns, dm_per_wave, waves,
 // chan_block), in the order plans try them.
 extern const int kIntShapes[][4];

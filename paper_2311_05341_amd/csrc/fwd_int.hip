@@ -39,6 +39,7 @@ namespace {
 
 constexpr uint32_t kOddSel = 0x0C030C01u;
 constexpr int kBufferRsrcFlags = 0x00020000;  // raw (untyped) buffer access, word 3 of the descriptor
+constexpr int kXcdCount = 8;                   // MI355X: 8 accelerator complex dies, one L2 each
 
 // Read-only tables read with wave-uniform addresses go through the constant
 // address space, which the compiler always serves with scalar loads; a vector
@@ -142,12 +143,15 @@ __device__ __forceinline__ v4i_t make_rsrc(const void *base, int bytes) {
 // its own conservative wait for these LDS writes before every later LDS read:
 // the kernel waits for them explicitly (wait_vmcnt) and orders them with
 // lds_barrier().
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"  // m0 is reserved, but nothing else in these kernels uses it
 __device__ __forceinline__ void dma16(const v4i_t &rs, uint32_t voff, uint32_t lds_addr) {
   asm volatile("s_mov_b32 m0, %1\n\ts_nop 0\n\tbuffer_load_dwordx4 %0, %2, 0 offen lds"
                :
                : "v"(voff), "s"(lds_addr), "s"(rs)
                : "memory", "m0");
 }
+#pragma clang diagnostic pop
 
 // LDS layout of a tile: two phase buffers, the ring, a 1 KB scratch area.
 struct TileLds {
@@ -340,11 +344,31 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
   }
 }
 
-// One workgroup per tile; grid = (DM blocks, time tiles).
+// Workgroup -> tile map.  Workgroups are handed to the XCDs (each with its own
+// L2) round-robin by linear id, so workgroup w runs on XCD w % n_xcd.  Each
+// XCD is given whole time tiles (all DM blocks of tile x, x + n_xcd, ...):
+// the workgroups resident on an XCD then stage the same input rows, which its
+// L2 serves once.  Tiles left over after the last full round go linearly.
+__device__ __forceinline__ void tile_of(int w, int n_dblk, int n_tiles, int n_xcd, int &dblk, int &tblk) {
+  const int full = n_tiles / n_xcd * n_xcd;
+  if (w < n_dblk * full) {
+    const int x = w % n_xcd, k = w / n_xcd;
+    tblk = x + n_xcd * (k / n_dblk);
+    dblk = k % n_dblk;
+  } else {
+    const int r = w - n_dblk * full;
+    tblk = full + r / n_dblk;
+    dblk = r % n_dblk;
+  }
+}
+
+// One workgroup per tile; 1-D grid of n_dblk * n_tiles workgroups.
 template <int NS, int R, int NW, int CB, bool U4>
-__global__ __launch_bounds__(NW * 64) void fwd_int_kernel(IntArgs a) {
+__global__ __launch_bounds__(NW * 64) void fwd_int_kernel(IntArgs a, int n_dblk, int n_tiles, int n_xcd) {
   extern __shared__ __align__(16) uint8_t lds[];
-  fwd_int_tile<NS, R, NW, CB, U4>(lds, a, blockIdx.x, blockIdx.y);
+  int dblk, tblk;
+  tile_of(blockIdx.x, n_dblk, n_tiles, n_xcd, dblk, tblk);
+  fwd_int_tile<NS, R, NW, CB, U4>(lds, a, dblk, tblk);
 }
 
 __global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0ull; }
@@ -397,7 +421,7 @@ __global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc
 // per LDS stage), in the order the plan tries them.
 #define DD_INT_SHAPES(X)                                                                                    \
   X(16, 2, 16, 8) X(16, 4, 8, 8) X(16, 2, 16, 4) X(16, 4, 8, 4) X(16, 1, 16, 8) X(16, 1, 16, 4) X(16, 1, 16, 2) \
-  X(16, 1, 16, 1)
+  X(16, 1, 16, 1) X(16, 1, 4, 1) X(16, 1, 1, 1)
 
 template <int NS, int R, int NW, int CB>
 int launch_int_shape(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, hipStream_t st) {
@@ -415,16 +439,20 @@ int launch_int_shape(const dd_plan &p, const void *d_in, float *d_out, int64_t o
   a.n_dm = p.desc.n_dm;
   a.row_bytes = t.row_bytes;
   const int64_t tiles_t = (p.n_out + 64 * NS - 1) / (64 * NS);
-  if (tiles_t > 65535) return (int)hipErrorInvalidConfiguration;
-  dim3 grid((unsigned)((p.desc.n_dm + NW * R - 1) / (NW * R)), (unsigned)tiles_t);
+  const int64_t n_dblk = (p.desc.n_dm + NW * R - 1) / (NW * R);
+  if (tiles_t * n_dblk >= ((int64_t)1 << 31)) return (int)hipErrorInvalidConfiguration;
+  dim3 grid((unsigned)(tiles_t * n_dblk));
+  const int n_xcd = kXcdCount;
   const void *fn = p.desc.dtype == DD_U4 ? (const void *)fwd_int_kernel<NS, R, NW, CB, true>
                                          : (const void *)fwd_int_kernel<NS, R, NW, CB, false>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, t.lds_bytes);
   if (e != hipSuccess) return (int)e;
   if (p.desc.dtype == DD_U4)
-    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, true>), grid, dim3(NW * 64), t.lds_bytes, st, a);
+    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, true>), grid, dim3(NW * 64), t.lds_bytes, st, a, (int)n_dblk,
+                       (int)tiles_t, n_xcd);
   else
-    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, false>), grid, dim3(NW * 64), t.lds_bytes, st, a);
+    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, false>), grid, dim3(NW * 64), t.lds_bytes, st, a, (int)n_dblk,
+                       (int)tiles_t, n_xcd);
   return (int)hipGetLastError();
 }
 

@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <climits>
 #include <new>
 #include <thread>
 
@@ -104,22 +105,6 @@ int32_t max_dm_block_span(const dd_plan &p, int dm_block) {
   return span;
 }
 
-// Largest spread max_c shift - min_c shift over channel blocks [b*cb, b*cb+cb), any DM.
-int32_t max_chan_block_span(const dd_plan &p, int chan_block) {
-  const int nc = p.desc.n_chan, nd = p.desc.n_dm;
-  int32_t span = 0;
-  for (int d = 0; d < nd; ++d) {
-    const int32_t *row = p.shift.data() + (size_t)d * nc;
-    for (int lo = 0; lo < nc; lo += chan_block) {
-      const int hi = std::min(lo + chan_block, nc);
-      int32_t mn = row[lo], mx = row[lo];
-      for (int c = lo + 1; c < hi; ++c) { mn = std::min(mn, row[c]); mx = std::max(mx, row[c]); }
-      span = std::max(span, mx - mn);
-    }
-  }
-  return span;
-}
-
 static const int kLdsLimit = 160 * 1024;
 
 static int round_up(int64_t v, int a) { return (int)((v + a - 1) / a * a); }
@@ -191,29 +176,97 @@ dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves,
   return DD_OK;
 }
 
+// Tables of the float kernel in direction `adjoint` for shape (ns, per_wave,
+// waves, row_block); see FloatTables.
+static dd_status build_float_tables(const dd_plan &p, bool adjoint, const int *shape, int lds_limit,
+                                    FloatTables *t) {
+  const int nc = p.desc.n_chan, nd = p.desc.n_dm;
+  const int ns = shape[0], per_wave = shape[1], waves = shape[2], rb = shape[3];
+  const int n_rows = adjoint ? nd : nc, n_out = adjoint ? nc : nd;
+  const int oblk = waves * per_wave;
+  const int n_oblk = (n_out + oblk - 1) / oblk;
+  auto sh = [&](int o, int k) -> int32_t {
+    return adjoint ? -p.shift[(size_t)k * nc + o] : p.shift[(size_t)o * nc + k];
+  };
+  // staging bases and the largest spread
+  std::vector<int32_t> sbase;
+  try {
+    sbase.assign((size_t)n_oblk * n_rows, 0);
+  } catch (const std::bad_alloc &) {
+    return fail(DD_ERR_NOMEM, "table allocation failed");
+  }
+  int64_t span = 0;
+  for (int b = 0; b < n_oblk; ++b)
+    for (int k = 0; k < n_rows; ++k) {
+      int32_t mn = INT32_MAX, mx = INT32_MIN;
+      for (int o = b * oblk; o < std::min(n_out, (b + 1) * oblk); ++o) {
+        const int32_t v = sh(o, k);
+        mn = std::min(mn, v);
+        mx = std::max(mx, v);
+      }
+      sbase[(size_t)b * n_rows + k] = mn & ~3;  // rounds toward minus infinity
+      span = std::max<int64_t>(span, (int64_t)mx - mn);
+    }
+  const int64_t floats = ((int64_t)64 * ns + span + 4 + 3) / 4 * 4;
+  if (floats * 4 > (1 << 24)) return fail(DD_ERR_RANGE, "delay spread too large");
+  t->row_bytes = (int)(floats * 4);
+  const int64_t lds = (int64_t)3 * rb * t->row_bytes + 1024;  // ring of 3 slots and a 1 KiB load sink
+  if (lds > lds_limit) return fail(DD_ERR_RANGE, "staged row block exceeds LDS");
+  if (rb * ((t->row_bytes + 1023) / 1024) > std::min(64, 16 * waves))  // the kernel's load segments per block
+    return fail(DD_ERR_RANGE, "too many staging segments");
+  if (t->row_bytes > 65536) return fail(DD_ERR_RANGE, "staged rows too long for 16-bit LDS offsets");
+  t->ns = ns;
+  t->per_wave = per_wave;
+  t->waves = waves;
+  t->row_block = rb;
+  t->lds_bytes = (int)lds;
+  const int rp = per_wave < 2 ? 2 : per_wave;
+  const int nrp = (n_rows + rb - 1) / rb * rb;
+  try {
+    t->offs.assign((size_t)n_oblk * waves * nrp * rp, 0);
+  } catch (const std::bad_alloc &) {
+    return fail(DD_ERR_NOMEM, "table allocation failed");
+  }
+  for (int b = 0; b < n_oblk; ++b)
+    for (int w = 0; w < waves; ++w)
+      for (int r = 0; r < per_wave; ++r) {
+        const int o = std::min(b * oblk + w * per_wave + r, n_out - 1);
+        uint16_t *dst = t->offs.data() + (((size_t)b * waves + w) * nrp) * rp + r;
+        for (int k = 0; k < n_rows; ++k)
+          dst[(size_t)k * rp] = (uint16_t)(4 * (sh(o, k) - sbase[(size_t)b * n_rows + k]));
+      }
+  t->sbase = std::move(sbase);
+  return DD_OK;
+}
+
+dd_status choose_float_tiles(dd_plan &p) {
+  for (int dir = 0; dir < 2; ++dir) {
+    FloatTables &dst = dir ? p.ftab_adj : p.ftab_fwd;
+    dd_status last = DD_ERR_RANGE;
+    for (int i = 0; i < kNumF32Shapes; ++i) {
+      FloatTables t;
+      last = build_float_tables(p, dir == 1, kF32Shapes[i], kLdsLimit, &t);
+      if (last == DD_OK) {
+        dst = std::move(t);
+        break;
+      }
+      if (last == DD_ERR_NOMEM) return last;
+    }
+    if (last != DD_OK) return fail(DD_ERR_RANGE, "delay spread exceeds every compiled float staging shape");
+  }
+  TileCfg &f = p.fwd;
+  f.ns = p.ftab_fwd.ns;
+  f.dm_per_wave = p.ftab_fwd.per_wave;
+  f.waves = p.ftab_fwd.waves;
+  f.chan_block = p.ftab_fwd.row_block;
+  f.row_bytes = p.ftab_fwd.row_bytes;
+  f.lds_bytes = p.ftab_fwd.lds_bytes;
+  return DD_OK;
+}
+
 dd_status choose_forward_tiles(dd_plan &p) {
   TileCfg t;
-  if (p.desc.dtype == DD_F32) {
-    t.ns = 16;
-    t.dm_per_wave = 4;
-    t.waves = 4;
-    for (;;) {
-      const int span = max_dm_block_span(p, t.waves * t.dm_per_wave);
-      t.row_bytes = row_bytes_for(p.desc.dtype, t.ns, span);
-      for (t.chan_block = 16; t.chan_block >= 1; t.chan_block /= 2) {
-        t.lds_bytes = t.chan_block * t.row_bytes;
-        if (t.lds_bytes <= kLdsLimit) break;
-      }
-      if (t.chan_block >= 1) {
-        p.span_fwd = span;
-        p.fwd = t;
-        return DD_OK;
-      }
-      if (t.dm_per_wave > 1) { t.dm_per_wave /= 2; continue; }
-      if (t.waves > 1) { t.waves /= 2; continue; }
-      return fail(DD_ERR_RANGE, "delay spread of one DM block exceeds the LDS staging capacity");
-    }
-  }
+  if (p.desc.dtype == DD_F32) return choose_float_tiles(p);
   dd_status last = DD_ERR_RANGE;
   int first = 0;
   if (const char *env = getenv("DD_INT_SHAPE")) {  // force a compiled shape by index (tuning experiments)
@@ -241,54 +294,15 @@ dd_status choose_forward_tiles(dd_plan &p) {
   return fail(DD_ERR_RANGE, "delay spread of a DM block exceeds every compiled staging shape");
 }
 
-dd_status choose_adjoint_tiles(dd_plan &p) {
-  TileCfg t;
-  t.ns = 16; t.dm_per_wave = 4; t.waves = 4; t.chan_block = 16;  // dm_per_wave = channels per wave here
-  for (;;) {
-    const int span = max_chan_block_span(p, t.waves * t.dm_per_wave);
-    t.row_bytes = round_up((int64_t)(64 * t.ns + span + 4 + 4 + 4) * 4, 16);
-    for (t.chan_block = 16; t.chan_block >= 1; t.chan_block /= 2) {  // DM rows per stage
-      t.lds_bytes = t.chan_block * t.row_bytes;
-      if (t.lds_bytes <= kLdsLimit) break;
-    }
-    if (t.chan_block >= 1) {
-      p.span_adj = span;
-      p.adj = t;
-      return DD_OK;
-    }
-    if (t.dm_per_wave > 1) { t.dm_per_wave /= 2; continue; }
-    if (t.waves > 1) { t.waves /= 2; continue; }
-    return fail(DD_ERR_RANGE, "channel delay spread exceeds LDS staging capacity");
-  }
-}
-
-// Adjoint tables: the shift table transposed to [n_chan][n_dm] (a workgroup
-// walks DMs for fixed channels) and, per adjoint channel block and DM, the
-// largest delay of the block's channels (the base of the staged y rows).
-void build_adjoint_tables(dd_plan &p) {
-  const int nc = p.desc.n_chan, nd = p.desc.n_dm;
-  const int cpb = p.adj.waves * p.adj.dm_per_wave;
-  const int nblk = (nc + cpb - 1) / cpb;
-  p.shift_t.assign((size_t)nc * nd, 0);
-  for (int d = 0; d < nd; ++d)
-    for (int c = 0; c < nc; ++c) p.shift_t[(size_t)c * nd + d] = p.shift[(size_t)d * nc + c];
-  p.smax.assign((size_t)nblk * nd, 0);
-  for (int b = 0; b < nblk; ++b)
-    for (int d = 0; d < nd; ++d) {
-      int32_t m = 0;
-      for (int c = b * cpb; c < std::min(nc, (b + 1) * cpb); ++c) m = std::max(m, p.shift[(size_t)d * nc + c]);
-      p.smax[(size_t)b * nd + d] = m;
-    }
-}
-
 static size_t up256(size_t v) { return (v + 255) / 256 * 256; }
 
 // Device workspace layout.  Integer plans: [offs uint16][sbase int32].
-// Float plans: [shift int32][shift transposed int32][adjoint block maxima int32].
+// Float plans: [forward offs][forward sbase][adjoint offs][adjoint sbase].
 size_t table_bytes(const dd_plan &p) {
   if (p.desc.dtype != DD_F32)
     return up256(p.itab.offs.size() * sizeof(uint16_t)) + up256(p.itab.sbase.size() * sizeof(int32_t));
-  return up256((p.shift.size() + p.shift_t.size() + p.smax.size()) * sizeof(int32_t));
+  return up256(p.ftab_fwd.offs.size() * 2) + up256(p.ftab_fwd.sbase.size() * 4) + up256(p.ftab_adj.offs.size() * 2) +
+         up256(p.ftab_adj.sbase.size() * 4);
 }
 
 }  // namespace dd
