@@ -11,7 +11,7 @@ forward kernel, and the CPU oracle timed on a bounded sample of the same
 workload.
 
   python bench.py [--steps K] [--warmup W] [--workload headline|lowfreq_u4|grad_f32|small]
-                  [--adjoint] [--no-cpu-baseline]
+                  [--adjoint] [--no-cpu-baseline] [--no-autotune]
 """
 from __future__ import annotations
 
@@ -28,6 +28,11 @@ sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz = 39.32e12 32-bit VALU lane-operations per second.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# LDS: 128 bytes per clock per CU for 4- and 8-byte reads (the widths the accumulate loops use).
+LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
+# LDS bytes the accumulate loop reads per add: one byte per 8- or 4-bit sample
+# (4-bit samples are unpacked to bytes when staged), four per float.
+LDS_BYTES_PER_ADD = {"u8": 1, "u4": 1, "f32": 4}
 
 
 def log(msg):
@@ -102,6 +107,7 @@ def main():
     ap.add_argument("--workload", default="headline")
     ap.add_argument("--adjoint", action="store_true", help="time the adjoint instead of the forward")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default tile choice")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first, as a known-size reference for memory counters")
     args = ap.parse_args()
@@ -132,12 +138,20 @@ def main():
         log("copy calibration: 1 GiB read + 1 GiB written")
     x = make_input(dd, torch, synth, cfg, plan)
     out = torch.empty((plan.n_dm, plan.out_pitch), dtype=torch.float32, device="cuda")
+    direction = 1 if args.adjoint else 0
     if args.adjoint:
         y = torch.randn((plan.n_dm, plan.out_pitch), device="cuda")
         g = torch.empty((plan.n_chan, plan.in_row_elems), dtype=torch.float32, device="cuda")
         step = lambda: plan.adjoint(y, out=g)  # noqa: E731
     else:
         step = lambda: plan.forward(x, out=out)  # noqa: E731
+    tune = None
+    if not args.no_autotune:
+        t = time.perf_counter()
+        tune = plan.autotune(y, g, direction=1) if args.adjoint else plan.autotune(x, out)
+        tune["seconds"] = time.perf_counter() - t
+        log("autotune %.1f s: %s" % (tune["seconds"], tune))
+    tiles = plan.tiles(direction)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -181,9 +195,13 @@ def main():
         "x_realtime_streaming": plan.n_out * cfg["t_samp"] / (ms_step * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tadds/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
-                     "kernel": "fwd_int_kernel" if cfg["dtype"] != "f32" else (
-                         "adj_f32_kernel" if args.adjoint else "fwd_f32_kernel"),
+                     "kernel": "fwd_int_kernel" if cfg["dtype"] != "f32" else "f32_kernel",
                      "kernel_ms": k_avg},
+        "lds_roofline": {"achieved": achieved * LDS_BYTES_PER_ADD[cfg["dtype"]], "peak": LDS_PEAK_TBS,
+                         "unit": "TB/s", "frac": achieved * LDS_BYTES_PER_ADD[cfg["dtype"]] / LDS_PEAK_TBS,
+                         "bytes_per_add": LDS_BYTES_PER_ADD[cfg["dtype"]]},
+        "tiles": tiles,
+        "autotune": tune,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline ...")

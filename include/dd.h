@@ -81,8 +81,29 @@ typedef struct {
   int64_t in_pitch_bytes;     /* effective input row pitch */
   size_t dev_table_bytes;     /* device workspace dd_plan_bind needs (shift table + tiling tables) */
   const int32_t *host_shift;  /* the FP64-derived table, int32 [n_dm][n_chan]; owned by the plan */
-  int32_t kernel_ns, kernel_dm_per_wave, kernel_waves, kernel_chan_block; /* chosen tile shape */
+  int32_t kernel_ns, kernel_dm_per_wave, kernel_waves, kernel_chan_block; /* forward tile shape */
+  int32_t kernel_order;       /* forward workgroup order (see dd_tiles) */
+  size_t tune_ws_bytes;       /* device workspace dd_plan_autotune needs (tables of any shape) */
 } dd_plan_info;
+
+/* A tile choice for one direction of a plan.  A workgroup computes
+ * waves * per_wave output rows (DM rows forward, channels adjoint) over 64 * ns
+ * output samples, staging row_block input rows (channels forward, DM rows
+ * adjoint) per LDS stage. */
+typedef struct {
+  int32_t shape;  /* index of a shape compiled into the library for the plan's dtype */
+  int32_t order;  /* workgroup order: 0 = time tiles fastest, 1 = each XCD takes whole time tiles */
+  int32_t ns, per_wave, waves, row_block; /* the shape (output of dd_plan_get_tiles) */
+} dd_tiles;
+
+/* Result of dd_plan_autotune.  Times are per launch over the timed span. */
+typedef struct {
+  int32_t n_tried;           /* (shape, order) candidates timed */
+  dd_tiles best;             /* fastest candidate, now the plan's choice */
+  double best_ms;            /* its time */
+  double default_ms;         /* time of the choice the plan had before tuning */
+  int64_t timed_out_samples; /* output samples per row computed by each timed launch */
+} dd_tune_report;
 
 typedef struct dd_plan dd_plan;
 typedef struct dd_batch dd_batch;
@@ -141,6 +162,45 @@ dd_status dd_execute(const dd_plan *plan, const void *d_in, float *d_out, int64_
  */
 dd_status dd_execute_adjoint(const dd_plan *plan, const float *d_y, int64_t y_pitch,
                              float *d_grad_in, void *stream);
+
+/*
+ * Tile shapes and their tuning.  The tile shape (output rows per workgroup,
+ * samples per lane, input rows per LDS stage) and the workgroup order decide
+ * speed only: results are bitwise identical for every choice (exact integer
+ * sums; fixed-order float sums).  dd_plan_create picks the first compiled
+ * shape that holds the plan's delay spread, or the choice recorded for an
+ * identical plan in the tuning cache (below).
+ *
+ * direction: 0 = forward; 1 = adjoint (DD_F32 plans only).
+ *
+ * dd_plan_shape_count: number of compiled shapes for the plan's dtype.
+ * dd_plan_get_tiles: current choice for `direction`.
+ * dd_plan_set_tiles: rebuild the plan's tables for compiled shape `shape` and
+ *   workgroup order `order` (0 or 1).  DD_ERR_RANGE (plan unchanged) if the shape
+ *   cannot stage the plan's delay spread.  On success the plan is unbound:
+ *   query dev_table_bytes again and call dd_plan_bind before executing.
+ * dd_plan_autotune: time every (shape, order) that holds the plan's spread and
+ *   keep the fastest.  Each candidate runs on the caller's buffers over the
+ *   first timed_out_samples output samples of every row (all of them for small
+ *   plans; about 10^12 adds per launch otherwise), once to warm up and twice
+ *   timed with HIP events on `stream`.  The call synchronises `stream`.
+ *     forward: d_src is the input (as dd_execute), d_dst the output with
+ *              `pitch` = out_pitch;
+ *     adjoint: d_src is y with `pitch` = y_pitch, d_dst the gradient (as
+ *              dd_execute_adjoint).
+ *   d_dst's contents are unspecified afterwards.  d_ws (>= tune_ws_bytes of
+ *   dd_plan_query, 16-byte aligned) receives each candidate's tables; on
+ *   success the plan is bound to d_ws with the winner's tables.  If the
+ *   environment variable DD_TUNE_CACHE names a file, the winner is appended to
+ *   it (one text line per plan and direction) and later dd_plan_create calls
+ *   for an identical plan description apply it.  *report may be NULL.
+ *   Errors: DD_ERR_ARG, DD_ERR_ALIGN, DD_ERR_DTYPE, DD_ERR_HIP (plan unbound then).
+ */
+dd_status dd_plan_shape_count(const dd_plan *plan, int32_t *n);
+dd_status dd_plan_get_tiles(const dd_plan *plan, int32_t direction, dd_tiles *tiles);
+dd_status dd_plan_set_tiles(dd_plan *plan, int32_t direction, int32_t shape, int32_t order);
+dd_status dd_plan_autotune(dd_plan *plan, int32_t direction, const void *d_src, float *d_dst, int64_t pitch,
+                           void *d_ws, size_t ws_bytes, void *stream, dd_tune_report *report);
 
 /*
  * Batch of independent forward transforms ("beams"), each with its own plan

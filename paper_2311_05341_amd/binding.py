@@ -40,7 +40,21 @@ class PlanInfo(ctypes.Structure):
                 ("n_chan", ctypes.c_int32), ("in_pitch_bytes", ctypes.c_int64),
                 ("dev_table_bytes", ctypes.c_size_t), ("host_shift", ctypes.POINTER(ctypes.c_int32)),
                 ("kernel_ns", ctypes.c_int32), ("kernel_dm_per_wave", ctypes.c_int32),
-                ("kernel_waves", ctypes.c_int32), ("kernel_chan_block", ctypes.c_int32)]
+                ("kernel_waves", ctypes.c_int32), ("kernel_chan_block", ctypes.c_int32),
+                ("kernel_order", ctypes.c_int32), ("tune_ws_bytes", ctypes.c_size_t)]
+
+
+class Tiles(ctypes.Structure):
+    _fields_ = [("shape", ctypes.c_int32), ("order", ctypes.c_int32), ("ns", ctypes.c_int32),
+                ("per_wave", ctypes.c_int32), ("waves", ctypes.c_int32), ("row_block", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("n_tried", ctypes.c_int32), ("best", Tiles), ("best_ms", ctypes.c_double),
+                ("default_ms", ctypes.c_double), ("timed_out_samples", ctypes.c_int64)]
 
 
 _vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
@@ -56,6 +70,14 @@ _lib.dd_execute.argtypes = [_vp, _vp, _vp, _i64, _vp]
 _lib.dd_execute.restype = _i32
 _lib.dd_execute_adjoint.argtypes = [_vp, _vp, _i64, _vp, _vp]
 _lib.dd_execute_adjoint.restype = _i32
+_lib.dd_plan_shape_count.argtypes = [_vp, ctypes.POINTER(_i32)]
+_lib.dd_plan_shape_count.restype = _i32
+_lib.dd_plan_get_tiles.argtypes = [_vp, _i32, ctypes.POINTER(Tiles)]
+_lib.dd_plan_get_tiles.restype = _i32
+_lib.dd_plan_set_tiles.argtypes = [_vp, _i32, _i32, _i32]
+_lib.dd_plan_set_tiles.restype = _i32
+_lib.dd_plan_autotune.argtypes = [_vp, _i32, _vp, _vp, _i64, _vp, _sz, _vp, ctypes.POINTER(TuneReport)]
+_lib.dd_plan_autotune.restype = _i32
 _lib.dd_batch_create.argtypes = [ctypes.POINTER(_vp), _i32, ctypes.POINTER(_vp)]
 _lib.dd_batch_create.restype = _i32
 _lib.dd_batch_workspace_bytes.argtypes = [_vp, ctypes.POINTER(_sz)]
@@ -117,9 +139,8 @@ class Plan:
         h = _vp()
         _check(_lib.dd_plan_create(ctypes.byref(d), ctypes.byref(h)), "dd_plan_create")
         self._h = h
-        info = PlanInfo()
-        _check(_lib.dd_plan_query(h, ctypes.byref(info)), "dd_plan_query")
-        self.info = info
+        self._query()
+        info = self.info
         self.n_chan, self.n_samp, self.n_dm = int(n_chan), int(n_samp), int(n_dm)
         self.n_out = int(info.n_out)
         self.max_shift = int(info.max_shift)
@@ -129,6 +150,53 @@ class Plan:
         self.device = None
         if bind:
             self.bind(device)
+
+    def _query(self):
+        info = PlanInfo()
+        _check(_lib.dd_plan_query(self._h, ctypes.byref(info)), "dd_plan_query")
+        self.info = info
+
+    @property
+    def n_shapes(self) -> int:
+        n = _i32()
+        _check(_lib.dd_plan_shape_count(self._h, ctypes.byref(n)), "dd_plan_shape_count")
+        return int(n.value)
+
+    def tiles(self, direction=0) -> dict:
+        """Current tile choice of the forward (0) or adjoint (1) kernel."""
+        t = Tiles()
+        _check(_lib.dd_plan_get_tiles(self._h, int(direction), ctypes.byref(t)), "dd_plan_get_tiles")
+        return t.as_dict()
+
+    def set_tiles(self, direction, shape, order=0, stream=None):
+        """Switch to compiled shape `shape` with workgroup order `order` and re-bind."""
+        _check(_lib.dd_plan_set_tiles(self._h, int(direction), int(shape), int(order)), "dd_plan_set_tiles")
+        self._query()
+        if self.device is not None:
+            self.bind(self.device, stream)
+
+    def autotune(self, src, dst, direction=0, stream=None) -> dict:
+        """Time every feasible tile choice on (src, dst) and keep the fastest (dd_plan_autotune).
+
+        Forward: src = input, dst = output [n_dm][>= n_out].  Adjoint: src = y
+        [n_dm][>= n_out], dst = gradient [n_chan][in_row_elems].  dst is overwritten."""
+        if direction == 0:
+            self._check_input(src)
+            self._check_output(dst)
+            pitch = dst.stride(0)
+        else:
+            self._check_y(src)
+            self._check_grad(dst)
+            pitch = src.stride(0)
+        with torch.cuda.device(self.device):
+            ws = torch.empty(int(self.info.tune_ws_bytes), dtype=torch.uint8, device=self.device)
+            rep = TuneReport()
+            _check(_lib.dd_plan_autotune(self._h, int(direction), src.data_ptr(), dst.data_ptr(), pitch, ws.data_ptr(),
+                                         ws.numel(), _stream_handle(stream), ctypes.byref(rep)), "dd_plan_autotune")
+        self._query()
+        self.bind(self.device, stream)  # a workspace of the winner's size
+        return {"n_tried": int(rep.n_tried), "best": rep.best.as_dict(), "best_ms": rep.best_ms,
+                "default_ms": rep.default_ms, "timed_out_samples": int(rep.timed_out_samples)}
 
     @property
     def shift(self) -> np.ndarray:
@@ -161,27 +229,39 @@ class Plan:
         if x.shape[1] < need:
             raise ValueError("input rows are shorter than n_samp")
 
+    def _check_output(self, out):
+        if (out.dtype != torch.float32 or out.device != self.device or out.dim() != 2 or out.shape[0] != self.n_dm
+                or out.shape[1] < self.n_out or out.stride(1) != 1):
+            raise ValueError("out must be float32 [n_dm][>= n_out] with contiguous rows on %s" % self.device)
+
+    def _check_y(self, y):
+        if (y.dtype != torch.float32 or y.device != self.device or y.dim() != 2 or y.shape[0] != self.n_dm
+                or y.shape[1] < self.n_out or y.stride(1) != 1):
+            raise ValueError("y must be float32 [n_dm][>= n_out] with contiguous rows on %s" % self.device)
+
+    def _check_grad(self, g):
+        if (g.dtype != torch.float32 or g.device != self.device or g.dim() != 2 or g.shape[0] != self.n_chan
+                or g.shape[1] < self.n_samp or g.stride(1) != 1 or g.stride(0) * 4 != self.in_pitch_bytes):
+            raise ValueError("gradient buffer must be float32 [n_chan][in_row_elems] on %s" % self.device)
+
     def forward(self, x, out=None, stream=None):
         """S = dedisperse(x): float32 [n_dm][n_out] (a view of an [n_dm][out_pitch] buffer)."""
         self._check_input(x)
         if out is None:
             out = torch.empty((self.n_dm, self.out_pitch), dtype=torch.float32, device=self.device)
-        if out.dtype != torch.float32 or out.dim() != 2 or out.shape[0] != self.n_dm or out.stride(1) != 1:
-            raise ValueError("out must be float32 [n_dm][>= n_out]")
+        self._check_output(out)
         _check(_lib.dd_execute(self._h, x.data_ptr(), out.data_ptr(), out.stride(0), _stream_handle(stream)),
                "dd_execute")
         return out[:, : self.n_out]
 
     def adjoint(self, y, out=None, stream=None):
         """g = A^T y for float32 plans: float32 [n_chan][n_samp] (view of a pitched buffer)."""
-        if y.dtype != torch.float32 or y.dim() != 2 or y.shape[0] != self.n_dm or y.stride(1) != 1:
-            raise ValueError("y must be float32 [n_dm][>= n_out] with contiguous rows")
-        if y.shape[1] < self.n_out:
-            raise ValueError("y rows shorter than n_out")
+        self._check_y(y)
         if y.stride(0) % 4 or y.data_ptr() % 16:
             y = _pad_rows(y, self.n_out)
         if out is None:
             out = torch.empty((self.n_chan, self.in_row_elems), dtype=torch.float32, device=self.device)
+        self._check_grad(out)
         _check(_lib.dd_execute_adjoint(self._h, y.data_ptr(), y.stride(0), out.data_ptr(), _stream_handle(stream)),
                "dd_execute_adjoint")
         return out[:, : self.n_samp]

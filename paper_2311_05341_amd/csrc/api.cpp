@@ -30,6 +30,44 @@ static int64_t packed_row_bytes(int dtype, int64_t n_samp) {
   return n_samp;
 }
 
+dd_status hip_error(int e, const char *what) { return hip_fail(e, what); }
+
+// Enqueue the upload of the plan's current tables into `ws` and mark the plan
+// bound to it on the current device.
+dd_status upload_tables(dd_plan &p, void *ws, void *stream) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  hipStream_t st = (hipStream_t)stream;
+  uint8_t *base = (uint8_t *)ws;
+  if (p.desc.dtype != DD_F32) {
+    const size_t ob = p.itab.offs.size() * sizeof(uint16_t);
+    p.int_offs_off = 0;
+    p.int_sbase_off = (ob + 255) / 256 * 256;
+    e = hipMemcpyAsync(base, p.itab.offs.data(), ob, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(base + p.int_sbase_off, p.itab.sbase.data(), p.itab.sbase.size() * 4, hipMemcpyHostToDevice,
+                         st);
+    if (e != hipSuccess) return hip_fail(e, "table upload");
+  } else {
+    size_t off = 0;
+    FloatTables *tabs[2] = {&p.ftab_fwd, &p.ftab_adj};
+    for (FloatTables *t : tabs) {
+      t->offs_off = off;
+      if (e == hipSuccess) e = hipMemcpyAsync(base + off, t->offs.data(), t->offs.size() * 2, hipMemcpyHostToDevice, st);
+      off += (t->offs.size() * 2 + 255) / 256 * 256;
+      t->sbase_off = off;
+      if (e == hipSuccess) e = hipMemcpyAsync(base + off, t->sbase.data(), t->sbase.size() * 4, hipMemcpyHostToDevice, st);
+      off += (t->sbase.size() * 4 + 255) / 256 * 256;
+    }
+    if (e != hipSuccess) return hip_fail(e, "table upload");
+  }
+  p.d_tables = ws;
+  p.device = dev;
+  p.bound = true;
+  return DD_OK;
+}
+
 }  // namespace dd
 
 using namespace dd;
@@ -75,6 +113,7 @@ dd_status dd_plan_create(const dd_plan_desc *desc, dd_plan **out) {
   p->desc.in_pitch_bytes = pitch;
   dd_status st = build_shift_table(*p);
   if (st == DD_OK) st = choose_forward_tiles(*p);
+  if (st == DD_OK) apply_tune_cache(*p);
   if (st != DD_OK) {
     delete p;
     return st;
@@ -99,6 +138,8 @@ dd_status dd_plan_query(const dd_plan *p, dd_plan_info *info) {
   info->kernel_dm_per_wave = p->fwd.dm_per_wave;
   info->kernel_waves = p->fwd.waves;
   info->kernel_chan_block = p->fwd.chan_block;
+  info->kernel_order = p->fwd.order;
+  info->tune_ws_bytes = tune_table_bytes(*p);
   return DD_OK;
 }
 
@@ -106,37 +147,7 @@ dd_status dd_plan_bind(dd_plan *p, void *ws, size_t bytes, void *stream) {
   if (!p || !ws) return fail(DD_ERR_ARG, "null argument");
   if (!aligned16(ws)) return fail(DD_ERR_ALIGN, "workspace must be 16-byte aligned");
   if (bytes < table_bytes(*p)) return fail(DD_ERR_ARG, "workspace smaller than dev_table_bytes");
-  int dev = -1;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  hipStream_t st = (hipStream_t)stream;
-  uint8_t *base = (uint8_t *)ws;
-  if (p->desc.dtype != DD_F32) {
-    const size_t ob = p->itab.offs.size() * sizeof(uint16_t);
-    p->int_offs_off = 0;
-    p->int_sbase_off = (ob + 255) / 256 * 256;
-    e = hipMemcpyAsync(base, p->itab.offs.data(), ob, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(base + p->int_sbase_off, p->itab.sbase.data(), p->itab.sbase.size() * 4,
-                         hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "table upload");
-  } else {
-    size_t off = 0;
-    FloatTables *tabs[2] = {&p->ftab_fwd, &p->ftab_adj};
-    for (FloatTables *t : tabs) {
-      t->offs_off = off;
-      if (e == hipSuccess) e = hipMemcpyAsync(base + off, t->offs.data(), t->offs.size() * 2, hipMemcpyHostToDevice, st);
-      off += (t->offs.size() * 2 + 255) / 256 * 256;
-      t->sbase_off = off;
-      if (e == hipSuccess) e = hipMemcpyAsync(base + off, t->sbase.data(), t->sbase.size() * 4, hipMemcpyHostToDevice, st);
-      off += (t->sbase.size() * 4 + 255) / 256 * 256;
-    }
-    if (e != hipSuccess) return hip_fail(e, "table upload");
-  }
-  p->d_tables = ws;
-  p->device = dev;
-  p->bound = true;
-  return DD_OK;
+  return upload_tables(*p, ws, stream);
 }
 
 static dd_status check_exec(const dd_plan *p) {

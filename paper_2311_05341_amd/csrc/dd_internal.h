@@ -18,12 +18,22 @@ dd_status fail(dd_status st, const std::string &msg);
 // of `dm_per_wave` rows.  Channels are staged `chan_block` at a time into LDS
 // rows of `row_bytes` bytes (unpacked samples).
 struct TileCfg {
+  int shape = 0;         // index into kIntShapes / kF32Shapes
+  int order = 0;         // workgroup order, a TileOrder
   int ns = 32;           // samples per lane (16 or 32)
   int dm_per_wave = 4;   // DM rows per wave
   int waves = 4;         // waves per workgroup
   int chan_block = 16;   // channels per LDS stage
   int row_bytes = 0;     // LDS bytes per staged channel row
   int lds_bytes = 0;     // total dynamic LDS
+};
+
+// Order of the workgroups of a 1-D grid over (time tile, output block) pairs.
+// Workgroup w runs on XCD w % 8 (round-robin dispatch).
+enum TileOrder {
+  kOrderTimeFirst = 0,  // consecutive workgroups take consecutive time tiles of one output block
+  kOrderXcdTiles = 1,   // each XCD takes whole time tiles, every output block of a tile in turn
+  kNumOrders = 2
 };
 
 // Device tables of the integer forward kernel for one tile shape: per DM
@@ -42,6 +52,7 @@ struct IntTables {
 // k rounded down to 4 floats; per (block, wave, row, output of the wave): the
 // LDS byte offset 4 * (sh - sbase) of the window in the staged row.
 struct FloatTables {
+  int shape = 0, order = 0;  // index into kF32Shapes, TileOrder
   int ns = 0, per_wave = 0, waves = 0, row_block = 0;
   int row_bytes = 0, lds_bytes = 0;
   std::vector<uint16_t> offs;  // [n_oblk][waves][n_rows rounded up to row_block][max(per_wave, 2)]
@@ -77,8 +88,19 @@ dd_status build_shift_table(dd_plan &p);
 int32_t max_dm_block_span(const dd_plan &p, int dm_block);
 int row_bytes_for(int dtype, int ns, int span);
 dd_status choose_forward_tiles(dd_plan &p);
-dd_status choose_float_tiles(dd_plan &p);
+// Rebuild the tables of one direction (0 forward, 1 adjoint) for compiled
+// shape `shape` and TileOrder `order`.  DD_ERR_RANGE if the shape cannot hold
+// the plan's delay spread; the plan is unchanged then.
+dd_status set_tiles(dd_plan &p, int direction, int shape, int order);
+int num_shapes(const dd_plan &p);
 size_t table_bytes(const dd_plan &p);
+// Enqueue the upload of the current tables into `ws` and mark the plan bound (api.cpp).
+dd_status upload_tables(dd_plan &p, void *ws, void *stream);
+dd_status hip_error(int e, const char *what);
+// Apply tile choices recorded in the tuning cache file, if any (tune.cpp).
+void apply_tune_cache(dd_plan &p);
+// Upper bound of table_bytes over every shape set_tiles can choose.
+size_t tune_table_bytes(const dd_plan &p);
 
 // One beam of a batch, as the persistent kernel sees it.
 struct BeamDesc {
@@ -94,9 +116,13 @@ struct BeamDesc {
 dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves, int chan_block, int lds_limit,
                            IntTables *t);
 
-// Kernel launchers (kernels.hip).  Return hipError_t as int.
-int launch_forward_int(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream);
-int launch_forward_f32(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream);
+// Kernel launchers (fwd_int.hip, kernels_f32.hip).  Return hipError_t as int.
+// `out_limit` > 0 computes only the first out_limit output samples of every
+// output row (shorter launches for tile tuning); <= 0 computes all.
+int launch_forward_int(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream,
+                       int64_t out_limit = 0);
+int launch_forward_f32(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream,
+                       int64_t out_limit = 0);
 // Float tile shapes compiled into the library: (ns, per_wave, waves, row_block).
 extern const int kF32Shapes[][4];
 extern const int kNumF32Shapes;
@@ -104,7 +130,8 @@ extern const int kNumF32Shapes;
 // chan_block), in the order plans try them.
 extern const int kIntShapes[][4];
 extern const int kNumIntShapes;
-int launch_adjoint(const dd_plan &p, const float *d_y, int64_t y_pitch, float *d_grad, void *stream);
+int launch_adjoint(const dd_plan &p, const float *d_y, int64_t y_pitch, float *d_grad, void *stream,
+                   int64_t out_limit = 0);
 
 // Persistent batched forward: kernel entry, its launch geometry and the
 // counter-reset kernel, for recording into a graph.

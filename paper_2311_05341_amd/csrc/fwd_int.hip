@@ -345,11 +345,18 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
 }
 
 // Workgroup -> tile map.  Workgroups are handed to the XCDs (each with its own
-// L2) round-robin by linear id, so workgroup w runs on XCD w % n_xcd.  Each
-// XCD is given whole time tiles (all DM blocks of tile x, x + n_xcd, ...):
-// the workgroups resident on an XCD then stage the same input rows, which its
-// L2 serves once.  Tiles left over after the last full round go linearly.
+// L2) round-robin by linear id, so workgroup w runs on XCD w % n_xcd.
+// n_xcd == 0: time tiles fastest (neighbouring tiles, whose staged rows
+// overlap by the delay spread, run at once on different XCDs).  Otherwise each
+// XCD is given whole time tiles (all DM blocks of tile x, x + n_xcd, ...), so
+// the workgroups resident on one XCD stage nearby input rows through its L2.
+// Tiles left over after the last full round go in tile order.
 __device__ __forceinline__ void tile_of(int w, int n_dblk, int n_tiles, int n_xcd, int &dblk, int &tblk) {
+  if (n_xcd == 0) {
+    tblk = w % n_tiles;
+    dblk = w / n_tiles;
+    return;
+  }
   const int full = n_tiles / n_xcd * n_xcd;
   if (w < n_dblk * full) {
     const int x = w % n_xcd, k = w / n_xcd;
@@ -424,7 +431,8 @@ __global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc
   X(16, 1, 16, 1) X(16, 1, 4, 1) X(16, 1, 1, 1)
 
 template <int NS, int R, int NW, int CB>
-int launch_int_shape(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, hipStream_t st) {
+int launch_int_shape(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, hipStream_t st,
+                     int64_t out_limit) {
   const TileCfg &t = p.fwd;
   IntArgs a;
   a.x = (const uint8_t *)d_in;
@@ -433,16 +441,16 @@ int launch_int_shape(const dd_plan &p, const void *d_in, float *d_out, int64_t o
   a.out = d_out;
   a.pitch = p.in_pitch_bytes;
   a.n_samp = p.desc.n_samp;
-  a.n_out = p.n_out;
+  a.n_out = out_limit > 0 && out_limit < p.n_out ? out_limit : p.n_out;
   a.out_pitch = out_pitch;
   a.n_chan = p.desc.n_chan;
   a.n_dm = p.desc.n_dm;
   a.row_bytes = t.row_bytes;
-  const int64_t tiles_t = (p.n_out + 64 * NS - 1) / (64 * NS);
+  const int64_t tiles_t = (a.n_out + 64 * NS - 1) / (64 * NS);
   const int64_t n_dblk = (p.desc.n_dm + NW * R - 1) / (NW * R);
   if (tiles_t * n_dblk >= ((int64_t)1 << 31)) return (int)hipErrorInvalidConfiguration;
   dim3 grid((unsigned)(tiles_t * n_dblk));
-  const int n_xcd = kXcdCount;
+  const int n_xcd = t.order == kOrderXcdTiles ? kXcdCount : 0;
   const void *fn = p.desc.dtype == DD_U4 ? (const void *)fwd_int_kernel<NS, R, NW, CB, true>
                                          : (const void *)fwd_int_kernel<NS, R, NW, CB, false>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, t.lds_bytes);
@@ -463,11 +471,12 @@ const int kIntShapes[][4] = {DD_INT_SHAPES(DD_ROW)};
 #undef DD_ROW
 const int kNumIntShapes = (int)(sizeof(kIntShapes) / sizeof(kIntShapes[0]));
 
-int launch_forward_int(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream) {
+int launch_forward_int(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream,
+                       int64_t out_limit) {
   const TileCfg &t = p.fwd;
 #define DD_TRY(NS, R, NW, CB)                                                       \
   if (t.ns == NS && t.dm_per_wave == R && t.waves == NW && t.chan_block == CB)     \
-    return launch_int_shape<NS, R, NW, CB>(p, d_in, d_out, out_pitch, (hipStream_t)stream);
+    return launch_int_shape<NS, R, NW, CB>(p, d_in, d_out, out_pitch, (hipStream_t)stream, out_limit);
   DD_INT_SHAPES(DD_TRY)
 #undef DD_TRY
   return (int)hipErrorInvalidValue;

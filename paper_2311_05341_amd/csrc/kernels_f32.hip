@@ -73,7 +73,15 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
+// Workgroup w -> (output block, time tile).  n_xcd == 0: time tiles fastest.
+// Otherwise the XCD w % n_xcd takes whole time tiles (x, x + n_xcd, ...),
+// all output blocks of one tile in turn; leftover tiles go in tile order.
 __device__ __forceinline__ void tile_of(int w, int n_oblk, int n_tiles, int n_xcd, int &oblk, int &tblk) {
+  if (n_xcd == 0) {
+    tblk = w % n_tiles;
+    oblk = w / n_tiles;
+    return;
+  }
   const int full = n_tiles / n_xcd * n_xcd;
   if (w < n_oblk * full) {
     const int x = w % n_xcd, k = w / n_xcd;
@@ -212,7 +220,7 @@ __global__ __launch_bounds__(NW * 64) void f32_kernel(FArgs a, int n_oblk, int n
   X(16, 2, 16, 8) X(16, 2, 16, 4) X(16, 1, 16, 4) X(16, 1, 16, 2) X(16, 1, 16, 1) X(16, 1, 4, 1) X(16, 1, 1, 1)
 
 template <int NS, int R, int NW, int CB>
-int launch_f32_shape(const FArgs &a, int lds_bytes, hipStream_t st) {
+int launch_f32_shape(const FArgs &a, int lds_bytes, int n_xcd, hipStream_t st) {
   const int64_t tiles = (a.out_len + 64 * NS - 1) / (64 * NS);
   const int64_t n_oblk = (a.n_outputs + NW * R - 1) / (NW * R);
   if (tiles * n_oblk >= ((int64_t)1 << 31)) return (int)hipErrorInvalidConfiguration;
@@ -220,13 +228,16 @@ int launch_f32_shape(const FArgs &a, int lds_bytes, hipStream_t st) {
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   if (e != hipSuccess) return (int)e;
   hipLaunchKernelGGL((f32_kernel<NS, R, NW, CB>), dim3((unsigned)(tiles * n_oblk)), dim3(NW * 64), lds_bytes, st, a,
-                     (int)n_oblk, (int)tiles, kXcdCount);
+                     (int)n_oblk, (int)tiles, n_xcd);
   return (int)hipGetLastError();
 }
 
-int launch_f32(const FloatTables &t, const FArgs &a, hipStream_t st) {
-#define DD_TRY(NS, R, NW, CB) \
-  if (t.ns == NS && t.per_wave == R && t.waves == NW && t.row_block == CB) return launch_f32_shape<NS, R, NW, CB>(a, t.lds_bytes, st);
+int launch_f32(const FloatTables &t, FArgs a, int64_t out_limit, hipStream_t st) {
+  if (out_limit > 0 && out_limit < a.out_len) a.out_len = (int32_t)out_limit;
+  const int n_xcd = t.order == kOrderXcdTiles ? kXcdCount : 0;
+#define DD_TRY(NS, R, NW, CB)                                               \
+  if (t.ns == NS && t.per_wave == R && t.waves == NW && t.row_block == CB) \
+    return launch_f32_shape<NS, R, NW, CB>(a, t.lds_bytes, n_xcd, st);
   DD_F32_SHAPES(DD_TRY)
 #undef DD_TRY
   return (int)hipErrorInvalidValue;
@@ -239,7 +250,8 @@ const int kF32Shapes[][4] = {DD_F32_SHAPES(DD_ROW)};
 #undef DD_ROW
 const int kNumF32Shapes = (int)(sizeof(kF32Shapes) / sizeof(kF32Shapes[0]));
 
-int launch_forward_f32(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream) {
+int launch_forward_f32(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream,
+                       int64_t out_limit) {
   const FloatTables &t = p.ftab_fwd;
   FArgs a;
   a.x = (const float *)d_in;
@@ -253,10 +265,11 @@ int launch_forward_f32(const dd_plan &p, const void *d_in, float *d_out, int64_t
   a.n_outputs = p.desc.n_dm;
   a.out_len = (int32_t)p.n_out;
   a.row_bytes = t.row_bytes;
-  return launch_f32(t, a, (hipStream_t)stream);
+  return launch_f32(t, a, out_limit, (hipStream_t)stream);
 }
 
-int launch_adjoint(const dd_plan &p, const float *d_y, int64_t y_pitch, float *d_grad, void *stream) {
+int launch_adjoint(const dd_plan &p, const float *d_y, int64_t y_pitch, float *d_grad, void *stream,
+                   int64_t out_limit) {
   const FloatTables &t = p.ftab_adj;
   FArgs a;
   a.x = d_y;
@@ -270,7 +283,7 @@ int launch_adjoint(const dd_plan &p, const float *d_y, int64_t y_pitch, float *d
   a.n_outputs = p.desc.n_chan;
   a.out_len = (int32_t)p.desc.n_samp;
   a.row_bytes = t.row_bytes;
-  return launch_f32(t, a, (hipStream_t)stream);
+  return launch_f32(t, a, out_limit, (hipStream_t)stream);
 }
 
 }  // namespace dd

@@ -239,59 +239,66 @@ static dd_status build_float_tables(const dd_plan &p, bool adjoint, const int *s
   return DD_OK;
 }
 
-dd_status choose_float_tiles(dd_plan &p) {
-  for (int dir = 0; dir < 2; ++dir) {
-    FloatTables &dst = dir ? p.ftab_adj : p.ftab_fwd;
-    dd_status last = DD_ERR_RANGE;
-    for (int i = 0; i < kNumF32Shapes; ++i) {
-      FloatTables t;
-      last = build_float_tables(p, dir == 1, kF32Shapes[i], kLdsLimit, &t);
-      if (last == DD_OK) {
-        dst = std::move(t);
-        break;
-      }
-      if (last == DD_ERR_NOMEM) return last;
+int num_shapes(const dd_plan &p) { return p.desc.dtype == DD_F32 ? kNumF32Shapes : kNumIntShapes; }
+
+dd_status set_tiles(dd_plan &p, int direction, int shape, int order) {
+  if (direction != 0 && !(direction == 1 && p.desc.dtype == DD_F32))
+    return fail(DD_ERR_ARG, "direction must be 0 (forward) or 1 (adjoint, float plans)");
+  if (shape < 0 || shape >= num_shapes(p)) return fail(DD_ERR_ARG, "no such tile shape");
+  if (order < 0 || order >= kNumOrders) return fail(DD_ERR_ARG, "no such workgroup order");
+  TileCfg t;
+  t.shape = shape;
+  t.order = order;
+  if (p.desc.dtype == DD_F32) {
+    FloatTables ft;
+    const dd_status st = build_float_tables(p, direction == 1, kF32Shapes[shape], kLdsLimit, &ft);
+    if (st != DD_OK) return st;
+    ft.shape = shape;
+    ft.order = order;
+    if (direction == 1) {
+      p.ftab_adj = std::move(ft);
+      return DD_OK;
     }
-    if (last != DD_OK) return fail(DD_ERR_RANGE, "delay spread exceeds every compiled float staging shape");
+    t.ns = ft.ns;
+    t.dm_per_wave = ft.per_wave;
+    t.waves = ft.waves;
+    t.chan_block = ft.row_block;
+    t.row_bytes = ft.row_bytes;
+    t.lds_bytes = ft.lds_bytes;
+    p.ftab_fwd = std::move(ft);
+    p.fwd = t;
+    return DD_OK;
   }
-  TileCfg &f = p.fwd;
-  f.ns = p.ftab_fwd.ns;
-  f.dm_per_wave = p.ftab_fwd.per_wave;
-  f.waves = p.ftab_fwd.waves;
-  f.chan_block = p.ftab_fwd.row_block;
-  f.row_bytes = p.ftab_fwd.row_bytes;
-  f.lds_bytes = p.ftab_fwd.lds_bytes;
+  const int *k = kIntShapes[shape];
+  IntTables tab;
+  const dd_status st = build_int_tables(p, k[0], k[1], k[2], k[3], kLdsLimit, &tab);
+  if (st != DD_OK) return st;
+  t.ns = k[0];
+  t.dm_per_wave = k[1];
+  t.waves = k[2];
+  t.chan_block = k[3];
+  t.row_bytes = tab.row_bytes;
+  t.lds_bytes = tab.lds_bytes;
+  p.fwd = t;
+  p.span_fwd = max_dm_block_span(p, t.waves * t.dm_per_wave);
+  p.itab = std::move(tab);
   return DD_OK;
 }
 
+// Default tiles: the first compiled shape (they are listed fastest first) that
+// holds the plan's delay spread, with time tiles fastest in the grid.
 dd_status choose_forward_tiles(dd_plan &p) {
-  TileCfg t;
-  if (p.desc.dtype == DD_F32) return choose_float_tiles(p);
-  dd_status last = DD_ERR_RANGE;
-  int first = 0;
-  if (const char *env = getenv("DD_INT_SHAPE")) {  // force a compiled shape by index (tuning experiments)
-    first = atoi(env);
-    if (first < 0 || first >= kNumIntShapes) first = 0;
-  }
-  for (int i = first; i < kNumIntShapes; ++i) {
-    IntTables tab;
-    const int *k = kIntShapes[i];
-    last = build_int_tables(p, k[0], k[1], k[2], k[3], kLdsLimit, &tab);
-    if (last == DD_OK) {
-      t.ns = k[0];
-      t.dm_per_wave = k[1];
-      t.waves = k[2];
-      t.chan_block = k[3];
-      t.row_bytes = tab.row_bytes;
-      t.lds_bytes = tab.lds_bytes;
-      p.fwd = t;
-      p.span_fwd = max_dm_block_span(p, t.waves * t.dm_per_wave);
-      p.itab = std::move(tab);
-      return DD_OK;
+  const int dirs = p.desc.dtype == DD_F32 ? 2 : 1;
+  for (int dir = 0; dir < dirs; ++dir) {
+    dd_status last = DD_ERR_RANGE;
+    for (int i = 0; i < num_shapes(p); ++i) {
+      last = set_tiles(p, dir, i, kOrderTimeFirst);
+      if (last == DD_OK || last == DD_ERR_NOMEM) break;
     }
     if (last == DD_ERR_NOMEM) return last;
+    if (last != DD_OK) return fail(DD_ERR_RANGE, "delay spread exceeds every compiled staging shape");
   }
-  return fail(DD_ERR_RANGE, "delay spread of a DM block exceeds every compiled staging shape");
+  return DD_OK;
 }
 
 static size_t up256(size_t v) { return (v + 255) / 256 * 256; }
@@ -303,6 +310,31 @@ size_t table_bytes(const dd_plan &p) {
     return up256(p.itab.offs.size() * sizeof(uint16_t)) + up256(p.itab.sbase.size() * sizeof(int32_t));
   return up256(p.ftab_fwd.offs.size() * 2) + up256(p.ftab_fwd.sbase.size() * 4) + up256(p.ftab_adj.offs.size() * 2) +
          up256(p.ftab_adj.sbase.size() * 4);
+}
+
+// Table sizes follow the layouts of build_int_tables / build_float_tables
+// (offs: per output block, wave and padded row, max(per_wave, 2) uint16
+// entries; sbase: per output block and row, one int32).
+static size_t shape_table_bytes(int64_t n_out, int64_t n_rows, const int *k) {
+  const int64_t per_wave = k[1], waves = k[2], rb = k[3];
+  const int64_t n_oblk = (n_out + waves * per_wave - 1) / (waves * per_wave);
+  const int64_t rows_pad = (n_rows + rb - 1) / rb * rb;
+  return up256((size_t)(n_oblk * waves * rows_pad * std::max<int64_t>(per_wave, 2) * 2)) +
+         up256((size_t)(n_oblk * n_rows * 4));
+}
+
+size_t tune_table_bytes(const dd_plan &p) {
+  const int64_t nc = p.desc.n_chan, nd = p.desc.n_dm;
+  size_t fwd = 0, adj = 0;
+  if (p.desc.dtype != DD_F32) {
+    for (int i = 0; i < kNumIntShapes; ++i) fwd = std::max(fwd, shape_table_bytes(nd, nc, kIntShapes[i]));
+    return fwd;
+  }
+  for (int i = 0; i < kNumF32Shapes; ++i) {
+    fwd = std::max(fwd, shape_table_bytes(nd, nc, kF32Shapes[i]));
+    adj = std::max(adj, shape_table_bytes(nc, nd, kF32Shapes[i]));
+  }
+  return fwd + adj;
 }
 
 }  // namespace dd

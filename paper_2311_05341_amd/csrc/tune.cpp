@@ -1,0 +1,247 @@
+// Tile-shape selection: explicit choice, timing-based autotuning on the
+// caller's buffers, and a small text cache of tuned choices.
+//
+// Every compiled shape computes bitwise the same result (integer sums are
+// exact, float sums use one fixed order), so the choice only affects speed.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+static const char kCacheTag[] = "dd-tune-v1";
+static std::mutex g_cache_mutex;
+
+static const int *shape_params(const dd_plan &p, int shape) {
+  return p.desc.dtype == DD_F32 ? kF32Shapes[shape] : kIntShapes[shape];
+}
+
+static void current_tiles(const dd_plan &p, int dir, int *shape, int *order) {
+  if (p.desc.dtype == DD_F32 && dir == 1) {
+    *shape = p.ftab_adj.shape;
+    *order = p.ftab_adj.order;
+  } else {
+    *shape = p.fwd.shape;
+    *order = p.fwd.order;
+  }
+}
+
+// FNV-1a over a byte range (identifies an explicit frequency table).
+static uint64_t fnv1a(const void *data, size_t n, uint64_t h = 1469598103934665603ull) {
+  const uint8_t *b = (const uint8_t *)data;
+  for (size_t i = 0; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+  return h;
+}
+
+// Cache key: every field of the plan description that changes the tables or
+// the kernels' work, doubles in exact hexadecimal form; no spaces.
+static std::string cache_key(const dd_plan &p, int dir) {
+  const dd_plan_desc &d = p.desc;
+  const uint64_t fh = p.freqs.empty() ? 0 : fnv1a(p.freqs.data(), p.freqs.size() * sizeof(double));
+  char buf[512];
+  snprintf(buf, sizeof buf, "dtype=%d,nchan=%d,nsamp=%lld,fhigh=%a,bw=%a,freqs=%016llx,tsamp=%a,dm0=%a,dmstep=%a,ndm=%d,"
+           "pitch=%lld,dir=%d",
+           (int)d.dtype, (int)d.n_chan, (long long)d.n_samp, d.f_high_mhz, d.chan_bw_mhz, (unsigned long long)fh,
+           d.t_samp_s, d.dm_start, d.dm_step, (int)d.n_dm, (long long)p.in_pitch_bytes, dir);
+  return buf;
+}
+
+// Cache line: "<tag> <key> <shape> <order> <ns> <per_wave> <waves> <row_block> <ms>".
+// The shape's parameters are stored too, so a line written by a library with
+// a different list of compiled shapes is ignored rather than misapplied.
+void apply_tune_cache(dd_plan &p) {
+  const char *path = getenv("DD_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::lock_guard<std::mutex> lock(g_cache_mutex);
+  FILE *f = fopen(path, "r");
+  if (!f) return;
+  const int dirs = p.desc.dtype == DD_F32 ? 2 : 1;
+  int want_shape[2] = {-1, -1}, want_order[2] = {0, 0};
+  std::string keys[2];
+  for (int dir = 0; dir < dirs; ++dir) keys[dir] = cache_key(p, dir);
+  char line[1024];
+  while (fgets(line, sizeof line, f)) {
+    char tag[32], key[600];
+    int shape, order, k[4];
+    double ms;
+    if (sscanf(line, "%31s %599s %d %d %d %d %d %d %lf", tag, key, &shape, &order, &k[0], &k[1], &k[2], &k[3], &ms) != 9)
+      continue;
+    if (strcmp(tag, kCacheTag) != 0) continue;
+    for (int dir = 0; dir < dirs; ++dir) {
+      if (keys[dir] != key || shape < 0 || shape >= num_shapes(p)) continue;
+      const int *s = shape_params(p, shape);
+      if (s[0] != k[0] || s[1] != k[1] || s[2] != k[2] || s[3] != k[3]) continue;
+      want_shape[dir] = shape;  // the last matching line wins
+      want_order[dir] = order;
+    }
+  }
+  fclose(f);
+  for (int dir = 0; dir < dirs; ++dir)
+    if (want_shape[dir] >= 0) set_tiles(p, dir, want_shape[dir], want_order[dir]);  // keeps the default on failure
+}
+
+static void append_tune_cache(const dd_plan &p, int dir, int shape, int order, double ms) {
+  const char *path = getenv("DD_TUNE_CACHE");
+  if (!path || !*path) return;
+  std::lock_guard<std::mutex> lock(g_cache_mutex);
+  FILE *f = fopen(path, "a");
+  if (!f) return;
+  const int *s = shape_params(p, shape);
+  fprintf(f, "%s %s %d %d %d %d %d %d %.6f\n", kCacheTag, cache_key(p, dir).c_str(), shape, order, s[0], s[1], s[2],
+          s[3], ms);
+  fclose(f);
+}
+
+}  // namespace dd
+
+using namespace dd;
+
+extern "C" {
+
+dd_status dd_plan_shape_count(const dd_plan *p, int32_t *n) {
+  if (!p || !n) return fail(DD_ERR_ARG, "null argument");
+  *n = num_shapes(*p);
+  return DD_OK;
+}
+
+dd_status dd_plan_get_tiles(const dd_plan *p, int32_t dir, dd_tiles *t) {
+  if (!p || !t) return fail(DD_ERR_ARG, "null argument");
+  if (dir == 1 && p->desc.dtype != DD_F32) return fail(DD_ERR_DTYPE, "the adjoint is defined for float32 plans only");
+  if (dir != 0 && dir != 1) return fail(DD_ERR_ARG, "direction must be 0 or 1");
+  int shape, order;
+  current_tiles(*p, dir, &shape, &order);
+  const int *s = shape_params(*p, shape);
+  t->shape = shape;
+  t->order = order;
+  t->ns = s[0];
+  t->per_wave = s[1];
+  t->waves = s[2];
+  t->row_block = s[3];
+  return DD_OK;
+}
+
+dd_status dd_plan_set_tiles(dd_plan *p, int32_t dir, int32_t shape, int32_t order) {
+  if (!p) return fail(DD_ERR_ARG, "null plan");
+  if (dir == 1 && p->desc.dtype != DD_F32) return fail(DD_ERR_DTYPE, "the adjoint is defined for float32 plans only");
+  const dd_status st = set_tiles(*p, dir, shape, order);
+  if (st == DD_OK) p->bound = false;
+  return st;
+}
+
+dd_status dd_plan_autotune(dd_plan *p, int32_t dir, const void *src, float *dst, int64_t pitch, void *ws,
+                           size_t ws_bytes, void *stream, dd_tune_report *rep) {
+  if (!p || !src || !dst || !ws) return fail(DD_ERR_ARG, "null argument");
+  if (dir == 1 && p->desc.dtype != DD_F32) return fail(DD_ERR_DTYPE, "the adjoint is defined for float32 plans only");
+  if (dir != 0 && dir != 1) return fail(DD_ERR_ARG, "direction must be 0 or 1");
+  if (((uintptr_t)src | (uintptr_t)dst | (uintptr_t)ws) & 15u) return fail(DD_ERR_ALIGN, "buffers must be 16-byte aligned");
+  if (pitch < p->n_out) return fail(DD_ERR_ARG, "pitch < n_out");
+  if (pitch % 4) return fail(DD_ERR_ALIGN, "pitch must be a multiple of 4 elements");
+  if (ws_bytes < tune_table_bytes(*p)) return fail(DD_ERR_ARG, "workspace smaller than tune_ws_bytes");
+  int dev = -1;
+  if (p->bound && hipGetDevice(&dev) == hipSuccess && dev != p->device) p->bound = false;
+
+  int orig_shape, orig_order;
+  current_tiles(*p, dir, &orig_shape, &orig_order);
+  p->bound = false;
+  const int64_t out_len = dir == 0 ? p->n_out : p->desc.n_samp;
+  // About 1e12 adds per timed launch, in whole groups of 8 tiles of 1024 samples.
+  const double adds_per_sample = (double)p->desc.n_dm * (double)p->desc.n_chan;
+  int64_t lim = (int64_t)ceil(1e12 / adds_per_sample);
+  lim = std::max<int64_t>(16384, (lim + 8191) / 8192 * 8192);
+  if (lim >= out_len) lim = 0;  // the whole span
+
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_error(he, "hipEventCreate");
+  }
+  auto run = [&]() -> int {
+    if (dir == 1) return launch_adjoint(*p, (const float *)src, pitch, dst, stream, lim);
+    if (p->desc.dtype == DD_F32) return launch_forward_f32(*p, src, dst, pitch, stream, lim);
+    return launch_forward_int(*p, src, dst, pitch, stream, lim);
+  };
+  // Upload the current tables, warm up, then time two launches.
+  auto time_current = [&](double *ms) -> dd_status {
+    dd_status s = upload_tables(*p, ws, stream);
+    if (s != DD_OK) return s;
+    int e = run();
+    if (!e) e = (int)hipEventRecord(e0, st);
+    for (int i = 0; i < 2 && !e; ++i) e = run();
+    if (!e) e = (int)hipEventRecord(e1, st);
+    if (!e) e = (int)hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (!e) e = (int)hipEventElapsedTime(&t, e0, e1);
+    if (e) return hip_error(e, "tuning launch");
+    *ms = 0.5 * (double)t;
+    return DD_OK;
+  };
+
+  dd_status status = DD_OK;
+  double default_ms = 0.0, best_ms = 0.0;
+  int best_shape = orig_shape, best_order = orig_order, tried = 0;
+  status = time_current(&default_ms);
+  if (status == DD_OK) {
+    best_ms = default_ms;
+    tried = 1;
+    for (int s = 0; s < num_shapes(*p) && status == DD_OK; ++s)
+      for (int o = 0; o < kNumOrders && status == DD_OK; ++o) {
+        if (s == orig_shape && o == orig_order) continue;
+        const dd_status ts = set_tiles(*p, dir, s, o);
+        if (ts == DD_ERR_RANGE) continue;  // this shape cannot stage the plan's spread
+        if (ts != DD_OK) {
+          status = ts;
+          break;
+        }
+        double ms = 0.0;
+        status = time_current(&ms);
+        if (status != DD_OK) break;
+        ++tried;
+        if (ms < best_ms) {
+          best_ms = ms;
+          best_shape = s;
+          best_order = o;
+        }
+      }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status != DD_OK) {
+    const std::string msg = dd_last_error();
+    (void)hipStreamSynchronize(st);  // no upload may still read host tables that set_tiles replaces
+    set_tiles(*p, dir, orig_shape, orig_order);
+    p->bound = false;
+    return fail(status, msg);
+  }
+  status = set_tiles(*p, dir, best_shape, best_order);
+  if (status == DD_OK) status = upload_tables(*p, ws, stream);
+  if (status == DD_OK) {
+    const hipError_t se = hipStreamSynchronize(st);
+    if (se != hipSuccess) status = hip_error(se, "hipStreamSynchronize");
+  }
+  if (status != DD_OK) {
+    p->bound = false;
+    return status;
+  }
+  append_tune_cache(*p, dir, best_shape, best_order, best_ms);
+  if (rep) {
+    memset(rep, 0, sizeof(*rep));
+    rep->n_tried = tried;
+    dd_plan_get_tiles(p, dir, &rep->best);
+    rep->best_ms = best_ms;
+    rep->default_ms = default_ms;
+    rep->timed_out_samples = lim ? lim : out_len;
+  }
+  return DD_OK;
+}
+
+}  // extern "C"

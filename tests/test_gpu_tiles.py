@@ -1,0 +1,133 @@
+"""GPU checks that the tile choice changes speed only.
+
+For every compiled shape that holds a plan's delay spread, in both workgroup
+orders, the forward (and for float plans the adjoint) must give bitwise the
+same result as the oracle-checked default.  The autotuner must leave a
+feasible choice with the same results, and its cache line must reproduce that
+choice for an identical plan.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from helpers import host_input, oracle_table, plan_for
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import paper_2311_05341_amd as dd
+    assert torch.cuda.is_available()
+    return dd
+
+
+def _case(dtype):
+    # several time tiles with a ragged tail, DM blocks with a tail, channels
+    # not a multiple of any staging block
+    return dict(dtype=dtype, n_chan=203, n_samp=30002, f_high=1400.0, chan_bw=0.9, t_samp=64e-6,
+                dm_start=3.0, dm_step=0.75, n_dm=77, seed=41)
+
+
+def _choices(dd, plan, direction):
+    out = []
+    for s in range(plan.n_shapes):
+        for o in (0, 1):
+            try:
+                plan.set_tiles(direction, s, o)
+            except dd.DDError as e:
+                assert e.name == "DD_ERR_RANGE"
+                continue
+            out.append((s, o))
+    return out
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u4"])
+def test_integer_tiles_bit_exact(dd, dtype):
+    cfg = _case(dtype)
+    s = oracle_table(cfg)
+    x, _ = host_input(cfg, s)
+    want = oracle.forward(x, dtype, cfg["n_samp"], s)
+    plan = plan_for(dd, cfg)
+    xd = torch.from_numpy(x).cuda()
+    choices = _choices(dd, plan, 0)
+    assert len(choices) >= 4
+    for s_, o in choices:
+        plan.set_tiles(0, s_, o)
+        print("shape", s_, "order", o, plan.tiles(0), flush=True)
+        got = plan.forward(xd)
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), want), (s_, o)
+
+
+def test_float_tiles_bitwise_invariant(dd):
+    cfg = _case("f32")
+    s = oracle_table(cfg)
+    x, _ = host_input(cfg, s)
+    plan = plan_for(dd, cfg)
+    xd = torch.from_numpy(x).cuda()
+    n_out = plan.n_out
+    y = synth.normal_f32(cfg["n_dm"], n_out, 77)
+    yd = torch.from_numpy(np.ascontiguousarray(np.pad(y, ((0, 0), (0, plan.out_pitch - n_out))))).cuda()
+    want_f, abs_f = oracle.forward_f32(x, cfg["n_samp"], s)
+    want_a = oracle.adjoint(y, cfg["n_chan"], cfg["n_samp"], s)
+    ref = {}
+    for direction in (0, 1):
+        for s_, o in _choices(dd, plan, direction):
+            plan.set_tiles(direction, s_, o)
+            print("direction", direction, "shape", s_, "order", o, flush=True)
+            got = (plan.forward(xd) if direction == 0 else plan.adjoint(yd)).cpu().numpy()
+            if direction not in ref:
+                ref[direction] = got
+                if direction == 0:
+                    assert np.all(np.abs(got - want_f) <= 1e-5 * abs_f)
+                else:
+                    abs_a = oracle.adjoint(np.abs(y), cfg["n_chan"], cfg["n_samp"], s)
+                    assert np.all(np.abs(got - want_a) <= 1e-5 * abs_a)
+            assert np.array_equal(got, ref[direction]), (direction, s_, o)
+
+
+def test_autotune_forward_and_cache(dd, tmp_path, monkeypatch):
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("DD_TUNE_CACHE", str(cache))
+    cfg = synth.CONFIGS["small"]
+    s = oracle_table(cfg)
+    x, _ = host_input(cfg, s)
+    want = oracle.forward(x, "u8", cfg["n_samp"], s)
+    plan = plan_for(dd, cfg)
+    xd = torch.from_numpy(x).cuda()
+    out = torch.empty((plan.n_dm, plan.out_pitch), dtype=torch.float32, device="cuda")
+    rep = plan.autotune(xd, out)
+    print(rep, flush=True)
+    assert rep["n_tried"] >= 2 and rep["best_ms"] > 0 and rep["best_ms"] <= rep["default_ms"]
+    assert rep["timed_out_samples"] == plan.n_out
+    t = plan.tiles(0)
+    assert t == rep["best"]
+    got = plan.forward(xd, out=out)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), want)
+    line = cache.read_text().strip().splitlines()[-1].split()
+    assert line[0] == "dd-tune-v1" and int(line[2]) == t["shape"] and int(line[3]) == t["order"]
+    again = plan_for(dd, cfg)
+    assert again.tiles(0) == t
+
+
+def test_autotune_adjoint(dd, monkeypatch):
+    monkeypatch.delenv("DD_TUNE_CACHE", raising=False)
+    cfg = _case("f32")
+    s = oracle_table(cfg)
+    plan = plan_for(dd, cfg)
+    y = synth.normal_f32(cfg["n_dm"], plan.n_out, 78)
+    yd = torch.from_numpy(np.ascontiguousarray(np.pad(y, ((0, 0), (0, plan.out_pitch - plan.n_out))))).cuda()
+    before = plan.adjoint(yd).cpu().numpy()
+    g = torch.empty((plan.n_chan, plan.in_row_elems), dtype=torch.float32, device="cuda")
+    rep = plan.autotune(yd, g, direction=1)
+    print(rep, flush=True)
+    assert rep["n_tried"] >= 2 and plan.tiles(1) == rep["best"]
+    after = plan.adjoint(yd).cpu().numpy()
+    assert np.array_equal(after, before)
+    want = oracle.adjoint(y, cfg["n_chan"], cfg["n_samp"], s)
+    abs_a = oracle.adjoint(np.abs(y), cfg["n_chan"], cfg["n_samp"], s)
+    assert np.all(np.abs(after - want) <= 1e-5 * abs_a)

@@ -1,0 +1,129 @@
+"""Host-side checks of tile-shape selection (no GPU needed).
+
+Every compiled shape either holds a plan's delay spread (then its tables fit
+the tuning workspace bound) or is refused with DD_ERR_RANGE, leaving the plan
+as it was.  The tuning cache applies a recorded choice to an identical plan
+and ignores lines whose shape parameters do not match the library's.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+
+
+@pytest.fixture(scope="module")
+def dd():
+    import paper_2311_05341_amd as dd
+    return dd
+
+
+def _plan(dd, cfg, **kw):
+    args = dict(n_chan=cfg["n_chan"], n_samp=cfg["n_samp"], dtype=cfg["dtype"], f_high=cfg["f_high"],
+                chan_bw=cfg["chan_bw"], t_samp=cfg["t_samp"], dm_start=cfg["dm_start"],
+                dm_step=cfg["dm_step"], n_dm=cfg["n_dm"], bind=False)
+    args.update(kw)
+    return dd.Plan(**args)
+
+
+def _status(dd, fn):
+    with pytest.raises(dd.DDError) as e:
+        fn()
+    return e.value.name
+
+
+@pytest.mark.parametrize("name", ["small", "lowfreq_u4", "grad_f32"])
+def test_every_shape_feasible_or_refused(dd, name):
+    cfg = synth.CONFIGS[name]
+    p = _plan(dd, cfg)
+    dirs = [0, 1] if cfg["dtype"] == "f32" else [0]
+    bound = p.info.tune_ws_bytes
+    assert p.info.dev_table_bytes <= bound
+    for direction in dirs:
+        ok = 0
+        for s in range(p.n_shapes):
+            for o in (0, 1):
+                before = p.tiles(direction)
+                try:
+                    p.set_tiles(direction, s, o)
+                except dd.DDError as e:
+                    assert e.name == "DD_ERR_RANGE"
+                    assert p.tiles(direction) == before
+                    continue
+                ok += 1
+                t = p.tiles(direction)
+                assert (t["shape"], t["order"]) == (s, o)
+                assert p.info.dev_table_bytes <= bound
+                if direction == 0:
+                    assert (p.info.kernel_ns, p.info.kernel_dm_per_wave, p.info.kernel_waves,
+                            p.info.kernel_chan_block, p.info.kernel_order) == (
+                        t["ns"], t["per_wave"], t["waves"], t["row_block"], o)
+        assert ok >= 2  # at least one shape, in both orders
+
+
+def test_tiles_argument_errors(dd):
+    p = _plan(dd, synth.CONFIGS["small"])
+    assert _status(dd, lambda: p.tiles(1)) == "DD_ERR_DTYPE"
+    assert _status(dd, lambda: p.set_tiles(1, 0, 0)) == "DD_ERR_DTYPE"
+    assert _status(dd, lambda: p.set_tiles(0, p.n_shapes, 0)) == "DD_ERR_ARG"
+    assert _status(dd, lambda: p.set_tiles(0, -1, 0)) == "DD_ERR_ARG"
+    assert _status(dd, lambda: p.set_tiles(0, 0, 2)) == "DD_ERR_ARG"
+
+
+def test_default_tiles_time_first(dd):
+    for name in ["small", "headline", "lowfreq_u4", "grad_f32"]:
+        p = _plan(dd, synth.CONFIGS[name])
+        assert p.tiles(0)["order"] == 0
+        assert p.info.kernel_order == 0
+
+
+_KEY_FMT = (b"dtype=%d,nchan=%d,nsamp=%lld,fhigh=%a,bw=%a,freqs=%016llx,tsamp=%a,dm0=%a,dmstep=%a,ndm=%d,"
+            b"pitch=%lld,dir=%d")
+
+
+def _cache_key(cfg, dtype_code, pitch, direction):
+    """The cache's plan key, formatted by the C library's own printf (hex-float doubles)."""
+    libc = ctypes.CDLL(None)
+    buf = ctypes.create_string_buffer(600)
+    d = ctypes.c_double
+    libc.snprintf(buf, 600, _KEY_FMT, ctypes.c_int(dtype_code), ctypes.c_int(cfg["n_chan"]),
+                  ctypes.c_longlong(cfg["n_samp"]), d(cfg["f_high"]), d(cfg["chan_bw"]), ctypes.c_ulonglong(0),
+                  d(cfg["t_samp"]), d(cfg["dm_start"]), d(cfg["dm_step"]), ctypes.c_int(cfg["n_dm"]),
+                  ctypes.c_longlong(pitch), ctypes.c_int(direction))
+    return buf.value.decode()
+
+
+def test_tune_cache_applied(dd, tmp_path, monkeypatch):
+    cfg = synth.CONFIGS["small"]
+    p0 = _plan(dd, cfg)
+    feasible = []
+    for s in range(p0.n_shapes):
+        try:
+            p0.set_tiles(0, s, 1)
+            feasible.append((s, p0.tiles(0)))
+        except dd.DDError:
+            pass
+    assert len(feasible) >= 2
+    shape, t = feasible[-1]
+    key = _cache_key(cfg, 1, p0.in_pitch_bytes, 0)
+    path = tmp_path / "tune.txt"
+    other_key = key.replace("ndm=%d" % cfg["n_dm"], "ndm=%d" % (cfg["n_dm"] + 1))
+    params = "%d %d %d %d" % (t["ns"], t["per_wave"], t["waves"], t["row_block"])
+    path.write_text("dd-tune-v1 %s %d 1 %s 1.0\n" % (key, shape, params) +
+                    "dd-tune-v1 %s 0 0 %s 1.0\n" % (other_key, params) +
+                    "garbage line\n")
+    monkeypatch.setenv("DD_TUNE_CACHE", str(path))
+    p = _plan(dd, cfg)
+    assert (p.tiles(0)["shape"], p.tiles(0)["order"]) == (shape, 1)
+    # a line whose shape parameters disagree with the compiled shape is ignored
+    path.write_text("dd-tune-v1 %s %d 1 %d %s 1.0\n" % (key, shape, t["ns"] + 1, params.split(" ", 1)[1]))
+    p = _plan(dd, cfg)
+    assert p.tiles(0)["order"] == 0
+    # a different plan does not pick up the line
+    path.write_text("dd-tune-v1 %s %d 1 %s 1.0\n" % (key, shape, params))
+    p = _plan(dd, cfg, n_dm=cfg["n_dm"] - 1)
+    assert p.tiles(0)["order"] == 0
+    monkeypatch.delenv("DD_TUNE_CACHE")
+    p = _plan(dd, cfg)
+    assert p.tiles(0)["order"] == 0
