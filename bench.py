@@ -10,7 +10,7 @@ x-real-time factor (N_t * t_samp / t_step), the VALU roofline fraction of the
 forward kernel, and the CPU oracle timed on a bounded sample of the same
 workload.
 
-  python bench.py [--steps K] [--warmup W] [--workload headline|lowfreq_u4|grad_f32|small]
+  python bench.py [--steps K] [--warmup W] [--workload headline|lowfreq_u4|grad_f32|small|batch48]
                   [--adjoint] [--no-cpu-baseline] [--no-autotune]
 """
 from __future__ import annotations
@@ -99,6 +99,148 @@ def cpu_baseline(cfg, seconds_target=15.0):
                       % (len(rows), cfg["n_dm"], cfg["n_chan"], n_out, adds, dt)}
 
 
+BATCH_CHUNKS = 2  # time chunks per beam of the 48-beam job (its outputs would not fit HBM at once)
+
+
+def setup_batch48(dd, torch, synth, n_chunks=BATCH_CHUNKS, log=log):
+    """The 48-beam job: inputs resident in HBM, one persistent batch per time chunk.
+
+    Every beam's whole filterbank (99 GB in total) is generated in device
+    memory.  The whole job's outputs (217 GB) plus inputs exceed one MI355X's
+    288 GB, so each beam's outputs are produced in n_chunks time chunks into
+    one reused per-beam buffer, as a streaming search would consume them; chunk
+    k of every beam is one dd.Batch (one graph-replayed persistent launch).
+    Returns (beams, chunkers, inputs, outputs, batches)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    beams = synth.batch_beams()
+    keys = ["n_chan", "n_samp", "dtype", "f_high", "chan_bw", "t_samp", "dm_start", "dm_step", "n_dm"]
+    t = time.perf_counter()
+
+    def chunker(b):
+        return dd.TimeChunks(dict({k: b[k] for k in keys}, in_pitch_bytes=b["pitch"]), n_chunks, bind=False)
+
+    with ThreadPoolExecutor(8) as pool:
+        chunkers = list(pool.map(chunker, beams))
+    log("batch: %d beams, %d plans in %.1f s" % (len(beams), sum(len(set(map(id, c.plans))) for c in chunkers),
+                                                   time.perf_counter() - t))
+    dev = torch.device("cuda", torch.cuda.current_device())
+    in_bytes = sum(b["n_chan"] * b["pitch"] for b in beams)
+    out_bytes = sum(b["n_dm"] * ((c.chunk_len + 3) // 4 * 4) * 4 for b, c in zip(beams, chunkers))
+    free, _ = torch.cuda.mem_get_info()
+    log("batch: inputs %.1f GB, chunk outputs %.1f GB, device free %.1f GB" % (in_bytes / 1e9, out_bytes / 1e9,
+                                                                               free / 1e9))
+    if in_bytes + out_bytes > 0.95 * free:
+        raise SystemExit("the 48-beam job needs %.1f GB of device memory, %.1f GB are free"
+                         % ((in_bytes + out_bytes) / 1e9, free / 1e9))
+    for c in chunkers:
+        for p in set(c.plans):
+            p.bind(dev)
+    table = torch.from_numpy(synth.gaussian_table()).cuda()
+    stream = torch.cuda.current_stream().cuda_stream
+    inputs, outputs = [], []
+    for b, c in zip(beams, chunkers):
+        x = torch.empty((b["n_chan"], b["pitch"]), dtype=torch.uint8, device=dev)
+        synth.gaussian_u8_device(x.data_ptr(), b["n_chan"], b["n_samp"], b["pitch"], b["seed"], table.data_ptr(),
+                                 stream)
+        inputs.append(x)
+        outputs.append(torch.empty((b["n_dm"], (c.chunk_len + 3) // 4 * 4), dtype=torch.float32, device=dev))
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    batches = []
+    for k in range(n_chunks):
+        idx = [i for i, c in enumerate(chunkers) if k < len(c)]
+        batches.append((idx, dd.Batch([chunkers[i].plans[k] for i in idx],
+                                      [chunkers[i].input_view(inputs[i], k) for i in idx],
+                                      [outputs[i] for i in idx])))
+    torch.cuda.synchronize()
+    log("batch: %d batches bound in %.1f s" % (len(batches), time.perf_counter() - t))
+    return beams, chunkers, inputs, outputs, batches
+
+
+def bench_batch48(args, dd, torch, synth):
+    beams, chunkers, inputs, outputs, batches = setup_batch48(dd, torch, synth)
+    adds = float(sum(b["n_dm"] * c.n_out * b["n_chan"] for b, c in zip(beams, chunkers)))
+    stream = torch.cuda.current_stream()
+
+    def batched():
+        for _, bt in batches:
+            bt.run()
+
+    def plain():
+        for k in range(len(batches)):
+            for i, c in enumerate(chunkers):
+                if k < len(c):
+                    c.plans[k].forward(c.input_view(inputs[i], k), out=outputs[i])
+
+    def timed(step, steps, per_launch=False):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        launch_ms, wall = [], []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if per_launch:
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(len(batches) + 1)]
+                ev[0].record(stream)
+                for j, (_, bt) in enumerate(batches):
+                    bt.run()
+                    ev[j + 1].record(stream)
+            else:
+                step()
+            torch.cuda.synchronize()
+            wall.append(time.perf_counter() - t0)
+            if per_launch:
+                launch_ms += [ev[j].elapsed_time(ev[j + 1]) for j in range(len(batches))]
+        return float(np.mean(wall)) * 1e3, launch_ms
+
+    log("timing batched ...")
+    ms_batched, launch_ms = timed(batched, args.steps, per_launch=True)
+    log("batched: %.1f ms/step, launches %s ms" % (ms_batched, ["%.1f" % v for v in launch_ms]))
+    log("timing 48 plain calls per chunk ...")
+    ms_plain, _ = timed(plain, args.steps)
+    log("plain: %.1f ms/step" % ms_plain)
+    value = adds / (ms_batched * 1e-3) / 1e12
+    kernel_ms = float(np.sum(launch_ms)) / args.steps
+    achieved = adds / (kernel_ms * 1e-3) / 1e12
+    beam_seconds = sum(b["n_samp"] * b["t_samp"] for b in beams)
+    rec = {
+        "metric": "Tadds/s (48 beams, batched)",
+        "value": value,
+        "unit": "Tadds/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_batched,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": "batch48", "beams": len(beams), "time_chunks": len(batches),
+                   "adds_per_step": adds, "input_bytes": sum(b["n_chan"] * b["pitch"] for b in beams),
+                   "n_chan_set": sorted(set(b["n_chan"] for b in beams)),
+                   "n_samp_range": [min(b["n_samp"] for b in beams), max(b["n_samp"] for b in beams)],
+                   "n_dm_range": [min(b["n_dm"] for b in beams), max(b["n_dm"] for b in beams)]},
+        "plain_calls": {"value": adds / (ms_plain * 1e-3) / 1e12, "unit": "Tadds/s", "ms_per_step": ms_plain,
+                        "calls_per_step": sum(len(c) for c in chunkers)},
+        "batched_over_plain": ms_plain / ms_batched,
+        "x_realtime_beams": beam_seconds / (ms_batched * 1e-3),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tadds/s",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "fwd_int_batched_kernel",
+                     "kernel_ms": kernel_ms},
+        "lds_roofline": {"achieved": achieved, "peak": LDS_PEAK_TBS, "unit": "TB/s", "frac": achieved / LDS_PEAK_TBS,
+                         "bytes_per_add": 1},
+    }
+    if not args.no_cpu_baseline:
+        big = max(beams, key=lambda b: b["n_chan"] * b["n_samp"] * b["n_dm"])
+        log("cpu baseline on the largest beam ...")
+        rec["cpu_baseline"] = cpu_baseline(dict(big, pulses=[]), seconds_target=12.0)
+        rec["cpu_baseline"]["sample"] = "largest beam: " + rec["cpu_baseline"]["sample"]
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +263,8 @@ def main():
     import paper_2311_05341_amd as dd
     import synth
 
+    if args.workload == "batch48":
+        return bench_batch48(args, dd, torch, synth)
     cfg = synth.CONFIGS[args.workload]
     log("workload %s: %s" % (args.workload, {k: v for k, v in cfg.items() if k != "pulses"}))
     t = time.perf_counter()

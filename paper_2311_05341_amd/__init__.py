@@ -15,3 +15,4 @@ from .binding import (  # noqa: F401
     Plan,
     dedisperse,
 )
+from .chunks import TimeChunks  # noqa: F401
