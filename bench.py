@@ -33,6 +33,11 @@ LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
 # LDS bytes the accumulate loop reads per add: one byte per 8- or 4-bit sample
 # (4-bit samples are unpacked to bytes when staged), four per float.
 LDS_BYTES_PER_ADD = {"u8": 1, "u4": 1, "f32": 4}
+# The integer kernels add four 8-bit samples per 32-bit word and two channels per
+# v_add3_u32 (one v_perm_b32 + one v_add3_u32 per two channel-words for each of
+# the even/odd byte lanes): 8 sample-adds per 4 VALU ops, so twice the one-add-per-lane peak.
+INT_FORM = "SWAR bytes in 32-bit words, v_perm_b32 + v_add3_u32 (2 sample-adds per VALU lane-op)"
+F32_FORM = "v_add_f32 (1 add per VALU lane-op)"
 
 
 def log(msg):
@@ -229,7 +234,8 @@ def bench_batch48(args, dd, torch, synth):
         "x_realtime_beams": beam_seconds / (ms_batched * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tadds/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "fwd_int_batched_kernel",
-                     "kernel_ms": kernel_ms},
+                     "kernel_ms": kernel_ms, "instruction_form": INT_FORM, "peak_instruction_form": 2 * VALU_PEAK_TOPS,
+                     "frac_instruction_form": achieved / (2 * VALU_PEAK_TOPS)},
         "lds_roofline": {"achieved": achieved, "peak": LDS_PEAK_TBS, "unit": "TB/s", "frac": achieved / LDS_PEAK_TBS,
                          "bytes_per_add": 1},
     }
@@ -250,6 +256,8 @@ def main():
     ap.add_argument("--adjoint", action="store_true", help="time the adjoint instead of the forward")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default tile choice")
+    ap.add_argument("--tiles", default=None, metavar="SHAPE,ORDER",
+                    help="use this compiled tile shape index and workgroup order instead of autotuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first, as a known-size reference for memory counters")
     args = ap.parse_args()
@@ -290,7 +298,10 @@ def main():
     else:
         step = lambda: plan.forward(x, out=out)  # noqa: E731
     tune = None
-    if not args.no_autotune:
+    if args.tiles:
+        shape, order = (int(v) for v in args.tiles.split(","))
+        plan.set_tiles(direction, shape, order)
+    elif not args.no_autotune:
         t = time.perf_counter()
         tune = plan.autotune(y, g, direction=1) if args.adjoint else plan.autotune(x, out)
         tune["seconds"] = time.perf_counter() - t
@@ -340,7 +351,10 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tadds/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
                      "kernel": "fwd_int_kernel" if cfg["dtype"] != "f32" else "f32_kernel",
-                     "kernel_ms": k_avg},
+                     "kernel_ms": k_avg,
+                     "instruction_form": INT_FORM if cfg["dtype"] != "f32" else F32_FORM,
+                     "peak_instruction_form": VALU_PEAK_TOPS * (2 if cfg["dtype"] != "f32" else 1),
+                     "frac_instruction_form": achieved / (VALU_PEAK_TOPS * (2 if cfg["dtype"] != "f32" else 1))},
         "lds_roofline": {"achieved": achieved * LDS_BYTES_PER_ADD[cfg["dtype"]], "peak": LDS_PEAK_TBS,
                          "unit": "TB/s", "frac": achieved * LDS_BYTES_PER_ADD[cfg["dtype"]] / LDS_PEAK_TBS,
                          "bytes_per_add": LDS_BYTES_PER_ADD[cfg["dtype"]]},

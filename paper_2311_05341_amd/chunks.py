@@ -44,14 +44,20 @@ class TimeChunks:
         plans = {}
         for _, n in self.spans:
             if n not in plans:
-                plans[n] = Plan(**dict(args, n_samp=n + self.max_shift))
+                n_samp = n + self.max_shift
+                if self.desc["dtype"] == "u4":
+                    # 4-bit rows hold whole bytes: with an odd max shift a chunk computes
+                    # one more column, the next chunk's first (identical values)
+                    n_samp += n_samp & 1
+                plans[n] = Plan(**dict(args, n_samp=n_samp))
         self.plans = [plans[n] for _, n in self.spans]
         for p, (_, n) in zip(self.plans, self.spans):
-            assert p.max_shift == self.max_shift and p.n_out == n
+            assert p.max_shift == self.max_shift and n <= p.n_out <= n + 1
 
     @property
     def chunk_len(self) -> int:
-        return self.spans[0][1]
+        """Output columns a per-chunk output buffer must hold (any chunk)."""
+        return max(p.n_out for p in self.plans)
 
     def input_view(self, x, k: int):
         """Input columns of chunk k: a view of the whole input x (rows of in_pitch_bytes)."""

@@ -131,3 +131,22 @@ def test_autotune_adjoint(dd, monkeypatch):
     want = oracle.adjoint(y, cfg["n_chan"], cfg["n_samp"], s)
     abs_a = oracle.adjoint(np.abs(y), cfg["n_chan"], cfg["n_samp"], s)
     assert np.all(np.abs(after - want) <= 1e-5 * abs_a)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u4", "f32"])
+def test_time_chunks_equal_whole(dd, dtype):
+    """Chunks over column views of one input give the whole-input columns bit for bit."""
+    cfg = _case(dtype)
+    s = oracle_table(cfg)
+    x, _ = host_input(cfg, s)
+    desc = {k: cfg[k] for k in ["n_chan", "n_samp", "dtype", "f_high", "chan_bw", "t_samp", "dm_start", "dm_step",
+                                "n_dm"]}
+    whole = plan_for(dd, cfg)
+    xd = torch.from_numpy(x).cuda()
+    ref = whole.forward(xd).clone()
+    tc = dd.TimeChunks(desc, 3)
+    out = torch.full((whole.n_dm, whole.out_pitch), -1.0, device="cuda")
+    for k, p in enumerate(tc.plans):
+        p.forward(tc.input_view(xd, k), out=tc.output_view(out, k))
+    torch.cuda.synchronize()
+    assert torch.equal(out[:, : whole.n_out], ref)

@@ -127,3 +127,23 @@ def test_tune_cache_applied(dd, tmp_path, monkeypatch):
     monkeypatch.delenv("DD_TUNE_CACHE")
     p = _plan(dd, cfg)
     assert p.tiles(0)["order"] == 0
+
+
+@pytest.mark.parametrize("dtype,n_chunks", [("u8", 1), ("u8", 3), ("u4", 4), ("f32", 5)])
+def test_time_chunks_cover_the_output(dd, dtype, n_chunks):
+    cfg = dict(synth.CONFIGS["small"], dtype=dtype)
+    desc = {k: cfg[k] for k in ["n_chan", "n_samp", "dtype", "f_high", "chan_bw", "t_samp", "dm_start", "dm_step",
+                                "n_dm"]}
+    tc = dd.TimeChunks(desc, n_chunks, bind=False)
+    whole = _plan(dd, cfg)
+    assert tc.n_out == whole.n_out and tc.max_shift == whole.max_shift
+    assert len(tc) == n_chunks
+    unit = {"u8": 16, "u4": 32, "f32": 4}[dtype]
+    t = 0
+    for (t0, n), p in zip(tc.spans, tc.plans):
+        assert t0 == t and t0 % unit == 0 and n > 0
+        assert p.max_shift == whole.max_shift and p.in_pitch_bytes == whole.in_pitch_bytes
+        assert p.n_out == n or (dtype == "u4" and p.n_out == n + 1 and t0 + n < whole.n_out)
+        assert np.array_equal(p.shift, whole.shift)
+        t += n
+    assert t == whole.n_out
