@@ -180,10 +180,12 @@ dd_status dd_execute_adjoint(const dd_plan *plan, const float *d_y, int64_t y_pi
  *   cannot stage the plan's delay spread.  On success the plan is unbound:
  *   query dev_table_bytes again and call dd_plan_bind before executing.
  * dd_plan_autotune: time every (shape, order) that holds the plan's spread and
- *   keep the fastest.  Each candidate runs on the caller's buffers over the
- *   first timed_out_samples output samples of every row (all of them for small
- *   plans; about 10^12 adds per launch otherwise), once to warm up and twice
- *   timed with HIP events on `stream`.  The call synchronises `stream`.
+ *   keep the fastest (the current choice stays unless another is at least 1%
+ *   faster).  Each candidate runs on the caller's buffers over the first
+ *   timed_out_samples output samples of every row (all of them for small plans;
+ *   otherwise an eighth of the job, between 10^12 and 4*10^12 adds per launch),
+ *   once to warm up and twice timed with HIP events on `stream`.  The call
+ *   synchronises `stream`.
  *     forward: d_src is the input (as dd_execute), d_dst the output with
  *              `pitch` = out_pitch;
  *     adjoint: d_src is y with `pitch` = y_pitch, d_dst the gradient (as

@@ -383,7 +383,7 @@ __global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0
 // Persistent batched forward kernel.  Workgroups repeatedly claim the next work
 // item (beam, DM block, time tile) from a device counter; items are numbered
 // beam by beam with the beams in decreasing cost order and, inside a beam,
-// DM block fastest.  A workgroup returns at its first claim past the last
+// time tile fastest (as the plain launch's default order).  A workgroup returns at its first claim past the last
 // item, so every wave reaches the exit.
 template <int NS, int R, int NW, int CB, bool U4>
 __global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc *__restrict__ beams, int n_beams,
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc
     }
     const BeamDesc &b = beams[lo];
     const long long k = item - b.item_begin;
-    const int tblk = (int)(k / b.tiles_d), dblk = (int)(k - (long long)tblk * b.tiles_d);
+    const int dblk = (int)(k / b.tiles_t), tblk = (int)(k - (long long)dblk * b.tiles_t);
     IntArgs a;
     a.x = b.x;
     a.offs = b.offs;

@@ -151,9 +151,12 @@ dd_status dd_plan_autotune(dd_plan *p, int32_t dir, const void *src, float *dst,
   current_tiles(*p, dir, &orig_shape, &orig_order);
   p->bound = false;
   const int64_t out_len = dir == 0 ? p->n_out : p->desc.n_samp;
-  // About 1e12 adds per timed launch, in whole groups of 8 tiles of 1024 samples.
+  // Timed span: an eighth of the job (so that the input streamed per output
+  // block exceeds the caches, as in the full launch), at least 1e12 and at most
+  // 4e12 adds, in whole groups of 8 tiles of 1024 samples.
   const double adds_per_sample = (double)p->desc.n_dm * (double)p->desc.n_chan;
-  int64_t lim = (int64_t)ceil(1e12 / adds_per_sample);
+  const double target = std::min(4e12, std::max(1e12, adds_per_sample * (double)out_len / 8.0));
+  int64_t lim = (int64_t)ceil(target / adds_per_sample);
   lim = std::max<int64_t>(16384, (lim + 8191) / 8192 * 8192);
   if (lim >= out_len) lim = 0;  // the whole span
 
@@ -221,6 +224,11 @@ dd_status dd_plan_autotune(dd_plan *p, int32_t dir, const void *src, float *dst,
     set_tiles(*p, dir, orig_shape, orig_order);
     p->bound = false;
     return fail(status, msg);
+  }
+  if (best_ms > 0.99 * default_ms) {  // within timing noise of the current choice: keep it
+    best_shape = orig_shape;
+    best_order = orig_order;
+    best_ms = default_ms;
   }
   status = set_tiles(*p, dir, best_shape, best_order);
   if (status == DD_OK) status = upload_tables(*p, ws, stream);

@@ -27,8 +27,8 @@ def dd():
 def _case(dtype):
     # several time tiles with a ragged tail, DM blocks with a tail, channels
     # not a multiple of any staging block
-    return dict(dtype=dtype, n_chan=203, n_samp=30002, f_high=1400.0, chan_bw=0.9, t_samp=64e-6,
-                dm_start=3.0, dm_step=0.75, n_dm=77, seed=41)
+    return dict(dtype=dtype, n_chan=203, n_samp=30016, f_high=1400.0, chan_bw=0.9, t_samp=64e-6,
+                dm_start=3.0, dm_step=0.77, n_dm=77, seed=41)
 
 
 def _choices(dd, plan, direction):
