@@ -175,10 +175,28 @@ __device__ __forceinline__ TileLds tile_lds(int row_bytes) {
   return L;
 }
 
-// Issue the direct loads of block `cb` (first channel) into ring slot `slot`.
+// Stage bases of the channels this wave loads for block `cb` (first channel).
+// Scalar loads: issued one block before stage_dma needs them, so their
+// latency hides behind a whole block of work.
 template <int NW, int CB, int MAXT, bool U4>
-__device__ __forceinline__ void stage_dma(const IntArgs &a, const int32_t *sb, int64_t t0, int cb, uint8_t *lds,
-                                          const TileLds &L, int slot, int wave, int lane) {
+__device__ __forceinline__ void stage_bases(const IntArgs &a, const int32_t *sb, int cb, const TileLds &L, int wave,
+                                            int32_t (&base)[MAXT]) {
+  const int raw_bytes = U4 ? L.row_bytes / 2 : L.row_bytes;
+  const int segs = (raw_bytes + 1023) >> 10;
+#pragma unroll
+  for (int m = 0; m < MAXT; ++m) {
+    const int s = wave + m * NW;
+    const int cc = s < CB * segs ? s / segs : 0;
+    const int c = __builtin_amdgcn_readfirstlane(min(cb + cc, a.n_chan - 1));
+    base[m] = scalar_load(sb, c);
+  }
+}
+
+// Issue the direct loads of block `cb` (first channel) into ring slot `slot`;
+// `base` comes from stage_bases for the same block.
+template <int NW, int CB, int MAXT, bool U4>
+__device__ __forceinline__ void stage_dma(const IntArgs &a, const int32_t (&base_in)[MAXT], int64_t t0, int cb,
+                                          uint8_t *lds, const TileLds &L, int slot, int wave, int lane) {
   const int raw_bytes = U4 ? L.row_bytes / 2 : L.row_bytes;  // bytes of one row to stage
   const int segs = (raw_bytes + 1023) >> 10;
   // Bounds are checked per 32-bit word, so the limit is the row length rounded
@@ -192,7 +210,7 @@ __device__ __forceinline__ void stage_dma(const IntArgs &a, const int32_t *sb, i
     const int j0 = seg_ok ? (s - cc * segs) << 6 : 0;  // first 16-byte chunk of the segment
     const bool chan_ok = seg_ok && cb + cc < a.n_chan;
     const int c = __builtin_amdgcn_readfirstlane(min(cb + cc, a.n_chan - 1));
-    const int32_t base = chan_ok ? scalar_load(sb, c) : 0;
+    const int32_t base = chan_ok ? base_in[m] : 0;
     const v4i_t rs = make_rsrc(a.x + (int64_t)c * a.pitch, chan_ok ? row_valid_bytes : 0);
     // first staged byte of the row: sample t0 + base (a multiple of 32 for 4-bit input)
     const uint32_t row0 = U4 ? (uint32_t)((t0 + base) >> 1) : (uint32_t)(t0 + base);
@@ -203,14 +221,30 @@ __device__ __forceinline__ void stage_dma(const IntArgs &a, const int32_t *sb, i
   }
 }
 
+// This thread's chunks of a block: chunk i = threadIdx.x + NT*n is chunk j of
+// row cc, i = cc * row_chunks + j.  The first (cc, j) and the per-step
+// increments are computed once per tile; the walk needs no division.
+struct ChunkWalk {
+  int cc0, j0, dcc, dj, row_chunks;
+};
+
+template <int NT>
+__device__ __forceinline__ ChunkWalk chunk_walk(const TileLds &L) {
+  ChunkWalk w;
+  w.row_chunks = L.row_bytes >> 4;
+  w.cc0 = (int)threadIdx.x / w.row_chunks;
+  w.j0 = (int)threadIdx.x - w.cc0 * w.row_chunks;
+  w.dcc = NT / w.row_chunks;
+  w.dj = NT - w.dcc * w.row_chunks;
+  return w;
+}
+
 // Build the byte-phase copies of block (ring slot `slot`) into phase buffer `pb`.
 template <int NT, int CB, bool U4>
-__device__ __forceinline__ void build_phases(uint8_t *lds, const TileLds &L, int slot, int pb) {
-  const int row_chunks = L.row_bytes >> 4;
+__device__ __forceinline__ void build_phases(uint8_t *lds, const TileLds &L, const ChunkWalk &cw, int slot, int pb) {
   const uint8_t *ring = lds + L.ring_base + slot * L.ring_slot;
   uint8_t *dst = lds + pb * L.phase_buf;
-  for (int i = threadIdx.x; i < CB * row_chunks; i += NT) {
-    const int cc = i / row_chunks, j = i - cc * row_chunks;
+  for (int cc = cw.cc0, j = cw.j0; cc < CB;) {
     uint32_t w[5];
     if (!U4) {
       const uint8_t *src = ring + cc * L.ring_row + 16 * j;
@@ -234,6 +268,12 @@ __device__ __forceinline__ void build_phases(uint8_t *lds, const TileLds &L, int
     uint8_t *p0 = dst + cc * 4 * L.row_bytes + 16 * j;
     *(uint4 *)p0 = make_uint4(w[0], w[1], w[2], w[3]);
     write_phases(p0, L.row_bytes, w);
+    cc += cw.dcc;
+    j += cw.dj;
+    if (j >= cw.row_chunks) {
+      j -= cw.row_chunks;
+      ++cc;
+    }
   }
 }
 
@@ -269,11 +309,21 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
   }
 
   const int nblk = chan_pad / CB;
+  int32_t bases[MAXT];
 #pragma unroll
-  for (int k = 0; k < kRing; ++k) stage_dma<NW, CB, MAXT, U4>(a, sb, t0, k * CB, lds, L, k, wave, lane);
+  for (int k = 0; k < kRing; ++k) {
+    stage_bases<NW, CB, MAXT, U4>(a, sb, k * CB, L, wave, bases);
+    stage_dma<NW, CB, MAXT, U4>(a, bases, t0, k * CB, lds, L, k, wave, lane);
+  }
+  stage_bases<NW, CB, MAXT, U4>(a, sb, kRing * CB, L, wave, bases);
+  // Offsets of block 0; each iteration fetches those of the next block.
+  uint32_t ow[CB * NOW];
+#pragma unroll
+  for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, q);
+  const ChunkWalk cw = chunk_walk<NT>(L);
   wait_vmcnt<(kRing - 1) * MAXT>();
   lds_barrier();
-  build_phases<NT, CB, U4>(lds, L, 0, 0);
+  build_phases<NT, CB, U4>(lds, L, cw, 0, 0);
 
   const uint8_t *lane_base = lds + 4 * lane;
   int since_flush = 0;
@@ -283,19 +333,14 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
     // slot b % kRing or phase buffer (b+1) % 2 any more.
     wait_vmcnt<(kRing - 2) * MAXT>();
     lds_barrier();
-    stage_dma<NW, CB, MAXT, U4>(a, sb, t0, (b + kRing) * CB, lds, L, b % kRing, wave, lane);  // zeros past the end
-    if (b + 1 < nblk) build_phases<NT, CB, U4>(lds, L, (b + 1) % kRing, (b + 1) & 1);
+    stage_dma<NW, CB, MAXT, U4>(a, bases, t0, (b + kRing) * CB, lds, L, b % kRing, wave, lane);  // zeros past the end
+    if (b + 1 < nblk) build_phases<NT, CB, U4>(lds, L, cw, (b + 1) % kRing, (b + 1) & 1);
     // Sum block b.  Each (channel, DM row) pair reads NS/4 aligned words of
     // the byte phase that puts its window on a word boundary; the table entry
     // is that word's byte offset inside the channel's four copies.  Lane i
     // owns words i, i+64, i+128, ... of the window, so every read is one
-    // contiguous, bank-conflict-free 256-byte access per wave.  All offsets of
-    // the block come in one scalar load and the channel loop is unrolled, so
-    // the reads of several pairs are in flight together.
-    uint32_t ow[CB * NOW];
-    const int oi = __builtin_amdgcn_readfirstlane(b * CB * NOW);
-#pragma unroll
-    for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, oi + q);
+    // contiguous, bank-conflict-free 256-byte access per wave.  The channel
+    // loop is unrolled, so the reads of several pairs are in flight together.
     const uint8_t *blk = lane_base + (b & 1) * L.phase_buf;
 #pragma unroll
     for (int cc = 0; cc < CB; ++cc) {
@@ -317,6 +362,14 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
       flush<NS, R>(mix, odd, tot);
       since_flush = 0;
     }
+    // Scalar loads for the next iteration: its offsets and the stage bases of
+    // the block it stages.  Issued after this block's LDS reads, so that no
+    // wait for them (LDS and scalar loads share one counter) falls inside the
+    // summation; the barrier's wait absorbs their latency.
+    const int oi = __builtin_amdgcn_readfirstlane(min(b + 1, nblk - 1) * CB * NOW);
+#pragma unroll
+    for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, oi + q);
+    stage_bases<NW, CB, MAXT, U4>(a, sb, (b + kRing + 1) * CB, L, wave, bases);
   }
   wait_vmcnt<0>();  // the trailing all-zero loads must land before the LDS is reused
   lds_barrier();
@@ -428,7 +481,7 @@ __global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc
 // per LDS stage), in the order the plan tries them.
 #define DD_INT_SHAPES(X)                                                                                    \
   X(16, 2, 16, 8) X(16, 4, 8, 8) X(16, 2, 16, 4) X(16, 4, 8, 4) X(16, 1, 16, 8) X(16, 1, 16, 4) X(16, 1, 16, 2) \
-  X(16, 1, 16, 1) X(16, 1, 4, 1) X(16, 1, 1, 1)
+  X(16, 1, 16, 1) X(16, 1, 4, 1) X(16, 1, 1, 1) X(8, 2, 16, 8) X(16, 2, 8, 4) X(8, 4, 16, 8)
 
 template <int NS, int R, int NW, int CB>
 int launch_int_shape(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, hipStream_t st,

@@ -105,9 +105,24 @@ struct FArgs {
   int32_t row_bytes;             // LDS bytes of one staged row
 };
 
+// Stage bases of the rows this wave loads for block `kb` (first row); scalar
+// loads issued one block before stage_dma needs them.
 template <int NW, int CB, int MAXT>
-__device__ __forceinline__ void stage_dma(const FArgs &a, const int32_t *sb, int64_t t0, int kb, uint8_t *slot,
-                                          uint8_t *sink, int wave, int lane) {
+__device__ __forceinline__ void stage_bases(const FArgs &a, const int32_t *sb, int kb, int wave,
+                                            int32_t (&base)[MAXT]) {
+  const int segs = (a.row_bytes + 1023) >> 10;
+#pragma unroll
+  for (int m = 0; m < MAXT; ++m) {
+    const int s = wave + m * NW;
+    const int kk = s < CB * segs ? s / segs : 0;
+    const int k = __builtin_amdgcn_readfirstlane(min(kb + kk, a.n_rows - 1));
+    base[m] = scalar_load(sb, k);
+  }
+}
+
+template <int NW, int CB, int MAXT>
+__device__ __forceinline__ void stage_dma(const FArgs &a, const int32_t (&base_in)[MAXT], int64_t t0, int kb,
+                                          uint8_t *slot, uint8_t *sink, int wave, int lane) {
   const int segs = (a.row_bytes + 1023) >> 10;
 #pragma unroll
   for (int m = 0; m < MAXT; ++m) {
@@ -117,7 +132,7 @@ __device__ __forceinline__ void stage_dma(const FArgs &a, const int32_t *sb, int
     const int j0 = seg_ok ? (s - kk * segs) << 6 : 0;
     const bool row_ok = seg_ok && kb + kk < a.n_rows;
     const int k = __builtin_amdgcn_readfirstlane(min(kb + kk, a.n_rows - 1));
-    const int32_t base = row_ok ? scalar_load(sb, k) : 0;
+    const int32_t base = row_ok ? base_in[m] : 0;
     const v4i_t rs = make_rsrc(a.x + (int64_t)k * a.row_pitch, row_ok ? 4 * a.row_len : 0);
     // first staged float: time t0 + base (a multiple of 4, possibly negative for the adjoint:
     // the offset then wraps past the row and reads zeros)
@@ -152,9 +167,16 @@ __device__ __forceinline__ void f32_tile(uint8_t *lds, const FArgs &a, int oblk,
     for (int j = 0; j < NS; ++j) tot[r][j] = part[r][j] = 0.0f;
 
   uint8_t *sink = lds + kRing * slot_bytes;  // 1 KiB after the ring: target of the padding loads
+  int32_t bases[MAXT];
 #pragma unroll
-  for (int k = 0; k < kRing - 1; ++k)
-    stage_dma<NW, CB, MAXT>(a, sb, t0, k * CB, lds + k * slot_bytes, sink, wave, lane);
+  for (int k = 0; k < kRing - 1; ++k) {
+    stage_bases<NW, CB, MAXT>(a, sb, k * CB, wave, bases);
+    stage_dma<NW, CB, MAXT>(a, bases, t0, k * CB, lds + k * slot_bytes, sink, wave, lane);
+  }
+  stage_bases<NW, CB, MAXT>(a, sb, (kRing - 1) * CB, wave, bases);
+  uint32_t ow[CB * NOW];  // offsets of block 0; each iteration fetches the next block's
+#pragma unroll
+  for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, q);
 
   const uint8_t *lane_base = lds + 4 * lane;
   for (int b = 0; b < nblk; ++b) {
@@ -162,12 +184,8 @@ __device__ __forceinline__ void f32_tile(uint8_t *lds, const FArgs &a, int oblk,
     // wave's have, and nobody reads the slot of block b-1 any more.
     wait_vmcnt<(kRing - 2) * MAXT>();
     lds_barrier();
-    stage_dma<NW, CB, MAXT>(a, sb, t0, (b + kRing - 1) * CB, lds + ((b + kRing - 1) % kRing) * slot_bytes, sink,
+    stage_dma<NW, CB, MAXT>(a, bases, t0, (b + kRing - 1) * CB, lds + ((b + kRing - 1) % kRing) * slot_bytes, sink,
                             wave, lane);  // zeros past the end
-    uint32_t ow[CB * NOW];
-    const int oi = __builtin_amdgcn_readfirstlane(b * CB * NOW);
-#pragma unroll
-    for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, oi + q);
     const uint8_t *blk = lane_base + (b % kRing) * slot_bytes;
 #pragma unroll
     for (int kk = 0; kk < CB; ++kk) {
@@ -189,6 +207,13 @@ __device__ __forceinline__ void f32_tile(uint8_t *lds, const FArgs &a, int oblk,
           part[r][j] = 0.0f;
         }
     }
+    // Scalar loads for the next iteration (its offsets, the stage bases of the
+    // block it stages), after this block's LDS reads: LDS and scalar loads
+    // share one wait counter, so none of their waits lands in the summation.
+    const int oi = __builtin_amdgcn_readfirstlane(min(b + 1, nblk - 1) * CB * NOW);
+#pragma unroll
+    for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, oi + q);
+    stage_bases<NW, CB, MAXT>(a, sb, (b + kRing) * CB, wave, bases);
   }
   wait_vmcnt<0>();
   lds_barrier();

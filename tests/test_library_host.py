@@ -106,5 +106,5 @@ def test_plan_tile_shapes(dd):
     for name in ["small", "headline", "lowfreq_u4", "grad_f32"]:
         p = _plan(dd, synth.CONFIGS[name])
         i = p.info
-        assert i.kernel_ns in (16, 32) and i.kernel_waves >= 1 and i.kernel_dm_per_wave >= 1
+        assert i.kernel_ns in (8, 16, 32) and i.kernel_waves >= 1 and i.kernel_dm_per_wave >= 1
         assert 256 % i.kernel_chan_block == 0
