@@ -14,6 +14,9 @@ HIPCC_FLAGS = [
     "-ffp-contract=off",
     # never emit packed FP32 arithmetic (v_pk_add/mul/fma_f32)
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # keep single-lane atomics plain: the wave-level atomic rewrite waits for the
+    # result at once, which would expose the batched kernel's claim-ahead latency
+    "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
     "-Wall",
 ]
 

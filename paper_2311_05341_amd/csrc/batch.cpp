@@ -167,10 +167,11 @@ dd_status dd_batch_bind(dd_batch *b, const void *const *d_in, float *const *d_ou
   }
   if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("batch upload: ") + hipGetErrorString(e));
 
-  BatchLaunch L;
+  BatchLaunch L = {};
   int le = batch_kernels(b->tile.ns, b->tile.dm_per_wave, b->tile.waves, b->tile.chan_block, b->dtype == DD_U4,
                          b->lds_bytes, &L);
   if (le) return fail(DD_ERR_HIP, std::string("batch kernel setup: ") + hipGetErrorString((hipError_t)le));
+  if (!L.reset_fn || !L.main_fn) return fail(DD_ERR_HIP, "batch kernel setup: missing kernel entry");
   release_graph(b);
   unsigned long long *counter = (unsigned long long *)base;
   const BeamDesc *descs = (const BeamDesc *)(base + up256(sizeof(unsigned long long)));

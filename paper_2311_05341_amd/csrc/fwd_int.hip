@@ -433,30 +433,33 @@ __global__ __launch_bounds__(NW * 64) void fwd_int_kernel(IntArgs a, int n_dblk,
 
 __global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0ull; }
 
-// Persistent batched forward kernel.  Workgroups repeatedly claim the next work
-// item (beam, DM block, time tile) from a device counter; items are numbered
-// beam by beam with the beams in decreasing cost order and, inside a beam,
-// time tile fastest (as the plain launch's default order).  A workgroup returns at its first claim past the last
-// item, so every wave reaches the exit.
+// Persistent batched forward kernel.  Workgroups claim work items (beam, DM
+// block, time tile) from a device counter; items are numbered beam by beam
+// with the beams in decreasing cost order and, inside a beam, time tile
+// fastest (as the plain launch's default order).  The claim of the next item
+// is issued when an item starts and read when it ends, so its latency hides
+// behind the tile.  Claims only grow, so the beam index only moves forward.
+// A workgroup returns at its first claim past the last item: every wave
+// reaches the exit.  Between items no extra barrier is needed for the LDS: a
+// tile ends with all of its LDS reads complete behind its final barrier.
 template <int NS, int R, int NW, int CB, bool U4>
 __global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc *__restrict__ beams, int n_beams,
                                                                    long long n_items,
                                                                    unsigned long long *__restrict__ counter) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ long long claimed;
+  if (threadIdx.x == 0) claimed = (long long)atomicAdd(counter, 1ull);
+  __syncthreads();
+  long long item = claimed;
+  int lo = 0;
   for (;;) {
-    __syncthreads();
-    if (threadIdx.x == 0) claimed = (long long)atomicAdd(counter, 1ull);
-    __syncthreads();
-    const unsigned long long raw = (unsigned long long)claimed;
-    const long long item = (long long)(((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(raw >> 32)) << 32) |
-                                       (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)raw));
+    item = (long long)(((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)((unsigned long long)item >> 32))
+                        << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)item));
     if (item >= n_items) return;
-    int lo = 0, hi = n_beams - 1;  // last beam whose item_begin <= item
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (beams[mid].item_begin <= item) lo = mid; else hi = mid - 1;
-    }
+    unsigned long long next = 0;
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1ull);  // the following claim, read after this tile
+    while (lo + 1 < n_beams && scalar_load(&beams[lo + 1].item_begin, 0) <= item) ++lo;
     const BeamDesc &b = beams[lo];
     const long long k = item - b.item_begin;
     const int dblk = (int)(k / b.tiles_t), tblk = (int)(k - (long long)dblk * b.tiles_t);
@@ -474,6 +477,9 @@ __global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc
     a.row_bytes = b.row_bytes;
 
     fwd_int_tile<NS, R, NW, CB, U4>(lds, a, dblk, tblk);
+    if (threadIdx.x == 0) claimed = (long long)next;
+    lds_barrier();  // publishes the claim; the tile's stores may still be in flight
+    item = claimed;  // read before this wave's first barrier of the next tile; rewritten only after it
   }
 }
 
