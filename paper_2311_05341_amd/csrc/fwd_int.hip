@@ -175,49 +175,74 @@ __device__ __forceinline__ TileLds tile_lds(int row_bytes) {
   return L;
 }
 
-// Stage bases of the channels this wave loads for block `cb` (first channel).
-// Scalar loads: issued one block before stage_dma needs them, so their
-// latency hides behind a whole block of work.
+// This wave's load segments of a block, the same for every block of a tile:
+// segment s = wave + m*NW is 64 lanes x 16 bytes of channel cc starting at
+// chunk j0 (segs = ceil(raw row bytes / 1 KiB) per channel).  Segments past
+// the block's last are padding loads: every wave issues exactly MAXT loads per
+// block, so a fixed vmcnt wait is exact; padding loads read nothing
+// (zero-size buffer) and land in the scratch area.
+template <int MAXT>
+struct DmaPlan {
+  int cc[MAXT];            // channel within the block (0 for padding)
+  uint32_t lds_off[MAXT];  // byte offset of the segment inside a ring slot
+  uint32_t voff[MAXT];     // this lane's byte offset inside the staged raw row
+  bool ok[MAXT];           // a real segment (wave-uniform)
+  bool lane_ok[MAXT];      // this lane's 16 bytes lie inside the raw row (always true for padding)
+};
+
 template <int NW, int CB, int MAXT, bool U4>
-__device__ __forceinline__ void stage_bases(const IntArgs &a, const int32_t *sb, int cb, const TileLds &L, int wave,
-                                            int32_t (&base)[MAXT]) {
-  const int raw_bytes = U4 ? L.row_bytes / 2 : L.row_bytes;
+__device__ __forceinline__ DmaPlan<MAXT> dma_plan(const TileLds &L, int wave, int lane) {
+  DmaPlan<MAXT> d;
+  const int raw_bytes = U4 ? L.row_bytes / 2 : L.row_bytes;  // bytes of one row to stage
   const int segs = (raw_bytes + 1023) >> 10;
 #pragma unroll
   for (int m = 0; m < MAXT; ++m) {
     const int s = wave + m * NW;
-    const int cc = s < CB * segs ? s / segs : 0;
-    const int c = __builtin_amdgcn_readfirstlane(min(cb + cc, a.n_chan - 1));
+    d.ok[m] = s < CB * segs;
+    const int cc = d.ok[m] ? s / segs : 0;
+    const int j0 = d.ok[m] ? (s - cc * segs) << 6 : 0;  // first 16-byte chunk of the segment
+    d.cc[m] = cc;
+    d.lds_off[m] = (uint32_t)(cc * L.ring_row + 16 * j0);
+    d.voff[m] = 16u * (uint32_t)(j0 + lane);
+    d.lane_ok[m] = !d.ok[m] || 16 * (j0 + lane) < raw_bytes;
+  }
+  return d;
+}
+
+// Stage bases of the channels this wave loads for block `cb` (first channel).
+// Scalar loads: issued one block before stage_dma needs them, so their
+// latency hides behind a whole block of work.
+template <int MAXT>
+__device__ __forceinline__ void stage_bases(const IntArgs &a, const int32_t *sb, int cb, const DmaPlan<MAXT> &d,
+                                            int32_t (&base)[MAXT]) {
+#pragma unroll
+  for (int m = 0; m < MAXT; ++m) {
+    const int c = __builtin_amdgcn_readfirstlane(min(cb + d.cc[m], a.n_chan - 1));
     base[m] = scalar_load(sb, c);
   }
 }
 
 // Issue the direct loads of block `cb` (first channel) into ring slot `slot`;
 // `base` comes from stage_bases for the same block.
-template <int NW, int CB, int MAXT, bool U4>
-__device__ __forceinline__ void stage_dma(const IntArgs &a, const int32_t (&base_in)[MAXT], int64_t t0, int cb,
-                                          uint8_t *lds, const TileLds &L, int slot, int wave, int lane) {
-  const int raw_bytes = U4 ? L.row_bytes / 2 : L.row_bytes;  // bytes of one row to stage
-  const int segs = (raw_bytes + 1023) >> 10;
+template <int MAXT, bool U4>
+__device__ __forceinline__ void stage_dma(const IntArgs &a, const DmaPlan<MAXT> &d, const int32_t (&base_in)[MAXT],
+                                          int64_t t0, int cb, uint8_t *lds, const TileLds &L, int slot) {
   // Bounds are checked per 32-bit word, so the limit is the row length rounded
   // up to 16 bytes (still inside the row pitch).
   const int row_valid_bytes = (int)(((U4 ? a.n_samp / 2 : a.n_samp) + 15) & ~(int64_t)15);
+  const uint32_t slot_addr =
+      __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void_t *)(lds + L.ring_base + slot * L.ring_slot));
+  const uint32_t scratch_addr = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void_t *)(lds + L.scratch));
 #pragma unroll
   for (int m = 0; m < MAXT; ++m) {
-    const int s = wave + m * NW;
-    const bool seg_ok = s < CB * segs;  // wave-uniform
-    const int cc = seg_ok ? s / segs : 0;
-    const int j0 = seg_ok ? (s - cc * segs) << 6 : 0;  // first 16-byte chunk of the segment
-    const bool chan_ok = seg_ok && cb + cc < a.n_chan;
-    const int c = __builtin_amdgcn_readfirstlane(min(cb + cc, a.n_chan - 1));
+    const bool chan_ok = d.ok[m] && cb + d.cc[m] < a.n_chan;  // wave-uniform
+    const int c = __builtin_amdgcn_readfirstlane(min(cb + d.cc[m], a.n_chan - 1));
     const int32_t base = chan_ok ? base_in[m] : 0;
     const v4i_t rs = make_rsrc(a.x + (int64_t)c * a.pitch, chan_ok ? row_valid_bytes : 0);
     // first staged byte of the row: sample t0 + base (a multiple of 32 for 4-bit input)
     const uint32_t row0 = U4 ? (uint32_t)((t0 + base) >> 1) : (uint32_t)(t0 + base);
-    const int j = j0 + lane;
-    uint8_t *dst = seg_ok ? lds + L.ring_base + slot * L.ring_slot + cc * L.ring_row + 16 * j0 : lds + L.scratch;
-    const uint32_t lds_addr = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void_t *)dst);
-    if (!seg_ok || 16 * j < raw_bytes) dma16(rs, seg_ok ? row0 + 16u * (uint32_t)j : 0u, lds_addr);
+    const uint32_t lds_addr = d.ok[m] ? slot_addr + d.lds_off[m] : scratch_addr;
+    if (d.lane_ok[m]) dma16(rs, row0 + d.voff[m], lds_addr);
   }
 }
 
@@ -309,13 +334,14 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
   }
 
   const int nblk = chan_pad / CB;
+  const DmaPlan<MAXT> dp = dma_plan<NW, CB, MAXT, U4>(L, wave, lane);
   int32_t bases[MAXT];
 #pragma unroll
   for (int k = 0; k < kRing; ++k) {
-    stage_bases<NW, CB, MAXT, U4>(a, sb, k * CB, L, wave, bases);
-    stage_dma<NW, CB, MAXT, U4>(a, bases, t0, k * CB, lds, L, k, wave, lane);
+    stage_bases<MAXT>(a, sb, k * CB, dp, bases);
+    stage_dma<MAXT, U4>(a, dp, bases, t0, k * CB, lds, L, k);
   }
-  stage_bases<NW, CB, MAXT, U4>(a, sb, kRing * CB, L, wave, bases);
+  stage_bases<MAXT>(a, sb, kRing * CB, dp, bases);
   // Offsets of block 0; each iteration fetches those of the next block.
   uint32_t ow[CB * NOW];
 #pragma unroll
@@ -333,7 +359,7 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
     // slot b % kRing or phase buffer (b+1) % 2 any more.
     wait_vmcnt<(kRing - 2) * MAXT>();
     lds_barrier();
-    stage_dma<NW, CB, MAXT, U4>(a, bases, t0, (b + kRing) * CB, lds, L, b % kRing, wave, lane);  // zeros past the end
+    stage_dma<MAXT, U4>(a, dp, bases, t0, (b + kRing) * CB, lds, L, b % kRing);  // zeros past the end
     if (b + 1 < nblk) build_phases<NT, CB, U4>(lds, L, cw, (b + 1) % kRing, (b + 1) & 1);
     // Sum block b.  Each (channel, DM row) pair reads NS/4 aligned words of
     // the byte phase that puts its window on a word boundary; the table entry
@@ -369,7 +395,7 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
     const int oi = __builtin_amdgcn_readfirstlane(min(b + 1, nblk - 1) * CB * NOW);
 #pragma unroll
     for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, oi + q);
-    stage_bases<NW, CB, MAXT, U4>(a, sb, (b + kRing + 1) * CB, L, wave, bases);
+    stage_bases<MAXT>(a, sb, (b + kRing + 1) * CB, dp, bases);
   }
   wait_vmcnt<0>();  // the trailing all-zero loads must land before the LDS is reused
   lds_barrier();

@@ -36,7 +36,12 @@ constexpr int kRing = 3;
 constexpr int kStageSegs = 64;
 constexpr int kMaxSegsPerWave = 16;
 
+constexpr int max_loads_per_wave(int segs, int nw) {
+  return (segs + nw - 1) / nw < kMaxSegsPerWave ? (segs + nw - 1) / nw : kMaxSegsPerWave;
+}
+
 typedef int v4i_t __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void_t;
 
 template <typename T>
 __device__ __forceinline__ T scalar_load(const T *p, int64_t i) {
@@ -105,43 +110,68 @@ struct FArgs {
   int32_t row_bytes;             // LDS bytes of one staged row
 };
 
-// Stage bases of the rows this wave loads for block `kb` (first row); scalar
-// loads issued one block before stage_dma needs them.
+// This wave's load segments of a block, the same for every block of a tile:
+// segment s = wave + m*NW is 64 lanes x 16 bytes of row kk starting at chunk
+// j0 (segs = ceil(row_bytes / 1 KiB) per row).  Segments past the block's
+// last are padding loads: every wave issues exactly MAXT loads per block, so a
+// fixed vmcnt wait is exact; padding loads read nothing (zero-size buffer) and
+// land in the sink.
+template <int MAXT>
+struct DmaPlan {
+  int kk[MAXT];            // row within the block (0 for padding)
+  uint32_t lds_off[MAXT];  // byte offset of the segment inside a ring slot
+  uint32_t voff[MAXT];     // this lane's byte offset inside the staged row
+  bool ok[MAXT];           // a real segment (wave-uniform)
+  bool lane_ok[MAXT];      // this lane's 16 bytes lie inside the row (always true for padding)
+};
+
 template <int NW, int CB, int MAXT>
-__device__ __forceinline__ void stage_bases(const FArgs &a, const int32_t *sb, int kb, int wave,
-                                            int32_t (&base)[MAXT]) {
-  const int segs = (a.row_bytes + 1023) >> 10;
+__device__ __forceinline__ DmaPlan<MAXT> dma_plan(int row_bytes, int row_stride, int wave, int lane) {
+  DmaPlan<MAXT> d;
+  const int segs = (row_bytes + 1023) >> 10;
 #pragma unroll
   for (int m = 0; m < MAXT; ++m) {
     const int s = wave + m * NW;
-    const int kk = s < CB * segs ? s / segs : 0;
-    const int k = __builtin_amdgcn_readfirstlane(min(kb + kk, a.n_rows - 1));
+    d.ok[m] = s < CB * segs;
+    const int kk = d.ok[m] ? s / segs : 0;
+    const int j0 = d.ok[m] ? (s - kk * segs) << 6 : 0;
+    d.kk[m] = kk;
+    d.lds_off[m] = (uint32_t)(kk * row_stride + 16 * j0);
+    d.voff[m] = 16u * (uint32_t)(j0 + lane);
+    d.lane_ok[m] = !d.ok[m] || 16 * (j0 + lane) < row_bytes;
+  }
+  return d;
+}
+
+// Stage bases of the rows this wave loads for block `kb` (first row); scalar
+// loads issued one block before stage_dma needs them.
+template <int MAXT>
+__device__ __forceinline__ void stage_bases(const FArgs &a, const int32_t *sb, int kb, const DmaPlan<MAXT> &d,
+                                            int32_t (&base)[MAXT]) {
+#pragma unroll
+  for (int m = 0; m < MAXT; ++m) {
+    const int k = __builtin_amdgcn_readfirstlane(min(kb + d.kk[m], a.n_rows - 1));
     base[m] = scalar_load(sb, k);
   }
 }
 
-template <int NW, int CB, int MAXT>
-__device__ __forceinline__ void stage_dma(const FArgs &a, const int32_t (&base_in)[MAXT], int64_t t0, int kb,
-                                          uint8_t *slot, uint8_t *sink, int wave, int lane) {
-  const int segs = (a.row_bytes + 1023) >> 10;
+// Issue this wave's loads of block `kb` into ring slot `slot` (rows `row_stride` apart).
+template <int MAXT>
+__device__ __forceinline__ void stage_dma(const FArgs &a, const DmaPlan<MAXT> &d, const int32_t (&base_in)[MAXT],
+                                          int64_t t0, int kb, uint8_t *slot, uint8_t *sink) {
+  const uint32_t slot_addr = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void_t *)slot);
+  const uint32_t sink_addr = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void_t *)sink);
 #pragma unroll
   for (int m = 0; m < MAXT; ++m) {
-    const int s = wave + m * NW;
-    const bool seg_ok = s < CB * segs;  // wave-uniform
-    const int kk = seg_ok ? s / segs : 0;
-    const int j0 = seg_ok ? (s - kk * segs) << 6 : 0;
-    const bool row_ok = seg_ok && kb + kk < a.n_rows;
-    const int k = __builtin_amdgcn_readfirstlane(min(kb + kk, a.n_rows - 1));
+    const bool row_ok = d.ok[m] && kb + d.kk[m] < a.n_rows;  // wave-uniform
+    const int k = __builtin_amdgcn_readfirstlane(min(kb + d.kk[m], a.n_rows - 1));
     const int32_t base = row_ok ? base_in[m] : 0;
     const v4i_t rs = make_rsrc(a.x + (int64_t)k * a.row_pitch, row_ok ? 4 * a.row_len : 0);
     // first staged float: time t0 + base (a multiple of 4, possibly negative for the adjoint:
     // the offset then wraps past the row and reads zeros)
-    const uint32_t row0 = 4u * (uint32_t)(t0 + base);
-    const int j = j0 + lane;
-    uint8_t *dst = seg_ok ? slot + kk * a.row_bytes + 16 * j0 : sink;
-    const uint32_t lds_addr =
-        __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(__attribute__((address_space(3))) void *)dst);
-    if (!seg_ok || 16 * j < a.row_bytes) dma16(rs, seg_ok ? row0 + 16u * (uint32_t)j : 0u, lds_addr);
+    const uint32_t voff = 4u * (uint32_t)(t0 + base) + d.voff[m];
+    const uint32_t lds_addr = d.ok[m] ? slot_addr + d.lds_off[m] : sink_addr;
+    if (d.lane_ok[m]) dma16(rs, voff, lds_addr);
   }
 }
 
@@ -149,7 +179,7 @@ template <int NS, int R, int NW, int CB>
 __device__ __forceinline__ void f32_tile(uint8_t *lds, const FArgs &a, int oblk, int tblk) {
   constexpr int RP = R < 2 ? 2 : R;
   constexpr int NOW = RP / 2;
-  constexpr int MAXT = (kStageSegs + NW - 1) / NW < kMaxSegsPerWave ? (kStageSegs + NW - 1) / NW : kMaxSegsPerWave;
+  constexpr int MAXT = max_loads_per_wave(kStageSegs, NW);
   static_assert(32 % CB == 0, "blocks must tile the groups of 32 rows");
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -167,13 +197,14 @@ __device__ __forceinline__ void f32_tile(uint8_t *lds, const FArgs &a, int oblk,
     for (int j = 0; j < NS; ++j) tot[r][j] = part[r][j] = 0.0f;
 
   uint8_t *sink = lds + kRing * slot_bytes;  // 1 KiB after the ring: target of the padding loads
+  const DmaPlan<MAXT> dp = dma_plan<NW, CB, MAXT>(a.row_bytes, a.row_bytes, wave, lane);
   int32_t bases[MAXT];
 #pragma unroll
   for (int k = 0; k < kRing - 1; ++k) {
-    stage_bases<NW, CB, MAXT>(a, sb, k * CB, wave, bases);
-    stage_dma<NW, CB, MAXT>(a, bases, t0, k * CB, lds + k * slot_bytes, sink, wave, lane);
+    stage_bases<MAXT>(a, sb, k * CB, dp, bases);
+    stage_dma<MAXT>(a, dp, bases, t0, k * CB, lds + k * slot_bytes, sink);
   }
-  stage_bases<NW, CB, MAXT>(a, sb, (kRing - 1) * CB, wave, bases);
+  stage_bases<MAXT>(a, sb, (kRing - 1) * CB, dp, bases);
   uint32_t ow[CB * NOW];  // offsets of block 0; each iteration fetches the next block's
 #pragma unroll
   for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, q);
@@ -184,8 +215,8 @@ __device__ __forceinline__ void f32_tile(uint8_t *lds, const FArgs &a, int oblk,
     // wave's have, and nobody reads the slot of block b-1 any more.
     wait_vmcnt<(kRing - 2) * MAXT>();
     lds_barrier();
-    stage_dma<NW, CB, MAXT>(a, bases, t0, (b + kRing - 1) * CB, lds + ((b + kRing - 1) % kRing) * slot_bytes, sink,
-                            wave, lane);  // zeros past the end
+    stage_dma<MAXT>(a, dp, bases, t0, (b + kRing - 1) * CB, lds + ((b + kRing - 1) % kRing) * slot_bytes,
+                    sink);  // zeros past the end
     const uint8_t *blk = lane_base + (b % kRing) * slot_bytes;
 #pragma unroll
     for (int kk = 0; kk < CB; ++kk) {
@@ -213,7 +244,7 @@ __device__ __forceinline__ void f32_tile(uint8_t *lds, const FArgs &a, int oblk,
     const int oi = __builtin_amdgcn_readfirstlane(min(b + 1, nblk - 1) * CB * NOW);
 #pragma unroll
     for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, oi + q);
-    stage_bases<NW, CB, MAXT>(a, sb, (b + kRing) * CB, wave, bases);
+    stage_bases<MAXT>(a, sb, (b + kRing) * CB, dp, bases);
   }
   wait_vmcnt<0>();
   lds_barrier();
