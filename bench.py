@@ -16,8 +16,11 @@ workload.
 from __future__ import annotations
 
 import argparse
+import glob
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -42,6 +45,32 @@ F32_FORM = "v_add_f32 (1 add per VALU lane-op)"
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def measured_traffic(workload, tiles):
+    """Memory traffic per launch from a committed rocprofv3 counter summary.
+
+    profiles/*_counters.md hold a ```traffic block (FETCH_SIZE + WRITE_SIZE per
+    launch, calibrated against a 1 GiB copy) with the workload, the tile choice
+    and the SHA-256 of the kernel source they were measured on.  The figure is
+    used only if all three match the run; otherwise the traffic is unknown (None).
+    """
+    want_tiles = "%d,%d" % (tiles["shape"], tiles["order"])
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_counters.md"))):
+        with open(path) as fh:
+            text = fh.read()
+        for block in re.findall(r"```traffic\n(.*?)```", text, re.S):
+            kv = dict(line.split(": ", 1) for line in block.strip().splitlines() if ": " in line)
+            if kv.get("workload") != workload or kv.get("tiles") != want_tiles:
+                continue
+            src = os.path.join(ROOT, kv.get("source", ""))
+            if not os.path.isfile(src):
+                continue
+            with open(src, "rb") as fh:
+                if hashlib.sha256(fh.read()).hexdigest() != kv.get("source_sha256"):
+                    continue
+            return int(kv["traffic_bytes_per_launch"]), os.path.relpath(path, ROOT)
+    return None, None
 
 
 def make_input(dd, torch, synth, cfg, plan):
@@ -327,6 +356,7 @@ def main():
     value = adds / (ms_step * 1e-3) / 1e12
     k_avg = float(np.mean(kernel_ms))
     achieved = adds / (k_avg * 1e-3) / 1e12
+    traffic, traffic_src = (None, None) if args.adjoint else measured_traffic(args.workload, tiles)
     log("steps: kernel ms %s, wall ms/step %.3f" % (["%.3f" % v for v in kernel_ms], ms_step))
     rec = {
         "metric": "Tadds/s" + (" (adjoint)" if args.adjoint else ""),
@@ -349,7 +379,8 @@ def main():
         "x_realtime": cfg["n_samp"] * cfg["t_samp"] / (ms_step * 1e-3),
         "x_realtime_streaming": plan.n_out * cfg["t_samp"] / (ms_step * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tadds/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic, "traffic_unit": "bytes per launch",
+                     "traffic_source": traffic_src,
                      "kernel": "fwd_int_kernel" if cfg["dtype"] != "f32" else "f32_kernel",
                      "kernel_ms": k_avg,
                      "instruction_form": INT_FORM if cfg["dtype"] != "f32" else F32_FORM,

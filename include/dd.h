@@ -92,7 +92,8 @@ typedef struct {
  * adjoint) per LDS stage. */
 typedef struct {
   int32_t shape;  /* index of a shape compiled into the library for the plan's dtype */
-  int32_t order;  /* workgroup order: 0 = time tiles fastest, 1 = each XCD takes whole time tiles */
+  int32_t order;  /* workgroup order: 0 = time tiles fastest, 1 = each XCD takes whole time tiles,
+                     2 = each XCD takes its time tiles for 4 output blocks at a time */
   int32_t ns, per_wave, waves, row_block; /* the shape (output of dd_plan_get_tiles) */
 } dd_tiles;
 
@@ -176,7 +177,7 @@ dd_status dd_execute_adjoint(const dd_plan *plan, const float *d_y, int64_t y_pi
  * dd_plan_shape_count: number of compiled shapes for the plan's dtype.
  * dd_plan_get_tiles: current choice for `direction`.
  * dd_plan_set_tiles: rebuild the plan's tables for compiled shape `shape` and
- *   workgroup order `order` (0 or 1).  DD_ERR_RANGE (plan unchanged) if the shape
+ *   workgroup order `order` (0, 1 or 2).  DD_ERR_RANGE (plan unchanged) if the shape
  *   cannot stage the plan's delay spread.  On success the plan is unbound:
  *   query dev_table_bytes again and call dd_plan_bind before executing.
  * dd_plan_autotune: time every (shape, order) that holds the plan's spread and

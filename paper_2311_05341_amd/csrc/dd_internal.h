@@ -33,7 +33,8 @@ struct TileCfg {
 enum TileOrder {
   kOrderTimeFirst = 0,  // consecutive workgroups take consecutive time tiles of one output block
   kOrderXcdTiles = 1,   // each XCD takes whole time tiles, every output block of a tile in turn
-  kNumOrders = 2
+  kOrderDmGroups = 2,   // each XCD takes its time tiles for 4 output blocks at a time (tile_order.h)
+  kNumOrders = 3
 };
 
 // Device tables of the integer forward kernel for one tile shape: per DM

@@ -33,13 +33,13 @@
 #include <stdint.h>
 
 #include "dd_internal.h"
+#include "tile_order.h"
 
 namespace dd {
 namespace {
 
 constexpr uint32_t kOddSel = 0x0C030C01u;
 constexpr int kBufferRsrcFlags = 0x00020000;  // raw (untyped) buffer access, word 3 of the descriptor
-constexpr int kXcdCount = 8;                   // MI355X: 8 accelerator complex dies, one L2 each
 
 // Read-only tables read with wave-uniform addresses go through the constant
 // address space, which the compiler always serves with scalar loads; a vector
@@ -423,37 +423,12 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
   }
 }
 
-// Workgroup -> tile map.  Workgroups are handed to the XCDs (each with its own
-// L2) round-robin by linear id, so workgroup w runs on XCD w % n_xcd.
-// n_xcd == 0: time tiles fastest (neighbouring tiles, whose staged rows
-// overlap by the delay spread, run at once on different XCDs).  Otherwise each
-// XCD is given whole time tiles (all DM blocks of tile x, x + n_xcd, ...), so
-// the workgroups resident on one XCD stage nearby input rows through its L2.
-// Tiles left over after the last full round go in tile order.
-__device__ __forceinline__ void tile_of(int w, int n_dblk, int n_tiles, int n_xcd, int &dblk, int &tblk) {
-  if (n_xcd == 0) {
-    tblk = w % n_tiles;
-    dblk = w / n_tiles;
-    return;
-  }
-  const int full = n_tiles / n_xcd * n_xcd;
-  if (w < n_dblk * full) {
-    const int x = w % n_xcd, k = w / n_xcd;
-    tblk = x + n_xcd * (k / n_dblk);
-    dblk = k % n_dblk;
-  } else {
-    const int r = w - n_dblk * full;
-    tblk = full + r / n_dblk;
-    dblk = r % n_dblk;
-  }
-}
-
 // One workgroup per tile; 1-D grid of n_dblk * n_tiles workgroups.
 template <int NS, int R, int NW, int CB, bool U4>
-__global__ __launch_bounds__(NW * 64) void fwd_int_kernel(IntArgs a, int n_dblk, int n_tiles, int n_xcd) {
+__global__ __launch_bounds__(NW * 64) void fwd_int_kernel(IntArgs a, int n_dblk, int n_tiles, int order) {
   extern __shared__ __align__(16) uint8_t lds[];
   int dblk, tblk;
-  tile_of(blockIdx.x, n_dblk, n_tiles, n_xcd, dblk, tblk);
+  tile_of(blockIdx.x, n_dblk, n_tiles, order, dblk, tblk);
   fwd_int_tile<NS, R, NW, CB, U4>(lds, a, dblk, tblk);
 }
 
@@ -535,17 +510,16 @@ int launch_int_shape(const dd_plan &p, const void *d_in, float *d_out, int64_t o
   const int64_t n_dblk = (p.desc.n_dm + NW * R - 1) / (NW * R);
   if (tiles_t * n_dblk >= ((int64_t)1 << 31)) return (int)hipErrorInvalidConfiguration;
   dim3 grid((unsigned)(tiles_t * n_dblk));
-  const int n_xcd = t.order == kOrderXcdTiles ? kXcdCount : 0;
   const void *fn = p.desc.dtype == DD_U4 ? (const void *)fwd_int_kernel<NS, R, NW, CB, true>
                                          : (const void *)fwd_int_kernel<NS, R, NW, CB, false>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, t.lds_bytes);
   if (e != hipSuccess) return (int)e;
   if (p.desc.dtype == DD_U4)
     hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, true>), grid, dim3(NW * 64), t.lds_bytes, st, a, (int)n_dblk,
-                       (int)tiles_t, n_xcd);
+                       (int)tiles_t, t.order);
   else
     hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, false>), grid, dim3(NW * 64), t.lds_bytes, st, a, (int)n_dblk,
-                       (int)tiles_t, n_xcd);
+                       (int)tiles_t, t.order);
   return (int)hipGetLastError();
 }
 

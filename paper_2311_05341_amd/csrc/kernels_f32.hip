@@ -24,12 +24,12 @@
 #include <stdint.h>
 
 #include "dd_internal.h"
+#include "tile_order.h"
 
 namespace dd {
 namespace {
 
 constexpr int kBufferRsrcFlags = 0x00020000;  // raw (untyped) buffer access, word 3 of the descriptor
-constexpr int kXcdCount = 8;                   // MI355X: 8 accelerator complex dies, one L2 each
 constexpr int kRing = 3;
 // Load segments (1 KiB each) per block: at most min(kStageSegs, kMaxSegsPerWave * NW),
 // checked on the host.  A wave has at most (kRing - 1) * kMaxSegsPerWave loads in flight.
@@ -76,27 +76,6 @@ template <int N>
 __device__ __forceinline__ void wait_vmcnt() {
   static_assert(N >= 0 && N < 64, "vmcnt range");
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
-}
-
-// Workgroup w -> (output block, time tile).  n_xcd == 0: time tiles fastest.
-// Otherwise the XCD w % n_xcd takes whole time tiles (x, x + n_xcd, ...),
-// all output blocks of one tile in turn; leftover tiles go in tile order.
-__device__ __forceinline__ void tile_of(int w, int n_oblk, int n_tiles, int n_xcd, int &oblk, int &tblk) {
-  if (n_xcd == 0) {
-    tblk = w % n_tiles;
-    oblk = w / n_tiles;
-    return;
-  }
-  const int full = n_tiles / n_xcd * n_xcd;
-  if (w < n_oblk * full) {
-    const int x = w % n_xcd, k = w / n_xcd;
-    tblk = x + n_xcd * (k / n_oblk);
-    oblk = k % n_oblk;
-  } else {
-    const int r = w - n_oblk * full;
-    tblk = full + r / n_oblk;
-    oblk = r % n_oblk;
-  }
 }
 
 struct FArgs {
@@ -265,10 +244,10 @@ __device__ __forceinline__ void f32_tile(uint8_t *lds, const FArgs &a, int oblk,
 }
 
 template <int NS, int R, int NW, int CB>
-__global__ __launch_bounds__(NW * 64) void f32_kernel(FArgs a, int n_oblk, int n_tiles, int n_xcd) {
+__global__ __launch_bounds__(NW * 64) void f32_kernel(FArgs a, int n_oblk, int n_tiles, int order) {
   extern __shared__ __align__(16) uint8_t lds[];
   int oblk, tblk;
-  tile_of(blockIdx.x, n_oblk, n_tiles, n_xcd, oblk, tblk);
+  tile_of(blockIdx.x, n_oblk, n_tiles, order, oblk, tblk);
   f32_tile<NS, R, NW, CB>(lds, a, oblk, tblk);
 }
 
@@ -276,7 +255,7 @@ __global__ __launch_bounds__(NW * 64) void f32_kernel(FArgs a, int n_oblk, int n
   X(16, 2, 16, 8) X(16, 2, 16, 4) X(16, 1, 16, 4) X(16, 1, 16, 2) X(16, 1, 16, 1) X(16, 1, 4, 1) X(16, 1, 1, 1)
 
 template <int NS, int R, int NW, int CB>
-int launch_f32_shape(const FArgs &a, int lds_bytes, int n_xcd, hipStream_t st) {
+int launch_f32_shape(const FArgs &a, int lds_bytes, int order, hipStream_t st) {
   const int64_t tiles = (a.out_len + 64 * NS - 1) / (64 * NS);
   const int64_t n_oblk = (a.n_outputs + NW * R - 1) / (NW * R);
   if (tiles * n_oblk >= ((int64_t)1 << 31)) return (int)hipErrorInvalidConfiguration;
@@ -284,16 +263,15 @@ int launch_f32_shape(const FArgs &a, int lds_bytes, int n_xcd, hipStream_t st) {
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds_bytes);
   if (e != hipSuccess) return (int)e;
   hipLaunchKernelGGL((f32_kernel<NS, R, NW, CB>), dim3((unsigned)(tiles * n_oblk)), dim3(NW * 64), lds_bytes, st, a,
-                     (int)n_oblk, (int)tiles, n_xcd);
+                     (int)n_oblk, (int)tiles, order);
   return (int)hipGetLastError();
 }
 
 int launch_f32(const FloatTables &t, FArgs a, int64_t out_limit, hipStream_t st) {
   if (out_limit > 0 && out_limit < a.out_len) a.out_len = (int32_t)out_limit;
-  const int n_xcd = t.order == kOrderXcdTiles ? kXcdCount : 0;
 #define DD_TRY(NS, R, NW, CB)                                               \
   if (t.ns == NS && t.per_wave == R && t.waves == NW && t.row_block == CB) \
-    return launch_f32_shape<NS, R, NW, CB>(a, t.lds_bytes, n_xcd, st);
+    return launch_f32_shape<NS, R, NW, CB>(a, t.lds_bytes, t.order, st);
   DD_F32_SHAPES(DD_TRY)
 #undef DD_TRY
   return (int)hipErrorInvalidValue;

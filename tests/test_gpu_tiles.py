@@ -34,7 +34,7 @@ def _case(dtype):
 def _choices(dd, plan, direction):
     out = []
     for s in range(plan.n_shapes):
-        for o in (0, 1):
+        for o in (0, 1, 2):
             try:
                 plan.set_tiles(direction, s, o)
             except dd.DDError as e:

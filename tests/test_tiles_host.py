@@ -43,7 +43,7 @@ def test_every_shape_feasible_or_refused(dd, name):
     for direction in dirs:
         ok = 0
         for s in range(p.n_shapes):
-            for o in (0, 1):
+            for o in (0, 1, 2):
                 before = p.tiles(direction)
                 try:
                     p.set_tiles(direction, s, o)
@@ -68,14 +68,14 @@ def test_tiles_argument_errors(dd):
     assert _status(dd, lambda: p.set_tiles(1, 0, 0)) == "DD_ERR_DTYPE"
     assert _status(dd, lambda: p.set_tiles(0, p.n_shapes, 0)) == "DD_ERR_ARG"
     assert _status(dd, lambda: p.set_tiles(0, -1, 0)) == "DD_ERR_ARG"
-    assert _status(dd, lambda: p.set_tiles(0, 0, 2)) == "DD_ERR_ARG"
+    assert _status(dd, lambda: p.set_tiles(0, 0, 3)) == "DD_ERR_ARG"
 
 
-def test_default_tiles_time_first(dd):
+def test_default_tiles_grouped_order(dd):
     for name in ["small", "headline", "lowfreq_u4", "grad_f32"]:
         p = _plan(dd, synth.CONFIGS[name])
-        assert p.tiles(0)["order"] == 0
-        assert p.info.kernel_order == 0
+        assert p.tiles(0)["order"] == 2
+        assert p.info.kernel_order == 2
 
 
 _KEY_FMT = (b"dtype=%d,nchan=%d,nsamp=%lld,fhigh=%a,bw=%a,freqs=%016llx,tsamp=%a,dm0=%a,dmstep=%a,ndm=%d,"
@@ -119,14 +119,14 @@ def test_tune_cache_applied(dd, tmp_path, monkeypatch):
     # a line whose shape parameters disagree with the compiled shape is ignored
     path.write_text("dd-tune-v1 %s %d 1 %d %s 1.0\n" % (key, shape, t["ns"] + 1, params.split(" ", 1)[1]))
     p = _plan(dd, cfg)
-    assert p.tiles(0)["order"] == 0
+    assert p.tiles(0)["order"] == 2
     # a different plan does not pick up the line
     path.write_text("dd-tune-v1 %s %d 1 %s 1.0\n" % (key, shape, params))
     p = _plan(dd, cfg, n_dm=cfg["n_dm"] - 1)
-    assert p.tiles(0)["order"] == 0
+    assert p.tiles(0)["order"] == 2
     monkeypatch.delenv("DD_TUNE_CACHE")
     p = _plan(dd, cfg)
-    assert p.tiles(0)["order"] == 0
+    assert p.tiles(0)["order"] == 2
 
 
 @pytest.mark.parametrize("dtype,n_chunks", [("u8", 1), ("u8", 3), ("u4", 4), ("f32", 5)])
