@@ -71,6 +71,12 @@ static inline int64_t x_u4(const uint8_t *x, int64_t pitch_bytes, int c, int64_t
   return (t & 1) ? (b >> 4) : (b & 15);
 }
 
+/* 16-bit: little-endian unsigned samples, two bytes each (pitch in bytes). */
+static inline int64_t x_u16(const uint8_t *x, int64_t pitch_bytes, int c, int64_t t) {
+  const uint8_t *p = x + (int64_t)c * pitch_bytes + 2 * t;
+  return (int64_t)p[0] | ((int64_t)p[1] << 8);
+}
+
 /* Every read x(c, t + shift) with t < n_out must stay inside [0, n_samp). */
 static int shifts_in_range(const int32_t *shift, int n_chan, int n_dm, int64_t n_samp,
                            int64_t n_out) {
@@ -83,13 +89,14 @@ static int shifts_in_range(const int32_t *shift, int n_chan, int n_dm, int64_t n
 /*
  * Forward transform on a set of DM rows.  rows == NULL means all n_rows = n_dm
  * rows in order; otherwise out row r holds DM row rows[r].  out is
- * [n_rows][n_out] float.  dtype: 1 = u8, 2 = u4 (pitch in bytes), 3 = f32
- * (use oracle_forward_f32 instead).
+ * [n_rows][n_out] float, each int64 sum converted once to float (round to
+ * nearest even; exact below 2^24).  dtype: 1 = u8, 2 = u4 (pitch in bytes),
+ * 4 = u16 (pitch in bytes); 3 = f32 uses oracle_forward_f32 instead.
  */
 int oracle_forward_int(int dtype, const uint8_t *x, int64_t pitch, int n_chan, int64_t n_samp,
                        const int32_t *shift, int n_dm, int64_t n_out,
                        const int32_t *rows, int n_rows, float *out) {
-  if (dtype != 1 && dtype != 2) return -1;
+  if (dtype != 1 && dtype != 2 && dtype != 4) return -1;
   if (!shifts_in_range(shift, n_chan, n_dm, n_samp, n_out)) return -1;
   int bad = 0;
 #pragma omp parallel
@@ -113,8 +120,10 @@ int oracle_forward_int(int dtype, const uint8_t *x, int64_t pitch, int n_chan, i
         int64_t s = shift[(int64_t)d * n_chan + c];
         if (dtype == 1) {
           for (int64_t t = 0; t < n_out; ++t) acc[t] += x_u8(x, pitch, c, t + s);
-        } else {
+        } else if (dtype == 2) {
           for (int64_t t = 0; t < n_out; ++t) acc[t] += x_u4(x, pitch, c, t + s);
+        } else {
+          for (int64_t t = 0; t < n_out; ++t) acc[t] += x_u16(x, pitch, c, t + s);
         }
       }
       for (int64_t t = 0; t < n_out; ++t) out[(int64_t)r * n_out + t] = (float)acc[t];

@@ -120,16 +120,22 @@ def forward(x: np.ndarray, dtype: str, n_samp: int, shift: np.ndarray, rows=None
     """Forward transform of integer input; float32 [len(rows)][n_out].
 
     x is uint8 [n_chan][pitch]; for dtype "u4" the pitch is in bytes and holds
-    two samples per byte, the even sample in the low nibble.
+    two samples per byte, the even sample in the low nibble.  For dtype "u16"
+    x is uint16 [n_chan][pitch] (little-endian samples).
     """
     lib = _load()
-    assert x.dtype == np.uint8 and x.ndim == 2 and x.flags.c_contiguous
+    assert x.ndim == 2 and x.flags.c_contiguous
     n_dm, n_chan = shift.shape
     assert x.shape[0] == n_chan
-    code = {"u8": 1, "u4": 2}[dtype]
+    code = {"u8": 1, "u4": 2, "u16": 4}[dtype]
+    if code == 4:
+        assert x.dtype == np.uint16 and x.shape[1] >= n_samp
+        x = x.astype("<u2", copy=False).view(np.uint8)
+    else:
+        assert x.dtype == np.uint8
     if code == 1:
         assert x.shape[1] >= n_samp
-    else:
+    elif code == 2:
         assert n_samp % 2 == 0 and x.shape[1] >= n_samp // 2
     n_out = n_out_for(shift, n_samp)
     r, nr = _rows_arg(rows, n_dm)

@@ -148,6 +148,10 @@ def _tiny_case(rng, dtype):
         x[:, 3::11] = 255
     elif dtype == "u4":
         x = rng.integers(0, 16, (n_chan, n_samp)).astype(np.uint8)
+    elif dtype == "u16":
+        x = rng.integers(0, 65536, (n_chan, n_samp)).astype(np.uint16)
+        x[:, ::7] = 0
+        x[:, 3::11] = 65535
     else:
         x = rng.standard_normal((n_chan, n_samp)).astype(np.float32)
         x[:, ::5] = 0.0
@@ -159,10 +163,10 @@ def _pack_u4(v):
     return (v[:, 0::2] | (v[:, 1::2] << 4)).astype(np.uint8)
 
 
-@pytest.mark.parametrize("dtype", ["u8", "u4", "f32"])
+@pytest.mark.parametrize("dtype", ["u8", "u4", "u16", "f32"])
 def test_forward_equals_literal_eq3(dtype):
     """Brute-force Eq. 3 (oracle/eq3_literal.py, independent code) on tiny random inputs."""
-    rng = np.random.default_rng({"u8": 11, "u4": 12, "f32": 13}[dtype])
+    rng = np.random.default_rng({"u8": 11, "u4": 12, "f32": 13, "u16": 14}[dtype])
     for _ in range(12):
         k = _tiny_case(rng, dtype)
         dms = [k["start"] + d * k["step"] for d in range(k["n_dm"])]
@@ -179,6 +183,9 @@ def test_forward_equals_literal_eq3(dtype):
             assert got.tolist() == ref
         elif dtype == "u4":
             got = oracle.forward(_pack_u4(k["x"]), "u4", k["n_samp"], s)
+            assert got.tolist() == ref
+        elif dtype == "u16":  # at most 8 channels: every sum is below 2^24, so float32 is exact
+            got = oracle.forward(k["x"], "u16", k["n_samp"], s)
             assert got.tolist() == ref
         else:
             got, _ = oracle.forward_f32(k["x"], k["n_samp"], s)
@@ -275,6 +282,40 @@ def test_forward_u4_equals_u8_equals_f32():
     c, _ = oracle.forward_f32(unpacked.astype(np.float32), n_samp, s)
     assert np.array_equal(a, b)
     assert np.array_equal(a.astype(np.float64), c)
+
+
+def test_forward_u16_small_values_equal_u8():
+    """16-bit samples below 256 give exactly the 8-bit result."""
+    cfg, s, x = _small()
+    a = oracle.forward(x, "u8", cfg["n_samp"], s, rows=[0, 7, 100, 255])
+    b = oracle.forward(x.astype(np.uint16), "u16", cfg["n_samp"], s, rows=[0, 7, 100, 255])
+    assert np.array_equal(a, b)
+
+
+def test_forward_u16_little_endian_samples():
+    """A 16-bit sample is its low byte plus 256 times its high byte (little-endian)."""
+    raw = np.zeros((1, 2 * 64), dtype=np.uint8)
+    raw[0, 2 * 5], raw[0, 2 * 5 + 1] = 0x01, 0x02  # sample 5 = 0x0201 = 513
+    raw[0, 2 * 9 + 1] = 0xFF                         # sample 9 = 0xFF00 = 65280
+    x = raw.view("<u2")
+    s = np.zeros((1, 1), dtype=np.int32)  # one channel, one DM, no delay
+    out = oracle.forward(np.ascontiguousarray(x), "u16", 64, s)
+    want = np.zeros(64, dtype=np.float32)
+    want[5], want[9] = 513.0, 65280.0
+    assert np.array_equal(out[0], want)
+
+
+def test_forward_u16_sums_round_to_float32_nearest_even():
+    """Sums above 2^24 are converted once to float32, rounding to nearest even."""
+    n_chan, n_samp = 257, 32
+    x = np.full((n_chan, n_samp), 65535, dtype=np.uint16)
+    x[256, :] = 257                      # 256 * 65535 + 257 = 2^24 + 1, halfway between two floats
+    x[256, 1] = 258                      # 2^24 + 2 is a float32
+    x[256, 2] = 259                      # 2^24 + 3 rounds up to 2^24 + 4 (even mantissa)
+    s = np.zeros((1, n_chan), dtype=np.int32)
+    out = oracle.forward(x, "u16", n_samp, s)[0]
+    assert out[0] == np.float32(2 ** 24) and out[1] == np.float32(2 ** 24 + 2) and out[2] == np.float32(2 ** 24 + 4)
+    assert 256 * 65535 + 257 == 2 ** 24 + 1
 
 
 def _dense_matrix(s, n_samp):

@@ -27,6 +27,9 @@ MUTANTS = {
     "adjoint reads transposed table": ("int64_t s = shift[(int64_t)d * n_chan + c];\n      const float *yr", "int64_t s = shift[(int64_t)c * n_dm + d];\n      const float *yr"),
     "adjoint delays the wrong way": ("gr[t + s] += (double)yr[t];", "gr[t + (n_samp - n_out - s)] += (double)yr[t];"),
     "f32 forward drops last channel": ("for (int c = 0; c < n_chan; ++c) {\n      const float *row", "for (int c = 0; c < n_chan - 1; ++c) {\n      const float *row"),
+    "16-bit bytes swapped": ("return (int64_t)p[0] | ((int64_t)p[1] << 8);", "return (int64_t)p[1] | ((int64_t)p[0] << 8);"),
+    "16-bit sample stride of one byte": ("const uint8_t *p = x + (int64_t)c * pitch_bytes + 2 * t;", "const uint8_t *p = x + (int64_t)c * pitch_bytes + t;"),
+    "16-bit high byte dropped": ("return (int64_t)p[0] | ((int64_t)p[1] << 8);", "return (int64_t)p[0];"),
     "normalised by channel count": ("out[(int64_t)r * n_out + t] = (float)acc[t];", "out[(int64_t)r * n_out + t] = (float)(acc[t] / n_chan);"),
 }
 
@@ -40,6 +43,9 @@ PIN_CALLS = [
     ("literal u8", pins.test_forward_equals_literal_eq3, ("u8",)),
     ("literal u4", pins.test_forward_equals_literal_eq3, ("u4",)),
     ("literal f32", pins.test_forward_equals_literal_eq3, ("f32",)),
+    ("literal u16", pins.test_forward_equals_literal_eq3, ("u16",)),
+    ("u16 little-endian", pins.test_forward_u16_little_endian_samples, ()),
+    ("u16 == u8", pins.test_forward_u16_small_values_equal_u8, ()),
     ("dm0", pins.test_forward_dm0_is_channel_sum, ()),
     ("pulse", pins.test_forward_injected_pulse, ()),
     ("u4 == u8 == f32", pins.test_forward_u4_equals_u8_equals_f32, ()),
