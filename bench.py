@@ -10,7 +10,7 @@ x-real-time factor (N_t * t_samp / t_step), the VALU roofline fraction of the
 forward kernel, and the CPU oracle timed on a bounded sample of the same
 workload.
 
-  python bench.py [--steps K] [--warmup W] [--workload headline|lowfreq_u4|grad_f32|small|batch48]
+  python bench.py [--steps K] [--warmup W] [--workload headline|lowfreq_u4|headline_u16|grad_f32|small|batch48]
                   [--adjoint] [--no-cpu-baseline] [--no-autotune]
 """
 from __future__ import annotations
@@ -35,12 +35,14 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
 # LDS bytes the accumulate loop reads per add: one byte per 8- or 4-bit sample
 # (4-bit samples are unpacked to bytes when staged), four per float.
-LDS_BYTES_PER_ADD = {"u8": 1, "u4": 1, "f32": 4}
+LDS_BYTES_PER_ADD = {"u8": 1, "u4": 1, "u16": 2, "f32": 4}
 # The integer kernels add four 8-bit samples per 32-bit word and two channels per
 # v_add3_u32 (one v_perm_b32 + one v_add3_u32 per two channel-words for each of
 # the even/odd byte lanes): 8 sample-adds per 4 VALU ops, so twice the one-add-per-lane peak.
 INT_FORM = "SWAR bytes in 32-bit words, v_perm_b32 + v_add3_u32 (2 sample-adds per VALU lane-op)"
 F32_FORM = "v_add_f32 (1 add per VALU lane-op)"
+U16_FORM = "two 16-bit samples per word, one SDWA v_add_u32 per sample (1 sample-add per VALU lane-op)"
+FORMS = {"u8": (INT_FORM, 2), "u4": (INT_FORM, 2), "u16": (U16_FORM, 1), "f32": (F32_FORM, 1)}
 
 
 def log(msg):
@@ -92,6 +94,18 @@ def make_input(dd, torch, synth, cfg, plan):
     elif cfg["dtype"] == "u4":
         x = torch.empty((n_chan, plan.in_pitch_bytes), dtype=torch.uint8, device="cuda")
         synth.uniform_u4_device(x.data_ptr(), n_chan, n_samp, plan.in_pitch_bytes, cfg["seed"], stream)
+    elif cfg["dtype"] == "u16":
+        pitch = plan.in_pitch_bytes // 2
+        x = torch.empty((n_chan, pitch), dtype=torch.uint16, device="cuda")
+        table = torch.from_numpy(synth.gaussian_table16()).cuda()
+        synth.gaussian_u16_device(x.data_ptr(), n_chan, n_samp, pitch, cfg["seed"], table.data_ptr(), stream)
+        shift = plan.shift
+        xi = x.view(torch.int16)  # torch has no uint16 gather/scatter on the GPU; same bytes as int16
+        for dp, width, t0 in cfg.get("pulses", []):
+            def at(r, c):
+                return xi[torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda()].cpu().numpy().view(np.uint16)
+            rows, cols, vals, _ = synth.boxcar_updates(at, shift[dp], t0, width, cfg["amp"], 65535)
+            xi[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()] = torch.from_numpy(vals.view(np.int16)).cuda()
     else:
         x = torch.from_numpy(synth.normal_f32(cfg["n_chan"], n_samp, cfg["seed"])).cuda()
     torch.cuda.synchronize()
@@ -112,6 +126,9 @@ def cpu_baseline(cfg, seconds_target=15.0):
     elif cfg["dtype"] == "u4":
         x = synth.uniform_u4_packed(cfg["n_chan"], cfg["n_samp"], cfg["seed"])
         run = lambda rows: oracle.forward(x, "u4", cfg["n_samp"], s, rows=rows)  # noqa: E731
+    elif cfg["dtype"] == "u16":
+        x = synth.gaussian_u16(cfg["n_chan"], cfg["n_samp"], cfg["seed"])
+        run = lambda rows: oracle.forward(x, "u16", cfg["n_samp"], s, rows=rows)  # noqa: E731
     else:
         x = synth.normal_f32(cfg["n_chan"], cfg["n_samp"], cfg["seed"])
         run = lambda rows: oracle.forward_f32(x, cfg["n_samp"], s, rows=rows, with_abs=False)  # noqa: E731
@@ -369,7 +386,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"u8": "u8", "u4": "u4", "f32": "f32"}[cfg["dtype"]],
+        "dtype": cfg["dtype"],
         "data": "synthetic",
         "config": {"workload": args.workload, "n_chan": cfg["n_chan"], "n_samp": cfg["n_samp"],
                    "n_dm": cfg["n_dm"], "dm_step": cfg["dm_step"], "t_samp_s": cfg["t_samp"],
@@ -383,9 +400,9 @@ def main():
                      "traffic_source": traffic_src,
                      "kernel": "fwd_int_kernel" if cfg["dtype"] != "f32" else "f32_kernel",
                      "kernel_ms": k_avg,
-                     "instruction_form": INT_FORM if cfg["dtype"] != "f32" else F32_FORM,
-                     "peak_instruction_form": VALU_PEAK_TOPS * (2 if cfg["dtype"] != "f32" else 1),
-                     "frac_instruction_form": achieved / (VALU_PEAK_TOPS * (2 if cfg["dtype"] != "f32" else 1))},
+                     "instruction_form": FORMS[cfg["dtype"]][0],
+                     "peak_instruction_form": VALU_PEAK_TOPS * FORMS[cfg["dtype"]][1],
+                     "frac_instruction_form": achieved / (VALU_PEAK_TOPS * FORMS[cfg["dtype"]][1])},
         "lds_roofline": {"achieved": achieved * LDS_BYTES_PER_ADD[cfg["dtype"]], "peak": LDS_PEAK_TBS,
                          "unit": "TB/s", "frac": achieved * LDS_BYTES_PER_ADD[cfg["dtype"]] / LDS_PEAK_TBS,
                          "bytes_per_add": LDS_BYTES_PER_ADD[cfg["dtype"]]},

@@ -53,8 +53,9 @@ typedef enum {
 } dd_status;
 
 /* Input sample encodings.  DD_U4 holds two samples per byte, the even time
- * sample in the low nibble. */
-typedef enum { DD_U8 = 1, DD_U4 = 2, DD_F32 = 3 } dd_dtype;
+ * sample in the low nibble.  DD_U16 holds unsigned 16-bit samples, low byte
+ * first (the paper's three integer precisions, Sec. 5). */
+typedef enum { DD_U8 = 1, DD_U4 = 2, DD_F32 = 3, DD_U16 = 4 } dd_dtype;
 
 /* Plan description (Sec. 2 problem statement; fixed-step DM plan of Sec. 5.1). */
 typedef struct {
@@ -136,12 +137,15 @@ dd_status dd_plan_bind(dd_plan *plan, void *d_workspace, size_t bytes, void *str
 /*
  * Forward transform (Eq. 3 / Algorithm 1) on `stream`.
  *   d_in   device pointer, [n_chan] rows of in_pitch_bytes; row c holds x(c, 0..n_samp-1)
- *          as uint8, packed uint4 or float32 per the plan's dtype.  16-byte aligned.
+ *          as uint8, packed uint4, uint16 or float32 per the plan's dtype.  16-byte aligned.
  *   d_out  device pointer, float32 [n_dm][out_pitch]; row d, columns 0..n_out-1 receive
  *          S(d, t).  Columns >= n_out are not written.  16-byte aligned.
  *   out_pitch  elements between output rows, >= n_out, multiple of 4.
- * Integer inputs accumulate exactly in int32 and are converted once to float32
- * (exact: every sum is below 2^24 for n_chan <= 65793).  Float input
+ * Integer inputs accumulate exactly in 32-bit integers and are converted once
+ * to float32: exact for 8- and 4-bit input (every sum is below 2^24 for
+ * n_chan <= 65793 resp. 1118481); 16-bit sums (n_chan <= 65537) are exact
+ * below 2^24 and rounded to nearest even above, as the conversion of the exact
+ * sum would be.  Float input
  * accumulates in float32 in a fixed order: channels in groups of 32 summed in
  * order, then the group sums in order; the result does not depend on the tile shape.
  * Errors: DD_ERR_ARG, DD_ERR_ALIGN, DD_ERR_NOT_BOUND, DD_ERR_HIP.
@@ -212,8 +216,8 @@ dd_status dd_plan_autotune(dd_plan *plan, int32_t direction, const void *d_src, 
  * items first.  The launch sequence is recorded once as a HIP graph and
  * replayed by every dd_execute_batched call.
  *
- * dd_batch_create: plans[0..n-1] must be DD_U8 or DD_U4 plans and outlive the
- *   batch.  Errors: DD_ERR_ARG, DD_ERR_DTYPE, DD_ERR_NOMEM.
+ * dd_batch_create: plans[0..n-1] must be integer plans (DD_U8, DD_U4 or DD_U16),
+ *   all of one dtype, and outlive the batch.  Errors: DD_ERR_ARG, DD_ERR_DTYPE, DD_ERR_NOMEM.
  * dd_batch_workspace_bytes: device workspace dd_batch_bind needs.
  * dd_batch_bind: d_in[b], d_out[b], out_pitch[b] as for dd_execute of plan b;
  *   d_workspace holds the work list, descriptors, the beams' tables and the

@@ -6,6 +6,7 @@ binding (ctypes + torch device memory and streams).
 """
 from .binding import (  # noqa: F401
     DD_F32,
+    DD_U16,
     DD_U4,
     DD_U8,
     LIB_PATH,

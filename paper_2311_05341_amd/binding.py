@@ -21,8 +21,10 @@ if not os.path.exists(LIB_PATH):
 
 _lib = ctypes.CDLL(LIB_PATH)
 
-DD_U8, DD_U4, DD_F32 = 1, 2, 3
-_DTYPES = {"u8": DD_U8, "u4": DD_U4, "f32": DD_F32}
+DD_U8, DD_U4, DD_F32, DD_U16 = 1, 2, 3, 4
+_DTYPES = {"u8": DD_U8, "u4": DD_U4, "f32": DD_F32, "u16": DD_U16}
+# torch element type and bytes per element of an input row, per dtype
+_IN_TORCH = {"u8": (torch.uint8, 1), "u4": (torch.uint8, 1), "u16": (torch.uint16, 2), "f32": (torch.float32, 4)}
 STATUS = {0: "DD_OK", -1: "DD_ERR_ARG", -2: "DD_ERR_TOO_SHORT", -3: "DD_ERR_RANGE", -4: "DD_ERR_ALIGN",
           -5: "DD_ERR_DTYPE", -6: "DD_ERR_NOT_BOUND", -7: "DD_ERR_HIP", -8: "DD_ERR_NOMEM"}
 
@@ -213,14 +215,14 @@ class Plan:
 
     @property
     def in_row_elems(self) -> int:
-        return self.in_pitch_bytes // (4 if self.dtype == "f32" else 1)
+        return self.in_pitch_bytes // _IN_TORCH[self.dtype][1]
 
     def empty_input(self):
-        dt = torch.float32 if self.dtype == "f32" else torch.uint8
+        dt = _IN_TORCH[self.dtype][0]
         return torch.empty((self.n_chan, self.in_row_elems), dtype=dt, device=self.device)
 
     def _check_input(self, x):
-        dt = torch.float32 if self.dtype == "f32" else torch.uint8
+        dt = _IN_TORCH[self.dtype][0]
         if x.dtype != dt or x.device != self.device or x.dim() != 2 or x.shape[0] != self.n_chan:
             raise ValueError("input must be %s [n_chan][...] on %s" % (dt, self.device))
         if x.stride(1) != 1 or x.stride(0) * x.element_size() != self.in_pitch_bytes:

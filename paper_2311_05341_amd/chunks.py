@@ -12,7 +12,7 @@ from __future__ import annotations
 
 from .binding import Plan
 
-_UNIT = {"u8": 16, "u4": 32, "f32": 4}  # samples per 16 bytes: chunk starts stay 16-byte aligned
+_UNIT = {"u8": 16, "u4": 32, "u16": 8, "f32": 4}  # samples per 16 bytes: chunk starts stay 16-byte aligned
 
 
 class TimeChunks:

@@ -26,6 +26,7 @@ static bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 static int64_t packed_row_bytes(int dtype, int64_t n_samp) {
   if (dtype == DD_U4) return n_samp / 2;
+  if (dtype == DD_U16) return n_samp * 2;
   if (dtype == DD_F32) return n_samp * 4;
   return n_samp;
 }
@@ -79,7 +80,8 @@ dd_status dd_plan_create(const dd_plan_desc *desc, dd_plan **out) {
   *out = nullptr;
   const dd_plan_desc &d = *desc;
   if (d.n_chan <= 0 || d.n_dm <= 0 || d.n_samp <= 0) return fail(DD_ERR_ARG, "n_chan, n_dm and n_samp must be positive");
-  if (d.dtype != DD_U8 && d.dtype != DD_U4 && d.dtype != DD_F32) return fail(DD_ERR_ARG, "unknown dtype");
+  if (d.dtype != DD_U8 && d.dtype != DD_U4 && d.dtype != DD_U16 && d.dtype != DD_F32)
+    return fail(DD_ERR_ARG, "unknown dtype");
   if (d.dtype == DD_U4 && (d.n_samp & 1)) return fail(DD_ERR_ARG, "n_samp must be even for 4-bit input");
   if (!(d.t_samp_s > 0.0) || !isfinite(d.t_samp_s)) return fail(DD_ERR_ARG, "t_samp must be positive");
   if (!(d.f_high_mhz > 0.0) || !isfinite(d.f_high_mhz)) return fail(DD_ERR_RANGE, "f_high must be positive");
@@ -90,6 +92,8 @@ dd_status dd_plan_create(const dd_plan_desc *desc, dd_plan **out) {
   // Exactness of int32 accumulation and float output: every sum below 2^24.
   if (d.dtype == DD_U8 && d.n_chan > 65793) return fail(DD_ERR_RANGE, "more than 65793 8-bit channels cannot be summed exactly in float32");
   if (d.dtype == DD_U4 && d.n_chan > 1118481) return fail(DD_ERR_RANGE, "too many 4-bit channels for exact float32 output");
+  // 16-bit: the per-sample 32-bit totals must not wrap: 65535 * n_chan < 2^32.
+  if (d.dtype == DD_U16 && d.n_chan > 65537) return fail(DD_ERR_RANGE, "more than 65537 16-bit channels overflow 32-bit sums");
   const int64_t row = packed_row_bytes(d.dtype, d.n_samp);
   const int64_t pitch = d.in_pitch_bytes ? d.in_pitch_bytes : row;
   if (pitch < row) return fail(DD_ERR_ARG, "in_pitch_bytes smaller than one row");

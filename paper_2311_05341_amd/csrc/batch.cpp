@@ -52,9 +52,9 @@ dd_status dd_batch_create(const dd_plan *const *plans, int32_t n, dd_batch **out
   b->dtype = plans[0] ? plans[0]->desc.dtype : 0;
   for (int i = 0; i < n; ++i) {
     if (!plans[i]) { delete b; return fail(DD_ERR_ARG, "null plan in batch"); }
-    if (plans[i]->desc.dtype != DD_U8 && plans[i]->desc.dtype != DD_U4) {
+    if (plans[i]->desc.dtype != DD_U8 && plans[i]->desc.dtype != DD_U4 && plans[i]->desc.dtype != DD_U16) {
       delete b;
-      return fail(DD_ERR_DTYPE, "batches take 8-bit or 4-bit plans");
+      return fail(DD_ERR_DTYPE, "batches take integer (8-, 4- or 16-bit) plans");
     }
     if (plans[i]->desc.dtype != b->dtype) { delete b; return fail(DD_ERR_DTYPE, "all beams of a batch share one dtype"); }
     b->plans.push_back(plans[i]);
@@ -168,7 +168,7 @@ dd_status dd_batch_bind(dd_batch *b, const void *const *d_in, float *const *d_ou
   if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("batch upload: ") + hipGetErrorString(e));
 
   BatchLaunch L = {};
-  int le = batch_kernels(b->tile.ns, b->tile.dm_per_wave, b->tile.waves, b->tile.chan_block, b->dtype == DD_U4,
+  int le = batch_kernels(b->tile.ns, b->tile.dm_per_wave, b->tile.waves, b->tile.chan_block, b->dtype,
                          b->lds_bytes, &L);
   if (le) return fail(DD_ERR_HIP, std::string("batch kernel setup: ") + hipGetErrorString((hipError_t)le));
   if (!L.reset_fn || !L.main_fn) return fail(DD_ERR_HIP, "batch kernel setup: missing kernel entry");

@@ -141,6 +141,6 @@ struct BatchLaunch {
   const void *main_fn;
   int grid, block, lds_bytes;
 };
-int batch_kernels(int ns, int dm_per_wave, int waves, int chan_block, bool u4, int lds_bytes, BatchLaunch *out);
+int batch_kernels(int ns, int dm_per_wave, int waves, int chan_block, int dtype, int lds_bytes, BatchLaunch *out);
 
 }  // namespace dd

@@ -1,4 +1,4 @@
-// Integer forward kernels (uint8 and packed uint4 input) for gfx950.
+// Integer forward kernels (uint8, packed uint4 and uint16 input) for gfx950.
 //
 // Forward transform, Sec. 2, Eq. 3:  S(d, t) = sum_c x(c, t + shift(c, d)).
 //
@@ -26,6 +26,17 @@
 //     mix - (odd << 8) = sum b0 + 2^16 * sum b2        (mod 2^32)
 // recovers the even samples exactly.  Every 256 channels both are flushed into
 // per-sample int32 totals, which stay below 2^24 and convert to float exactly.
+//
+// 16-bit input.  A word holds two samples; a 16-bit window starts on an even
+// byte, so two copies (shifted by 0 and 2 bytes) align every window.  Per word
+// w = [lo hi] a lane adds
+//     mix += w          (the low half carries into the high half)
+//     odd += w >> 16    (the high samples alone)
+// and at the end lo_total = mix - (odd << 16) (mod 2^32): exact while every
+// total stays below 2^32, i.e. for up to 65537 channels.  Two channels' adds
+// fuse into one v_add3, so a sample costs one VALU lane-operation.  The float
+// conversion rounds to nearest even above 2^24, as the host's int64-to-float
+// conversion does.
 //
 // Grid order: blockIdx.x runs over DM blocks, so the workgroups resident at any
 // time share a few time tiles and read the same input rows through L2/MALL.
@@ -61,16 +72,23 @@ __device__ __forceinline__ uint4 unpack_u4(uint2 p) {
   return r;
 }
 
-// Write phases 1..3 of one 16-byte chunk whose phase-0 words are w[0..3] and
-// whose next word is w[4]; `dst` points at the chunk in phase 0.
+// Copies of a staged row: four byte phases for 8- and 4-bit samples, two
+// (0 and 2 bytes) for 16-bit samples.
+template <int BITS>
+constexpr int num_phases() { return BITS == 16 ? 2 : 4; }
+
+// Write the shifted copies of one 16-byte chunk whose phase-0 words are
+// w[0..3] and whose next word is w[4]; `dst` points at the chunk in copy 0.
+template <int BITS>
 __device__ __forceinline__ void write_phases(uint8_t *dst, int row_bytes, const uint32_t (&w)[5]) {
 #pragma unroll
-  for (int p = 1; p < 4; ++p) {
+  for (int p = 1; p < num_phases<BITS>(); ++p) {
+    const int sh = BITS == 16 ? 2 * p : p;  // byte shift of copy p
     uint4 v;
-    v.x = __builtin_amdgcn_alignbyte(w[1], w[0], p);
-    v.y = __builtin_amdgcn_alignbyte(w[2], w[1], p);
-    v.z = __builtin_amdgcn_alignbyte(w[3], w[2], p);
-    v.w = __builtin_amdgcn_alignbyte(w[4], w[3], p);
+    v.x = __builtin_amdgcn_alignbyte(w[1], w[0], sh);
+    v.y = __builtin_amdgcn_alignbyte(w[2], w[1], sh);
+    v.z = __builtin_amdgcn_alignbyte(w[3], w[2], sh);
+    v.w = __builtin_amdgcn_alignbyte(w[4], w[3], sh);
     *(uint4 *)(dst + p * row_bytes) = v;
   }
 }
@@ -155,20 +173,20 @@ __device__ __forceinline__ void dma16(const v4i_t &rs, uint32_t voff, uint32_t l
 
 // LDS layout of a tile: two phase buffers, the ring, a 1 KB scratch area.
 struct TileLds {
-  int row_bytes;    // one byte-phase copy of a row
-  int phase_buf;    // CB * 4 * row_bytes
+  int row_bytes;    // one copy of a row
+  int phase_buf;    // CB * copies * row_bytes
   int ring_row;     // stride of a raw row in a ring slot (multiple of 16, >= raw bytes + 16)
   int ring_slot;    // CB * ring_row
   int ring_base;    // 2 * phase_buf
   int scratch;      // ring_base + kRing * ring_slot
 };
 
-template <int CB, bool U4>
+template <int CB, int BITS>
 __device__ __forceinline__ TileLds tile_lds(int row_bytes) {
   TileLds L;
   L.row_bytes = row_bytes;
-  L.phase_buf = CB * 4 * row_bytes;
-  L.ring_row = (U4 ? row_bytes / 2 : row_bytes) + 16;
+  L.phase_buf = CB * num_phases<BITS>() * row_bytes;
+  L.ring_row = (BITS == 4 ? row_bytes / 2 : row_bytes) + 16;
   L.ring_slot = CB * L.ring_row;
   L.ring_base = 2 * L.phase_buf;
   L.scratch = L.ring_base + kRing * L.ring_slot;
@@ -190,10 +208,10 @@ struct DmaPlan {
   bool lane_ok[MAXT];      // this lane's 16 bytes lie inside the raw row (always true for padding)
 };
 
-template <int NW, int CB, int MAXT, bool U4>
+template <int NW, int CB, int MAXT, int BITS>
 __device__ __forceinline__ DmaPlan<MAXT> dma_plan(const TileLds &L, int wave, int lane) {
   DmaPlan<MAXT> d;
-  const int raw_bytes = U4 ? L.row_bytes / 2 : L.row_bytes;  // bytes of one row to stage
+  const int raw_bytes = BITS == 4 ? L.row_bytes / 2 : L.row_bytes;  // bytes of one row to stage
   const int segs = (raw_bytes + 1023) >> 10;
 #pragma unroll
   for (int m = 0; m < MAXT; ++m) {
@@ -224,12 +242,13 @@ __device__ __forceinline__ void stage_bases(const IntArgs &a, const int32_t *sb,
 
 // Issue the direct loads of block `cb` (first channel) into ring slot `slot`;
 // `base` comes from stage_bases for the same block.
-template <int MAXT, bool U4>
+template <int MAXT, int BITS>
 __device__ __forceinline__ void stage_dma(const IntArgs &a, const DmaPlan<MAXT> &d, const int32_t (&base_in)[MAXT],
                                           int64_t t0, int cb, uint8_t *lds, const TileLds &L, int slot) {
   // Bounds are checked per 32-bit word, so the limit is the row length rounded
   // up to 16 bytes (still inside the row pitch).
-  const int row_valid_bytes = (int)(((U4 ? a.n_samp / 2 : a.n_samp) + 15) & ~(int64_t)15);
+  const int64_t row_len = BITS == 4 ? a.n_samp / 2 : BITS == 16 ? 2 * a.n_samp : a.n_samp;
+  const int row_valid_bytes = (int)((row_len + 15) & ~(int64_t)15);
   const uint32_t slot_addr =
       __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void_t *)(lds + L.ring_base + slot * L.ring_slot));
   const uint32_t scratch_addr = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void_t *)(lds + L.scratch));
@@ -239,8 +258,10 @@ __device__ __forceinline__ void stage_dma(const IntArgs &a, const DmaPlan<MAXT> 
     const int c = __builtin_amdgcn_readfirstlane(min(cb + d.cc[m], a.n_chan - 1));
     const int32_t base = chan_ok ? base_in[m] : 0;
     const v4i_t rs = make_rsrc(a.x + (int64_t)c * a.pitch, chan_ok ? row_valid_bytes : 0);
-    // first staged byte of the row: sample t0 + base (a multiple of 32 for 4-bit input)
-    const uint32_t row0 = U4 ? (uint32_t)((t0 + base) >> 1) : (uint32_t)(t0 + base);
+    // first staged byte of the row: sample t0 + base (a multiple of 16 bytes' worth of samples)
+    const uint32_t row0 = BITS == 4    ? (uint32_t)((t0 + base) >> 1)
+                          : BITS == 16 ? (uint32_t)(2 * (t0 + base))
+                                       : (uint32_t)(t0 + base);
     const uint32_t lds_addr = d.ok[m] ? slot_addr + d.lds_off[m] : scratch_addr;
     if (d.lane_ok[m]) dma16(rs, row0 + d.voff[m], lds_addr);
   }
@@ -264,14 +285,14 @@ __device__ __forceinline__ ChunkWalk chunk_walk(const TileLds &L) {
   return w;
 }
 
-// Build the byte-phase copies of block (ring slot `slot`) into phase buffer `pb`.
-template <int NT, int CB, bool U4>
+// Build the shifted copies of block (ring slot `slot`) into phase buffer `pb`.
+template <int NT, int CB, int BITS>
 __device__ __forceinline__ void build_phases(uint8_t *lds, const TileLds &L, const ChunkWalk &cw, int slot, int pb) {
   const uint8_t *ring = lds + L.ring_base + slot * L.ring_slot;
   uint8_t *dst = lds + pb * L.phase_buf;
   for (int cc = cw.cc0, j = cw.j0; cc < CB;) {
     uint32_t w[5];
-    if (!U4) {
+    if (BITS != 4) {
       const uint8_t *src = ring + cc * L.ring_row + 16 * j;
       const uint4 v = *(const uint4 *)src;
       w[0] = v.x;
@@ -290,9 +311,9 @@ __device__ __forceinline__ void build_phases(uint8_t *lds, const TileLds &L, con
       w[3] = v.w;
       w[4] = n.x;
     }
-    uint8_t *p0 = dst + cc * 4 * L.row_bytes + 16 * j;
+    uint8_t *p0 = dst + cc * num_phases<BITS>() * L.row_bytes + 16 * j;
     *(uint4 *)p0 = make_uint4(w[0], w[1], w[2], w[3]);
-    write_phases(p0, L.row_bytes, w);
+    write_phases<BITS>(p0, L.row_bytes, w);
     cc += cw.dcc;
     j += cw.dj;
     if (j >= cw.row_chunks) {
@@ -310,9 +331,11 @@ __device__ __forceinline__ void wait_vmcnt() {
 }
 
 // One tile: DM block `dblk`, time tile `tblk`.
-template <int NS, int R, int NW, int CB, bool U4>
+template <int NS, int R, int NW, int CB, int BITS>
 __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int dblk, int tblk) {
   constexpr int NT = NW * 64;
+  constexpr int NPH = num_phases<BITS>();
+  constexpr int NWD = BITS == 16 ? NS / 2 : NS / 4;  // 32-bit words per lane and window
   constexpr int RP = R < 2 ? 2 : R;  // uint16 slots per channel in the offset table
   constexpr int NOW = RP / 2;        // uint32 words per channel
   constexpr int MAXT = (kStageSegs + NW - 1) / NW;
@@ -322,24 +345,26 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
   const int chan_pad = (a.n_chan + CB - 1) / CB * CB;
   const uint32_t *woffs = a.offs + ((int64_t)dblk * NW + wave) * chan_pad * NOW;
   const int32_t *sb = a.sbase + (int64_t)dblk * a.n_chan;
-  const TileLds L = tile_lds<CB, U4>(a.row_bytes);
+  const TileLds L = tile_lds<CB, BITS>(a.row_bytes);
 
-  uint32_t tot[R][NS], mix[R][NS / 4], odd[R][NS / 4];
+  // 8/4-bit: mix/odd are the SIMD-in-word accumulators, tot the flushed totals.
+  // 16-bit: mix sums whole words, odd the high samples (see the file comment).
+  uint32_t tot[R][NS], mix[R][NWD], odd[R][NWD];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
 #pragma unroll
     for (int j = 0; j < NS; ++j) tot[r][j] = 0;
 #pragma unroll
-    for (int k = 0; k < NS / 4; ++k) mix[r][k] = odd[r][k] = 0;
+    for (int k = 0; k < NWD; ++k) mix[r][k] = odd[r][k] = 0;
   }
 
   const int nblk = chan_pad / CB;
-  const DmaPlan<MAXT> dp = dma_plan<NW, CB, MAXT, U4>(L, wave, lane);
+  const DmaPlan<MAXT> dp = dma_plan<NW, CB, MAXT, BITS>(L, wave, lane);
   int32_t bases[MAXT];
 #pragma unroll
   for (int k = 0; k < kRing; ++k) {
     stage_bases<MAXT>(a, sb, k * CB, dp, bases);
-    stage_dma<MAXT, U4>(a, dp, bases, t0, k * CB, lds, L, k);
+    stage_dma<MAXT, BITS>(a, dp, bases, t0, k * CB, lds, L, k);
   }
   stage_bases<MAXT>(a, sb, kRing * CB, dp, bases);
   // Offsets of block 0; each iteration fetches those of the next block.
@@ -349,7 +374,7 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
   const ChunkWalk cw = chunk_walk<NT>(L);
   wait_vmcnt<(kRing - 1) * MAXT>();
   lds_barrier();
-  build_phases<NT, CB, U4>(lds, L, cw, 0, 0);
+  build_phases<NT, CB, BITS>(lds, L, cw, 0, 0);
 
   const uint8_t *lane_base = lds + 4 * lane;
   int since_flush = 0;
@@ -359,8 +384,8 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
     // slot b % kRing or phase buffer (b+1) % 2 any more.
     wait_vmcnt<(kRing - 2) * MAXT>();
     lds_barrier();
-    stage_dma<MAXT, U4>(a, dp, bases, t0, (b + kRing) * CB, lds, L, b % kRing);  // zeros past the end
-    if (b + 1 < nblk) build_phases<NT, CB, U4>(lds, L, cw, (b + 1) % kRing, (b + 1) & 1);
+    stage_dma<MAXT, BITS>(a, dp, bases, t0, (b + kRing) * CB, lds, L, b % kRing);  // zeros past the end
+    if (b + 1 < nblk) build_phases<NT, CB, BITS>(lds, L, cw, (b + 1) % kRing, (b + 1) & 1);
     // Sum block b.  Each (channel, DM row) pair reads NS/4 aligned words of
     // the byte phase that puts its window on a word boundary; the table entry
     // is that word's byte offset inside the channel's four copies.  Lane i
@@ -370,23 +395,30 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
     const uint8_t *blk = lane_base + (b & 1) * L.phase_buf;
 #pragma unroll
     for (int cc = 0; cc < CB; ++cc) {
-      const uint8_t *chan = blk + cc * 4 * L.row_bytes;
+      const uint8_t *chan = blk + cc * NPH * L.row_bytes;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const uint32_t e = (ow[cc * NOW + (r >> 1)] >> (16 * (r & 1))) & 0xFFFFu;
         const uint32_t *p = (const uint32_t *)(chan + e);
 #pragma unroll
-        for (int k = 0; k < NS / 4; ++k) {
+        for (int k = 0; k < NWD; ++k) {
           const uint32_t w = p[64 * k];
-          mix[r][k] += w;
-          odd[r][k] += __builtin_amdgcn_perm(w, w, kOddSel);
+          if constexpr (BITS == 16) {
+            mix[r][k] += w;
+            odd[r][k] += w >> 16;
+          } else {
+            mix[r][k] += w;
+            odd[r][k] += __builtin_amdgcn_perm(w, w, kOddSel);
+          }
         }
       }
     }
-    since_flush += CB;
-    if (since_flush >= 256 || b + 1 == nblk) {
-      flush<NS, R>(mix, odd, tot);
-      since_flush = 0;
+    if constexpr (BITS != 16) {
+      since_flush += CB;
+      if (since_flush >= 256 || b + 1 == nblk) {
+        flush<NS, R>(mix, odd, tot);
+        since_flush = 0;
+      }
     }
     // Scalar loads for the next iteration: its offsets and the stage bases of
     // the block it stages.  Issued after this block's LDS reads, so that no
@@ -400,14 +432,26 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
   wait_vmcnt<0>();  // the trailing all-zero loads must land before the LDS is reused
   lds_barrier();
 
-  // Word k of lane i holds samples t0 + 4*(i + 64k) + 0..3: stores are
-  // contiguous across the wave.
+  // Word k of lane i holds samples t0 + 4*(i + 64k) + 0..3 (16-bit: t0 +
+  // 2*(i + 64k) + 0..1): stores are contiguous across the wave.
   const int d0 = dblk * (NW * R) + wave * R;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int d = d0 + r;
     if (d >= a.n_dm) break;
     float *orow = a.out + (int64_t)d * a.out_pitch;
+    if constexpr (BITS == 16) {
+#pragma unroll
+      for (int k = 0; k < NWD; ++k) {
+        const int64_t t = t0 + 2 * (int64_t)(lane + 64 * k);
+        const uint32_t lo = mix[r][k] - (odd[r][k] << 16);
+        if (t + 1 < a.n_out)
+          *(float2 *)(orow + t) = make_float2((float)lo, (float)odd[r][k]);
+        else if (t < a.n_out)
+          orow[t] = (float)lo;
+      }
+      continue;
+    }
 #pragma unroll
     for (int k = 0; k < NS / 4; ++k) {
       const int64_t t = t0 + 4 * (int64_t)(lane + 64 * k);
@@ -424,12 +468,12 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
 }
 
 // One workgroup per tile; 1-D grid of n_dblk * n_tiles workgroups.
-template <int NS, int R, int NW, int CB, bool U4>
+template <int NS, int R, int NW, int CB, int BITS>
 __global__ __launch_bounds__(NW * 64) void fwd_int_kernel(IntArgs a, int n_dblk, int n_tiles, int order) {
   extern __shared__ __align__(16) uint8_t lds[];
   int dblk, tblk;
   tile_of(blockIdx.x, n_dblk, n_tiles, order, dblk, tblk);
-  fwd_int_tile<NS, R, NW, CB, U4>(lds, a, dblk, tblk);
+  fwd_int_tile<NS, R, NW, CB, BITS>(lds, a, dblk, tblk);
 }
 
 __global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0ull; }
@@ -443,7 +487,7 @@ __global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0
 // A workgroup returns at its first claim past the last item: every wave
 // reaches the exit.  Between items no extra barrier is needed for the LDS: a
 // tile ends with all of its LDS reads complete behind its final barrier.
-template <int NS, int R, int NW, int CB, bool U4>
+template <int NS, int R, int NW, int CB, int BITS>
 __global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc *__restrict__ beams, int n_beams,
                                                                    long long n_items,
                                                                    unsigned long long *__restrict__ counter) {
@@ -477,7 +521,7 @@ __global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc
     a.n_dm = b.n_dm;
     a.row_bytes = b.row_bytes;
 
-    fwd_int_tile<NS, R, NW, CB, U4>(lds, a, dblk, tblk);
+    fwd_int_tile<NS, R, NW, CB, BITS>(lds, a, dblk, tblk);
     if (threadIdx.x == 0) claimed = (long long)next;
     lds_barrier();  // publishes the claim; the tile's stores may still be in flight
     item = claimed;  // read before this wave's first barrier of the next tile; rewritten only after it
@@ -509,17 +553,22 @@ int launch_int_shape(const dd_plan &p, const void *d_in, float *d_out, int64_t o
   const int64_t tiles_t = (a.n_out + 64 * NS - 1) / (64 * NS);
   const int64_t n_dblk = (p.desc.n_dm + NW * R - 1) / (NW * R);
   if (tiles_t * n_dblk >= ((int64_t)1 << 31)) return (int)hipErrorInvalidConfiguration;
-  dim3 grid((unsigned)(tiles_t * n_dblk));
-  const void *fn = p.desc.dtype == DD_U4 ? (const void *)fwd_int_kernel<NS, R, NW, CB, true>
-                                         : (const void *)fwd_int_kernel<NS, R, NW, CB, false>;
+  const dim3 grid((unsigned)(tiles_t * n_dblk)), block(NW * 64);
+  const int bits = p.desc.dtype == DD_U4 ? 4 : p.desc.dtype == DD_U16 ? 16 : 8;
+  const void *fn = bits == 4    ? (const void *)fwd_int_kernel<NS, R, NW, CB, 4>
+                   : bits == 16 ? (const void *)fwd_int_kernel<NS, R, NW, CB, 16>
+                                : (const void *)fwd_int_kernel<NS, R, NW, CB, 8>;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, t.lds_bytes);
   if (e != hipSuccess) return (int)e;
-  if (p.desc.dtype == DD_U4)
-    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, true>), grid, dim3(NW * 64), t.lds_bytes, st, a, (int)n_dblk,
+  if (bits == 4)
+    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, 4>), grid, block, t.lds_bytes, st, a, (int)n_dblk, (int)tiles_t,
+                       t.order);
+  else if (bits == 16)
+    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, 16>), grid, block, t.lds_bytes, st, a, (int)n_dblk,
                        (int)tiles_t, t.order);
   else
-    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, false>), grid, dim3(NW * 64), t.lds_bytes, st, a, (int)n_dblk,
-                       (int)tiles_t, t.order);
+    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, 8>), grid, block, t.lds_bytes, st, a, (int)n_dblk, (int)tiles_t,
+                       t.order);
   return (int)hipGetLastError();
 }
 
@@ -541,12 +590,13 @@ int launch_forward_int(const dd_plan &p, const void *d_in, float *d_out, int64_t
   return (int)hipErrorInvalidValue;
 }
 
-int batch_kernels(int ns, int dm_per_wave, int waves, int chan_block, bool u4, int lds_bytes, BatchLaunch *out) {
+int batch_kernels(int ns, int dm_per_wave, int waves, int chan_block, int dtype, int lds_bytes, BatchLaunch *out) {
   const void *fn = nullptr;
-#define DD_TRY(NS, R, NW, CB)                                                               \
-  if (ns == NS && dm_per_wave == R && waves == NW && chan_block == CB)                      \
-    fn = u4 ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, true>                      \
-            : (const void *)fwd_int_batched_kernel<NS, R, NW, CB, false>;
+#define DD_TRY(NS, R, NW, CB)                                                                    \
+  if (ns == NS && dm_per_wave == R && waves == NW && chan_block == CB)                           \
+    fn = dtype == DD_U4    ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, 4>               \
+         : dtype == DD_U16 ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, 16>              \
+                           : (const void *)fwd_int_batched_kernel<NS, R, NW, CB, 8>;
   DD_INT_SHAPES(DD_TRY)
 #undef DD_TRY
   if (!fn) return (int)hipErrorInvalidValue;

@@ -118,33 +118,40 @@ static int round_up(int64_t v, int a) { return (int)((v + a - 1) / a * a); }
 // rounded down to 4 and a lane reads ns/4 + 1 chunks of 4 floats.
 int row_bytes_for(int dtype, int ns, int span) {
   if (dtype == DD_F32) return 4 * round_up((int64_t)64 * ns + span + 8, 4);
+  if (dtype == DD_U16) return round_up(2 * ((int64_t)64 * ns + span + 8 + 8), 16);
   const int unit = dtype == DD_U4 ? 32 : 16;
   return round_up((int64_t)64 * ns + span + unit + 16, unit);
 }
 
 // Tables of the integer forward kernel for tile shape (ns, dm_per_wave, waves).
 // For DM block b, channel c: sbase = shift(c, first DM of b) rounded down to
-// the staging unit; for each DM d of the block, with v = shift(c, d) - sbase
-// the window's offset in the staged row, the entry is the LDS byte offset of
-// its first word inside the channel's four byte-phase copies (each row_bytes
-// long): (v % 4) * row_bytes + (v - v % 4).
+// the staging unit (the samples in 16 bytes: 16 for u8, 32 for u4, 8 for u16);
+// for each DM d of the block, with v = shift(c, d) - sbase the window's offset
+// in the staged row, the entry is the LDS byte offset of its first word inside
+// the channel's shifted copies (each row_bytes long): for 8- and 4-bit samples
+// (one byte each once staged) four copies, (v % 4) * row_bytes + (v - v % 4);
+// for 16-bit samples (byte offset 2v) two copies,
+// (v % 2) * row_bytes + 2 * (v - v % 2).
 // Fails with DD_ERR_RANGE if even one channel per LDS stage does not fit.
 dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves, int chan_block, int lds_limit,
                            IntTables *t) {
   const int nc = p.desc.n_chan, nd = p.desc.n_dm;
   const int dblk = waves * dm_per_wave;
-  const int unit = p.desc.dtype == DD_U4 ? 32 : 16;
+  const bool u16 = p.desc.dtype == DD_U16;
+  const int unit = p.desc.dtype == DD_U4 ? 32 : u16 ? 8 : 16;
+  const int copies = u16 ? 2 : 4;
   const int span = max_dm_block_span(p, dblk);
-  const int64_t rb = (int64_t)64 * ns + span + unit + 16;
-  if (rb > (1 << 24)) return fail(DD_ERR_RANGE, "delay spread too large");
-  t->row_bytes = round_up(rb, unit);
-  // LDS: two buffers of 4 byte-phase copies, a ring of 3 raw slots (rows of
-  // raw bytes + 16), 1 KB of scratch.  Loads per block: 1 KB segments of raw rows.
+  const int64_t rs = (int64_t)64 * ns + span + unit + 16;  // samples of a staged row
+  if (rs > (1 << 23)) return fail(DD_ERR_RANGE, "delay spread too large");
+  t->row_bytes = u16 ? round_up(2 * rs, 16) : round_up(rs, unit);
+  // LDS: two buffers of the shifted copies, a ring of 3 raw slots (rows of raw
+  // bytes + 16), 1 KB of scratch.  Loads per block: 1 KB segments of raw rows.
   const int raw = p.desc.dtype == DD_U4 ? t->row_bytes / 2 : t->row_bytes;
-  const int64_t lds = (int64_t)2 * chan_block * 4 * t->row_bytes + (int64_t)3 * chan_block * (raw + 16) + 1024;
+  const int64_t lds =
+      (int64_t)2 * chan_block * copies * t->row_bytes + (int64_t)3 * chan_block * (raw + 16) + 1024;
   if (lds > lds_limit) return fail(DD_ERR_RANGE, "staged channel block exceeds LDS");
   if (chan_block * ((raw + 1023) / 1024) > 16) return fail(DD_ERR_RANGE, "too many staging segments");  // kStageSegs
-  if ((int64_t)4 * t->row_bytes > 65536) return fail(DD_ERR_RANGE, "staged rows too long for 16-bit LDS offsets");
+  if ((int64_t)copies * t->row_bytes > 65536) return fail(DD_ERR_RANGE, "staged rows too long for 16-bit LDS offsets");
   t->chan_block = chan_block;
   t->lds_bytes = (int)lds;
   const int n_dblk = (nd + dblk - 1) / dblk;
@@ -166,10 +173,11 @@ dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves,
         const int32_t *sd = p.shift.data() + (size_t)d * nc;
         uint16_t *o = t->offs.data() + (((size_t)b * waves + w) * ncp) * rp + r;
         for (int c = 0; c < nc; ++c) {
-          // window offset v inside the staged row -> byte offset of its first
-          // word inside the channel's four byte-phase copies
+          // window offset v (samples) inside the staged row -> byte offset of
+          // its first word inside the channel's shifted copies
           const int32_t v = sd[c] - sb[c];
-          o[(size_t)c * rp] = (uint16_t)((v & 3) * t->row_bytes + (v & ~3));
+          o[(size_t)c * rp] = u16 ? (uint16_t)((v & 1) * t->row_bytes + 2 * (v & ~1))
+                                  : (uint16_t)((v & 3) * t->row_bytes + (v & ~3));
         }
       }
   }

@@ -65,6 +65,8 @@ def _cpu_lib():
         lib.synth_u8_table.argtypes = [vp, i32, i64, i64, u64, i64, vp]
         lib.synth_u8_table.restype = None
         lib.synth_u4_packed.argtypes = [vp, i32, i64, i64, u64, i64]
+        lib.synth_u16_table.argtypes = [vp, i32, i64, i64, u64, i64, vp]
+        lib.synth_u16_table.restype = None
         lib.synth_u4_packed.restype = None
         _cpu = lib
     return _cpu
@@ -80,6 +82,8 @@ def _gpu_lib():
         lib.synth_u8_table_gpu.argtypes = [vp, i32, i64, i64, u64, i64, vp, vp]
         lib.synth_u8_table_gpu.restype = i32
         lib.synth_u4_packed_gpu.argtypes = [vp, i32, i64, i64, u64, i64, vp]
+        lib.synth_u16_table_gpu.argtypes = [vp, i32, i64, i64, u64, i64, vp, vp]
+        lib.synth_u16_table_gpu.restype = ctypes.c_int
         lib.synth_u4_packed_gpu.restype = i32
         _gpu = lib
     return _gpu
@@ -103,6 +107,33 @@ def gaussian_u8(n_chan: int, n_samp: int, seed: int, mean: float = 128.0, sigma:
     table = gaussian_table(mean, sigma)
     _cpu_lib().synth_u8_table(out.ctypes.data, n_chan, n_samp, pitch, seed, t_start, table.ctypes.data)
     return out
+
+
+def gaussian_table16(mean: float = 32768.0, sigma: float = 4096.0) -> np.ndarray:
+    """uint16[65536] quantile table of N(mean, sigma), rounded to nearest, clipped to 0..65535."""
+    from scipy.special import ndtri
+    p = (np.arange(65536, dtype=np.float64) + 0.5) / 65536.0
+    v = np.clip(np.rint(mean + sigma * ndtri(p)), 0.0, 65535.0)
+    return v.astype(np.uint16)
+
+
+def gaussian_u16(n_chan: int, n_samp: int, seed: int, mean: float = 32768.0, sigma: float = 4096.0,
+                 pitch: int | None = None, t_start: int = 0) -> np.ndarray:
+    """uint16 [n_chan][pitch] (pitch in samples): the same draws as gaussian_u8 through a 16-bit table."""
+    pitch = n_samp if pitch is None else pitch
+    assert pitch >= n_samp and n_chan > 0 and n_samp > 0
+    out = np.zeros((n_chan, pitch), dtype=np.uint16)
+    table = gaussian_table16(mean, sigma)
+    _cpu_lib().synth_u16_table(out.ctypes.data, n_chan, n_samp, pitch, seed, t_start, table.ctypes.data)
+    return out
+
+
+def gaussian_u16_device(ptr: int, n_chan: int, n_samp: int, pitch: int, seed: int, table_ptr: int,
+                        stream: int = 0, t_start: int = 0) -> None:
+    """Fill device memory at ``ptr`` exactly as :func:`gaussian_u16` would (16-bit table on the device)."""
+    rc = _gpu_lib().synth_u16_table_gpu(ptr, n_chan, n_samp, pitch, seed, t_start, table_ptr, stream)
+    if rc != 0:
+        raise RuntimeError("synth_u16_table_gpu failed (%d)" % rc)
 
 
 def uniform_u4_packed(n_chan: int, n_samp: int, seed: int, pitch_bytes: int | None = None,
@@ -149,8 +180,8 @@ def normal_f32(n_chan: int, n_samp: int, seed: int, pitch: int | None = None) ->
     return out
 
 
-def boxcar_updates(x_at, delay: np.ndarray, t0: int, width: int, amp: int):
-    """Positions and new values of a dispersed boxcar pulse, clipped at 255.
+def boxcar_updates(x_at, delay: np.ndarray, t0: int, width: int, amp: int, top: int = 255):
+    """Positions and new values of a dispersed boxcar pulse, clipped at ``top`` (255 for 8-bit).
 
     ``x_at(rows, cols)`` returns the current uint8 values at those positions
     (from a host array, or regenerated from the counter generator).  Returns
@@ -162,14 +193,15 @@ def boxcar_updates(x_at, delay: np.ndarray, t0: int, width: int, amp: int):
     rows = np.repeat(np.arange(n_chan, dtype=np.int64), width)
     cols = (t0 + delay.astype(np.int64)[:, None] + np.arange(width, dtype=np.int64)[None, :]).reshape(-1)
     before = np.asarray(x_at(rows, cols), dtype=np.int64)
-    after = np.minimum(before + amp, 255)
+    after = np.minimum(before + amp, top)
     applied = (after - before).reshape(n_chan, width)
-    return rows, cols, after.astype(np.uint8), applied
+    return rows, cols, after.astype(np.uint8 if top <= 255 else np.uint16), applied
 
 
 def inject_boxcar_u8(x: np.ndarray, delay: np.ndarray, t0: int, width: int, amp: int) -> np.ndarray:
-    """Add a dispersed boxcar to a host array in place; returns the applied increments."""
-    rows, cols, vals, applied = boxcar_updates(lambda r, c: x[r, c], delay, t0, width, amp)
+    """Add a dispersed boxcar to a host array (uint8 or uint16) in place; returns the applied increments."""
+    top = 65535 if x.dtype == np.uint16 else 255
+    rows, cols, vals, applied = boxcar_updates(lambda r, c: x[r, c], delay, t0, width, amp, top)
     x[rows, cols] = vals
     return applied
 
@@ -187,6 +219,9 @@ CONFIGS = {
     "lowfreq_u4": dict(dtype="u4", n_chan=4096, n_samp=1 << 19, f_high=190.0, chan_bw=70.0 / 4096,
                        t_samp=327.68e-6, dm_start=0.0, dm_step=0.1, n_dm=2048, seed=3,
                        pulses=[], amp=0),
+    "headline_u16": dict(dtype="u16", n_chan=8192, n_samp=1 << 20, f_high=1500.0, chan_bw=300.0 / 8192,
+                         t_samp=64e-6, dm_start=0.0, dm_step=0.5, n_dm=4000, seed=6,
+                         pulses=[(100, 1, 100_000), (1600, 4, 460_000), (3800, 16, 820_000)], amp=2560),
     "grad_f32": dict(dtype="f32", n_chan=1024, n_samp=1 << 17, f_high=1500.0, chan_bw=300.0 / 1024,
                      t_samp=128e-6, dm_start=0.0, dm_step=1.0, n_dm=1024, seed=4,
                      target_seed=40, fd_seed=41, pulses=[], amp=0),

@@ -31,6 +31,21 @@ __global__ void synth_u8_kernel(uint8_t *__restrict__ out, int n_chan, int64_t n
   }
 }
 
+// One thread writes 8 consecutive 16-bit samples (2 hashes) of one row.
+__global__ void synth_u16_kernel(uint16_t *__restrict__ out, int n_chan, int64_t n_samp, int64_t pitch,
+                                 uint64_t seed, int64_t t_start, const uint16_t *__restrict__ table) {
+  const int c = blockIdx.y;
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
+  if (c >= n_chan || t >= n_samp) return;
+  const uint64_t base = synth_row_base(seed, c);
+  uint16_t *row = out + (int64_t)c * pitch;
+  for (int k = 0; k < 8 && t + k < n_samp; ++k) {
+    const int64_t g = t_start + t + k;
+    const uint64_t h = synth_splitmix64(base + (uint64_t)(g >> 2));
+    row[t + k] = table[(h >> (16 * (g & 3))) & 0xFFFF];
+  }
+}
+
 __global__ void synth_u4_kernel(uint8_t *__restrict__ out, int n_chan, int64_t n_samp, int64_t pitch_bytes,
                                 uint64_t seed, int64_t t_start) {
   const int c = blockIdx.y;
@@ -54,6 +69,15 @@ extern "C" int synth_u8_table_gpu(uint8_t *d_out, int n_chan, int64_t n_samp, in
   if (n_chan <= 0 || n_samp <= 0 || n_chan > 65535) return (int)hipErrorInvalidValue;
   const int64_t per_row = (n_samp + 16 * 256 - 1) / (16 * 256);
   hipLaunchKernelGGL(synth_u8_kernel, dim3((unsigned)per_row, (unsigned)n_chan), dim3(256), 0,
+                     (hipStream_t)stream, d_out, n_chan, n_samp, pitch, seed, t_start, d_table);
+  return (int)hipGetLastError();
+}
+
+extern "C" int synth_u16_table_gpu(uint16_t *d_out, int n_chan, int64_t n_samp, int64_t pitch, uint64_t seed,
+                                   int64_t t_start, const uint16_t *d_table, void *stream) {
+  if (n_chan <= 0 || n_samp <= 0 || n_chan > 65535 || pitch < n_samp) return (int)hipErrorInvalidValue;
+  const int64_t per_row = (n_samp + 8 * 256 - 1) / (8 * 256);
+  hipLaunchKernelGGL(synth_u16_kernel, dim3((unsigned)per_row, (unsigned)n_chan), dim3(256), 0,
                      (hipStream_t)stream, d_out, n_chan, n_samp, pitch, seed, t_start, d_table);
   return (int)hipGetLastError();
 }

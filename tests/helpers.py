@@ -20,6 +20,8 @@ def host_input(cfg, shift=None, pitch=None):
         x = synth.gaussian_u8(cfg["n_chan"], cfg["n_samp"], cfg["seed"], pitch=pitch)
     elif dt == "u4":
         x = synth.uniform_u4_packed(cfg["n_chan"], cfg["n_samp"], cfg["seed"], pitch_bytes=pitch)
+    elif dt == "u16":
+        x = synth.gaussian_u16(cfg["n_chan"], cfg["n_samp"], cfg["seed"], pitch=pitch)
     else:
         x = synth.normal_f32(cfg["n_chan"], cfg["n_samp"], cfg["seed"], pitch=pitch)
     applied = {}

@@ -65,3 +65,26 @@ def test_batched_single_beam_and_u4(dd):
     torch.cuda.synchronize()
     want = oracle.forward(x, "u4", cfg["n_samp"], s)
     assert np.array_equal(out.cpu().numpy(), want)
+
+
+def test_batched_u16_beams(dd):
+    """Three 16-bit beams of different shapes in one batch: bit-exact against the oracle."""
+    beams = [dict(dtype="u16", n_chan=96, n_samp=40000, f_high=1400.0, chan_bw=1.5, t_samp=64e-6,
+                  dm_start=0.0, dm_step=0.5, n_dm=40, seed=61),
+             dict(dtype="u16", n_chan=300, n_samp=30008, f_high=1500.0, chan_bw=0.8, t_samp=128e-6,
+                  dm_start=5.0, dm_step=1.0, n_dm=33, seed=62),
+             dict(dtype="u16", n_chan=17, n_samp=20000, f_high=800.0, chan_bw=2.0, t_samp=64e-6,
+                  dm_start=0.0, dm_step=0.25, n_dm=65, seed=63)]
+    plans, xs, hosts, tables = [], [], [], []
+    for cfg in beams:
+        s = oracle_table(cfg)
+        x = synth.gaussian_u16(cfg["n_chan"], cfg["n_samp"], cfg["seed"])
+        plans.append(plan_for(dd, cfg))
+        xs.append(torch.from_numpy(x).cuda())
+        hosts.append(x)
+        tables.append(s)
+    outs = dd.Batch(plans, xs).run()
+    torch.cuda.synchronize()
+    for b, cfg in enumerate(beams):
+        want = oracle.forward(hosts[b], "u16", cfg["n_samp"], tables[b])
+        assert np.array_equal(outs[b].cpu().numpy(), want), b

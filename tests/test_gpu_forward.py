@@ -68,18 +68,18 @@ RAGGED = [  # (n_chan, n_samp, n_dm): tails in every tile dimension, >256 channe
 
 
 @pytest.mark.parametrize("case", RAGGED)
-@pytest.mark.parametrize("dtype", ["u8", "u4", "f32"])
+@pytest.mark.parametrize("dtype", ["u8", "u4", "u16", "f32"])
 def test_ragged_shapes(dd, dtype, case):
     n_chan, n_samp, n_dm = case
     if dtype == "u4":
         n_samp += n_samp & 1
-    rng = np.random.default_rng(n_chan * 1000 + n_dm + {"u8": 0, "u4": 1, "f32": 2}[dtype])
+    rng = np.random.default_rng(n_chan * 1000 + n_dm + {"u8": 0, "u4": 1, "f32": 2, "u16": 3}[dtype])
     cfg = _random_case(rng, dtype, n_chan, n_samp, n_dm)
     s = oracle_table(cfg)
     n_out = oracle.n_out_for(s, n_samp)
     if n_out <= 0:
         pytest.skip("plan leaves no output")
-    elem = 4 if dtype == "f32" else 1
+    elem = {"f32": 4, "u16": 2}.get(dtype, 1)
     row = n_samp // 2 if dtype == "u4" else n_samp * elem
     pitch_bytes = (row + 15) // 16 * 16 + 16 * int(rng.integers(0, 3))  # padded rows
     pitch = pitch_bytes // elem
@@ -88,6 +88,9 @@ def test_ragged_shapes(dd, dtype, case):
         x[:, ::13] = 255
     elif dtype == "u4":
         x = rng.integers(0, 256, (n_chan, pitch)).astype(np.uint8)
+    elif dtype == "u16":
+        x = rng.integers(0, 65536, (n_chan, pitch)).astype(np.uint16)
+        x[:, ::13] = 65535
     else:
         x = rng.standard_normal((n_chan, pitch)).astype(np.float32)
     plan = plan_for(dd, cfg, in_pitch_bytes=pitch_bytes)
@@ -208,6 +211,45 @@ def test_lowfreq_u4_workload_sampled(dd):
     gpu_rowsum = out.double().sum(dim=1).cpu().numpy().astype(np.int64)
     cpu_rowsum = row_sums_by_prefix(lambda c: unpacked(xh[c:c + 1], n_samp)[0], s, plan.n_out)
     assert np.array_equal(gpu_rowsum, cpu_rowsum)
+
+
+def test_headline_u16_workload_sampled(dd):
+    """The headline shape with 16-bit samples (8192 ch x 2^20 x 4000 DMs), as bench.py times it.
+
+    Sums reach 2^29, so outputs above 2^24 are rounded once to float32; the
+    oracle rounds its exact int64 sums the same way, so sampled rows (DM 0, the
+    pulse rows, every 400th, random rows) compare bit for bit, and DM 0 equals
+    the float32 of the plain channel sum.
+    """
+    cfg = synth.CONFIGS["headline_u16"]
+    s = oracle_table(cfg)
+    n_chan, n_samp = cfg["n_chan"], cfg["n_samp"]
+    xd = torch.empty((n_chan, n_samp), dtype=torch.uint16, device="cuda")
+    table = torch.from_numpy(synth.gaussian_table16()).cuda()
+    synth.gaussian_u16_device(xd.data_ptr(), n_chan, n_samp, n_samp, cfg["seed"], table.data_ptr(),
+                              torch.cuda.current_stream().cuda_stream)
+    xh = synth.gaussian_u16(n_chan, n_samp, cfg["seed"])
+    for dp, width, t0 in cfg["pulses"]:
+        rows, cols, vals, _ = synth.boxcar_updates(lambda r, c: xh[r, c], s[dp], t0, width, cfg["amp"], 65535)
+        xh[rows, cols] = vals
+        # torch has no uint16 scatter on the GPU: write the same bytes through an int16 view
+        xd.view(torch.int16)[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()] = \
+            torch.from_numpy(vals.view(np.int16)).cuda()
+    torch.cuda.synchronize()
+    for c in [0, 4095, 8191]:
+        assert np.array_equal(xd[c].cpu().numpy(), xh[c])
+    plan = plan_for(dd, cfg)
+    out = plan.forward(xd)
+    torch.cuda.synchronize()
+    rows = sample_rows(cfg["n_dm"], cfg["pulses"], every=400, extra=6, seed=6)
+    got = out[rows].cpu().numpy()
+    want = oracle.forward(xh, "u16", n_samp, s, rows=rows)
+    assert np.array_equal(got, want)
+    dm0 = xh[:, :plan.n_out].sum(axis=0, dtype=np.int64).astype(np.float32)
+    assert np.array_equal(out[0].cpu().numpy(), dm0)
+    for dp, width, t0 in cfg["pulses"]:
+        if width <= 4:
+            assert int(np.argmax(out[:, t0].cpu().numpy())) == dp
 
 
 def test_grad_workload_forward_sampled(dd):

@@ -44,7 +44,7 @@ def _choices(dd, plan, direction):
     return out
 
 
-@pytest.mark.parametrize("dtype", ["u8", "u4"])
+@pytest.mark.parametrize("dtype", ["u8", "u4", "u16"])
 def test_integer_tiles_bit_exact(dd, dtype):
     cfg = _case(dtype)
     s = oracle_table(cfg)
@@ -133,7 +133,7 @@ def test_autotune_adjoint(dd, monkeypatch):
     assert np.all(np.abs(after - want) <= 1e-5 * abs_a)
 
 
-@pytest.mark.parametrize("dtype", ["u8", "u4", "f32"])
+@pytest.mark.parametrize("dtype", ["u8", "u4", "u16", "f32"])
 def test_time_chunks_equal_whole(dd, dtype):
     """Chunks over column views of one input give the whole-input columns bit for bit."""
     cfg = _case(dtype)

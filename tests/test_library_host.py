@@ -41,7 +41,7 @@ def test_header_symbols_exported(dd):
         assert hasattr(lib, n), "missing export " + n
 
 
-@pytest.mark.parametrize("name", ["small", "headline", "lowfreq_u4", "grad_f32"])
+@pytest.mark.parametrize("name", ["small", "headline", "lowfreq_u4", "headline_u16", "grad_f32"])
 def test_library_table_equals_oracle(dd, name):
     cfg = synth.CONFIGS[name]
     p = _plan(dd, cfg)
@@ -91,6 +91,8 @@ def test_error_codes(dd):
     assert _status(dd, lambda: _plan(dd, cfg, in_pitch_bytes=32770)) == "DD_ERR_ALIGN"
     assert _status(dd, lambda: _plan(dd, cfg, in_pitch_bytes=1000)) == "DD_ERR_ARG"
     assert _status(dd, lambda: _plan(dd, cfg, n_chan=70000, chan_bw=0.001)) == "DD_ERR_RANGE"
+    assert _status(dd, lambda: _plan(dd, cfg, dtype="u16", n_chan=65538, chan_bw=0.001)) == "DD_ERR_RANGE"
+    _plan(dd, cfg, dtype="u16", n_chan=65537, chan_bw=0.001, n_dm=2)  # the largest exact 16-bit plan
     assert _status(dd, lambda: _plan(dd, cfg, chan_freq=np.full(128, 1600.0))) == "DD_ERR_RANGE"  # above f_high
     p = _plan(dd, cfg)
     lib = ctypes.CDLL(dd.LIB_PATH)

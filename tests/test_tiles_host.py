@@ -33,7 +33,7 @@ def _status(dd, fn):
     return e.value.name
 
 
-@pytest.mark.parametrize("name", ["small", "lowfreq_u4", "grad_f32"])
+@pytest.mark.parametrize("name", ["small", "lowfreq_u4", "headline_u16", "grad_f32"])
 def test_every_shape_feasible_or_refused(dd, name):
     cfg = synth.CONFIGS[name]
     p = _plan(dd, cfg)
@@ -129,7 +129,7 @@ def test_tune_cache_applied(dd, tmp_path, monkeypatch):
     assert p.tiles(0)["order"] == 2
 
 
-@pytest.mark.parametrize("dtype,n_chunks", [("u8", 1), ("u8", 3), ("u4", 4), ("f32", 5)])
+@pytest.mark.parametrize("dtype,n_chunks", [("u8", 1), ("u8", 3), ("u4", 4), ("u16", 3), ("f32", 5)])
 def test_time_chunks_cover_the_output(dd, dtype, n_chunks):
     cfg = dict(synth.CONFIGS["small"], dtype=dtype)
     desc = {k: cfg[k] for k in ["n_chan", "n_samp", "dtype", "f_high", "chan_bw", "t_samp", "dm_start", "dm_step",
@@ -138,7 +138,7 @@ def test_time_chunks_cover_the_output(dd, dtype, n_chunks):
     whole = _plan(dd, cfg)
     assert tc.n_out == whole.n_out and tc.max_shift == whole.max_shift
     assert len(tc) == n_chunks
-    unit = {"u8": 16, "u4": 32, "f32": 4}[dtype]
+    unit = {"u8": 16, "u4": 32, "u16": 8, "f32": 4}[dtype]
     t = 0
     for (t0, n), p in zip(tc.spans, tc.plans):
         assert t0 == t and t0 % unit == 0 and n > 0
