@@ -9,6 +9,7 @@ passage of the paper each part follows.
 from .oracle import (  # noqa: F401
     KDM,
     adjoint,
+    bin_time,
     build,
     forward,
     forward_f32,

@@ -134,6 +134,50 @@ int oracle_forward_int(int dtype, const uint8_t *x, int64_t pitch, int n_chan, i
 }
 
 /*
+ * Time binning, the "downsampling" that Secs. 5.2 and 5.3 apply before the
+ * transform for high-DM ranges and that the real-time factor of Sec. 5.5
+ * counts (downsampling by `factor`): xb(c, j) = sum_{i < factor} x(c, j*factor + i)
+ * for j < n_samp / factor (a trailing partial bin is dropped).  Sums, not
+ * means, like the transform itself (no normalisation).  Integer input
+ * (dtype 1 = u8, 2 = u4, 4 = u16; pitch in bytes) -> int64 out[c][j];
+ * out_pitch in elements.  Returns -1 on bad arguments.
+ */
+int oracle_bin_int(int dtype, const uint8_t *x, int64_t pitch, int n_chan, int64_t n_samp, int factor,
+                   int64_t *out, int64_t out_pitch) {
+  if ((dtype != 1 && dtype != 2 && dtype != 4) || factor < 1 || n_chan < 1 || n_samp < 0) return -1;
+  const int64_t n_bins = n_samp / factor;
+  if (out_pitch < n_bins) return -1;
+#pragma omp parallel for schedule(static)
+  for (int c = 0; c < n_chan; ++c) {
+    for (int64_t j = 0; j < n_bins; ++j) {
+      int64_t acc = 0;
+      for (int i = 0; i < factor; ++i) {
+        const int64_t t = j * factor + i;
+        acc += dtype == 1 ? x_u8(x, pitch, c, t) : dtype == 2 ? x_u4(x, pitch, c, t) : x_u16(x, pitch, c, t);
+      }
+      out[(int64_t)c * out_pitch + j] = acc;
+    }
+  }
+  return 0;
+}
+
+/* Float binning in FP64: out[c][j] = sum_{i < factor} x[c][j*factor + i]. */
+int oracle_bin_f32(const float *x, int64_t pitch, int n_chan, int64_t n_samp, int factor, double *out,
+                   int64_t out_pitch) {
+  if (factor < 1 || n_chan < 1 || n_samp < 0) return -1;
+  const int64_t n_bins = n_samp / factor;
+  if (out_pitch < n_bins) return -1;
+#pragma omp parallel for schedule(static)
+  for (int c = 0; c < n_chan; ++c)
+    for (int64_t j = 0; j < n_bins; ++j) {
+      double acc = 0.0;
+      for (int i = 0; i < factor; ++i) acc += (double)x[(int64_t)c * pitch + j * factor + i];
+      out[(int64_t)c * out_pitch + j] = acc;
+    }
+  return 0;
+}
+
+/*
  * Forward transform for float input, in FP64.  out[r][t] is the FP64 sum and
  * abs_out (if not NULL) the FP64 sum of the absolute values of the same terms,
  * which scales the float tolerance.

@@ -2,7 +2,7 @@
 
 Builds ``liboracle.so`` with gcc (FP64, no FMA contraction, OpenMP) and exposes
 the shift table (Eq. 1 with the per-channel form of Sec. 4.1), the forward
-transform (Eq. 3 / Algorithm 1) and the scatter-form adjoint.
+transform (Eq. 3 / Algorithm 1), the scatter-form adjoint and time binning.
 """
 from __future__ import annotations
 
@@ -81,6 +81,10 @@ def _configure(lib):
     lib.oracle_forward_f32.restype = i32
     lib.oracle_adjoint_f64.argtypes = [vp, i64, i32, i64, vp, i32, i64, vp]
     lib.oracle_adjoint_f64.restype = i32
+    lib.oracle_bin_int.argtypes = [i32, vp, i64, i32, i64, i32, vp, i64]
+    lib.oracle_bin_int.restype = i32
+    lib.oracle_bin_f32.argtypes = [vp, i64, i32, i64, i32, vp, i64]
+    lib.oracle_bin_f32.restype = i32
     return lib
 
 
@@ -181,3 +185,33 @@ def adjoint(y: np.ndarray, n_chan: int, n_samp: int, shift: np.ndarray) -> np.nd
     if rc != 0:
         raise ValueError("oracle adjoint: bad arguments")
     return g
+
+
+def bin_time(x: np.ndarray, dtype: str, n_samp: int, factor: int) -> np.ndarray:
+    """Time binning by ``factor``: sums of ``factor`` consecutive samples, trailing partial bin dropped.
+
+    Integer input (uint8 for "u8"/"u4", uint16 for "u16") gives int64 [n_chan][n_samp // factor];
+    float32 input gives float64 sums.
+    """
+    lib = _load()
+    assert x.ndim == 2 and x.flags.c_contiguous
+    n_chan = x.shape[0]
+    n_bins = n_samp // factor
+    if dtype == "f32":
+        assert x.dtype == np.float32 and x.shape[1] >= n_samp
+        out = np.empty((n_chan, max(n_bins, 1)), dtype=np.float64)
+        rc = lib.oracle_bin_f32(_ptr(x), x.shape[1], n_chan, n_samp, factor, _ptr(out), out.shape[1])
+    else:
+        code = {"u8": 1, "u4": 2, "u16": 4}[dtype]
+        if code == 4:
+            assert x.dtype == np.uint16 and x.shape[1] >= n_samp
+            x = x.astype("<u2", copy=False).view(np.uint8)
+        else:
+            assert x.dtype == np.uint8
+            assert x.shape[1] >= (n_samp + 1) // 2 if code == 2 else x.shape[1] >= n_samp
+        out = np.empty((n_chan, max(n_bins, 1)), dtype=np.int64)
+        rc = lib.oracle_bin_int(code, _ptr(x), x.shape[1], n_chan, n_samp, factor, _ptr(out), out.shape[1])
+    if rc != 0:
+        raise ValueError("oracle bin: bad arguments")
+    return out[:, :n_bins]
+

@@ -423,3 +423,112 @@ def test_gradient_by_central_differences():
         fd = (loss(xp) - loss(xm)) / (2 * h)
         assert abs(fd - grad[c, t]) <= 1e-6 * max(1.0, abs(fd)), (c, t, fd, grad[c, t])
     assert grad[0, n_samp - 1] == 0.0 and grad[0, n_out] == 0.0  # channel 0 never delays
+
+
+# --------------------------------------------------------------------------------------
+# Time binning (the downsampling of Secs. 5.2, 5.3, 5.5 and 6): sums of `factor` consecutive samples
+# per channel, a trailing partial bin dropped.
+# --------------------------------------------------------------------------------------
+
+def _unpack_u4_numpy(packed, n_samp):
+    out = np.empty((packed.shape[0], packed.shape[1] * 2), dtype=np.int64)
+    out[:, 0::2] = packed & 15
+    out[:, 1::2] = packed >> 4
+    return out[:, :n_samp]
+
+
+def _bin_case(rng, dtype, n_chan, n_samp):
+    if dtype == "u8":
+        x = rng.integers(0, 256, (n_chan, n_samp)).astype(np.uint8)
+        return x, x.astype(np.int64)
+    if dtype == "u4":
+        v = rng.integers(0, 16, (n_chan, n_samp + (n_samp & 1))).astype(np.uint8)
+        packed = _pack_u4(v)
+        return packed, _unpack_u4_numpy(packed, n_samp)
+    if dtype == "u16":
+        x = rng.integers(0, 65536, (n_chan, n_samp)).astype(np.uint16)
+        return x, x.astype(np.int64)
+    x = rng.standard_normal((n_chan, n_samp)).astype(np.float32)
+    return x, x.astype(np.float64)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u4", "u16", "f32"])
+def test_bin_equals_reshape_sum(dtype):
+    """Binning equals numpy's reshape-and-sum over the whole bins, for ragged lengths."""
+    rng = np.random.default_rng({"u8": 31, "u4": 32, "u16": 33, "f32": 34}[dtype])
+    for n_samp, factor in [(1000, 1), (1000, 2), (1001, 3), (997, 7), (4099, 16), (300, 256), (255, 256)]:
+        x, vals = _bin_case(rng, dtype, 5, n_samp)
+        got = oracle.bin_time(x, dtype, n_samp, factor)
+        nb = n_samp // factor
+        want = vals[:, :nb * factor].reshape(5, nb, factor).sum(axis=2)
+        assert got.shape == (5, nb)
+        if dtype == "f32":
+            np.testing.assert_allclose(got, want, rtol=0, atol=1e-9)
+        else:
+            assert np.array_equal(got, want)
+
+
+def test_bin_factor_one_identity_constant_and_impulse():
+    rng = np.random.default_rng(35)
+    x, _ = _bin_case(rng, "u8", 3, 640)
+    assert np.array_equal(oracle.bin_time(x, "u8", 640, 1), x.astype(np.int64))
+    const = np.full((2, 640), 9, dtype=np.uint8)
+    for f in (2, 5, 64):
+        assert np.all(oracle.bin_time(const, "u8", 640, f) == 9 * f)
+    # one sample: lands in bin t // f of its own channel, or nowhere past the last whole bin
+    for t in (0, 1, 399, 400, 639):
+        imp = np.zeros((2, 640), dtype=np.uint8)
+        imp[1, t] = 200
+        got = oracle.bin_time(imp, "u8", 640, 8)
+        assert got[0].sum() == 0
+        assert got[1].sum() == 200 and got[1, t // 8] == 200
+        got3 = oracle.bin_time(imp, "u8", 640, 3)  # 213 whole bins cover samples 0..638
+        assert got3[1].sum() == (200 if t < 639 else 0)
+
+
+def test_bin_factors_compose():
+    """Binning by 2 and then by 3 equals binning by 6 (sums regroup)."""
+    rng = np.random.default_rng(36)
+    x, _ = _bin_case(rng, "u8", 4, 1203)
+    b2 = oracle.bin_time(x, "u8", 1203, 2)
+    b23 = oracle.bin_time(np.ascontiguousarray(b2.astype(np.uint16)), "u16", b2.shape[1], 3)
+    assert np.array_equal(b23, oracle.bin_time(x, "u8", 1203, 6))
+
+
+def test_binned_forward_dm0_is_sum_of_unbinned_dm0():
+    """At DM 0 every delay is zero, so the binned transform is the binned channel sum."""
+    cfg, s, x = _small()
+    n_samp, f = cfg["n_samp"], 4
+    b = oracle.bin_time(x, "u8", n_samp, f).astype(np.uint16)
+    sb = oracle.shift_table(cfg["n_chan"], cfg["f_high"], cfg["chan_bw"], cfg["t_samp"] * f, 0.0, 1.0, 1)
+    assert not sb.any()
+    got = oracle.forward(b, "u16", b.shape[1], sb)
+    assert s[0].max() == 0  # the unbinned plan's first row is DM 0 as well
+    row0 = oracle.forward(x, "u8", n_samp, s, rows=[0])[0].astype(np.int64)
+    n = len(row0) // f
+    assert np.array_equal(got[0, :n].astype(np.int64), row0[:n * f].reshape(-1, f).sum(1))
+    want = x.astype(np.int64).sum(axis=0)[:b.shape[1] * f].reshape(-1, f).sum(1)
+    assert np.array_equal(got[0].astype(np.int64), want)
+
+
+def test_binned_forward_with_delays_in_whole_bins():
+    """When every delay is a whole number of bins, binning commutes with the transform.
+
+    Channel frequencies are chosen (explicit table) so that Eq. 1 gives delays of
+    exactly f*m_c samples at the plan's single DM; on the grid of t_samp*f the same
+    frequencies give m_c bins, and S_binned(j) = sum_i S(j*f + i).
+    """
+    f_high, t_samp, dm, f = 1500.0, 64e-6, 400.0, 4
+    m = np.array([0, 1, 3, 4, 9, 13, 20, 31])
+    # f_c^-2 = f_high^-2 + f*m_c*t_samp/(k*DM), chosen with a small safety margin inside the rounding interval
+    freqs = (f_high ** -2 + f * m * t_samp / (4.148808e3 * dm)) ** -0.5
+    s1 = oracle.shift_table(len(m), f_high, 0.0, t_samp, dm, 0.0, 1, freqs=freqs)
+    sf = oracle.shift_table(len(m), f_high, 0.0, t_samp * f, dm, 0.0, 1, freqs=freqs)
+    assert s1[0].tolist() == (f * m).tolist() and sf[0].tolist() == m.tolist()
+    rng = np.random.default_rng(37)
+    n_samp = 4000
+    x = rng.integers(0, 256, (len(m), n_samp)).astype(np.uint8)
+    full = oracle.forward(x, "u8", n_samp, s1)[0].astype(np.int64)
+    b = oracle.bin_time(x, "u8", n_samp, f).astype(np.uint16)
+    got = oracle.forward(b, "u16", b.shape[1], sf)[0].astype(np.int64)
+    assert np.array_equal(got, full[:len(got) * f].reshape(-1, f).sum(1))

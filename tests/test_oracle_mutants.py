@@ -30,6 +30,11 @@ MUTANTS = {
     "16-bit bytes swapped": ("return (int64_t)p[0] | ((int64_t)p[1] << 8);", "return (int64_t)p[1] | ((int64_t)p[0] << 8);"),
     "16-bit sample stride of one byte": ("const uint8_t *p = x + (int64_t)c * pitch_bytes + 2 * t;", "const uint8_t *p = x + (int64_t)c * pitch_bytes + t;"),
     "16-bit high byte dropped": ("return (int64_t)p[0] | ((int64_t)p[1] << 8);", "return (int64_t)p[0];"),
+    "bin drops its last sample": ("for (int i = 0; i < factor; ++i) {\n        const int64_t t = j * factor + i;", "for (int i = 0; i < factor - 1; ++i) {\n        const int64_t t = j * factor + i;"),
+    "bin windows overlap": ("const int64_t t = j * factor + i;", "const int64_t t = j + i;"),
+    "bin keeps the partial last bin": ("const int64_t n_bins = n_samp / factor;\n  if (out_pitch < n_bins) return -1;\n#pragma omp parallel for schedule(static)\n  for (int c = 0; c < n_chan; ++c) {", "const int64_t n_bins = (n_samp + factor - 1) / factor;\n  if (out_pitch < n_bins) return -1;\n#pragma omp parallel for schedule(static)\n  for (int c = 0; c < n_chan; ++c) {"),
+    "bin averages instead of sums": ("      out[(int64_t)c * out_pitch + j] = acc;\n    }\n  }", "      out[(int64_t)c * out_pitch + j] = acc / factor;\n    }\n  }"),
+    "f32 bin skips first sample": ("for (int i = 0; i < factor; ++i) acc += (double)x[(int64_t)c * pitch + j * factor + i];", "for (int i = 1; i < factor; ++i) acc += (double)x[(int64_t)c * pitch + j * factor + i];"),
     "normalised by channel count": ("out[(int64_t)r * n_out + t] = (float)acc[t];", "out[(int64_t)r * n_out + t] = (float)(acc[t] / n_chan);"),
 }
 
@@ -52,6 +57,12 @@ PIN_CALLS = [
     ("dense", pins.test_forward_and_adjoint_against_dense_matrix, ()),
     ("dot exact", pins.test_adjoint_exact_dot_test_small_integers, ()),
     ("unread zero", pins.test_adjoint_unread_entries_are_zero, ()),
+    ("bin reshape u8", pins.test_bin_equals_reshape_sum, ("u8",)),
+    ("bin reshape f32", pins.test_bin_equals_reshape_sum, ("f32",)),
+    ("bin identity", pins.test_bin_factor_one_identity_constant_and_impulse, ()),
+    ("bin compose", pins.test_bin_factors_compose, ()),
+    ("binned dm0", pins.test_binned_forward_dm0_is_sum_of_unbinned_dm0, ()),
+    ("binned whole-bin delays", pins.test_binned_forward_with_delays_in_whole_bins, ()),
 ]
 
 
