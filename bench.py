@@ -10,8 +10,12 @@ x-real-time factor (N_t * t_samp / t_step), the VALU roofline fraction of the
 forward kernel, and the CPU oracle timed on a bounded sample of the same
 workload.
 
-  python bench.py [--steps K] [--warmup W] [--workload headline|lowfreq_u4|headline_u16|grad_f32|small|batch48]
+  python bench.py [--steps K] [--warmup W]
+                  [--workload headline|lowfreq_u4|headline_u16|grad_f32|small|batch48|tab_plans_8192|pipeline_high]
                   [--adjoint] [--no-cpu-baseline] [--no-autotune]
+
+The multi-range workloads (tab_plans_8192, pipeline_high) time one step as the
+whole survey: binning of the input once per factor plus every range's transform.
 """
 from __future__ import annotations
 
@@ -31,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz = 39.32e12 32-bit VALU lane-operations per second.
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
 # LDS: 128 bytes per clock per CU for 4- and 8-byte reads (the widths the accumulate loops use).
 LDS_PEAK_TBS = 256 * 128 * 2.4e9 / 1e12
 # LDS bytes the accumulate loop reads per add: one byte per 8- or 4-bit sample
@@ -293,6 +298,95 @@ def bench_batch48(args, dd, torch, synth):
     print(json.dumps(rec), flush=True)
 
 
+def bench_survey(args, dd, torch, synth):
+    """Multi-range DM plan (binning + one transform per range) over one 8-bit filterbank."""
+    cfg = synth.SURVEYS[args.workload]
+    n_chan, n_samp, t_samp = cfg["n_chan"], cfg["n_samp"], cfg["t_samp"]
+    pitch = (n_samp + 63) // 64 * 64
+    log("survey %s: %s" % (args.workload, {k: v for k, v in cfg.items() if k != "pulses"}))
+    sv = dd.Survey(n_chan, n_samp, "u8", cfg["f_high"], cfg["chan_bw"], t_samp, cfg["ranges"], in_pitch_bytes=pitch)
+    stream = torch.cuda.current_stream()
+    x = torch.empty((n_chan, pitch), dtype=torch.uint8, device="cuda")
+    table = torch.from_numpy(synth.gaussian_table()).cuda()
+    synth.gaussian_u8_device(x.data_ptr(), n_chan, n_samp, pitch, cfg["seed"], table.data_ptr(), stream.cuda_stream)
+    for dm, width, t0 in cfg["pulses"]:
+        delay = dd.Plan(n_chan, n_samp, "u8", cfg["f_high"], cfg["chan_bw"], t_samp, dm, 0.0, 1,
+                        in_pitch_bytes=pitch, bind=False).shift[0]
+
+        def at(r, c):
+            return x[torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda()].cpu().numpy()
+        rows, cols, vals, _ = synth.boxcar_updates(at, delay, t0, width, cfg["amp"])
+        x[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()] = torch.from_numpy(vals).cuda()
+    outs = sv.empty_outputs()
+    torch.cuda.synchronize()
+    tune_s = None
+    if not args.no_autotune:
+        t = time.perf_counter()
+        sv.autotune(x, outs)
+        tune_s = time.perf_counter() - t
+        log("autotune %.1f s" % tune_s)
+    for _ in range(args.warmup):
+        sv.run(x, outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sv.run(x, outs)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / args.steps
+    adds = float(sum(ri["n_dm"] * ri["n_out"] for ri in sv.range_info)) * n_chan
+
+    # Per-kernel breakdown: the same kernels launched one by one (binning into
+    # buffers of the survey's layout, each range through a plan with the survey's
+    # tile choice), each timed with HIP events on the current stream.
+    def timed(fn, reps):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+    binned, bins = {}, []
+    for f in sorted({r[3] for r in cfg["ranges"] if r[3] > 1}):
+        nb = n_samp // f
+        binned[f] = torch.empty((n_chan, (2 * nb + 255) // 256 * 128), dtype=torch.uint16, device="cuda")
+        ms = timed(lambda f=f: dd.bin_time(x, "u8", n_samp, f, out=binned[f]), 5)
+        nbytes = float(n_chan) * (nb * f + 2 * nb)  # whole bins read once, uint16 sums written once
+        bins.append({"factor": f, "ms": ms, "bytes": nbytes, "GB_s": nbytes / ms / 1e6,
+                     "frac_hbm": nbytes / ms / 1e6 / HBM_PEAK_GBS})
+    parts = []
+    for r, (start, step, n_dm, b) in enumerate(cfg["ranges"]):
+        ri = sv.range_info[r]
+        src = x if b == 1 else binned[b]
+        p = dd.Plan(n_chan, ri["n_samp"], ri["dtype"], cfg["f_high"], cfg["chan_bw"], ri["t_samp"], start, step,
+                    n_dm, in_pitch_bytes=src.stride(0) * src.element_size())
+        tl = sv.tiles(r)
+        p.set_tiles(0, tl["shape"], tl["order"])
+        ms = timed(lambda: p.forward(src, out=outs[r]), max(1, args.steps // 2))
+        a = float(n_dm) * ri["n_out"] * n_chan
+        parts.append({"range": r, "dm_start": start, "dm_step": step, "n_dm": n_dm, "bin": b, "input": ri["dtype"],
+                      "n_out": ri["n_out"], "ms": ms, "Tadds_s": a / ms / 1e9, "tiles": tl})
+        del p
+    dom = max(parts, key=lambda q: q["ms"])
+    log("survey parts: %s; bins: %s" % (parts, bins))
+    rec = {
+        "metric": "Tadds/s (multi-range survey)", "value": adds / ms_step / 1e9, "unit": "Tadds/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": args.workload, "n_chan": n_chan, "n_samp": n_samp, "t_samp_s": t_samp,
+                   "f_high_mhz": cfg["f_high"], "band_mhz": cfg["chan_bw"] * n_chan, "ranges": cfg["ranges"],
+                   "adds_per_step": adds},
+        "x_realtime": n_samp * t_samp / (ms_step * 1e-3),
+        "roofline": {"bound": "alu", "achieved": dom["Tadds_s"], "peak": VALU_PEAK_TOPS, "unit": "Tadds/s",
+                     "frac": dom["Tadds_s"] / VALU_PEAK_TOPS, "traffic": None, "kernel": "fwd_int_kernel",
+                     "range": dom["range"], "kernel_ms": dom["ms"]},
+        "parts": parts, "binning": bins, "autotune_s": tune_s,
+        "sum_of_parts_ms": sum(q["ms"] for q in parts) + sum(q["ms"] for q in bins),
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -319,6 +413,8 @@ def main():
 
     if args.workload == "batch48":
         return bench_batch48(args, dd, torch, synth)
+    if args.workload in synth.SURVEYS:
+        return bench_survey(args, dd, torch, synth)
     cfg = synth.CONFIGS[args.workload]
     log("workload %s: %s" % (args.workload, {k: v for k, v in cfg.items() if k != "pulses"}))
     t = time.perf_counter()

@@ -233,6 +233,80 @@ dd_status dd_batch_bind(dd_batch *batch, const void *const *d_in, float *const *
 dd_status dd_execute_batched(dd_batch *batch, void *stream);
 void dd_batch_destroy(dd_batch *batch);
 
+/*
+ * Time binning ("downsampling"), which Secs. 5.2 and 5.3 apply to the input of
+ * high-DM ranges and whose cost the real-time factor of Sec. 5.5 includes:
+ *
+ *     out(c, j) = sum_{i < factor} x(c, j*factor + i),   0 <= j < n_bins = n_samp / factor,
+ *
+ * sums without normalisation; a trailing partial bin is dropped.
+ *   dtype      input encoding (a dd_dtype); the output encoding is
+ *              dd_bin_out_dtype(dtype): DD_U8 and DD_U4 give exact uint16 sums,
+ *              DD_U16 gives float32 holding the exact integer sums, DD_F32 gives
+ *              float32 sums (float32 arithmetic, an order that depends only on
+ *              `factor`).
+ *   d_in       device pointer, [n_chan] rows of in_pitch_bytes (>= one packed row,
+ *              multiple of 16); samples 0..n_bins*factor-1 of each row are read.
+ *   factor     1..256 (keeps every integer sum exact in its output type).
+ *   d_out      device pointer, [n_chan] rows of out_pitch_bytes (>= n_bins output
+ *              elements, multiple of 16); columns 0..n_bins-1 are written, nothing
+ *              else.  Must not overlap d_in.
+ * Both pointers 16-byte aligned.  Asynchronous on `stream`; allocates nothing.
+ * Errors: DD_ERR_ARG, DD_ERR_TOO_SHORT (n_bins == 0), DD_ERR_ALIGN, DD_ERR_RANGE, DD_ERR_HIP.
+ */
+dd_status dd_bin_time(int32_t dtype, const void *d_in, int64_t in_pitch_bytes, int32_t n_chan, int64_t n_samp,
+                      int32_t factor, void *d_out, int64_t out_pitch_bytes, void *stream);
+/* Output encoding of dd_bin_time for an input encoding (0 for an unknown one). */
+int32_t dd_bin_out_dtype(int32_t dtype);
+
+/*
+ * Multi-range DM plan ("survey"): several DM ranges, each with its own fixed
+ * step and time-binning factor, over one filterbank (the plan of Table
+ * tab:plans in Sec. 5.2; the binned high-DM ranges of Sec. 5.3).
+ *
+ * Range r is an ordinary plan over the input binned by bin_r: n_samp / bin_r
+ * samples of t_samp * bin_r seconds in encoding dd_bin_out_dtype(dtype) (the
+ * input itself when bin_r == 1), with DM_d = dm_start_r + d * dm_step_r.  Its
+ * output is that plan's S(d, t), t counted in binned samples.  Ranges that
+ * share a factor share one binned copy.
+ *
+ * dd_survey_create: `base` gives the filterbank (n_chan, n_samp, dtype, band,
+ *   t_samp_s, in_pitch_bytes); its DM fields are ignored.  ranges[0..n-1]:
+ *   n_dm > 0, dm_step >= 0, dm_start >= 0, bin in 1..256.  Errors as
+ *   dd_plan_create for each range's plan, plus DD_ERR_ARG.
+ * dd_survey_plan: the plan of range r, owned by the survey (query it for
+ *   n_out; re-tiling it through dd_plan_set_tiles unbinds the survey).
+ * dd_survey_workspace_bytes: device workspace dd_survey_bind needs: the binned
+ *   copies plus every range's tables at their largest (so re-tiling or tuning
+ *   a range never changes the layout).
+ * dd_survey_bind: lay the workspace out (16-byte aligned, >= the size above)
+ *   and enqueue the table uploads on `stream`.  Errors: DD_ERR_ARG, DD_ERR_ALIGN, DD_ERR_HIP.
+ * dd_survey_autotune: bin the input, then dd_plan_autotune every range
+ *   (forward) on its own input and d_out[r]; leaves the survey bound.  Synchronises `stream`.
+ * dd_survey_execute: on `stream`, bin the input once per distinct factor > 1,
+ *   then run every range's forward transform: d_out[r] is float32
+ *   [n_dm_r][out_pitch[r]] as for dd_execute of range r's plan.
+ *   Errors: DD_ERR_ARG, DD_ERR_ALIGN, DD_ERR_NOT_BOUND, DD_ERR_HIP.
+ */
+typedef struct {
+  double dm_start; /* first trial DM of the range, pc cm^-3 */
+  double dm_step;  /* DM step of the range */
+  int32_t n_dm;    /* trial DMs in the range */
+  int32_t bin;     /* time-binning factor applied to the input for this range, 1..256 */
+} dd_range;
+
+typedef struct dd_survey dd_survey;
+
+dd_status dd_survey_create(const dd_plan_desc *base, const dd_range *ranges, int32_t n_ranges, dd_survey **out);
+dd_status dd_survey_plan(const dd_survey *survey, int32_t r, dd_plan **plan);
+dd_status dd_survey_workspace_bytes(const dd_survey *survey, size_t *bytes);
+dd_status dd_survey_bind(dd_survey *survey, void *d_workspace, size_t bytes, void *stream);
+dd_status dd_survey_autotune(dd_survey *survey, const void *d_in, float *const *d_out, const int64_t *out_pitch,
+                             void *stream);
+dd_status dd_survey_execute(const dd_survey *survey, const void *d_in, float *const *d_out,
+                            const int64_t *out_pitch, void *stream);
+void dd_survey_destroy(dd_survey *survey);
+
 /* Static text for a status code, and the calling thread's last error detail. */
 const char *dd_status_string(dd_status status);
 const char *dd_last_error(void);

@@ -10,10 +10,13 @@ from .binding import (  # noqa: F401
     DD_U4,
     DD_U8,
     LIB_PATH,
+    BIN_OUT,
     Batch,
     DDError,
     DedisperseFn,
     Plan,
+    Survey,
+    bin_time,
     dedisperse,
 )
 from .chunks import TimeChunks  # noqa: F401

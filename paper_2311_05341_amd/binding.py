@@ -90,6 +90,31 @@ _lib.dd_execute_batched.argtypes = [_vp, _vp]
 _lib.dd_execute_batched.restype = _i32
 _lib.dd_batch_destroy.argtypes = [_vp]
 _lib.dd_batch_destroy.restype = None
+_lib.dd_bin_time.argtypes = [_i32, _vp, _i64, _i32, _i64, _i32, _vp, _i64, _vp]
+_lib.dd_bin_time.restype = _i32
+_lib.dd_bin_out_dtype.argtypes = [_i32]
+_lib.dd_bin_out_dtype.restype = _i32
+
+
+class Range(ctypes.Structure):
+    _fields_ = [("dm_start", ctypes.c_double), ("dm_step", ctypes.c_double), ("n_dm", ctypes.c_int32),
+                ("bin", ctypes.c_int32)]
+
+
+_lib.dd_survey_create.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(Range), _i32, ctypes.POINTER(_vp)]
+_lib.dd_survey_create.restype = _i32
+_lib.dd_survey_plan.argtypes = [_vp, _i32, ctypes.POINTER(_vp)]
+_lib.dd_survey_plan.restype = _i32
+_lib.dd_survey_workspace_bytes.argtypes = [_vp, ctypes.POINTER(_sz)]
+_lib.dd_survey_workspace_bytes.restype = _i32
+_lib.dd_survey_bind.argtypes = [_vp, _vp, _sz, _vp]
+_lib.dd_survey_bind.restype = _i32
+_lib.dd_survey_autotune.argtypes = [_vp, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_i64), _vp]
+_lib.dd_survey_autotune.restype = _i32
+_lib.dd_survey_execute.argtypes = [_vp, _vp, ctypes.POINTER(_vp), ctypes.POINTER(_i64), _vp]
+_lib.dd_survey_execute.restype = _i32
+_lib.dd_survey_destroy.argtypes = [_vp]
+_lib.dd_survey_destroy.restype = None
 _lib.dd_status_string.argtypes = [_i32]
 _lib.dd_status_string.restype = ctypes.c_char_p
 _lib.dd_last_error.argtypes = []
@@ -118,6 +143,17 @@ def _round_up(v: int, a: int) -> int:
     return (v + a - 1) // a * a
 
 
+def _desc(n_chan, n_samp, dtype, f_high, chan_bw, t_samp, dm_start, dm_step, n_dm, freqs, in_pitch_bytes):
+    d = PlanDesc()
+    d.n_chan, d.n_samp, d.dtype = int(n_chan), int(n_samp), _DTYPES[dtype]
+    d.f_high_mhz, d.chan_bw_mhz, d.t_samp_s = float(f_high), float(chan_bw), float(t_samp)
+    d.dm_start, d.dm_step, d.n_dm = float(dm_start), float(dm_step), int(n_dm)
+    d.in_pitch_bytes = int(in_pitch_bytes)
+    if freqs is not None:
+        d.chan_freq_mhz = freqs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return d
+
+
 class Plan:
     """A dedispersion plan bound to the current device.
 
@@ -129,15 +165,9 @@ class Plan:
     def __init__(self, n_chan, n_samp, dtype, f_high, chan_bw, t_samp, dm_start, dm_step, n_dm,
                  chan_freq=None, in_pitch_bytes=0, device=None, bind=True):
         self.dtype = dtype
-        self._freqs = None
-        d = PlanDesc()
-        d.n_chan, d.n_samp, d.dtype = int(n_chan), int(n_samp), _DTYPES[dtype]
-        d.f_high_mhz, d.chan_bw_mhz, d.t_samp_s = float(f_high), float(chan_bw), float(t_samp)
-        d.dm_start, d.dm_step, d.n_dm = float(dm_start), float(dm_step), int(n_dm)
-        d.in_pitch_bytes = int(in_pitch_bytes)
-        if chan_freq is not None:
-            self._freqs = np.ascontiguousarray(chan_freq, dtype=np.float64)
-            d.chan_freq_mhz = self._freqs.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self._freqs = None if chan_freq is None else np.ascontiguousarray(chan_freq, dtype=np.float64)
+        d = _desc(n_chan, n_samp, dtype, f_high, chan_bw, t_samp, dm_start, dm_step, n_dm, self._freqs,
+                  in_pitch_bytes)
         h = _vp()
         _check(_lib.dd_plan_create(ctypes.byref(d), ctypes.byref(h)), "dd_plan_create")
         self._h = h
@@ -343,3 +373,150 @@ class Batch:
         if h is not None and _lib is not None:
             _lib.dd_batch_destroy(h)
             self._h = None
+
+
+#: Output encoding of time binning per input encoding (dd_bin_out_dtype).
+BIN_OUT = {"u8": "u16", "u4": "u16", "u16": "f32", "f32": "f32"}
+
+
+def _row_bytes(dtype, n_samp):
+    return {"u8": n_samp, "u4": (n_samp + 1) // 2, "u16": 2 * n_samp, "f32": 4 * n_samp}[dtype]
+
+
+def _check_rows(x, dtype, n_rows, n_samp, what):
+    tdt, eb = _IN_TORCH[dtype]
+    if x.dtype != tdt or x.dim() != 2 or x.shape[0] != n_rows or x.stride(1) != 1 or x.device.type != "cuda":
+        raise ValueError("%s must be a %s [%d][...] CUDA tensor with contiguous rows" % (what, tdt, n_rows))
+    if x.shape[1] * eb < _row_bytes(dtype, n_samp):
+        raise ValueError("%s rows are shorter than %d samples" % (what, n_samp))
+    if (x.stride(0) * eb) % 16 or x.data_ptr() % 16:
+        raise ValueError("%s must be 16-byte aligned with a row pitch that is a multiple of 16 bytes" % what)
+
+
+def bin_time(x, dtype, n_samp, factor, out=None, stream=None):
+    """Time binning (dd_bin_time): sums of ``factor`` consecutive samples of every row.
+
+    x: [n_chan][>= row] tensor in encoding ``dtype``; returns the binned rows,
+    encoding BIN_OUT[dtype], as a [n_chan][n_samp // factor] view of ``out``
+    (allocated with 16-byte rows when not given)."""
+    n_chan = x.shape[0]
+    _check_rows(x, dtype, n_chan, n_samp, "input")
+    n_bins = n_samp // factor
+    odt = BIN_OUT[dtype]
+    ot, ob = _IN_TORCH[odt]
+    if out is None:
+        out = torch.empty((n_chan, _round_up(max(n_bins, 1) * ob, 16) // ob), dtype=ot, device=x.device)
+    _check_rows(out, odt, n_chan, n_bins, "out")
+    with torch.cuda.device(x.device):
+        _check(_lib.dd_bin_time(_DTYPES[dtype], x.data_ptr(), x.stride(0) * _IN_TORCH[dtype][1], n_chan, n_samp,
+                                int(factor), out.data_ptr(), out.stride(0) * ob, _stream_handle(stream)),
+               "dd_bin_time")
+    return out[:, :n_bins]
+
+
+class Survey:
+    """Several DM ranges over one filterbank, each with its own step and time binning (dd_survey_*).
+
+    ranges: sequence of (dm_start, dm_step, n_dm, bin).  Range r is dedispersed
+    from the input binned by ``bin`` (n_samp // bin samples of t_samp * bin);
+    ``run`` returns one float32 [n_dm_r][n_out_r] view per range."""
+
+    def __init__(self, n_chan, n_samp, dtype, f_high, chan_bw, t_samp, ranges, chan_freq=None,
+                 in_pitch_bytes=0, device=None, stream=None, bind=True):
+        self.dtype = dtype
+        self.n_chan, self.n_samp = int(n_chan), int(n_samp)
+        self._freqs = None if chan_freq is None else np.ascontiguousarray(chan_freq, dtype=np.float64)
+        d = _desc(n_chan, n_samp, dtype, f_high, chan_bw, t_samp, 0.0, 0.0, 1, self._freqs, in_pitch_bytes)
+        rs = (Range * len(ranges))()
+        for i, (start, step, n_dm, b) in enumerate(ranges):
+            rs[i].dm_start, rs[i].dm_step, rs[i].n_dm, rs[i].bin = float(start), float(step), int(n_dm), int(b)
+        h = _vp()
+        _check(_lib.dd_survey_create(ctypes.byref(d), rs, len(ranges), ctypes.byref(h)), "dd_survey_create")
+        self._h = h
+        self.ranges = [tuple(r) for r in ranges]
+        self.in_pitch_bytes = int(in_pitch_bytes) or _row_bytes(dtype, self.n_samp)
+        self.range_info = []
+        for r, (start, step, n_dm, b) in enumerate(self.ranges):
+            ph = _vp()
+            _check(_lib.dd_survey_plan(h, r, ctypes.byref(ph)), "dd_survey_plan")
+            info = PlanInfo()
+            _check(_lib.dd_plan_query(ph, ctypes.byref(info)), "dd_plan_query")
+            n_out = int(info.n_out)
+            self.range_info.append({"n_dm": int(n_dm), "bin": int(b), "n_out": n_out, "out_pitch": _round_up(n_out, 4),
+                                    "n_samp": self.n_samp // int(b), "t_samp": float(t_samp) * int(b),
+                                    "dtype": dtype if int(b) == 1 else BIN_OUT[dtype],
+                                    "max_shift": int(info.max_shift)})
+        nbytes = _sz()
+        _check(_lib.dd_survey_workspace_bytes(h, ctypes.byref(nbytes)), "dd_survey_workspace_bytes")
+        self.workspace_bytes = int(nbytes.value)
+        self.workspace = self.device = None
+        if bind:
+            self.bind(device, stream)
+
+    def bind(self, device=None, stream=None):
+        """Allocate the workspace on ``device`` and bind (dd_survey_bind)."""
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+        nbytes = self.workspace_bytes
+        h = self._h
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=self.device)
+            _check(_lib.dd_survey_bind(h, self.workspace.data_ptr(), self.workspace.numel(), _stream_handle(stream)),
+                   "dd_survey_bind")
+
+    def tiles(self, r) -> dict:
+        """Forward tile choice of range r's plan."""
+        ph = _vp()
+        _check(_lib.dd_survey_plan(self._h, r, ctypes.byref(ph)), "dd_survey_plan")
+        t = Tiles()
+        _check(_lib.dd_plan_get_tiles(ph, 0, ctypes.byref(t)), "dd_plan_get_tiles")
+        return t.as_dict()
+
+    def shift(self, r) -> np.ndarray:
+        """Copy of range r's shift table (in binned samples), int32 [n_dm][n_chan]."""
+        ph = _vp()
+        _check(_lib.dd_survey_plan(self._h, r, ctypes.byref(ph)), "dd_survey_plan")
+        info = PlanInfo()
+        _check(_lib.dd_plan_query(ph, ctypes.byref(info)), "dd_plan_query")
+        n_dm = self.range_info[r]["n_dm"]
+        a = np.ctypeslib.as_array(info.host_shift, shape=(n_dm * self.n_chan,))
+        return a.reshape(n_dm, self.n_chan).copy()
+
+    def empty_outputs(self):
+        return [torch.empty((ri["n_dm"], ri["out_pitch"]), dtype=torch.float32, device=self.device)
+                for ri in self.range_info]
+
+    def _args(self, x, outs):
+        _check_rows(x, self.dtype, self.n_chan, self.n_samp, "input")
+        if x.device != self.device:
+            raise ValueError("input must be on %s" % self.device)
+        if outs is None:
+            outs = self.empty_outputs()
+        if len(outs) != len(self.range_info):
+            raise ValueError("one output per range")
+        for o, ri in zip(outs, self.range_info):
+            if (o.dtype != torch.float32 or o.device != self.device or o.dim() != 2 or o.shape[0] != ri["n_dm"]
+                    or o.shape[1] < ri["n_out"] or o.stride(1) != 1):
+                raise ValueError("outputs must be float32 [n_dm][>= n_out] with contiguous rows on %s" % self.device)
+        n = len(outs)
+        return outs, (_vp * n)(*[o.data_ptr() for o in outs]), (_i64 * n)(*[o.stride(0) for o in outs])
+
+    def run(self, x, outs=None, stream=None):
+        outs, ptrs, pitches = self._args(x, outs)
+        with torch.cuda.device(self.device):
+            _check(_lib.dd_survey_execute(self._h, x.data_ptr(), ptrs, pitches, _stream_handle(stream)),
+                   "dd_survey_execute")
+        return [o[:, : ri["n_out"]] for o, ri in zip(outs, self.range_info)]
+
+    def autotune(self, x, outs=None, stream=None):
+        """Tune every range's forward tiles on its own (binned) input; outputs are overwritten."""
+        outs, ptrs, pitches = self._args(x, outs)
+        with torch.cuda.device(self.device):
+            _check(_lib.dd_survey_autotune(self._h, x.data_ptr(), ptrs, pitches, _stream_handle(stream)),
+                   "dd_survey_autotune")
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and _lib is not None:
+            _lib.dd_survey_destroy(h)
+            self._h = None
+

@@ -143,4 +143,10 @@ struct BatchLaunch {
 };
 int batch_kernels(int ns, int dm_per_wave, int waves, int chan_block, int dtype, int lds_bytes, BatchLaunch *out);
 
+// Time binning (bin.hip): bytes per output element, and the launch.  The
+// caller has validated every argument (sizes, alignment, factor 1..256).
+int bin_out_bytes(int dtype);
+int launch_bin(int dtype, const void *in, int64_t in_pitch, int n_chan, int64_t n_samp, int factor, void *out,
+               int64_t out_pitch, void *stream);
+
 }  // namespace dd

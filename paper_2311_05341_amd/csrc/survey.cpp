@@ -1,0 +1,253 @@
+// Time binning and multi-range DM plans ("surveys"): the C ABI of the binning
+// kernels, and a survey object that bins the input once per factor and runs
+// one ordinary plan per DM range.  Declarations and contracts are in include/dd.h.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dd_internal.h"
+
+struct dd_survey {
+  int32_t n_chan = 0;
+  int64_t n_samp = 0;
+  int32_t dtype = 0;
+  int64_t in_pitch = 0;
+  std::vector<dd_range> ranges;
+  std::vector<dd_plan *> plans;     // one per range, owned
+  std::vector<int> slot_factor;     // distinct binning factors > 1, in first-use order
+  std::vector<int64_t> slot_pitch;  // bytes per binned row
+  std::vector<size_t> slot_off;     // workspace offset of each binned copy
+  std::vector<int> range_slot;      // per range: its binned copy, or -1 for the input itself
+  std::vector<size_t> tab_off, tab_bytes;  // per range: its tables in the workspace
+  size_t ws_bytes = 0;
+  // binding
+  uint8_t *ws = nullptr;
+  int device = -1;
+  bool bound = false;
+
+  ~dd_survey() {
+    for (dd_plan *p : plans) dd_plan_destroy(p);
+  }
+};
+
+namespace dd {
+namespace {
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int64_t input_row_bytes(int dtype, int64_t n_samp) {
+  switch (dtype) {
+    case DD_U8: return n_samp;
+    case DD_U4: return (n_samp + 1) / 2;
+    case DD_U16: return 2 * n_samp;
+    case DD_F32: return 4 * n_samp;
+  }
+  return -1;
+}
+
+bool valid_dtype(int dtype) { return dtype == DD_U8 || dtype == DD_U4 || dtype == DD_U16 || dtype == DD_F32; }
+
+// Input sources of every range: the caller's input or a binned copy.
+const void *range_input(const dd_survey &s, int r, const void *d_in) {
+  const int slot = s.range_slot[r];
+  return slot < 0 ? d_in : (const void *)(s.ws + s.slot_off[slot]);
+}
+
+dd_status check_survey_exec(const dd_survey *s, const void *d_in, float *const *d_out, const int64_t *out_pitch) {
+  if (!s || !d_in || !d_out || !out_pitch) return fail(DD_ERR_ARG, "null argument");
+  if (!s->bound) return fail(DD_ERR_NOT_BOUND, "survey is not bound to device workspace");
+  int dev = -1;
+  if (hipGetDevice(&dev) == hipSuccess && dev != s->device) return fail(DD_ERR_ARG, "survey is bound on another device");
+  if (!aligned16(d_in)) return fail(DD_ERR_ALIGN, "input must be 16-byte aligned");
+  for (size_t r = 0; r < s->plans.size(); ++r) {
+    const dd_plan &p = *s->plans[r];
+    if (!p.bound) return fail(DD_ERR_NOT_BOUND, "range " + std::to_string(r) + " was re-tiled: bind the survey again");
+    if (!d_out[r]) return fail(DD_ERR_ARG, "null output of range " + std::to_string(r));
+    if (!aligned16(d_out[r])) return fail(DD_ERR_ALIGN, "outputs must be 16-byte aligned");
+    if (out_pitch[r] < p.n_out) return fail(DD_ERR_ARG, "out_pitch < n_out for range " + std::to_string(r));
+    if (out_pitch[r] % 4) return fail(DD_ERR_ALIGN, "out_pitch must be a multiple of 4 elements");
+  }
+  return DD_OK;
+}
+
+dd_status bin_all(const dd_survey &s, const void *d_in, void *stream) {
+  for (size_t k = 0; k < s.slot_factor.size(); ++k) {
+    const int e = launch_bin(s.dtype, d_in, s.in_pitch, s.n_chan, s.n_samp, s.slot_factor[k], s.ws + s.slot_off[k],
+                             s.slot_pitch[k], stream);
+    if (e) return hip_error(e, "binning launch");
+  }
+  return DD_OK;
+}
+
+}  // namespace
+}  // namespace dd
+
+using namespace dd;
+
+extern "C" {
+
+int32_t dd_bin_out_dtype(int32_t dtype) {
+  if (dtype == DD_U8 || dtype == DD_U4) return DD_U16;
+  if (dtype == DD_U16 || dtype == DD_F32) return DD_F32;
+  return 0;
+}
+
+dd_status dd_bin_time(int32_t dtype, const void *d_in, int64_t in_pitch, int32_t n_chan, int64_t n_samp,
+                      int32_t factor, void *d_out, int64_t out_pitch, void *stream) {
+  if (!valid_dtype(dtype)) return fail(DD_ERR_ARG, "unknown dtype");
+  if (!d_in || !d_out) return fail(DD_ERR_ARG, "null buffer");
+  if (n_chan <= 0 || n_samp <= 0) return fail(DD_ERR_ARG, "n_chan and n_samp must be positive");
+  if (factor < 1 || factor > 256) return fail(DD_ERR_ARG, "factor must be in 1..256");
+  if (n_samp >= ((int64_t)1 << 40)) return fail(DD_ERR_RANGE, "n_samp must be below 2^40");
+  const int64_t n_bins = n_samp / factor;
+  if (n_bins == 0) return fail(DD_ERR_TOO_SHORT, "n_samp < factor: no whole bin");
+  if (!aligned16(d_in) || !aligned16(d_out)) return fail(DD_ERR_ALIGN, "buffers must be 16-byte aligned");
+  if (in_pitch < input_row_bytes(dtype, n_samp)) return fail(DD_ERR_ARG, "in_pitch_bytes smaller than one row");
+  if (out_pitch < n_bins * bin_out_bytes(dtype)) return fail(DD_ERR_ARG, "out_pitch_bytes smaller than one binned row");
+  if (in_pitch % 16 || out_pitch % 16) return fail(DD_ERR_ALIGN, "row pitches must be multiples of 16 bytes");
+  if ((double)in_pitch * n_chan > 9.0e18 || (double)out_pitch * n_chan > 9.0e18) return fail(DD_ERR_RANGE, "size overflow");
+  const uintptr_t a0 = (uintptr_t)d_in, a1 = a0 + (uintptr_t)(in_pitch * n_chan);
+  const uintptr_t b0 = (uintptr_t)d_out, b1 = b0 + (uintptr_t)(out_pitch * n_chan);
+  if (a0 < b1 && b0 < a1) return fail(DD_ERR_ARG, "input and output overlap");
+  const int e = launch_bin(dtype, d_in, in_pitch, n_chan, n_samp, factor, d_out, out_pitch, stream);
+  if (e) return hip_error(e, "binning launch");
+  return DD_OK;
+}
+
+dd_status dd_survey_create(const dd_plan_desc *base, const dd_range *ranges, int32_t n_ranges, dd_survey **out) {
+  if (!base || !ranges || !out) return fail(DD_ERR_ARG, "null argument");
+  *out = nullptr;
+  if (n_ranges <= 0) return fail(DD_ERR_ARG, "a survey needs at least one range");
+  if (!valid_dtype(base->dtype)) return fail(DD_ERR_ARG, "unknown dtype");
+  if (base->n_chan <= 0 || base->n_samp <= 0) return fail(DD_ERR_ARG, "n_chan and n_samp must be positive");
+  const int64_t row = input_row_bytes(base->dtype, base->n_samp);
+  const int64_t pitch = base->in_pitch_bytes ? base->in_pitch_bytes : row;
+  if (pitch < row) return fail(DD_ERR_ARG, "in_pitch_bytes smaller than one row");
+  if (pitch % 16) return fail(DD_ERR_ALIGN, "input row pitch must be a multiple of 16 bytes");
+  for (int r = 0; r < n_ranges; ++r) {
+    if (ranges[r].bin < 1 || ranges[r].bin > 256) return fail(DD_ERR_ARG, "range " + std::to_string(r) + ": bin must be in 1..256");
+    if (base->n_samp / ranges[r].bin == 0) return fail(DD_ERR_TOO_SHORT, "range " + std::to_string(r) + ": no whole bin");
+  }
+
+  dd_survey *s = new (std::nothrow) dd_survey();
+  if (!s) return fail(DD_ERR_NOMEM, "survey allocation failed");
+  try {
+    s->n_chan = base->n_chan;
+    s->n_samp = base->n_samp;
+    s->dtype = base->dtype;
+    s->in_pitch = pitch;
+    s->ranges.assign(ranges, ranges + n_ranges);
+    const int ob = bin_out_bytes(base->dtype);
+    size_t off = 0;
+    for (int r = 0; r < n_ranges; ++r) {
+      const int f = ranges[r].bin;
+      int slot = -1;
+      if (f > 1) {
+        for (size_t k = 0; k < s->slot_factor.size(); ++k)
+          if (s->slot_factor[k] == f) slot = (int)k;
+        if (slot < 0) {
+          slot = (int)s->slot_factor.size();
+          const int64_t bp = (int64_t)round_up((size_t)(base->n_samp / f) * ob, 256);
+          s->slot_factor.push_back(f);
+          s->slot_pitch.push_back(bp);
+          s->slot_off.push_back(off);
+          off += round_up((size_t)bp * (size_t)base->n_chan, 256);
+        }
+      }
+      s->range_slot.push_back(slot);
+      dd_plan_desc d = *base;
+      d.dm_start = ranges[r].dm_start;
+      d.dm_step = ranges[r].dm_step;
+      d.n_dm = ranges[r].n_dm;
+      if (f > 1) {
+        d.dtype = dd_bin_out_dtype(base->dtype);
+        d.n_samp = base->n_samp / f;
+        d.t_samp_s = base->t_samp_s * f;
+        d.in_pitch_bytes = s->slot_pitch[slot];
+      } else {
+        d.in_pitch_bytes = pitch;
+      }
+      dd_plan *p = nullptr;
+      const dd_status st = dd_plan_create(&d, &p);
+      if (st != DD_OK) {
+        const std::string msg = "range " + std::to_string(r) + ": " + dd_last_error();
+        delete s;
+        return fail(st, msg);
+      }
+      s->plans.push_back(p);
+    }
+    for (dd_plan *p : s->plans) {
+      const size_t tb = round_up(tune_table_bytes(*p), 256);
+      s->tab_off.push_back(off);
+      s->tab_bytes.push_back(tb);
+      off += tb;
+    }
+    s->ws_bytes = off;
+  } catch (const std::bad_alloc &) {
+    delete s;
+    return fail(DD_ERR_NOMEM, "survey allocation failed");
+  }
+  *out = s;
+  return DD_OK;
+}
+
+dd_status dd_survey_plan(const dd_survey *s, int32_t r, dd_plan **plan) {
+  if (!s || !plan) return fail(DD_ERR_ARG, "null argument");
+  if (r < 0 || r >= (int32_t)s->plans.size()) return fail(DD_ERR_ARG, "range index out of range");
+  *plan = s->plans[r];
+  return DD_OK;
+}
+
+dd_status dd_survey_workspace_bytes(const dd_survey *s, size_t *bytes) {
+  if (!s || !bytes) return fail(DD_ERR_ARG, "null argument");
+  *bytes = s->ws_bytes;
+  return DD_OK;
+}
+
+dd_status dd_survey_bind(dd_survey *s, void *ws, size_t bytes, void *stream) {
+  if (!s || !ws) return fail(DD_ERR_ARG, "null argument");
+  if (!aligned16(ws)) return fail(DD_ERR_ALIGN, "workspace must be 16-byte aligned");
+  if (bytes < s->ws_bytes) return fail(DD_ERR_ARG, "workspace smaller than dd_survey_workspace_bytes");
+  s->bound = false;
+  int dev = -1;
+  const hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+  for (size_t r = 0; r < s->plans.size(); ++r) {
+    const dd_status st = dd_plan_bind(s->plans[r], (uint8_t *)ws + s->tab_off[r], s->tab_bytes[r], stream);
+    if (st != DD_OK) return st;
+  }
+  s->ws = (uint8_t *)ws;
+  s->device = dev;
+  s->bound = true;
+  return DD_OK;
+}
+
+dd_status dd_survey_autotune(dd_survey *s, const void *d_in, float *const *d_out, const int64_t *out_pitch,
+                             void *stream) {
+  dd_status st = check_survey_exec(s, d_in, d_out, out_pitch);
+  if (st != DD_OK) return st;
+  st = bin_all(*s, d_in, stream);
+  for (size_t r = 0; r < s->plans.size() && st == DD_OK; ++r)
+    st = dd_plan_autotune(s->plans[r], 0, range_input(*s, (int)r, d_in), d_out[r], out_pitch[r], s->ws + s->tab_off[r],
+                          s->tab_bytes[r], stream, nullptr);
+  return st;
+}
+
+dd_status dd_survey_execute(const dd_survey *s, const void *d_in, float *const *d_out, const int64_t *out_pitch,
+                            void *stream) {
+  dd_status st = check_survey_exec(s, d_in, d_out, out_pitch);
+  if (st != DD_OK) return st;
+  st = bin_all(*s, d_in, stream);
+  for (size_t r = 0; r < s->plans.size() && st == DD_OK; ++r)
+    st = dd_execute(s->plans[r], range_input(*s, (int)r, d_in), d_out[r], out_pitch[r], stream);
+  return st;
+}
+
+void dd_survey_destroy(dd_survey *s) { delete s; }
+
+}  // extern "C"

@@ -228,6 +228,31 @@ CONFIGS = {
 }
 
 
+#: Multi-range DM plans over one filterbank: ranges are (dm_start, dm_step,
+#: n_dm, time-binning factor); pulses are (DM, width in samples, t0), injected
+#: along the unbinned delays of that DM.
+#:   survey_small    a small mixed plan for exhaustive parity (factors 1, 2, 4 and 3).
+#:   tab_plans_8192  the three-range plan of Table tab:plans (Sec. 5.2): 10 s at
+#:                   64 us, 1400 MHz centre, 300 MHz band, 8192 channels, no binning.
+#:   pipeline_high   the "High" pipeline case of Sec. 5.3 (1400 MHz centre, 300 MHz
+#:                   band, 64 us, 4096 channels, ~50 s, DM 0-3000): the three ranges
+#:                   above, then ranges binned by 2, 4 and 8 whose step doubles with
+#:                   the factor (about 3.6 binned samples of band-edge delay per step).
+SURVEYS = {
+    "survey_small": dict(dtype="u8", n_chan=128, n_samp=32770, f_high=1500.0, chan_bw=1.5625, t_samp=64e-6,
+                         ranges=[(0.0, 1.0, 100, 1), (100.0, 2.0, 60, 2), (220.0, 4.0, 40, 4), (380.0, 3.0, 30, 3)],
+                         seed=9, pulses=[(50.0, 2, 9000), (300.0, 4, 15000)], amp=40),
+    "tab_plans_8192": dict(dtype="u8", n_chan=8192, n_samp=156250, f_high=1550.0, chan_bw=300.0 / 8192,
+                           t_samp=64e-6, ranges=[(0.0, 0.1, 1500, 1), (150.0, 0.2, 750, 1), (300.0, 0.25, 800, 1)],
+                           seed=7, pulses=[(75.0, 1, 40_000), (250.0, 2, 80_000), (450.0, 4, 120_000)], amp=40),
+    "pipeline_high": dict(dtype="u8", n_chan=4096, n_samp=781250, f_high=1550.0, chan_bw=300.0 / 4096,
+                          t_samp=64e-6, ranges=[(0.0, 0.1, 1500, 1), (150.0, 0.2, 750, 1), (300.0, 0.25, 800, 1),
+                                                (500.0, 0.5, 1000, 2), (1000.0, 1.0, 1000, 4), (2000.0, 2.0, 500, 8)],
+                          seed=8, pulses=[(100.0, 1, 100_000), (700.0, 2, 300_000), (1500.0, 4, 500_000),
+                                          (2600.0, 8, 600_000)], amp=40),
+}
+
+
 def batch_beams(n_beams: int = 48, seed: int = 5):
     """Per-beam parameters of the multi-beam workload (48 beams by default).
 

@@ -110,3 +110,80 @@ def test_plan_tile_shapes(dd):
         i = p.info
         assert i.kernel_ns in (8, 16, 32) and i.kernel_waves >= 1 and i.kernel_dm_per_wave >= 1
         assert 256 % i.kernel_chan_block == 0
+
+
+def _bin_lib(dd):
+    lib = ctypes.CDLL(dd.LIB_PATH)
+    lib.dd_bin_time.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    return lib
+
+
+def test_bin_argument_checks(dd):
+    """Every rejected call returns its status before any device work."""
+    lib = _bin_lib(dd)
+    a, b = 1 << 20, 1 << 30  # 16-byte aligned addresses that are never dereferenced
+    ok = dict(dtype=1, d_in=a, in_pitch=1024, n_chan=4, n_samp=1000, factor=4, d_out=b, out_pitch=512)
+
+    def call(**kw):
+        k = dict(ok, **kw)
+        return lib.dd_bin_time(k["dtype"], k["d_in"], k["in_pitch"], k["n_chan"], k["n_samp"], k["factor"],
+                               k["d_out"], k["out_pitch"], None)
+    assert call(dtype=9) == -1
+    assert call(d_in=0) == -1 and call(d_out=0) == -1
+    assert call(n_chan=0) == -1 and call(n_samp=0) == -1
+    assert call(factor=0) == -1 and call(factor=257) == -1
+    assert call(n_samp=3) == -2
+    assert call(d_in=a + 8) == -4 and call(d_out=b + 4) == -4
+    assert call(in_pitch=992) == -1                      # shorter than a row of 1000 bytes
+    assert call(in_pitch=1032) == -4                     # not a multiple of 16
+    assert call(out_pitch=496) == -1                     # 250 bins of 2 bytes need 500
+    assert call(out_pitch=504) == -4
+    assert call(d_out=a + 2048) == -1                    # overlaps the input rows
+    assert call(dtype=2, in_pitch=496) == -1             # 4-bit rows of 1000 samples take 500 bytes
+    assert call(dtype=4, in_pitch=1024) == -1            # 16-bit rows take 2000 bytes
+    assert call(dtype=4, in_pitch=2000, out_pitch=992) == -1  # float sums take 4 bytes
+    assert [lib.dd_bin_out_dtype(t) for t in (1, 2, 3, 4, 7)] == [4, 4, 3, 3, 0]
+
+
+SURVEY_RANGES = [(0.0, 1.0, 60, 1), (60.0, 2.0, 40, 2), (140.0, 3.0, 30, 3), (230.0, 4.0, 8, 4)]
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u4", "u16", "f32"])
+def test_survey_range_plans_equal_oracle(dd, dtype):
+    """Range r is planned on the binned grid: t_samp * bin, n_samp // bin, the binned encoding."""
+    cfg = synth.CONFIGS["small"]
+    n_samp = cfg["n_samp"]
+    s = dd.Survey(cfg["n_chan"], n_samp, dtype, cfg["f_high"], cfg["chan_bw"], cfg["t_samp"], SURVEY_RANGES,
+                  bind=False)
+    need = 0
+    for r, (start, step, n_dm, b) in enumerate(SURVEY_RANGES):
+        want = oracle.shift_table(cfg["n_chan"], cfg["f_high"], cfg["chan_bw"], cfg["t_samp"] * b, start, step, n_dm)
+        assert np.array_equal(s.shift(r), want)
+        ri = s.range_info[r]
+        assert ri["n_out"] == oracle.n_out_for(want, n_samp // b) and ri["n_samp"] == n_samp // b
+        assert ri["dtype"] == (dtype if b == 1 else dd.BIN_OUT[dtype])
+        if b > 1:
+            need += cfg["n_chan"] * (n_samp // b) * (2 if dd.BIN_OUT[dtype] == "u16" else 4)
+    assert s.workspace_bytes >= need
+
+
+def test_survey_errors(dd):
+    cfg = synth.CONFIGS["small"]
+    base = (cfg["n_chan"], cfg["n_samp"], "u8", cfg["f_high"], cfg["chan_bw"], cfg["t_samp"])
+
+    def make(ranges, **kw):
+        args = list(base)
+        for i, k in enumerate(["n_chan", "n_samp", "dtype"]):
+            if k in kw:
+                args[i] = kw[k]
+        return dd.Survey(*args, ranges, bind=False)
+    assert _status(dd, lambda: make([(0.0, 1.0, 10, 0)])) == "DD_ERR_ARG"
+    assert _status(dd, lambda: make([(0.0, 1.0, 10, 257)])) == "DD_ERR_ARG"
+    assert _status(dd, lambda: make([(0.0, 1.0, 10, 64)], n_samp=48)) == "DD_ERR_TOO_SHORT"
+    with pytest.raises(dd.DDError) as e:  # the binned range is too short for its delays
+        make([(0.0, 1.0, 10, 1), (0.0, 20.0, 256, 16)])
+    assert e.value.name == "DD_ERR_TOO_SHORT" and "range 1" in str(e.value)
+    assert _status(dd, lambda: make([(0.0, 1.0, 10, 1)], dtype="u4", n_samp=32767)) == "DD_ERR_ARG"
+    make([(0.0, 1.0, 10, 2)], dtype="u4", n_samp=32767)  # odd length is fine once binned
+    assert _status(dd, lambda: make([])) == "DD_ERR_ARG"
