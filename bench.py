@@ -411,6 +411,13 @@ def main():
     import paper_2311_05341_amd as dd
     import synth
 
+    if args.copy_calibration:
+        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 1 GiB read + 1 GiB written")
     if args.workload == "batch48":
         return bench_batch48(args, dd, torch, synth)
     if args.workload in synth.SURVEYS:
@@ -423,13 +430,6 @@ def main():
     log("plan %.2f s: n_out=%d max_shift=%d tile ns=%d dm/wave=%d waves=%d chan_block=%d" % (
         time.perf_counter() - t, plan.n_out, plan.max_shift, plan.info.kernel_ns, plan.info.kernel_dm_per_wave,
         plan.info.kernel_waves, plan.info.kernel_chan_block))
-    if args.copy_calibration:
-        src = torch.ones(1 << 30, dtype=torch.uint8, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        log("copy calibration: 1 GiB read + 1 GiB written")
     x = make_input(dd, torch, synth, cfg, plan)
     out = torch.empty((plan.n_dm, plan.out_pitch), dtype=torch.float32, device="cuda")
     direction = 1 if args.adjoint else 0
