@@ -11,6 +11,7 @@ from .oracle import (  # noqa: F401
     adjoint,
     bin_time,
     build,
+    corner_turn,
     forward,
     forward_f32,
     lib_path,

@@ -134,6 +134,42 @@ int oracle_forward_int(int dtype, const uint8_t *x, int64_t pitch, int n_chan, i
 }
 
 /*
+ * Corner turn of the input (the "transposing of the input data" that the
+ * pipelines of Sec. 5.3 run before the transform and that the real-time factor
+ * of Sec. 5.5 counts): time-major spectra in[t][c] (each time sample holds all
+ * channels) to channel-major rows out[c][t], the layout Eq. 3 is evaluated on.
+ * dtype 1 = u8, 3 = f32, 4 = u16 (little-endian): element copy.  dtype 2 = u4:
+ * in a spectrum two channels share a byte (channel 2k in the low nibble), in an
+ * output row two time samples (sample 2k in the low nibble); n_samp even.
+ * Pitches in bytes.  Returns -1 on bad arguments.
+ */
+int oracle_corner_turn(int dtype, const uint8_t *in, int64_t in_pitch, int n_chan, int64_t n_samp, uint8_t *out,
+                       int64_t out_pitch) {
+  if (n_chan < 1 || n_samp < 1) return -1;
+  if (dtype == 2) {
+    if (n_samp % 2) return -1;
+    if (in_pitch < (n_chan + 1) / 2 || out_pitch < n_samp / 2) return -1;
+#pragma omp parallel for schedule(static)
+    for (int c = 0; c < n_chan; ++c) {
+      for (int64_t t = 0; t < n_samp; t += 2) {
+        const uint8_t b0 = in[t * in_pitch + c / 2], b1 = in[(t + 1) * in_pitch + c / 2];
+        const int v0 = (c % 2) ? (b0 >> 4) : (b0 & 15);
+        const int v1 = (c % 2) ? (b1 >> 4) : (b1 & 15);
+        out[(int64_t)c * out_pitch + t / 2] = (uint8_t)(v0 | (v1 << 4));
+      }
+    }
+    return 0;
+  }
+  const int es = dtype == 1 ? 1 : dtype == 4 ? 2 : dtype == 3 ? 4 : 0;
+  if (!es || in_pitch < (int64_t)n_chan * es || out_pitch < n_samp * es) return -1;
+#pragma omp parallel for schedule(static)
+  for (int c = 0; c < n_chan; ++c)
+    for (int64_t t = 0; t < n_samp; ++t)
+      for (int b = 0; b < es; ++b) out[(int64_t)c * out_pitch + t * es + b] = in[t * in_pitch + (int64_t)c * es + b];
+  return 0;
+}
+
+/*
  * Time binning, the "downsampling" that Secs. 5.2 and 5.3 apply before the
  * transform for high-DM ranges and that the real-time factor of Sec. 5.5
  * counts (downsampling by `factor`): xb(c, j) = sum_{i < factor} x(c, j*factor + i)

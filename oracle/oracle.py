@@ -2,7 +2,8 @@
 
 Builds ``liboracle.so`` with gcc (FP64, no FMA contraction, OpenMP) and exposes
 the shift table (Eq. 1 with the per-channel form of Sec. 4.1), the forward
-transform (Eq. 3 / Algorithm 1), the scatter-form adjoint and time binning.
+transform (Eq. 3 / Algorithm 1), the scatter-form adjoint, time binning and the
+input corner turn.
 """
 from __future__ import annotations
 
@@ -85,6 +86,8 @@ def _configure(lib):
     lib.oracle_bin_int.restype = i32
     lib.oracle_bin_f32.argtypes = [vp, i64, i32, i64, i32, vp, i64]
     lib.oracle_bin_f32.restype = i32
+    lib.oracle_corner_turn.argtypes = [i32, vp, i64, i32, i64, vp, i64]
+    lib.oracle_corner_turn.restype = i32
     return lib
 
 
@@ -214,4 +217,29 @@ def bin_time(x: np.ndarray, dtype: str, n_samp: int, factor: int) -> np.ndarray:
     if rc != 0:
         raise ValueError("oracle bin: bad arguments")
     return out[:, :n_bins]
+
+
+_CT_CODE = {"u8": 1, "u4": 2, "f32": 3, "u16": 4}
+_CT_ES = {"u8": 1, "u16": 2, "f32": 4}
+
+
+def corner_turn(spectra: np.ndarray, dtype: str, n_chan: int, n_samp: int) -> np.ndarray:
+    """Time-major spectra [n_samp][>= row] to channel-major rows [n_chan][row] (see oracle.c).
+
+    u8/u16/f32: element transpose; u4: channel pairs per byte in, time pairs per byte out."""
+    lib = _load()
+    assert spectra.ndim == 2 and spectra.flags.c_contiguous and spectra.shape[0] >= n_samp
+    raw = spectra.view(np.uint8)
+    if dtype == "u4":
+        out = np.empty((n_chan, n_samp // 2), dtype=np.uint8)
+        ob = out
+    else:
+        dt = {"u8": np.uint8, "u16": np.dtype("<u2"), "f32": np.float32}[dtype]
+        assert spectra.dtype == dt
+        out = np.empty((n_chan, n_samp), dtype=dt)
+        ob = out.view(np.uint8)
+    rc = lib.oracle_corner_turn(_CT_CODE[dtype], _ptr(raw), raw.shape[1], n_chan, n_samp, _ptr(ob), ob.shape[1])
+    if rc != 0:
+        raise ValueError("oracle corner turn: bad arguments")
+    return out
 

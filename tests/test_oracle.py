@@ -532,3 +532,66 @@ def test_binned_forward_with_delays_in_whole_bins():
     b = oracle.bin_time(x, "u8", n_samp, f).astype(np.uint16)
     got = oracle.forward(b, "u16", b.shape[1], sf)[0].astype(np.int64)
     assert np.array_equal(got, full[:len(got) * f].reshape(-1, f).sum(1))
+
+
+# --------------------------------------------------------------------------------------
+# Corner turn (the input transpose of the pipelines, Secs. 5.3 and 5.5): time-major
+# spectra to the channel-major rows Eq. 3 reads.
+# --------------------------------------------------------------------------------------
+
+def _nibbles_numpy(packed, n):
+    """Unpack nibble pairs (element 2k in the low nibble) along the last axis."""
+    out = np.empty(packed.shape[:-1] + (packed.shape[-1] * 2,), dtype=np.uint8)
+    out[..., 0::2] = packed & 15
+    out[..., 1::2] = packed >> 4
+    return out[..., :n]
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u16", "f32"])
+def test_corner_turn_is_numpy_transpose(dtype):
+    rng = np.random.default_rng(41)
+    for n_chan, n_samp, pad in [(1, 1, 0), (7, 13, 3), (300, 257, 16), (64, 1000, 0)]:
+        if dtype == "f32":
+            cm = rng.standard_normal((n_chan, n_samp)).astype(np.float32)
+        else:
+            cm = rng.integers(0, 256 if dtype == "u8" else 65536, (n_chan, n_samp)).astype(
+                np.uint8 if dtype == "u8" else np.uint16)
+        tm = np.zeros((n_samp, n_chan + pad), dtype=cm.dtype)
+        tm[:, :n_chan] = cm.T
+        got = oracle.corner_turn(tm, dtype, n_chan, n_samp)
+        assert got.dtype == cm.dtype and np.array_equal(got, cm)
+
+
+def test_corner_turn_u4_nibble_orders():
+    """4-bit spectra pack channel pairs, 4-bit rows pack time pairs, low nibble first."""
+    rng = np.random.default_rng(42)
+    for n_chan, n_samp in [(1, 2), (5, 10), (64, 200), (33, 64)]:
+        v = rng.integers(0, 16, (n_chan, n_samp)).astype(np.uint8)  # v[c][t]
+        vt = np.zeros((n_samp, n_chan + (n_chan & 1)), dtype=np.uint8)
+        vt[:, :n_chan] = v.T
+        spectra = (vt[:, 0::2] | (vt[:, 1::2] << 4)).astype(np.uint8)
+        rows = oracle.corner_turn(np.ascontiguousarray(spectra), "u4", n_chan, n_samp)
+        assert np.array_equal(_nibbles_numpy(rows, n_samp), v)
+    # one hand-made case: spectrum t holds channels (0, 1) = (t, 15 - t)
+    spectra = np.array([[t | ((15 - t) << 4)] for t in range(4)], dtype=np.uint8)
+    rows = oracle.corner_turn(spectra, "u4", 2, 4)
+    assert rows.tolist() == [[0x10, 0x32], [0xEF, 0xCD]]
+
+
+def test_corner_turn_round_trip_and_forward():
+    """Turning twice (roles of channels and times swapped) is the identity, and the turned
+    spectra dedisperse exactly as the channel-major original."""
+    cfg, s, x = _small()
+    n_chan, n_samp = cfg["n_chan"], cfg["n_samp"]
+    spectra = np.ascontiguousarray(x[:, :n_samp].T)
+    rows = oracle.corner_turn(spectra, "u8", n_chan, n_samp)
+    assert np.array_equal(oracle.corner_turn(rows, "u8", n_samp, n_chan), spectra)
+    assert np.array_equal(oracle.forward(rows, "u8", n_samp, s, rows=[0, 100, 255]),
+                          oracle.forward(x, "u8", n_samp, s, rows=[0, 100, 255]))
+    rng = np.random.default_rng(43)
+    v = rng.integers(0, 16, (6, 40)).astype(np.uint8)
+    packed_rows = (v[:, 0::2] | (v[:, 1::2] << 4)).astype(np.uint8)
+    vt = np.ascontiguousarray(v.T)
+    spectra4 = (vt[:, 0::2] | (vt[:, 1::2] << 4)).astype(np.uint8)
+    assert np.array_equal(oracle.corner_turn(np.ascontiguousarray(spectra4), "u4", 6, 40), packed_rows)
+    assert np.array_equal(oracle.corner_turn(packed_rows, "u4", 40, 6), spectra4)

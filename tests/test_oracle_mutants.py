@@ -35,6 +35,10 @@ MUTANTS = {
     "bin keeps the partial last bin": ("const int64_t n_bins = n_samp / factor;\n  if (out_pitch < n_bins) return -1;\n#pragma omp parallel for schedule(static)\n  for (int c = 0; c < n_chan; ++c) {", "const int64_t n_bins = (n_samp + factor - 1) / factor;\n  if (out_pitch < n_bins) return -1;\n#pragma omp parallel for schedule(static)\n  for (int c = 0; c < n_chan; ++c) {"),
     "bin averages instead of sums": ("      out[(int64_t)c * out_pitch + j] = acc;\n    }\n  }", "      out[(int64_t)c * out_pitch + j] = acc / factor;\n    }\n  }"),
     "f32 bin skips first sample": ("for (int i = 0; i < factor; ++i) acc += (double)x[(int64_t)c * pitch + j * factor + i];", "for (int i = 1; i < factor; ++i) acc += (double)x[(int64_t)c * pitch + j * factor + i];"),
+    "corner turn packs output nibbles high first": ("(uint8_t)(v0 | (v1 << 4));", "(uint8_t)(v1 | (v0 << 4));"),
+    "corner turn reads input nibbles high first": ("const int v0 = (c % 2) ? (b0 >> 4) : (b0 & 15);", "const int v0 = (c % 2) ? (b0 & 15) : (b0 >> 4);"),
+    "corner turn reads the next spectrum": ("out[(int64_t)c * out_pitch + t * es + b] = in[t * in_pitch + (int64_t)c * es + b];", "out[(int64_t)c * out_pitch + t * es + b] = in[(t + 1 < n_samp ? t + 1 : t) * in_pitch + (int64_t)c * es + b];"),
+    "corner turn reverses element bytes": ("out[(int64_t)c * out_pitch + t * es + b] = in[t * in_pitch + (int64_t)c * es + b];", "out[(int64_t)c * out_pitch + t * es + b] = in[t * in_pitch + (int64_t)c * es + (es - 1 - b)];"),
     "normalised by channel count": ("out[(int64_t)r * n_out + t] = (float)acc[t];", "out[(int64_t)r * n_out + t] = (float)(acc[t] / n_chan);"),
 }
 
@@ -63,6 +67,10 @@ PIN_CALLS = [
     ("bin compose", pins.test_bin_factors_compose, ()),
     ("binned dm0", pins.test_binned_forward_dm0_is_sum_of_unbinned_dm0, ()),
     ("binned whole-bin delays", pins.test_binned_forward_with_delays_in_whole_bins, ()),
+    ("corner turn u8", pins.test_corner_turn_is_numpy_transpose, ("u8",)),
+    ("corner turn u16", pins.test_corner_turn_is_numpy_transpose, ("u16",)),
+    ("corner turn u4", pins.test_corner_turn_u4_nibble_orders, ()),
+    ("corner turn round trip", pins.test_corner_turn_round_trip_and_forward, ()),
 ]
 
 
