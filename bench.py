@@ -299,24 +299,40 @@ def bench_batch48(args, dd, torch, synth):
 
 
 def bench_survey(args, dd, torch, synth):
-    """Multi-range DM plan (binning + one transform per range) over one 8-bit filterbank."""
+    """Multi-range DM plan (binning + one transform per range) over one 8-bit filterbank.
+
+    With --time-major the input is time-major spectra and every step starts with
+    the corner turn, as the paper's pipelines (and their real-time factor) do."""
     cfg = synth.SURVEYS[args.workload]
     n_chan, n_samp, t_samp = cfg["n_chan"], cfg["n_samp"], cfg["t_samp"]
+    tm = args.time_major
     pitch = (n_samp + 63) // 64 * 64
-    log("survey %s: %s" % (args.workload, {k: v for k, v in cfg.items() if k != "pulses"}))
-    sv = dd.Survey(n_chan, n_samp, "u8", cfg["f_high"], cfg["chan_bw"], t_samp, cfg["ranges"], in_pitch_bytes=pitch)
+    log("survey %s%s: %s" % (args.workload, " (time-major input)" if tm else "",
+                             {k: v for k, v in cfg.items() if k != "pulses"}))
+    sv = dd.Survey(n_chan, n_samp, "u8", cfg["f_high"], cfg["chan_bw"], t_samp, cfg["ranges"],
+                   in_pitch_bytes=n_chan if tm else pitch, time_major=tm)
     stream = torch.cuda.current_stream()
-    x = torch.empty((n_chan, pitch), dtype=torch.uint8, device="cuda")
     table = torch.from_numpy(synth.gaussian_table()).cuda()
-    synth.gaussian_u8_device(x.data_ptr(), n_chan, n_samp, pitch, cfg["seed"], table.data_ptr(), stream.cuda_stream)
+    if tm:  # spectra [n_samp][n_chan]: the generator's rows are time samples
+        x = torch.empty((n_samp, n_chan), dtype=torch.uint8, device="cuda")
+        synth.gaussian_u8_device(x.data_ptr(), n_samp, n_chan, n_chan, cfg["seed"], table.data_ptr(),
+                                 stream.cuda_stream)
+    else:
+        x = torch.empty((n_chan, pitch), dtype=torch.uint8, device="cuda")
+        synth.gaussian_u8_device(x.data_ptr(), n_chan, n_samp, pitch, cfg["seed"], table.data_ptr(),
+                                 stream.cuda_stream)
     for dm, width, t0 in cfg["pulses"]:
         delay = dd.Plan(n_chan, n_samp, "u8", cfg["f_high"], cfg["chan_bw"], t_samp, dm, 0.0, 1,
                         in_pitch_bytes=pitch, bind=False).shift[0]
 
+        def index(r, c):  # (channels, samples) as indices of x
+            r, c = torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda()
+            return (c, r) if tm else (r, c)
+
         def at(r, c):
-            return x[torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda()].cpu().numpy()
+            return x[index(r, c)].cpu().numpy()
         rows, cols, vals, _ = synth.boxcar_updates(at, delay, t0, width, cfg["amp"])
-        x[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()] = torch.from_numpy(vals).cuda()
+        x[index(rows, cols)] = torch.from_numpy(vals).cuda()
     outs = sv.empty_outputs()
     torch.cuda.synchronize()
     tune_s = None
@@ -347,18 +363,25 @@ def bench_survey(args, dd, torch, synth):
         e1.record(stream)
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
+    turn = None
+    rows_in = x
+    if tm:
+        rows_in = torch.empty((n_chan, pitch), dtype=torch.uint8, device="cuda")
+        ms = timed(lambda: dd.corner_turn(x, "u8", n_chan, n_samp, out=rows_in), 5)
+        nbytes = 2.0 * n_chan * n_samp
+        turn = {"ms": ms, "bytes": nbytes, "GB_s": nbytes / ms / 1e6, "frac_hbm": nbytes / ms / 1e6 / HBM_PEAK_GBS}
     binned, bins = {}, []
     for f in sorted({r[3] for r in cfg["ranges"] if r[3] > 1}):
         nb = n_samp // f
         binned[f] = torch.empty((n_chan, (2 * nb + 255) // 256 * 128), dtype=torch.uint16, device="cuda")
-        ms = timed(lambda f=f: dd.bin_time(x, "u8", n_samp, f, out=binned[f]), 5)
+        ms = timed(lambda f=f: dd.bin_time(rows_in, "u8", n_samp, f, out=binned[f]), 5)
         nbytes = float(n_chan) * (nb * f + 2 * nb)  # whole bins read once, uint16 sums written once
         bins.append({"factor": f, "ms": ms, "bytes": nbytes, "GB_s": nbytes / ms / 1e6,
                      "frac_hbm": nbytes / ms / 1e6 / HBM_PEAK_GBS})
     parts = []
     for r, (start, step, n_dm, b) in enumerate(cfg["ranges"]):
         ri = sv.range_info[r]
-        src = x if b == 1 else binned[b]
+        src = rows_in if b == 1 else binned[b]
         p = dd.Plan(n_chan, ri["n_samp"], ri["dtype"], cfg["f_high"], cfg["chan_bw"], ri["t_samp"], start, step,
                     n_dm, in_pitch_bytes=src.stride(0) * src.element_size())
         tl = sv.tiles(r)
@@ -369,20 +392,20 @@ def bench_survey(args, dd, torch, synth):
                       "n_out": ri["n_out"], "ms": ms, "Tadds_s": a / ms / 1e9, "tiles": tl})
         del p
     dom = max(parts, key=lambda q: q["ms"])
-    log("survey parts: %s; bins: %s" % (parts, bins))
+    log("survey parts: %s; bins: %s; corner turn: %s" % (parts, bins, turn))
     rec = {
         "metric": "Tadds/s (multi-range survey)", "value": adds / ms_step / 1e9, "unit": "Tadds/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
         "config": {"workload": args.workload, "n_chan": n_chan, "n_samp": n_samp, "t_samp_s": t_samp,
                    "f_high_mhz": cfg["f_high"], "band_mhz": cfg["chan_bw"] * n_chan, "ranges": cfg["ranges"],
-                   "adds_per_step": adds},
+                   "adds_per_step": adds, "input_layout": "time-major spectra" if tm else "channel-major rows"},
         "x_realtime": n_samp * t_samp / (ms_step * 1e-3),
         "roofline": {"bound": "alu", "achieved": dom["Tadds_s"], "peak": VALU_PEAK_TOPS, "unit": "Tadds/s",
                      "frac": dom["Tadds_s"] / VALU_PEAK_TOPS, "traffic": None, "kernel": "fwd_int_kernel",
                      "range": dom["range"], "kernel_ms": dom["ms"]},
-        "parts": parts, "binning": bins, "autotune_s": tune_s,
-        "sum_of_parts_ms": sum(q["ms"] for q in parts) + sum(q["ms"] for q in bins),
+        "parts": parts, "binning": bins, "corner_turn": turn, "autotune_s": tune_s,
+        "sum_of_parts_ms": sum(q["ms"] for q in parts) + sum(q["ms"] for q in bins) + (turn["ms"] if turn else 0.0),
     }
     print(json.dumps(rec), flush=True)
 
@@ -398,6 +421,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="keep the plan's default tile choice")
     ap.add_argument("--tiles", default=None, metavar="SHAPE,ORDER",
                     help="use this compiled tile shape index and workgroup order instead of autotuning")
+    ap.add_argument("--time-major", action="store_true",
+                    help="multi-range workloads: time-major spectra in, corner turn inside every step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first, as a known-size reference for memory counters")
     args = ap.parse_args()

@@ -260,6 +260,26 @@ dd_status dd_bin_time(int32_t dtype, const void *d_in, int64_t in_pitch_bytes, i
 int32_t dd_bin_out_dtype(int32_t dtype);
 
 /*
+ * Corner turn of the input (the transposing of the input data that the
+ * pipelines of Sec. 5.3 run before the transform and the real-time factor of
+ * Sec. 5.5 includes): time-major spectra to channel-major rows,
+ *
+ *     out(c, t) = in(t, c),   0 <= c < n_chan, 0 <= t < n_samp.
+ *
+ *   dtype      DD_U8, DD_U16 or DD_F32 (element transpose), or DD_U4: a spectrum
+ *              holds channel pairs per byte and an output row time pairs per byte,
+ *              the even index in the low nibble (n_samp even).
+ *   d_in       device pointer, [n_samp] spectra of in_pitch_bytes (>= the packed
+ *              spectrum, multiple of 16).
+ *   d_out      device pointer, [n_chan] rows of out_pitch_bytes (>= the packed row,
+ *              multiple of 16); exactly the row bytes are written.  Must not overlap d_in.
+ * Both 16-byte aligned.  Asynchronous on `stream`; allocates nothing.
+ * Errors: DD_ERR_ARG, DD_ERR_ALIGN, DD_ERR_RANGE, DD_ERR_HIP.
+ */
+dd_status dd_corner_turn(int32_t dtype, const void *d_in, int64_t in_pitch_bytes, int32_t n_chan, int64_t n_samp,
+                         void *d_out, int64_t out_pitch_bytes, void *stream);
+
+/*
  * Multi-range DM plan ("survey"): several DM ranges, each with its own fixed
  * step and time-binning factor, over one filterbank (the plan of Table
  * tab:plans in Sec. 5.2; the binned high-DM ranges of Sec. 5.3).
@@ -272,7 +292,10 @@ int32_t dd_bin_out_dtype(int32_t dtype);
  *
  * dd_survey_create: `base` gives the filterbank (n_chan, n_samp, dtype, band,
  *   t_samp_s, in_pitch_bytes); its DM fields are ignored.  ranges[0..n-1]:
- *   n_dm > 0, dm_step >= 0, dm_start >= 0, bin in 1..256.  Errors as
+ *   n_dm > 0, dm_step >= 0, dm_start >= 0, bin in 1..256.  flags: 0, or
+ *   DD_SURVEY_TIME_MAJOR: the input is time-major spectra ([n_samp] spectra of
+ *   base->in_pitch_bytes, as dd_corner_turn reads them); every execute first
+ *   turns it into a channel-major copy in the workspace.  Errors as
  *   dd_plan_create for each range's plan, plus DD_ERR_ARG.
  * dd_survey_plan: the plan of range r, owned by the survey (query it for
  *   n_out; re-tiling it through dd_plan_set_tiles unbinds the survey).
@@ -283,8 +306,8 @@ int32_t dd_bin_out_dtype(int32_t dtype);
  *   and enqueue the table uploads on `stream`.  Errors: DD_ERR_ARG, DD_ERR_ALIGN, DD_ERR_HIP.
  * dd_survey_autotune: bin the input, then dd_plan_autotune every range
  *   (forward) on its own input and d_out[r]; leaves the survey bound.  Synchronises `stream`.
- * dd_survey_execute: on `stream`, bin the input once per distinct factor > 1,
- *   then run every range's forward transform: d_out[r] is float32
+ * dd_survey_execute: on `stream`, corner-turn the input (DD_SURVEY_TIME_MAJOR),
+ *   bin it once per distinct factor > 1, then run every range's forward transform: d_out[r] is float32
  *   [n_dm_r][out_pitch[r]] as for dd_execute of range r's plan.
  *   Errors: DD_ERR_ARG, DD_ERR_ALIGN, DD_ERR_NOT_BOUND, DD_ERR_HIP.
  */
@@ -297,7 +320,10 @@ typedef struct {
 
 typedef struct dd_survey dd_survey;
 
-dd_status dd_survey_create(const dd_plan_desc *base, const dd_range *ranges, int32_t n_ranges, dd_survey **out);
+#define DD_SURVEY_TIME_MAJOR 1
+
+dd_status dd_survey_create(const dd_plan_desc *base, const dd_range *ranges, int32_t n_ranges, int32_t flags,
+                           dd_survey **out);
 dd_status dd_survey_plan(const dd_survey *survey, int32_t r, dd_plan **plan);
 dd_status dd_survey_workspace_bytes(const dd_survey *survey, size_t *bytes);
 dd_status dd_survey_bind(dd_survey *survey, void *d_workspace, size_t bytes, void *stream);

@@ -17,6 +17,7 @@ from .binding import (  # noqa: F401
     Plan,
     Survey,
     bin_time,
+    corner_turn,
     dedisperse,
 )
 from .chunks import TimeChunks  # noqa: F401

@@ -101,7 +101,10 @@ class Range(ctypes.Structure):
                 ("bin", ctypes.c_int32)]
 
 
-_lib.dd_survey_create.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(Range), _i32, ctypes.POINTER(_vp)]
+_lib.dd_corner_turn.argtypes = [_i32, _vp, _i64, _i32, _i64, _vp, _i64, _vp]
+_lib.dd_corner_turn.restype = _i32
+DD_SURVEY_TIME_MAJOR = 1
+_lib.dd_survey_create.argtypes = [ctypes.POINTER(PlanDesc), ctypes.POINTER(Range), _i32, _i32, ctypes.POINTER(_vp)]
 _lib.dd_survey_create.restype = _i32
 _lib.dd_survey_plan.argtypes = [_vp, _i32, ctypes.POINTER(_vp)]
 _lib.dd_survey_plan.restype = _i32
@@ -414,16 +417,50 @@ def bin_time(x, dtype, n_samp, factor, out=None, stream=None):
     return out[:, :n_bins]
 
 
+def _spectrum_bytes(dtype, n_chan):
+    return (n_chan + 1) // 2 if dtype == "u4" else n_chan * _IN_TORCH[dtype][1]
+
+
+def _check_spectra(x, dtype, n_chan, n_samp, what="spectra"):
+    tdt, eb = _IN_TORCH[dtype]
+    if x.dtype != tdt or x.dim() != 2 or x.shape[0] < n_samp or x.stride(1) != 1 or x.device.type != "cuda":
+        raise ValueError("%s must be a %s [n_samp][...] CUDA tensor with contiguous rows" % (what, tdt))
+    if x.shape[1] * eb < _spectrum_bytes(dtype, n_chan):
+        raise ValueError("%s hold fewer than %d channels" % (what, n_chan))
+    if (x.stride(0) * eb) % 16 or x.data_ptr() % 16:
+        raise ValueError("%s must be 16-byte aligned with a pitch that is a multiple of 16 bytes" % what)
+
+
+def corner_turn(spectra, dtype, n_chan, n_samp, out=None, stream=None):
+    """Time-major spectra [n_samp][...] to channel-major rows [n_chan][...] (dd_corner_turn).
+
+    Returns ``out`` (allocated with 16-byte rows when not given); 4-bit rows
+    hold n_samp // 2 bytes."""
+    _check_spectra(spectra, dtype, n_chan, n_samp)
+    tdt, eb = _IN_TORCH[dtype]
+    row = _row_bytes(dtype, n_samp)
+    if out is None:
+        out = torch.empty((n_chan, _round_up(row, 16) // eb), dtype=tdt, device=spectra.device)
+    _check_rows(out, dtype, n_chan, n_samp, "out")
+    with torch.cuda.device(spectra.device):
+        _check(_lib.dd_corner_turn(_DTYPES[dtype], spectra.data_ptr(), spectra.stride(0) * eb, n_chan, n_samp,
+                                   out.data_ptr(), out.stride(0) * eb, _stream_handle(stream)), "dd_corner_turn")
+    return out
+
+
 class Survey:
     """Several DM ranges over one filterbank, each with its own step and time binning (dd_survey_*).
 
     ranges: sequence of (dm_start, dm_step, n_dm, bin).  Range r is dedispersed
     from the input binned by ``bin`` (n_samp // bin samples of t_samp * bin);
-    ``run`` returns one float32 [n_dm_r][n_out_r] view per range."""
+    ``run`` returns one float32 [n_dm_r][n_out_r] view per range.  With
+    ``time_major`` the input is spectra [n_samp][...] (``in_pitch_bytes`` between
+    spectra), corner-turned on the device first."""
 
     def __init__(self, n_chan, n_samp, dtype, f_high, chan_bw, t_samp, ranges, chan_freq=None,
-                 in_pitch_bytes=0, device=None, stream=None, bind=True):
+                 in_pitch_bytes=0, device=None, stream=None, bind=True, time_major=False):
         self.dtype = dtype
+        self.time_major = bool(time_major)
         self.n_chan, self.n_samp = int(n_chan), int(n_samp)
         self._freqs = None if chan_freq is None else np.ascontiguousarray(chan_freq, dtype=np.float64)
         d = _desc(n_chan, n_samp, dtype, f_high, chan_bw, t_samp, 0.0, 0.0, 1, self._freqs, in_pitch_bytes)
@@ -431,10 +468,12 @@ class Survey:
         for i, (start, step, n_dm, b) in enumerate(ranges):
             rs[i].dm_start, rs[i].dm_step, rs[i].n_dm, rs[i].bin = float(start), float(step), int(n_dm), int(b)
         h = _vp()
-        _check(_lib.dd_survey_create(ctypes.byref(d), rs, len(ranges), ctypes.byref(h)), "dd_survey_create")
+        _check(_lib.dd_survey_create(ctypes.byref(d), rs, len(ranges), DD_SURVEY_TIME_MAJOR if time_major else 0,
+                                     ctypes.byref(h)), "dd_survey_create")
         self._h = h
         self.ranges = [tuple(r) for r in ranges]
-        self.in_pitch_bytes = int(in_pitch_bytes) or _row_bytes(dtype, self.n_samp)
+        self.in_pitch_bytes = int(in_pitch_bytes) or (_spectrum_bytes(dtype, self.n_chan) if time_major
+                                                       else _row_bytes(dtype, self.n_samp))
         self.range_info = []
         for r, (start, step, n_dm, b) in enumerate(self.ranges):
             ph = _vp()
@@ -486,9 +525,14 @@ class Survey:
                 for ri in self.range_info]
 
     def _args(self, x, outs):
-        _check_rows(x, self.dtype, self.n_chan, self.n_samp, "input")
+        if self.time_major:
+            _check_spectra(x, self.dtype, self.n_chan, self.n_samp, "input")
+        else:
+            _check_rows(x, self.dtype, self.n_chan, self.n_samp, "input")
         if x.device != self.device:
             raise ValueError("input must be on %s" % self.device)
+        if x.stride(0) * x.element_size() != self.in_pitch_bytes:
+            raise ValueError("input pitch must be the survey's %d bytes" % self.in_pitch_bytes)
         if outs is None:
             outs = self.empty_outputs()
         if len(outs) != len(self.range_info):

@@ -148,5 +148,8 @@ int batch_kernels(int ns, int dm_per_wave, int waves, int chan_block, int dtype,
 int bin_out_bytes(int dtype);
 int launch_bin(int dtype, const void *in, int64_t in_pitch, int n_chan, int64_t n_samp, int factor, void *out,
                int64_t out_pitch, void *stream);
+// Corner turn (corner.hip), arguments validated by the caller.
+int launch_corner_turn(int dtype, const void *in, int64_t in_pitch, int n_chan, int64_t n_samp, void *out,
+                       int64_t out_pitch, void *stream);
 
 }  // namespace dd

@@ -1,6 +1,7 @@
-// Time binning and multi-range DM plans ("surveys"): the C ABI of the binning
-// kernels, and a survey object that bins the input once per factor and runs
-// one ordinary plan per DM range.  Declarations and contracts are in include/dd.h.
+// Input corner turn, time binning and multi-range DM plans ("surveys"): the C
+// ABI of the corner-turn and binning kernels, and a survey object that turns
+// the input (if it arrives time-major), bins it once per factor and runs one
+// ordinary plan per DM range.  Declarations and contracts are in include/dd.h.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -14,7 +15,10 @@ struct dd_survey {
   int32_t n_chan = 0;
   int64_t n_samp = 0;
   int32_t dtype = 0;
-  int64_t in_pitch = 0;
+  int64_t in_pitch = 0;        // channel-major rows the binning and unbinned ranges read
+  bool time_major = false;     // input arrives as spectra; turned into the copy at turn_off
+  int64_t spectrum_pitch = 0;  // bytes between input spectra (time-major input)
+  size_t turn_off = 0;
   std::vector<dd_range> ranges;
   std::vector<dd_plan *> plans;     // one per range, owned
   std::vector<int> slot_factor;     // distinct binning factors > 1, in first-use order
@@ -52,10 +56,24 @@ int64_t input_row_bytes(int dtype, int64_t n_samp) {
 
 bool valid_dtype(int dtype) { return dtype == DD_U8 || dtype == DD_U4 || dtype == DD_U16 || dtype == DD_F32; }
 
-// Input sources of every range: the caller's input or a binned copy.
+int64_t spectrum_bytes(int dtype, int32_t n_chan) {
+  return dtype == DD_U4 ? ((int64_t)n_chan + 1) / 2 : input_row_bytes(dtype, 1) * n_chan;
+}
+
+bool overlap(const void *a, int64_t na, const void *b, int64_t nb) {
+  const uintptr_t a0 = (uintptr_t)a, a1 = a0 + (uintptr_t)na, b0 = (uintptr_t)b, b1 = b0 + (uintptr_t)nb;
+  return a0 < b1 && b0 < a1;
+}
+
+// The channel-major input: the caller's, or the turned copy.
+const void *rows_input(const dd_survey &s, const void *d_in) {
+  return s.time_major ? (const void *)(s.ws + s.turn_off) : d_in;
+}
+
+// Input sources of every range: the channel-major input or a binned copy.
 const void *range_input(const dd_survey &s, int r, const void *d_in) {
   const int slot = s.range_slot[r];
-  return slot < 0 ? d_in : (const void *)(s.ws + s.slot_off[slot]);
+  return slot < 0 ? rows_input(s, d_in) : (const void *)(s.ws + s.slot_off[slot]);
 }
 
 dd_status check_survey_exec(const dd_survey *s, const void *d_in, float *const *d_out, const int64_t *out_pitch) {
@@ -64,6 +82,8 @@ dd_status check_survey_exec(const dd_survey *s, const void *d_in, float *const *
   int dev = -1;
   if (hipGetDevice(&dev) == hipSuccess && dev != s->device) return fail(DD_ERR_ARG, "survey is bound on another device");
   if (!aligned16(d_in)) return fail(DD_ERR_ALIGN, "input must be 16-byte aligned");
+  if (s->time_major && overlap(d_in, s->spectrum_pitch * s->n_samp, s->ws, (int64_t)s->ws_bytes))
+    return fail(DD_ERR_ARG, "input overlaps the survey workspace");
   for (size_t r = 0; r < s->plans.size(); ++r) {
     const dd_plan &p = *s->plans[r];
     if (!p.bound) return fail(DD_ERR_NOT_BOUND, "range " + std::to_string(r) + " was re-tiled: bind the survey again");
@@ -75,9 +95,16 @@ dd_status check_survey_exec(const dd_survey *s, const void *d_in, float *const *
   return DD_OK;
 }
 
-dd_status bin_all(const dd_survey &s, const void *d_in, void *stream) {
+// Corner turn (time-major input) and binning, in that order, on `stream`.
+dd_status prepare_inputs(const dd_survey &s, const void *d_in, void *stream) {
+  if (s.time_major) {
+    const int e = launch_corner_turn(s.dtype, d_in, s.spectrum_pitch, s.n_chan, s.n_samp, s.ws + s.turn_off,
+                                     s.in_pitch, stream);
+    if (e) return hip_error(e, "corner-turn launch");
+  }
+  const void *rows = rows_input(s, d_in);
   for (size_t k = 0; k < s.slot_factor.size(); ++k) {
-    const int e = launch_bin(s.dtype, d_in, s.in_pitch, s.n_chan, s.n_samp, s.slot_factor[k], s.ws + s.slot_off[k],
+    const int e = launch_bin(s.dtype, rows, s.in_pitch, s.n_chan, s.n_samp, s.slot_factor[k], s.ws + s.slot_off[k],
                              s.slot_pitch[k], stream);
     if (e) return hip_error(e, "binning launch");
   }
@@ -111,24 +138,54 @@ dd_status dd_bin_time(int32_t dtype, const void *d_in, int64_t in_pitch, int32_t
   if (out_pitch < n_bins * bin_out_bytes(dtype)) return fail(DD_ERR_ARG, "out_pitch_bytes smaller than one binned row");
   if (in_pitch % 16 || out_pitch % 16) return fail(DD_ERR_ALIGN, "row pitches must be multiples of 16 bytes");
   if ((double)in_pitch * n_chan > 9.0e18 || (double)out_pitch * n_chan > 9.0e18) return fail(DD_ERR_RANGE, "size overflow");
-  const uintptr_t a0 = (uintptr_t)d_in, a1 = a0 + (uintptr_t)(in_pitch * n_chan);
-  const uintptr_t b0 = (uintptr_t)d_out, b1 = b0 + (uintptr_t)(out_pitch * n_chan);
-  if (a0 < b1 && b0 < a1) return fail(DD_ERR_ARG, "input and output overlap");
+  if (overlap(d_in, in_pitch * n_chan, d_out, out_pitch * n_chan)) return fail(DD_ERR_ARG, "input and output overlap");
   const int e = launch_bin(dtype, d_in, in_pitch, n_chan, n_samp, factor, d_out, out_pitch, stream);
   if (e) return hip_error(e, "binning launch");
   return DD_OK;
 }
 
-dd_status dd_survey_create(const dd_plan_desc *base, const dd_range *ranges, int32_t n_ranges, dd_survey **out) {
+dd_status dd_corner_turn(int32_t dtype, const void *d_in, int64_t in_pitch, int32_t n_chan, int64_t n_samp,
+                         void *d_out, int64_t out_pitch, void *stream) {
+  if (!valid_dtype(dtype)) return fail(DD_ERR_ARG, "unknown dtype");
+  if (!d_in || !d_out) return fail(DD_ERR_ARG, "null buffer");
+  if (n_chan <= 0 || n_samp <= 0) return fail(DD_ERR_ARG, "n_chan and n_samp must be positive");
+  if (dtype == DD_U4 && (n_samp & 1)) return fail(DD_ERR_ARG, "n_samp must be even for 4-bit rows");
+  if (n_samp >= ((int64_t)1 << 36)) return fail(DD_ERR_RANGE, "n_samp must be below 2^36");
+  if (!aligned16(d_in) || !aligned16(d_out)) return fail(DD_ERR_ALIGN, "buffers must be 16-byte aligned");
+  if (in_pitch < spectrum_bytes(dtype, n_chan)) return fail(DD_ERR_ARG, "in_pitch_bytes smaller than one spectrum");
+  if (out_pitch < input_row_bytes(dtype, n_samp)) return fail(DD_ERR_ARG, "out_pitch_bytes smaller than one row");
+  if (in_pitch % 16 || out_pitch % 16) return fail(DD_ERR_ALIGN, "pitches must be multiples of 16 bytes");
+  if ((double)in_pitch * n_samp > 9.0e18 || (double)out_pitch * n_chan > 9.0e18) return fail(DD_ERR_RANGE, "size overflow");
+  if (overlap(d_in, in_pitch * n_samp, d_out, out_pitch * n_chan)) return fail(DD_ERR_ARG, "input and output overlap");
+  const int e = launch_corner_turn(dtype, d_in, in_pitch, n_chan, n_samp, d_out, out_pitch, stream);
+  if (e) return hip_error(e, "corner-turn launch");
+  return DD_OK;
+}
+
+dd_status dd_survey_create(const dd_plan_desc *base, const dd_range *ranges, int32_t n_ranges, int32_t flags,
+                           dd_survey **out) {
   if (!base || !ranges || !out) return fail(DD_ERR_ARG, "null argument");
   *out = nullptr;
   if (n_ranges <= 0) return fail(DD_ERR_ARG, "a survey needs at least one range");
+  if (flags & ~DD_SURVEY_TIME_MAJOR) return fail(DD_ERR_ARG, "unknown survey flags");
   if (!valid_dtype(base->dtype)) return fail(DD_ERR_ARG, "unknown dtype");
   if (base->n_chan <= 0 || base->n_samp <= 0) return fail(DD_ERR_ARG, "n_chan and n_samp must be positive");
+  const bool time_major = (flags & DD_SURVEY_TIME_MAJOR) != 0;
   const int64_t row = input_row_bytes(base->dtype, base->n_samp);
-  const int64_t pitch = base->in_pitch_bytes ? base->in_pitch_bytes : row;
-  if (pitch < row) return fail(DD_ERR_ARG, "in_pitch_bytes smaller than one row");
-  if (pitch % 16) return fail(DD_ERR_ALIGN, "input row pitch must be a multiple of 16 bytes");
+  int64_t pitch, spitch = 0;
+  if (time_major) {
+    // the caller's pitch is between spectra; the turned copy gets 256-byte rows
+    const int64_t sb = spectrum_bytes(base->dtype, base->n_chan);
+    spitch = base->in_pitch_bytes ? base->in_pitch_bytes : sb;
+    if (spitch < sb) return fail(DD_ERR_ARG, "in_pitch_bytes smaller than one spectrum");
+    if (spitch % 16) return fail(DD_ERR_ALIGN, "spectrum pitch must be a multiple of 16 bytes");
+    if (base->dtype == DD_U4 && (base->n_samp & 1)) return fail(DD_ERR_ARG, "n_samp must be even for 4-bit input");
+    pitch = (int64_t)round_up((size_t)row, 256);
+  } else {
+    pitch = base->in_pitch_bytes ? base->in_pitch_bytes : row;
+    if (pitch < row) return fail(DD_ERR_ARG, "in_pitch_bytes smaller than one row");
+    if (pitch % 16) return fail(DD_ERR_ALIGN, "input row pitch must be a multiple of 16 bytes");
+  }
   for (int r = 0; r < n_ranges; ++r) {
     if (ranges[r].bin < 1 || ranges[r].bin > 256) return fail(DD_ERR_ARG, "range " + std::to_string(r) + ": bin must be in 1..256");
     if (base->n_samp / ranges[r].bin == 0) return fail(DD_ERR_TOO_SHORT, "range " + std::to_string(r) + ": no whole bin");
@@ -141,9 +198,15 @@ dd_status dd_survey_create(const dd_plan_desc *base, const dd_range *ranges, int
     s->n_samp = base->n_samp;
     s->dtype = base->dtype;
     s->in_pitch = pitch;
+    s->time_major = time_major;
+    s->spectrum_pitch = spitch;
     s->ranges.assign(ranges, ranges + n_ranges);
     const int ob = bin_out_bytes(base->dtype);
     size_t off = 0;
+    if (time_major) {
+      s->turn_off = 0;
+      off = round_up((size_t)pitch * (size_t)base->n_chan, 256);
+    }
     for (int r = 0; r < n_ranges; ++r) {
       const int f = ranges[r].bin;
       int slot = -1;
@@ -231,7 +294,7 @@ dd_status dd_survey_autotune(dd_survey *s, const void *d_in, float *const *d_out
                              void *stream) {
   dd_status st = check_survey_exec(s, d_in, d_out, out_pitch);
   if (st != DD_OK) return st;
-  st = bin_all(*s, d_in, stream);
+  st = prepare_inputs(*s, d_in, stream);
   for (size_t r = 0; r < s->plans.size() && st == DD_OK; ++r)
     st = dd_plan_autotune(s->plans[r], 0, range_input(*s, (int)r, d_in), d_out[r], out_pitch[r], s->ws + s->tab_off[r],
                           s->tab_bytes[r], stream, nullptr);
@@ -242,7 +305,7 @@ dd_status dd_survey_execute(const dd_survey *s, const void *d_in, float *const *
                             void *stream) {
   dd_status st = check_survey_exec(s, d_in, d_out, out_pitch);
   if (st != DD_OK) return st;
-  st = bin_all(*s, d_in, stream);
+  st = prepare_inputs(*s, d_in, stream);
   for (size_t r = 0; r < s->plans.size() && st == DD_OK; ++r)
     st = dd_execute(s->plans[r], range_input(*s, (int)r, d_in), d_out[r], out_pitch[r], stream);
   return st;

@@ -187,3 +187,40 @@ def test_survey_errors(dd):
     assert _status(dd, lambda: make([(0.0, 1.0, 10, 1)], dtype="u4", n_samp=32767)) == "DD_ERR_ARG"
     make([(0.0, 1.0, 10, 2)], dtype="u4", n_samp=32767)  # odd length is fine once binned
     assert _status(dd, lambda: make([])) == "DD_ERR_ARG"
+
+
+def test_corner_turn_argument_checks(dd):
+    lib = ctypes.CDLL(dd.LIB_PATH)
+    lib.dd_corner_turn.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_int64,
+                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    a, b = 1 << 20, 1 << 30
+    ok = dict(dtype=1, d_in=a, in_pitch=112, n_chan=100, n_samp=1000, d_out=b, out_pitch=1008)
+
+    def call(**kw):
+        k = dict(ok, **kw)
+        return lib.dd_corner_turn(k["dtype"], k["d_in"], k["in_pitch"], k["n_chan"], k["n_samp"], k["d_out"],
+                                  k["out_pitch"], None)
+    assert call(dtype=0) == -1 and call(d_in=0) == -1 and call(n_chan=0) == -1 and call(n_samp=0) == -1
+    assert call(dtype=2, n_samp=999) == -1            # 4-bit rows pack time pairs
+    assert call(in_pitch=96) == -1                    # a spectrum of 100 channels needs 100 bytes
+    assert call(in_pitch=104) == -4                   # not a multiple of 16
+    assert call(out_pitch=992) == -1 and call(out_pitch=1000) == -4
+    assert call(d_in=a + 4) == -4
+    assert call(d_out=a + 64) == -1                   # overlaps the spectra
+    assert call(dtype=4, in_pitch=192) == -1          # 16-bit spectra of 100 channels take 200 bytes
+    assert call(dtype=2, in_pitch=48, out_pitch=496) == -1  # 4-bit rows of 1000 samples take 500 bytes
+
+
+def test_survey_time_major_layout(dd):
+    """A time-major survey plans the same ranges and adds the turned copy to its workspace."""
+    cfg = synth.CONFIGS["small"]
+    args = (cfg["n_chan"], cfg["n_samp"], "u8", cfg["f_high"], cfg["chan_bw"], cfg["t_samp"], SURVEY_RANGES)
+    cm = dd.Survey(*args, bind=False)
+    tm = dd.Survey(*args, in_pitch_bytes=128, bind=False, time_major=True)
+    for r in range(len(SURVEY_RANGES)):
+        assert np.array_equal(cm.shift(r), tm.shift(r))
+        assert cm.range_info[r]["n_out"] == tm.range_info[r]["n_out"]
+    assert tm.workspace_bytes >= cm.workspace_bytes + cfg["n_chan"] * cfg["n_samp"]
+    with pytest.raises(dd.DDError) as e:  # spectrum pitch below one spectrum of 128 channels
+        dd.Survey(*args, in_pitch_bytes=112, bind=False, time_major=True)
+    assert e.value.name == "DD_ERR_ARG"
