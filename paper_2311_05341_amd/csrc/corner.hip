@@ -6,12 +6,20 @@
 //
 // An HBM-bound LDS-tiled transpose.  A workgroup of 256 lanes takes a tile of
 // TC channels x TT samples: it reads the tile's TT spectrum segments of 256
-// bytes with 16-byte loads (16 lanes per segment, 8 loads in flight per lane)
-// into LDS rows padded by 16 bytes, then writes TC output segments of 128 bytes,
-// each lane assembling 16-byte pieces of one channel row from LDS element reads
-// (consecutive lanes take consecutive channels: conflict-free byte reads).
-// Workgroups walk the channel tiles of one time tile consecutively, so the
-// spectra are read as contiguous runs.
+// bytes with 16-byte loads (16 lanes per segment, several loads in flight per
+// lane) into LDS, then writes TC output segments of 128 bytes.  Workgroups walk
+// the channel tiles of one time tile consecutively, so the spectra are read as
+// contiguous runs.
+//
+// 8-bit, 16-bit and float data (corner_turn_words_kernel): a lane takes one
+// 32-bit column of the tile (4, 2 or 1 channels) over the samples of one
+// 16-byte output piece, reads it as 32-bit words and transposes them in
+// registers with v_perm (a 4x4 byte transpose is 8 v_perm).  The 8 lanes that
+// share a column take its 8 output pieces, so every store instruction writes
+// whole 128-byte runs of 8 rows.  The 16-byte column blocks of LDS row r are
+// XOR-swizzled with the output piece r belongs to, which makes those reads
+// conflict-free.  4-bit data (corner_turn_kernel) assemble each output piece
+// from nibble reads.
 #include <hip/hip_runtime.h>
 
 #include "dd_internal.h"
@@ -136,6 +144,92 @@ __global__ __launch_bounds__(kCtThreads) void corner_turn_kernel(CtArgs a) {
   }
 }
 
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+  return __builtin_amdgcn_perm(hi, lo, sel);
+}
+
+// ES-byte elements (1, 2 or 4).  Tile: 256 input bytes x 128 output bytes per row;
+// 64 word columns x 8 output pieces = 512 units, two per lane.
+template <int DT>
+__global__ __launch_bounds__(kCtThreads) void corner_turn_words_kernel(CtArgs a) {
+  using G = CtGeom<DT>;
+  constexpr int ES = G::ES;
+  constexpr int R = 16 / ES;   // samples per 16-byte output piece = LDS rows per piece
+  constexpr int EPW = 4 / ES;  // channels per 32-bit word
+  static_assert(G::TC * ES == 256 && G::TT == 8 * R, "tile shape");
+  __shared__ __attribute__((aligned(16))) uint8_t tile[G::TT * 256];
+
+  const int ct = (int)(blockIdx.x % (unsigned)a.n_ctiles);
+  const int64_t t0 = (int64_t)(blockIdx.x / (unsigned)a.n_ctiles) * G::TT;
+  const int64_t b0 = (int64_t)ct * 256;
+  const int c0 = ct * G::TC;
+
+  // Read the TT x 256-byte block; 16-byte block k of row r goes to block k ^ (r / R).
+  constexpr int kLoads = G::TT * 16 / kCtThreads;
+  uint4 v[kLoads];
+#pragma unroll
+  for (int s = 0; s < kLoads; ++s) {
+    const int q = threadIdx.x + s * kCtThreads;
+    const int64_t t = t0 + q / 16;
+    const int64_t b = b0 + 16 * (q % 16);
+    // A chunk that starts inside the spectrum lies inside its 16-byte-multiple pitch.
+    v[s] = (t < a.n_samp && b < a.in_row_bytes) ? *(const uint4 *)(a.in + t * a.in_pitch + b) : make_uint4(0, 0, 0, 0);
+  }
+#pragma unroll
+  for (int s = 0; s < kLoads; ++s) {
+    const int q = threadIdx.x + s * kCtThreads;
+    const int r = q / 16;
+    *(uint4 *)(tile + r * 256 + 16 * ((q % 16) ^ (r / R))) = v[s];
+  }
+  __syncthreads();
+
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const int u = threadIdx.x + s * kCtThreads;
+    const int j = u % 8;   // output piece: samples R*j .. R*j + R-1 of the tile
+    const int w = u / 8;   // word column: channels EPW*w .. EPW*w + EPW-1 of the tile
+    uint32_t d[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) d[i] = *(const uint32_t *)(tile + (R * j + i) * 256 + 16 * ((w / 4) ^ j) + 4 * (w % 4));
+    uint32_t o[EPW][4];  // o[k] = the 16 output bytes of channel EPW*w + k
+    if constexpr (ES == 1) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const uint32_t x0 = perm(d[4 * g + 1], d[4 * g], 0x05010400u), x1 = perm(d[4 * g + 1], d[4 * g], 0x07030602u);
+        const uint32_t x2 = perm(d[4 * g + 3], d[4 * g + 2], 0x05010400u);
+        const uint32_t x3 = perm(d[4 * g + 3], d[4 * g + 2], 0x07030602u);
+        o[0][g] = perm(x2, x0, 0x05040100u);
+        o[1][g] = perm(x2, x0, 0x07060302u);
+        o[2][g] = perm(x3, x1, 0x05040100u);
+        o[3][g] = perm(x3, x1, 0x07060302u);
+      }
+    } else if constexpr (ES == 2) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        o[0][g] = perm(d[2 * g + 1], d[2 * g], 0x05040100u);
+        o[1][g] = perm(d[2 * g + 1], d[2 * g], 0x07060302u);
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) o[0][g] = d[g];
+    }
+    const int64_t ob = t0 * ES + 16 * j;  // byte of the row
+    if (ob >= a.out_row_bytes) continue;
+#pragma unroll
+    for (int k = 0; k < EPW; ++k) {
+      const int c = c0 + EPW * w + k;
+      if (c >= a.n_chan) break;
+      uint8_t *dst = a.out + (int64_t)c * a.out_pitch + ob;
+      if (ob + 16 <= a.out_row_bytes) {
+        *(uint4 *)dst = make_uint4(o[k][0], o[k][1], o[k][2], o[k][3]);
+      } else {  // the row's last, partial piece: only its own bytes
+        const int n = (int)(a.out_row_bytes - ob);
+        for (int i = 0; i < n; ++i) dst[i] = (uint8_t)(o[k][i >> 2] >> (8 * (i & 3)));
+      }
+    }
+  }
+}
+
 template <int DT>
 int launch_ct(const CtArgs &a0, hipStream_t st) {
   using G = CtGeom<DT>;
@@ -144,7 +238,10 @@ int launch_ct(const CtArgs &a0, hipStream_t st) {
   const int64_t n_ttiles = (a.n_samp + G::TT - 1) / G::TT;
   const int64_t blocks = n_ttiles * a.n_ctiles;
   if (blocks > 0x7fffffff) return (int)hipErrorInvalidValue;
-  hipLaunchKernelGGL(corner_turn_kernel<DT>, dim3((unsigned)blocks), dim3(kCtThreads), 0, st, a);
+  if constexpr (DT == DD_U4)
+    hipLaunchKernelGGL(corner_turn_kernel<DT>, dim3((unsigned)blocks), dim3(kCtThreads), 0, st, a);
+  else
+    hipLaunchKernelGGL(corner_turn_words_kernel<DT>, dim3((unsigned)blocks), dim3(kCtThreads), 0, st, a);
   return (int)hipGetLastError();
 }
 
