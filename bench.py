@@ -519,7 +519,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tadds/s",
                      "frac": achieved / VALU_PEAK_TOPS, "traffic": traffic, "traffic_unit": "bytes per launch",
                      "traffic_source": traffic_src,
-                     "kernel": "fwd_int_kernel" if cfg["dtype"] != "f32" else "f32_kernel",
+                     "kernel": ("f32_kernel" if cfg["dtype"] == "f32" else
+                                "fwd_direct_kernel" if tiles["row_block"] == 0 else "fwd_int_kernel"),
                      "kernel_ms": k_avg,
                      "instruction_form": FORMS[cfg["dtype"]][0],
                      "peak_instruction_form": VALU_PEAK_TOPS * FORMS[cfg["dtype"]][1],
@@ -530,6 +531,11 @@ def main():
         "tiles": tiles,
         "autotune": tune,
     }
+    if tiles["row_block"] == 0 and cfg["dtype"] != "f32":
+        # The direct-read kernel loads 16 + 4 bytes per 16 samples of 8-bit (or 32 of 4-bit) input
+        # from L1/L2 for every (channel, DM) pair: that load stream, not the VALU, bounds it.
+        per_add = {"u8": 20 / 16, "u4": 20 / 32, "u16": 36 / 16}[cfg["dtype"]]
+        rec["load_path"] = {"bytes_per_add": per_add, "achieved_TB_s": achieved * per_add}
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         rec["cpu_baseline"] = cpu_baseline(cfg)

@@ -41,7 +41,12 @@ dd_status upload_tables(dd_plan &p, void *ws, void *stream) {
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
   hipStream_t st = (hipStream_t)stream;
   uint8_t *base = (uint8_t *)ws;
-  if (p.desc.dtype != DD_F32) {
+  if (p.desc.dtype != DD_F32 && is_direct(p.fwd)) {
+    p.int_offs_off = 0;  // the direct kernel reads the plain shift table
+    p.int_sbase_off = 0;
+    e = hipMemcpyAsync(base, p.shift.data(), p.shift.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "table upload");
+  } else if (p.desc.dtype != DD_F32) {
     const size_t ob = p.itab.offs.size() * sizeof(uint16_t);
     p.int_offs_off = 0;
     p.int_sbase_off = (ob + 255) / 256 * 256;

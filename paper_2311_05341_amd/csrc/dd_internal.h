@@ -131,6 +131,15 @@ extern const int kNumF32Shapes;
 // chan_block), in the order plans try them.
 extern const int kIntShapes[][4];
 extern const int kNumIntShapes;
+// Direct-read shapes (fwd_direct.hip): (16, dm_per_wave, waves, 0).  An integer
+// plan's shape index s >= kNumIntShapes names kDirectShapes[s - kNumIntShapes];
+// such a plan's tables are its plain shift table.
+extern const int kDirectShapes[][4];
+extern const int kNumDirectShapes;
+inline const int *int_shape(int s) { return s < kNumIntShapes ? kIntShapes[s] : kDirectShapes[s - kNumIntShapes]; }
+inline bool is_direct(const TileCfg &t) { return t.chan_block == 0; }
+int launch_forward_direct(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream,
+                          int64_t out_limit = 0);
 int launch_adjoint(const dd_plan &p, const float *d_y, int64_t y_pitch, float *d_grad, void *stream,
                    int64_t out_limit = 0);
 

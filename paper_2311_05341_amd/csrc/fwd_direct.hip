@@ -1,0 +1,258 @@
+// Direct-read forward transform for integer input: the fallback for plans
+// whose delay spread across a DM block is too wide for LDS staging to pay.
+//
+// The LDS kernel stages, per channel, the union of the windows of a block's
+// DM rows: T + spread samples for T outputs.  When the delay grows by hundreds
+// of samples per DM step (low frequencies, coarse steps) that union is mostly
+// spread, each staged byte serves one or two DM rows, and building its byte
+// phases costs more than it saves.  This kernel reads every (channel, DM)
+// window straight from global memory instead and leaves the reuse between
+// neighbouring DM rows, whose windows overlap, to the L1 and L2 caches (the
+// cache-based variant of the paper's GPU implementation, Sec. 4; its results
+// cite a slowdown of up to 4x for it).
+//
+// Windows start at any sample, but the loads stay 4-byte aligned: a lane
+// loads the aligned words covering its 16-byte (8-bit input; 32-byte for
+// 16-bit) window plus one more, and funnel-shifts them (v_alignbit, by a
+// wave-uniform bit count) into the window's words.  Raw buffer loads with the
+// channel row's pitch as the record bound return zeros past the row, so no
+// read can leave the input.  In the last time tile, where a lane's window may
+// run past the row, the words are loaded one by one: a 4-byte-aligned word
+// lies wholly inside or wholly outside the 16-byte-multiple pitch, so the
+// bound check never drops bytes a valid output needs.
+//
+// Accumulation is the same exact SIMD-in-word arithmetic as the LDS kernel:
+// 8-bit words as mix/odd pairs flushed every 256 channels, 4-bit words first
+// split into their even and odd nibbles, 16-bit words as mix and high halves.
+//
+// A workgroup covers NW * R DM rows x 64 * NS samples; wave w owns R rows, lane
+// i samples NS*i .. NS*i + NS-1 of the tile (NS = 16, or 32 for 4-bit input).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dd_internal.h"
+#include "tile_order.h"
+
+namespace dd {
+namespace {
+
+constexpr uint32_t kOdd = 0x0C030C01u;  // v_perm: bytes 1 and 3 into bytes 0 and 2
+constexpr int kRsrcWord3 = 0x00020000;  // raw (untyped) buffer access
+constexpr int kUnroll = 2;              // channels whose loads are issued together
+
+struct DirectArgs {
+  const uint8_t *x;      // [n_chan][pitch] bytes
+  const int32_t *shift;  // [n_dm][n_chan]
+  float *out;            // [n_dm][out_pitch]
+  int64_t pitch, n_out, out_pitch;
+  int32_t n_chan, n_dm;
+};
+
+template <typename T>
+__device__ __forceinline__ T scalar_load(const T *p, int64_t i) {
+  return ((const __attribute__((address_space(4))) T *)p)[i];
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+template <int BITS>
+constexpr int lane_samples() { return BITS == 4 ? 32 : 16; }
+
+template <int BITS, int R, int NW>
+__global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n_dblk, int n_tiles, int order) {
+  constexpr int NS = lane_samples<BITS>();
+  constexpr int WORDS = NS * BITS / 32;  // window words per lane (4, or 8 for 16-bit)
+  int dblk, tblk;
+  tile_of((int)blockIdx.x, n_dblk, n_tiles, order, dblk, tblk);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int d0 = (dblk * NW + w) * R;
+  const int64_t t0 = (int64_t)tblk * 64 * NS;
+  const uint32_t vo = (uint32_t)((t0 + NS * lane) * BITS / 8);  // byte of the lane's first sample
+  const bool last_tile = t0 + 64 * NS > a.n_out;                 // wave-uniform
+  int drow[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) drow[r] = min(d0 + r, a.n_dm - 1);
+
+  // Totals per row and sample.  8-bit: exact int32; 4-bit: likewise; 16-bit: the
+  // word sums themselves (mix) and the high-half sums (hi), resolved at the end.
+  uint32_t tot[R][NS];
+  uint32_t mix[R][WORDS], odd[R][WORDS];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) tot[r][k] = 0;
+#pragma unroll
+    for (int k = 0; k < WORDS; ++k) mix[r][k] = odd[r][k] = 0;
+  }
+  constexpr int kFlush = BITS == 16 ? (1 << 30) : 256;  // channels between exact flushes
+  for (int cb = 0; cb < a.n_chan; cb += kFlush) {
+    const int ce = min(cb + kFlush, a.n_chan);
+    uint32_t me[R][WORDS], mo[R][WORDS], oe[R][WORDS], oo[R][WORDS];  // 4-bit: even / odd nibble words
+    if constexpr (BITS == 4) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < WORDS; ++k) me[r][k] = mo[r][k] = oe[r][k] = oo[r][k] = 0;
+    }
+    for (int c = cb; c < ce; c += kUnroll) {
+      uint32_t raw[kUnroll][R][WORDS + 1];
+      int sh[kUnroll][R];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int cc = min(c + u, ce - 1);
+        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(a.x + (int64_t)cc * a.pitch), (short)0, (int)a.pitch, kRsrcWord3);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int s = scalar_load(a.shift, (int64_t)drow[r] * a.n_chan + cc);
+          const int64_t bit = (int64_t)s * BITS;           // bit offset of the delay
+          const int soff = (int)(bit >> 5) * 4;            // aligned byte offset, wave-uniform
+          sh[u][r] = (int)(bit & 31);
+          if (!last_tile) {
+#pragma unroll
+            for (int q = 0; q < WORDS / 4; ++q) {
+              const v4i v = __builtin_amdgcn_raw_buffer_load_b128(rs, vo + 16 * q, soff, 0);
+              raw[u][r][4 * q] = v.x;
+              raw[u][r][4 * q + 1] = v.y;
+              raw[u][r][4 * q + 2] = v.z;
+              raw[u][r][4 * q + 3] = v.w;
+            }
+          } else {
+#pragma unroll
+            for (int q = 0; q < WORDS; ++q) raw[u][r][q] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo + 4 * q, soff, 0);
+          }
+          raw[u][r][WORDS] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo + 4 * WORDS, soff, 0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const uint32_t live = c + u < ce ? 0xFFFFFFFFu : 0u;  // the unrolled tail repeats a channel
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+#pragma unroll
+          for (int k = 0; k < WORDS; ++k) {
+            const uint32_t v = __builtin_amdgcn_alignbit(raw[u][r][k + 1], raw[u][r][k], sh[u][r]) & live;
+            if constexpr (BITS == 8) {
+              mix[r][k] += v;
+              odd[r][k] += __builtin_amdgcn_perm(v, v, kOdd);
+            } else if constexpr (BITS == 16) {
+              mix[r][k] += v;
+              odd[r][k] += v >> 16;
+            } else {
+              const uint32_t e = v & 0x0F0F0F0Fu, o = (v >> 4) & 0x0F0F0F0Fu;
+              me[r][k] += e;
+              oe[r][k] += __builtin_amdgcn_perm(e, e, kOdd);
+              mo[r][k] += o;
+              oo[r][k] += __builtin_amdgcn_perm(o, o, kOdd);
+            }
+          }
+        }
+      }
+    }
+    // Flush the block of at most 256 channels into the int32 totals.
+    // mix - (odd << 8) = sum of bytes 0 + 2^16 * sum of bytes 2 (each sum < 2^16).
+    if constexpr (BITS == 8) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < WORDS; ++k) {
+          const uint32_t e = mix[r][k] - (odd[r][k] << 8), o = odd[r][k];
+          tot[r][4 * k] += e & 0xFFFFu;
+          tot[r][4 * k + 1] += o & 0xFFFFu;
+          tot[r][4 * k + 2] += e >> 16;
+          tot[r][4 * k + 3] += o >> 16;
+          mix[r][k] = odd[r][k] = 0;
+        }
+    } else if constexpr (BITS == 4) {
+      // word k holds samples 8k .. 8k+7; even nibbles are samples 8k, 8k+2, 8k+4, 8k+6
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < WORDS; ++k) {
+          const uint32_t ee = me[r][k] - (oe[r][k] << 8), eo = oe[r][k];
+          const uint32_t oe2 = mo[r][k] - (oo[r][k] << 8), oo2 = oo[r][k];
+          tot[r][8 * k + 0] += ee & 0xFFFFu;
+          tot[r][8 * k + 2] += eo & 0xFFFFu;
+          tot[r][8 * k + 4] += ee >> 16;
+          tot[r][8 * k + 6] += eo >> 16;
+          tot[r][8 * k + 1] += oe2 & 0xFFFFu;
+          tot[r][8 * k + 3] += oo2 & 0xFFFFu;
+          tot[r][8 * k + 5] += oe2 >> 16;
+          tot[r][8 * k + 7] += oo2 >> 16;
+        }
+    }
+  }
+  if constexpr (BITS == 16) {
+    // low samples: mix - (hi << 16) (mod 2^32), exact for up to 65537 channels
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int k = 0; k < WORDS; ++k) {
+        tot[r][2 * k] = mix[r][k] - (odd[r][k] << 16);
+        tot[r][2 * k + 1] = odd[r][k];
+      }
+  }
+  const int64_t tl = t0 + NS * lane;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (d0 + r >= a.n_dm) break;
+    float *o = a.out + (int64_t)(d0 + r) * a.out_pitch + tl;
+    if (tl + NS <= a.n_out) {
+#pragma unroll
+      for (int k = 0; k < NS; k += 4)
+        *(float4 *)(o + k) = make_float4((float)tot[r][k], (float)tot[r][k + 1], (float)tot[r][k + 2], (float)tot[r][k + 3]);
+    } else {
+      for (int k = 0; k < NS && tl + k < a.n_out; ++k) o[k] = (float)tot[r][k];
+    }
+  }
+}
+
+// Compiled direct shapes: (samples per lane for 8-bit input, DM rows per wave, waves, 0).
+#define DD_DIRECT_SHAPES(X) X(4, 4) X(2, 8)
+
+template <int R, int NW>
+int launch_direct_shape(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, hipStream_t st,
+                        int64_t out_limit) {
+  DirectArgs a;
+  a.x = (const uint8_t *)d_in;
+  a.shift = (const int32_t *)((const uint8_t *)p.d_tables + p.int_offs_off);
+  a.out = d_out;
+  a.pitch = p.in_pitch_bytes;
+  a.n_out = out_limit > 0 && out_limit < p.n_out ? out_limit : p.n_out;
+  a.out_pitch = out_pitch;
+  a.n_chan = p.desc.n_chan;
+  a.n_dm = p.desc.n_dm;
+  const int bits = p.desc.dtype == DD_U4 ? 4 : p.desc.dtype == DD_U16 ? 16 : 8;
+  const int ns = bits == 4 ? 32 : 16;
+  const int64_t tiles_t = (a.n_out + 64 * ns - 1) / (64 * ns);
+  const int64_t n_dblk = (a.n_dm + NW * R - 1) / (NW * R);
+  if (tiles_t * n_dblk >= ((int64_t)1 << 31)) return (int)hipErrorInvalidConfiguration;
+  const dim3 grid((unsigned)(tiles_t * n_dblk)), block(NW * 64);
+  if (bits == 4)
+    hipLaunchKernelGGL((fwd_direct_kernel<4, R, NW>), grid, block, 0, st, a, (int)n_dblk, (int)tiles_t, p.fwd.order);
+  else if (bits == 16)
+    hipLaunchKernelGGL((fwd_direct_kernel<16, R, NW>), grid, block, 0, st, a, (int)n_dblk, (int)tiles_t, p.fwd.order);
+  else
+    hipLaunchKernelGGL((fwd_direct_kernel<8, R, NW>), grid, block, 0, st, a, (int)n_dblk, (int)tiles_t, p.fwd.order);
+  return (int)hipGetLastError();
+}
+
+}  // namespace
+
+#define DD_ROW(R, NW) {16, R, NW, 0},
+const int kDirectShapes[][4] = {DD_DIRECT_SHAPES(DD_ROW)};
+#undef DD_ROW
+const int kNumDirectShapes = (int)(sizeof(kDirectShapes) / sizeof(kDirectShapes[0]));
+
+int launch_forward_direct(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream,
+                          int64_t out_limit) {
+  const TileCfg &t = p.fwd;
+#define DD_TRY(R, NW) \
+  if (t.dm_per_wave == R && t.waves == NW) return launch_direct_shape<R, NW>(p, d_in, d_out, out_pitch, (hipStream_t)stream, out_limit);
+  DD_DIRECT_SHAPES(DD_TRY)
+#undef DD_TRY
+  return (int)hipErrorInvalidValue;
+}
+
+}  // namespace dd

@@ -582,6 +582,7 @@ const int kNumIntShapes = (int)(sizeof(kIntShapes) / sizeof(kIntShapes[0]));
 int launch_forward_int(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream,
                        int64_t out_limit) {
   const TileCfg &t = p.fwd;
+  if (is_direct(t)) return launch_forward_direct(p, d_in, d_out, out_pitch, stream, out_limit);
 #define DD_TRY(NS, R, NW, CB)                                                       \
   if (t.ns == NS && t.dm_per_wave == R && t.waves == NW && t.chan_block == CB)     \
     return launch_int_shape<NS, R, NW, CB>(p, d_in, d_out, out_pitch, (hipStream_t)stream, out_limit);

@@ -20,7 +20,7 @@ static const char kCacheTag[] = "dd-tune-v1";
 static std::mutex g_cache_mutex;
 
 static const int *shape_params(const dd_plan &p, int shape) {
-  return p.desc.dtype == DD_F32 ? kF32Shapes[shape] : kIntShapes[shape];
+  return p.desc.dtype == DD_F32 ? kF32Shapes[shape] : int_shape(shape);
 }
 
 static void current_tiles(const dd_plan &p, int dir, int *shape, int *order) {

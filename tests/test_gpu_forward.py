@@ -188,6 +188,28 @@ def test_headline_workload_sampled(dd):
             assert int(np.argmax(col)) == dp, (dp, int(np.argmax(col)))
 
 
+def test_lowfreq_wide_workload_sampled(dd):
+    """4096 channels at 120-190 MHz, 2^20 samples, 1024 DMs in steps of 0.5 (264 samples of extra
+    delay per step): the direct-read kernel, as the benchmark runs it.  Sampled rows bit-exact,
+    every row by the row-sum identity, DM 0 by the channel sum, pulses at their DM."""
+    cfg = synth.CONFIGS["lowfreq_wide"]
+    s = oracle_table(cfg)
+    xd, xh, applied = _device_u8(cfg, s)
+    plan = plan_for(dd, cfg)
+    assert plan.tiles(0)["row_block"] == 0
+    out = plan.forward(xd)
+    torch.cuda.synchronize()
+    n_out = plan.n_out
+    rows = sample_rows(cfg["n_dm"], cfg["pulses"], every=128, extra=4, seed=10)
+    assert np.array_equal(out[rows].cpu().numpy(), oracle.forward(xh, "u8", cfg["n_samp"], s, rows=rows))
+    gpu_rowsum = out.double().sum(dim=1).cpu().numpy().astype(np.int64)
+    assert np.array_equal(gpu_rowsum, row_sums_by_prefix(lambda c: xh[c], s, n_out))
+    assert np.array_equal(out[0].cpu().numpy().astype(np.int64), xh[:, :n_out].sum(axis=0, dtype=np.int64))
+    for i, (dp, width, t0) in enumerate(cfg["pulses"]):
+        assert applied[i].sum() > 0
+        assert int(np.argmax(out[:, t0].cpu().numpy())) == dp
+
+
 def test_lowfreq_u4_workload_sampled(dd):
     """4096 channels of packed 4-bit input at 120-190 MHz, 2^19 samples, 2048 DMs (delays > 10^5)."""
     cfg = synth.CONFIGS["lowfreq_u4"]

@@ -150,3 +150,33 @@ def test_time_chunks_equal_whole(dd, dtype):
         p.forward(tc.input_view(xd, k), out=tc.output_view(out, k))
     torch.cuda.synchronize()
     assert torch.equal(out[:, : whole.n_out], ref)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u4", "u16"])
+def test_direct_kernel_large_spread(dd, dtype):
+    """The direct-read kernel on a plan it is chosen for: 264 samples of delay per DM step,
+    more than 256 channels (exact flushes), a ragged last tile, odd delays for 4-bit input,
+    padded rows; every output bit-exact, both direct shapes, all orders."""
+    cfg = dict(dtype=dtype, n_chan=300, n_samp=50012, f_high=190.0, chan_bw=70.0 / 300, t_samp=327.68e-6,
+               dm_start=1.0, dm_step=0.5, n_dm=37, seed=43)
+    s = oracle_table(cfg)
+    pitch = {"u8": 50048, "u4": 25024, "u16": 50048}[dtype]
+    x, _ = host_input(cfg, s, pitch=pitch)
+    want = oracle.forward(x, dtype, cfg["n_samp"], s)
+    plan = plan_for(dd, cfg, in_pitch_bytes=pitch * (2 if dtype == "u16" else 1))
+    assert plan.tiles(0)["row_block"] == 0, plan.tiles(0)
+    xd = torch.from_numpy(x.view(np.int16)).cuda().view(torch.uint16) if dtype == "u16" else torch.from_numpy(x).cuda()
+    for shape in range(plan.n_shapes):
+        try:
+            plan.set_tiles(0, shape, 0)
+        except dd.DDError as e:  # an LDS shape that cannot stage this spread
+            assert e.name == "DD_ERR_RANGE"
+            continue
+        if plan.tiles(0)["row_block"] != 0:
+            continue
+        for o in (0, 1, 2):
+            plan.set_tiles(0, shape, o)
+            print("direct shape", shape, "order", o, flush=True)
+            got = plan.forward(xd)
+            torch.cuda.synchronize()
+            assert np.array_equal(got.cpu().numpy(), want), (shape, o)

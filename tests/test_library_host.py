@@ -224,3 +224,18 @@ def test_survey_time_major_layout(dd):
     with pytest.raises(dd.DDError) as e:  # spectrum pitch below one spectrum of 128 channels
         dd.Survey(*args, in_pitch_bytes=112, bind=False, time_major=True)
     assert e.value.name == "DD_ERR_ARG"
+
+
+def test_large_spread_plan_uses_direct_kernel(dd):
+    """Plans whose delay spread leaves only 1- or 2-channel LDS stages default to the direct-read
+    kernel (no staging: row_block 0), whose table is the plain shift table."""
+    cfg = synth.CONFIGS["lowfreq_wide"]
+    p = _plan(dd, cfg)
+    t = p.tiles(0)
+    assert t["row_block"] == 0 and t["shape"] >= 13
+    assert p.info.dev_table_bytes >= cfg["n_dm"] * cfg["n_chan"] * 4
+    assert p.info.tune_ws_bytes >= p.info.dev_table_bytes
+    for name in ["small", "headline", "lowfreq_u4", "headline_u16"]:  # narrow spreads keep LDS staging
+        assert _plan(dd, synth.CONFIGS[name]).tiles(0)["row_block"] > 0
+    p4 = _plan(dd, dict(cfg, dtype="u4"))
+    assert p4.tiles(0)["row_block"] == 0 and p4.tiles(0)["per_wave"] == 2
