@@ -155,6 +155,35 @@ def cpu_baseline(cfg, seconds_target=15.0):
                       % (len(rows), cfg["n_dm"], cfg["n_chan"], n_out, adds, dt)}
 
 
+def cpu_tiled_baseline(cfg, seconds_target=15.0):
+    """Time the paper's tiled CPU algorithm (Algorithm 2, libdd_cpu.so) on a bounded sample:
+    the first DM rows of the plan (neighbouring trials are what its tiling reuses), all
+    channels and output samples.  8-bit input only."""
+    import oracle
+    import synth
+    from paper_2311_05341_amd import cpu_tiled
+
+    s = oracle.shift_table(cfg["n_chan"], cfg["f_high"], cfg["chan_bw"], cfg["t_samp"], cfg["dm_start"],
+                           cfg["dm_step"], cfg["n_dm"])
+    n_out = oracle.n_out_for(s, cfg["n_samp"])
+    x = synth.gaussian_u8(cfg["n_chan"], cfg["n_samp"], cfg["seed"])
+    d_dm = cpu_tiled.DEFAULT_TILES[1]
+    probe = min(cfg["n_dm"], 2 * d_dm)
+    t = time.perf_counter()
+    cpu_tiled.forward_u8(x, s[:probe], n_out)
+    per_row = (time.perf_counter() - t) / probe
+    n_rows = int(min(cfg["n_dm"], max(probe, seconds_target / per_row // d_dm * d_dm)))
+    t = time.perf_counter()
+    cpu_tiled.forward_u8(x, s[:n_rows], n_out)
+    dt = time.perf_counter() - t
+    adds = float(n_rows) * n_out * cfg["n_chan"]
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": adds / dt / 1e12, "unit": "Tadds/s", "cores": threads, "kind": "tiled (Algorithm 2)",
+            "tiles": list(cpu_tiled.DEFAULT_TILES),
+            "sample": "first %d of %d DM rows, all %d channels x %d output samples (%.2e adds, %.1f s)"
+                      % (n_rows, cfg["n_dm"], cfg["n_chan"], n_out, adds, dt)}
+
+
 BATCH_CHUNKS = 2  # time chunks per beam of the 48-beam job (its outputs would not fit HBM at once)
 
 
@@ -539,6 +568,9 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         rec["cpu_baseline"] = cpu_baseline(cfg)
+        if cfg["dtype"] == "u8":
+            log("tiled cpu baseline ...")
+            rec["cpu_tiled"] = cpu_tiled_baseline(cfg)
     print(json.dumps(rec), flush=True)
 
 
