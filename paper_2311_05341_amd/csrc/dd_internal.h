@@ -87,7 +87,6 @@ namespace dd {
 // Host plan helpers (plan.cpp).
 dd_status build_shift_table(dd_plan &p);
 int32_t max_dm_block_span(const dd_plan &p, int dm_block);
-int row_bytes_for(int dtype, int ns, int span);
 dd_status choose_forward_tiles(dd_plan &p);
 // Rebuild the tables of one direction (0 forward, 1 adjoint) for compiled
 // shape `shape` and TileOrder `order`.  DD_ERR_RANGE if the shape cannot hold

@@ -109,20 +109,6 @@ static const int kLdsLimit = 160 * 1024;
 
 static int round_up(int64_t v, int a) { return (int)((v + a - 1) / a * a); }
 
-// LDS bytes of one staged row for a tile of `ns` samples per lane and a delay
-// spread `span`.  Integer rows hold unpacked uint8 samples starting at the
-// block's first-DM delay rounded down to the staging unit (16 samples for u8,
-// 32 for u4: one 16-byte global chunk); a lane reads ns/16 + 1 aligned 16-byte
-// chunks at offset up to span + unit - 1, so the row needs
-// 64*ns + span + unit + 15 bytes.  Float rows hold samples from the delay
-// rounded down to 4 and a lane reads ns/4 + 1 chunks of 4 floats.
-int row_bytes_for(int dtype, int ns, int span) {
-  if (dtype == DD_F32) return 4 * round_up((int64_t)64 * ns + span + 8, 4);
-  if (dtype == DD_U16) return round_up(2 * ((int64_t)64 * ns + span + 8 + 8), 16);
-  const int unit = dtype == DD_U4 ? 32 : 16;
-  return round_up((int64_t)64 * ns + span + unit + 16, unit);
-}
-
 // Tables of the integer forward kernel for tile shape (ns, dm_per_wave, waves).
 // For DM block b, channel c: sbase = shift(c, first DM of b) rounded down to
 // the staging unit (the samples in 16 bytes: 16 for u8, 32 for u4, 8 for u16);
