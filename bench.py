@@ -288,6 +288,16 @@ def bench_batch48(args, dd, torch, synth):
     beams, chunkers, inputs, outputs, batches = setup_batch48(dd, torch, synth)
     adds = float(sum(b["n_dm"] * c.n_out * b["n_chan"] for b, c in zip(beams, chunkers)))
     stream = torch.cuda.current_stream()
+    tune = None
+    if not args.no_autotune:
+        # the batch autotuner on the first chunk's batch; the other chunks take its shape
+        t = time.perf_counter()
+        tune = batches[0][1].autotune()
+        for _, bt in batches[1:]:
+            bt.set_tiles(tune["best"]["shape"])
+        torch.cuda.synchronize()
+        tune["seconds"] = time.perf_counter() - t
+        log("batch autotune: %s" % tune)
 
     def batched():
         for _, bt in batches:
@@ -359,6 +369,8 @@ def bench_batch48(args, dd, torch, synth):
                      "frac_instruction_form": achieved / (2 * VALU_PEAK_TOPS)},
         "lds_roofline": {"achieved": achieved, "peak": LDS_PEAK_TBS, "unit": "TB/s", "frac": achieved / LDS_PEAK_TBS,
                          "bytes_per_add": 1},
+        "batch_tiles": batches[0][1].tiles(),
+        "batch_autotune": tune,
     }
     if not args.no_cpu_baseline:
         big = max(beams, key=lambda b: b["n_chan"] * b["n_samp"] * b["n_dm"])

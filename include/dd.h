@@ -214,7 +214,8 @@ dd_status dd_plan_autotune(dd_plan *plan, int32_t direction, const void *d_src, 
  * (channel count, length, DM plan), run as ONE persistent kernel launch that
  * pulls (beam, DM block, time tile) work items from a device counter, largest
  * items first.  The launch sequence is recorded once as a HIP graph and
- * replayed by every dd_execute_batched call.
+ * replayed by every dd_execute_batched call.  All beams share one staged tile
+ * shape: the first that stages every beam, or the one dd_batch_autotune picks.
  *
  * dd_batch_create: plans[0..n-1] must be integer plans (DD_U8, DD_U4 or DD_U16),
  *   all of one dtype, and outlive the batch.  Errors: DD_ERR_ARG, DD_ERR_DTYPE, DD_ERR_NOMEM.
@@ -225,12 +226,25 @@ dd_status dd_plan_autotune(dd_plan *plan, int32_t direction, const void *d_src, 
  *   `stream` and records the graph; re-binding re-records it.
  *   Errors: DD_ERR_ARG, DD_ERR_ALIGN, DD_ERR_HIP.
  * dd_execute_batched: replay the graph on `stream`.  Errors: DD_ERR_NOT_BOUND, DD_ERR_HIP.
+ * dd_batch_get_tiles: the shared tile shape (order is always 0: work items are claimed dynamically).
+ * dd_batch_set_tiles: switch to compiled staged shape `shape` (DD_ERR_RANGE, batch unchanged, if a
+ *   beam cannot be staged with it); unbinds the batch, which keeps its workspace size.
+ * dd_batch_autotune: with the arguments of dd_batch_bind, time the default shape and every staged
+ *   shape with at least 32 DM rows per workgroup on the whole batch (one warm-up replay, one timed
+ *   replay with HIP events on `stream`), keep the fastest (the default stays unless another is at
+ *   least 1% faster) and leave the batch bound with it.  Outputs are overwritten.  Synchronises
+ *   `stream`.  *report may be NULL (timed_out_samples is 0: whole replays are timed).
+ *   Errors: as dd_batch_bind.
  */
 dd_status dd_batch_create(const dd_plan *const *plans, int32_t n, dd_batch **out);
 dd_status dd_batch_workspace_bytes(const dd_batch *batch, size_t *bytes);
 dd_status dd_batch_bind(dd_batch *batch, const void *const *d_in, float *const *d_out,
                         const int64_t *out_pitch, void *d_workspace, size_t bytes, void *stream);
 dd_status dd_execute_batched(dd_batch *batch, void *stream);
+dd_status dd_batch_get_tiles(const dd_batch *batch, dd_tiles *tiles);
+dd_status dd_batch_set_tiles(dd_batch *batch, int32_t shape);
+dd_status dd_batch_autotune(dd_batch *batch, const void *const *d_in, float *const *d_out, const int64_t *out_pitch,
+                            void *d_workspace, size_t bytes, void *stream, dd_tune_report *report);
 void dd_batch_destroy(dd_batch *batch);
 
 /*

@@ -88,6 +88,13 @@ _lib.dd_batch_bind.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ct
 _lib.dd_batch_bind.restype = _i32
 _lib.dd_execute_batched.argtypes = [_vp, _vp]
 _lib.dd_execute_batched.restype = _i32
+_lib.dd_batch_get_tiles.argtypes = [_vp, ctypes.POINTER(Tiles)]
+_lib.dd_batch_get_tiles.restype = _i32
+_lib.dd_batch_set_tiles.argtypes = [_vp, _i32]
+_lib.dd_batch_set_tiles.restype = _i32
+_lib.dd_batch_autotune.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i64), _vp, _sz, _vp,
+                                   ctypes.POINTER(TuneReport)]
+_lib.dd_batch_autotune.restype = _i32
 _lib.dd_batch_destroy.argtypes = [_vp]
 _lib.dd_batch_destroy.restype = None
 _lib.dd_bin_time.argtypes = [_i32, _vp, _i64, _i32, _i64, _i32, _vp, _i64, _vp]
@@ -361,11 +368,37 @@ class Batch:
         if outputs is None:
             outputs = [torch.empty((p.n_dm, p.out_pitch), dtype=torch.float32, device=dev) for p in plans]
         self.outputs = list(outputs)
-        ins = (_vp * n)(*[x.data_ptr() for x in self.inputs])
-        outs = (_vp * n)(*[o.data_ptr() for o in self.outputs])
-        pitches = (_i64 * n)(*[o.stride(0) for o in self.outputs])
-        _check(_lib.dd_batch_bind(h, ins, outs, pitches, self.workspace.data_ptr(), self.workspace.numel(),
+        self.bind(stream)
+
+    def _bind_args(self):
+        n = len(self.plans)
+        return ((_vp * n)(*[x.data_ptr() for x in self.inputs]), (_vp * n)(*[o.data_ptr() for o in self.outputs]),
+                (_i64 * n)(*[o.stride(0) for o in self.outputs]))
+
+    def bind(self, stream=None):
+        ins, outs, pitches = self._bind_args()
+        _check(_lib.dd_batch_bind(self._h, ins, outs, pitches, self.workspace.data_ptr(), self.workspace.numel(),
                                   _stream_handle(stream)), "dd_batch_bind")
+
+    def tiles(self) -> dict:
+        t = Tiles()
+        _check(_lib.dd_batch_get_tiles(self._h, ctypes.byref(t)), "dd_batch_get_tiles")
+        return t.as_dict()
+
+    def set_tiles(self, shape, stream=None):
+        """Switch every beam to compiled staged shape `shape` and re-bind."""
+        _check(_lib.dd_batch_set_tiles(self._h, int(shape)), "dd_batch_set_tiles")
+        self.bind(stream)
+
+    def autotune(self, stream=None) -> dict:
+        """Time the staged shapes on the whole batch and keep the fastest (dd_batch_autotune); outputs are
+        overwritten."""
+        ins, outs, pitches = self._bind_args()
+        rep = TuneReport()
+        _check(_lib.dd_batch_autotune(self._h, ins, outs, pitches, self.workspace.data_ptr(), self.workspace.numel(),
+                                      _stream_handle(stream), ctypes.byref(rep)), "dd_batch_autotune")
+        return {"n_tried": int(rep.n_tried), "best": rep.best.as_dict(), "best_ms": rep.best_ms,
+                "default_ms": rep.default_ms}
 
     def run(self, stream=None):
         _check(_lib.dd_execute_batched(self._h, _stream_handle(stream)), "dd_execute_batched")

@@ -17,6 +17,7 @@ using namespace dd;
 struct dd_batch {
   std::vector<const dd_plan *> plans;
   int dtype = 0;
+  int shape = 0;                // index of the shared LDS shape in kIntShapes
   TileCfg tile;                 // shared tile shape (ns, dm_per_wave, waves)
   std::vector<IntTables> tables;  // per beam (original index), for the shared shape
   int lds_bytes = 0;
@@ -42,6 +43,59 @@ static void release_graph(dd_batch *b) {
   b->graph = nullptr;
 }
 
+// Table bytes of one beam's plan under LDS shape k (offsets, stage bases), each
+// rounded up to 256 bytes.
+static void int_table_bytes(const dd_plan &p, const int *k, size_t *offs, size_t *sbase) {
+  const int64_t nd = p.desc.n_dm, nc = p.desc.n_chan, dblk = (int64_t)k[1] * k[2];
+  const int64_t n_dblk = (nd + dblk - 1) / dblk, rp = k[1] < 2 ? 2 : k[1], ncp = (nc + k[3] - 1) / k[3] * k[3];
+  *offs = up256((size_t)(n_dblk * k[2] * ncp * rp) * sizeof(uint16_t));
+  *sbase = up256((size_t)(n_dblk * nc) * sizeof(int32_t));
+}
+
+// Switch the batch to LDS shape s: every beam's tables, the launch geometry and
+// the work list.  DD_ERR_RANGE (batch unchanged) if a beam cannot be staged.
+static dd_status batch_set_shape(dd_batch *b, int s) {
+  const int n = (int)b->plans.size();
+  const int *k = kIntShapes[s];
+  std::vector<IntTables> tabs(n);
+  int lds = 0;
+  for (int i = 0; i < n; ++i) {
+    const dd_status st = build_int_tables(*b->plans[i], k[0], k[1], k[2], k[3], kBatchLdsLimit, &tabs[i]);
+    if (st != DD_OK) return st;
+    lds = std::max(lds, tabs[i].lds_bytes);
+  }
+  b->tables = std::move(tabs);
+  b->shape = s;
+  b->tile.ns = k[0];
+  b->tile.dm_per_wave = k[1];
+  b->tile.waves = k[2];
+  b->tile.chan_block = k[3];
+  b->lds_bytes = lds;
+  const int dm_tile = k[1] * k[2], t_tile = 64 * k[0];
+  b->descs.resize(n);
+  long long items = 0;
+  for (int q = 0; q < n; ++q) {
+    const int i = b->order[q];
+    const dd_plan &p = *b->plans[i];
+    BeamDesc &d = b->descs[q];
+    memset(&d, 0, sizeof(d));
+    d.n_chan = p.desc.n_chan;
+    d.n_dm = p.desc.n_dm;
+    d.n_samp = p.desc.n_samp;
+    d.n_out = p.n_out;
+    d.pitch = p.in_pitch_bytes;
+    d.row_bytes = b->tables[i].row_bytes;
+    d.chan_block = b->tables[i].chan_block;
+    d.tiles_t = (int)((p.n_out + t_tile - 1) / t_tile);
+    d.tiles_d = (p.desc.n_dm + dm_tile - 1) / dm_tile;
+    d.item_begin = items;
+    items += (long long)d.tiles_t * d.tiles_d;
+  }
+  b->n_items = items;
+  b->bound = false;
+  return DD_OK;
+}
+
 extern "C" {
 
 dd_status dd_batch_create(const dd_plan *const *plans, int32_t n, dd_batch **out) {
@@ -59,68 +113,40 @@ dd_status dd_batch_create(const dd_plan *const *plans, int32_t n, dd_batch **out
     if (plans[i]->desc.dtype != b->dtype) { delete b; return fail(DD_ERR_DTYPE, "all beams of a batch share one dtype"); }
     b->plans.push_back(plans[i]);
   }
-  // One tile shape for all beams: the first compiled shape every beam can stage
-  // (two workgroups' worth of LDS is not required: the kernel runs one per CU).
-  bool found = false;
-  for (int s = 0; s < kNumIntShapes && !found; ++s) {
-    b->tables.assign(n, IntTables());
-    bool ok = true;
-    int lds = 0;
-    for (int i = 0; i < n && ok; ++i) {
-      dd_status st = build_int_tables(*b->plans[i], kIntShapes[s][0], kIntShapes[s][1], kIntShapes[s][2],
-                                      kIntShapes[s][3], kBatchLdsLimit, &b->tables[i]);
-      if (st == DD_ERR_NOMEM) { delete b; return st; }
-      ok = st == DD_OK;
-      if (ok) lds = std::max(lds, b->tables[i].lds_bytes);
-    }
-    if (ok) {
-      b->tile.ns = kIntShapes[s][0];
-      b->tile.dm_per_wave = kIntShapes[s][1];
-      b->tile.waves = kIntShapes[s][2];
-      b->tile.chan_block = kIntShapes[s][3];
-      b->lds_bytes = lds;
-      found = true;
-    }
-  }
-  if (!found) { delete b; return fail(DD_ERR_RANGE, "a beam's delay spread exceeds the LDS staging capacity"); }
   // Work items: beams ordered by per-item cost (channels x DM rows per tile), largest first.
   b->order.resize(n);
   std::iota(b->order.begin(), b->order.end(), 0);
   std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c) {
     return b->plans[a]->desc.n_chan > b->plans[c]->desc.n_chan;
   });
-  const int dm_tile = b->tile.waves * b->tile.dm_per_wave, t_tile = 64 * b->tile.ns;
+  // Workspace layout: counter, descriptors, then per beam room for its tables
+  // under the largest compiled shape, so changing the shape never moves them.
   size_t off = up256(sizeof(unsigned long long)) + up256(sizeof(BeamDesc) * (size_t)n);
   b->table_off = off;
   b->table_offs.assign(n, 0);
   b->sbase_offs.assign(n, 0);
   for (int i = 0; i < n; ++i) {
+    size_t ob = 0, sbb = 0;
+    for (int s = 0; s < kNumIntShapes; ++s) {
+      size_t o, sb;
+      int_table_bytes(*b->plans[i], kIntShapes[s], &o, &sb);
+      ob = std::max(ob, o);
+      sbb = std::max(sbb, sb);
+    }
     b->table_offs[i] = off;
-    off += up256(b->tables[i].offs.size() * sizeof(uint16_t));
+    off += ob;
     b->sbase_offs[i] = off;
-    off += up256(b->tables[i].sbase.size() * sizeof(int32_t));
+    off += sbb;
   }
   b->ws_bytes = off;
-  b->descs.resize(n);
-  long long items = 0;
-  for (int k = 0; k < n; ++k) {
-    const int i = b->order[k];
-    const dd_plan &p = *b->plans[i];
-    BeamDesc &d = b->descs[k];
-    memset(&d, 0, sizeof(d));
-    d.n_chan = p.desc.n_chan;
-    d.n_dm = p.desc.n_dm;
-    d.n_samp = p.desc.n_samp;
-    d.n_out = p.n_out;
-    d.pitch = p.in_pitch_bytes;
-    d.row_bytes = b->tables[i].row_bytes;
-    d.chan_block = b->tables[i].chan_block;
-    d.tiles_t = (int)((p.n_out + t_tile - 1) / t_tile);
-    d.tiles_d = (p.desc.n_dm + dm_tile - 1) / dm_tile;
-    d.item_begin = items;
-    items += (long long)d.tiles_t * d.tiles_d;
+  // One tile shape for all beams: the first compiled shape every beam can stage
+  // (two workgroups' worth of LDS is not required: the kernel runs one per CU).
+  dd_status st = DD_ERR_RANGE;
+  for (int s = 0; s < kNumIntShapes && st != DD_OK; ++s) {
+    st = batch_set_shape(b, s);
+    if (st == DD_ERR_NOMEM) { delete b; return st; }
   }
-  b->n_items = items;
+  if (st != DD_OK) { delete b; return fail(DD_ERR_RANGE, "a beam's delay spread exceeds the LDS staging capacity"); }
   *out = b;
   return DD_OK;
 }
@@ -215,6 +241,109 @@ dd_status dd_execute_batched(dd_batch *b, void *stream) {
   if (!b->bound || !b->exec) return fail(DD_ERR_NOT_BOUND, "batch is not bound");
   hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
   if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
+  return DD_OK;
+}
+
+dd_status dd_batch_get_tiles(const dd_batch *b, dd_tiles *t) {
+  if (!b || !t) return fail(DD_ERR_ARG, "null argument");
+  const int *k = kIntShapes[b->shape];
+  t->shape = b->shape;
+  t->order = 0;
+  t->ns = k[0];
+  t->per_wave = k[1];
+  t->waves = k[2];
+  t->row_block = k[3];
+  return DD_OK;
+}
+
+dd_status dd_batch_set_tiles(dd_batch *b, int32_t shape) {
+  if (!b) return fail(DD_ERR_ARG, "null batch");
+  if (shape < 0 || shape >= kNumIntShapes) return fail(DD_ERR_ARG, "no such staged tile shape");
+  const dd_status st = batch_set_shape(b, shape);
+  if (st == DD_ERR_RANGE) return fail(st, "a beam's delay spread does not fit this shape");
+  return st;
+}
+
+dd_status dd_batch_autotune(dd_batch *b, const void *const *d_in, float *const *d_out, const int64_t *out_pitch,
+                            void *ws, size_t bytes, void *stream, dd_tune_report *rep) {
+  if (!b) return fail(DD_ERR_ARG, "null batch");
+  const int orig = b->shape;
+  hipStream_t st = (hipStream_t)stream;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return hip_error(he, "hipEventCreate");
+  }
+  // Bind shape s, replay once to warm up, then time one replay.
+  auto time_shape = [&](int s, double *ms) -> dd_status {
+    dd_status r = batch_set_shape(b, s);
+    if (r != DD_OK) return r;
+    r = dd_batch_bind(b, d_in, d_out, out_pitch, ws, bytes, stream);
+    if (r != DD_OK) return r;
+    hipError_t e = hipGraphLaunch(b->exec, st);
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    if (e == hipSuccess) e = hipGraphLaunch(b->exec, st);
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (e != hipSuccess) return hip_error(e, "batch tuning launch");
+    *ms = t;
+    return DD_OK;
+  };
+  double default_ms = 0.0, best_ms = 0.0;
+  int best = orig, tried = 0;
+  dd_status status = time_shape(orig, &default_ms);
+  if (status == DD_OK) {
+    best_ms = default_ms;
+    tried = 1;
+    // Candidates: shapes with at least 32 DM rows per workgroup (the smaller ones
+    // only pay where the batch's own default already had to fall back to them).
+    for (int s = 0; s < kNumIntShapes && status == DD_OK; ++s) {
+      if (s == orig || kIntShapes[s][1] * kIntShapes[s][2] < 32) continue;
+      double ms = 0.0;
+      const dd_status ts = time_shape(s, &ms);
+      if (ts == DD_ERR_RANGE) continue;
+      if (ts != DD_OK) {
+        status = ts;
+        break;
+      }
+      ++tried;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best = s;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status != DD_OK) {
+    const std::string msg = dd_last_error();
+    (void)hipStreamSynchronize(st);
+    (void)batch_set_shape(b, orig);
+    return fail(status, msg);
+  }
+  if (best_ms > 0.99 * default_ms) {  // within timing noise of the default: keep it
+    best = orig;
+    best_ms = default_ms;
+  }
+  status = batch_set_shape(b, best);
+  if (status == DD_OK) status = dd_batch_bind(b, d_in, d_out, out_pitch, ws, bytes, stream);
+  if (status == DD_OK) {
+    const hipError_t se = hipStreamSynchronize(st);
+    if (se != hipSuccess) status = hip_error(se, "hipStreamSynchronize");
+  }
+  if (status != DD_OK) return status;
+  if (rep) {
+    memset(rep, 0, sizeof(*rep));
+    rep->n_tried = tried;
+    dd_batch_get_tiles(b, &rep->best);
+    rep->best_ms = best_ms;
+    rep->default_ms = default_ms;
+    rep->timed_out_samples = 0;
+  }
   return DD_OK;
 }
 

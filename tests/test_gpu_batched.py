@@ -88,3 +88,37 @@ def test_batched_u16_beams(dd):
     for b, cfg in enumerate(beams):
         want = oracle.forward(hosts[b], "u16", cfg["n_samp"], tables[b])
         assert np.array_equal(outs[b].cpu().numpy(), want), b
+
+
+def test_batched_every_shape_and_autotune(dd):
+    """Every staged shape that holds the beams gives the same bits (equal to plain calls), and the
+    batch autotuner leaves the batch bound with one of them, results unchanged."""
+    beams = _beams(5, 78, 60000)
+    plans, xs = [], []
+    for cfg in beams:
+        x = synth.gaussian_u8(cfg["n_chan"], cfg["n_samp"], cfg["seed"], pitch=cfg["pitch"])
+        plans.append(plan_for(dd, cfg, in_pitch_bytes=cfg["pitch"]))
+        xs.append(torch.from_numpy(x).cuda())
+    plain = [p.forward(x).clone() for p, x in zip(plans, xs)]
+    batch = dd.Batch(plans, xs)
+    n_ok = 0
+    for shape in range(13):
+        try:
+            batch.set_tiles(shape)
+        except dd.DDError as e:
+            assert e.name == "DD_ERR_RANGE"
+            continue
+        assert batch.tiles()["shape"] == shape
+        outs = batch.run()
+        torch.cuda.synchronize()
+        print("batch shape", shape, flush=True)
+        for b in range(len(beams)):
+            assert torch.equal(outs[b], plain[b]), (shape, b)
+        n_ok += 1
+    assert n_ok >= 5
+    rep = batch.autotune()
+    assert rep["n_tried"] >= 2 and rep["best"]["shape"] == batch.tiles()["shape"]
+    outs = batch.run()
+    torch.cuda.synchronize()
+    for b in range(len(beams)):
+        assert torch.equal(outs[b], plain[b])
