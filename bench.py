@@ -54,47 +54,6 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-class ClockSampler:
-    """Read the GPU's current sclk/mclk once, a little after the timed region starts.
-
-    Runs `amd-smi metric --clock --json` in a child process from a helper
-    thread (no exec in this process); the raw current-clock fields are kept,
-    or None if the tool is missing or fails."""
-
-    def __init__(self, delay_s=0.5):
-        import threading
-        self.result = None
-        self._t = threading.Thread(target=self._run, args=(delay_s,), daemon=True)
-
-    def _run(self, delay_s):
-        import subprocess
-        time.sleep(delay_s)
-        try:
-            p = subprocess.run(["amd-smi", "metric", "--clock", "--json"], capture_output=True, text=True, timeout=20)
-            data = json.loads(p.stdout) if p.returncode == 0 else None
-        except Exception:  # tool missing or output not JSON: report nothing
-            data = None
-        if data is None:
-            return
-        gpus = data if isinstance(data, list) else data.get("gpu_data", [data])
-        clk = (gpus[0] or {}).get("clock", {}) if gpus else {}
-        pick = {}
-        for name in ("gfx_0", "mem_0", "sclk", "mclk"):
-            v = clk.get(name)
-            if isinstance(v, dict):
-                cur = v.get("clk", v.get("current"))
-                pick[name] = cur.get("value") if isinstance(cur, dict) else cur
-        self.result = pick or None
-
-    def start(self):
-        self._t.start()
-        return self
-
-    def join(self):
-        self._t.join(timeout=30)
-        return self.result
-
-
 def measured_traffic(workload, tiles):
     """Memory traffic per launch from a committed rocprofv3 counter summary.
 
@@ -563,7 +522,6 @@ def main():
     stream = torch.cuda.current_stream()
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
-    clocks = ClockSampler().start()
     t0 = time.perf_counter()
     for e0, e1 in events:
         e0.record(stream)
@@ -614,7 +572,6 @@ def main():
                          "bytes_per_add": LDS_BYTES_PER_ADD[cfg["dtype"]]},
         "tiles": tiles,
         "autotune": tune,
-        "gpu_clocks_mhz": clocks.join(),
     }
     if tiles["row_block"] == 0 and cfg["dtype"] != "f32":
         # The direct-read kernel loads 16 + 4 bytes per 16 samples of 8-bit (or 32 of 4-bit) input

@@ -62,11 +62,21 @@ def use_library(path):
     _lib = None if path is None else _configure(ctypes.CDLL(path))
 
 
+def _gpu_started() -> bool:
+    """True once this process has initialised a GPU through torch (no compiler may be started then)."""
+    import sys
+    torch = sys.modules.get("torch")
+    return bool(torch is not None and torch.cuda.is_initialized())
+
+
 def _load():
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if _gpu_started():
+            raise RuntimeError("liboracle.so is missing or older than oracle.c: run oracle.build() "
+                               "(or __graft_entry__.build()) before using a GPU in this process")
         build()
     _lib = _configure(ctypes.CDLL(_LIB))
     return _lib

@@ -28,6 +28,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import sys
 from functools import lru_cache
 
 import numpy as np
@@ -59,6 +60,9 @@ def _cpu_lib():
     if _cpu is None:
         src = os.path.join(_HERE, "gen.c")
         if not os.path.exists(_CPU_LIB) or os.path.getmtime(_CPU_LIB) < os.path.getmtime(src):
+            torch = sys.modules.get("torch")
+            if torch is not None and torch.cuda.is_initialized():  # no compiler after GPU start
+                raise RuntimeError("libsynth_cpu.so is missing or stale: run synth.build() first")
             build(gpu=False)
         lib = ctypes.CDLL(_CPU_LIB)
         vp, i32, i64, u64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64
