@@ -197,16 +197,21 @@ __device__ __forceinline__ void f32_tile(uint8_t *lds, const FArgs &a, int oblk,
     stage_dma<MAXT>(a, dp, bases, t0, (b + kRing - 1) * CB, lds + ((b + kRing - 1) % kRing) * slot_bytes,
                     sink);  // zeros past the end
     const uint8_t *blk = lane_base + (b % kRing) * slot_bytes;
+    // Reads run one (row, output) pair ahead of the adds in a second register set.
+    float wv[2][NS];
+    auto read_pair = [&](int q, float (&dst)[NS]) {
+      const int kk = q / R, r = q % R;
+      const uint32_t e = (ow[kk * NOW + (r >> 1)] >> (16 * (r & 1))) & 0xFFFFu;
+      const float *p = (const float *)(blk + kk * a.row_bytes + e);
 #pragma unroll
-    for (int kk = 0; kk < CB; ++kk) {
-      const uint8_t *row = blk + kk * a.row_bytes;
+      for (int j = 0; j < NS; ++j) dst[j] = p[64 * j];
+    };
+    read_pair(0, wv[0]);
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint32_t e = (ow[kk * NOW + (r >> 1)] >> (16 * (r & 1))) & 0xFFFFu;
-        const float *p = (const float *)(row + e);
+    for (int q = 0; q < CB * R; ++q) {
+      if (q + 1 < CB * R) read_pair(q + 1, wv[(q + 1) & 1]);
 #pragma unroll
-        for (int j = 0; j < NS; ++j) part[r][j] += p[64 * j];
-      }
+      for (int j = 0; j < NS; ++j) part[q % R][j] += wv[q & 1][j];
     }
     if (((b + 1) * CB) % 32 == 0 || b + 1 == nblk) {  // end of a group of 32 rows
 #pragma unroll
