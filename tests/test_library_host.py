@@ -239,3 +239,41 @@ def test_large_spread_plan_uses_direct_kernel(dd):
         assert _plan(dd, synth.CONFIGS[name]).tiles(0)["row_block"] > 0
     p4 = _plan(dd, dict(cfg, dtype="u4"))
     assert p4.tiles(0)["row_block"] == 0 and p4.tiles(0)["per_wave"] == 2
+
+
+def test_batch_tile_choice_host(dd):
+    """Batch shape selection on the host: the default stages every beam, set_tiles switches or
+    refuses (DD_ERR_RANGE, batch unchanged), and the workspace size does not depend on the shape."""
+    lib = ctypes.CDLL(dd.LIB_PATH)
+    lib.dd_batch_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]
+    lib.dd_batch_workspace_bytes.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]
+    lib.dd_batch_get_tiles.argtypes = [ctypes.c_void_p, ctypes.POINTER(dd.binding.Tiles)]
+    lib.dd_batch_set_tiles.argtypes = [ctypes.c_void_p, ctypes.c_int32]
+    lib.dd_batch_destroy.argtypes = [ctypes.c_void_p]
+    small = synth.CONFIGS["small"]
+    wide = dict(small, n_chan=64, chan_bw=0.3, dm_step=40.0, n_dm=40, n_samp=1 << 17)  # a wide delay spread
+    plans = [_plan(dd, small), _plan(dd, wide)]
+    arr = (ctypes.c_void_p * 2)(*[p._h for p in plans])
+    h = ctypes.c_void_p()
+    assert lib.dd_batch_create(arr, 2, ctypes.byref(h)) == 0
+    try:
+        t = dd.binding.Tiles()
+        assert lib.dd_batch_get_tiles(h, ctypes.byref(t)) == 0
+        ws0 = ctypes.c_size_t()
+        lib.dd_batch_workspace_bytes(h, ctypes.byref(ws0))
+        first = t.shape
+        assert lib.dd_batch_set_tiles(h, 13) == -1 and lib.dd_batch_set_tiles(h, -1) == -1
+        ok = []
+        for s in range(13):
+            rc = lib.dd_batch_set_tiles(h, s)
+            assert rc in (0, -3), rc
+            lib.dd_batch_get_tiles(h, ctypes.byref(t))
+            if rc == 0:
+                ok.append(s)
+                assert t.shape == s
+            ws = ctypes.c_size_t()
+            lib.dd_batch_workspace_bytes(h, ctypes.byref(ws))
+            assert ws.value == ws0.value
+        assert ok and ok[0] == first and len(ok) < 13  # the wide beam rules some shapes out
+    finally:
+        lib.dd_batch_destroy(h)
