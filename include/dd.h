@@ -185,7 +185,7 @@ dd_status dd_execute_adjoint(const dd_plan *plan, const float *d_y, int64_t y_pi
  *   cannot stage the plan's delay spread.  On success the plan is unbound:
  *   query dev_table_bytes again and call dd_plan_bind before executing.
  * dd_plan_autotune: time every (shape, order) that holds the plan's spread and
- *   keep the fastest (the current choice stays unless another is at least 1%
+ *   keep the fastest (the current choice stays unless another is at least 2%
  *   faster).  Each candidate runs on the caller's buffers over the first
  *   timed_out_samples output samples of every row (all of them for small plans;
  *   otherwise an eighth of the job, between 10^12 and 4*10^12 adds per launch),
@@ -232,7 +232,7 @@ dd_status dd_plan_autotune(dd_plan *plan, int32_t direction, const void *d_src, 
  * dd_batch_autotune: with the arguments of dd_batch_bind, time the default shape and every staged
  *   shape with at least 32 DM rows per workgroup on the whole batch (one warm-up replay, one timed
  *   replay with HIP events on `stream`), keep the fastest (the default stays unless another is at
- *   least 1% faster) and leave the batch bound with it.  Outputs are overwritten.  Synchronises
+ *   least 2% faster) and leave the batch bound with it.  Outputs are overwritten.  Synchronises
  *   `stream`.  *report may be NULL (timed_out_samples is 0: whole replays are timed).
  *   Errors: as dd_batch_bind.
  */

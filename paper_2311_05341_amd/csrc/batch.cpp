@@ -325,7 +325,7 @@ dd_status dd_batch_autotune(dd_batch *b, const void *const *d_in, float *const *
     (void)batch_set_shape(b, orig);
     return fail(status, msg);
   }
-  if (best_ms > 0.99 * default_ms) {  // within timing noise of the default: keep it
+  if (best_ms > 0.98 * default_ms) {  // within timing noise of the default: keep it
     best = orig;
     best_ms = default_ms;
   }

@@ -225,7 +225,10 @@ dd_status dd_plan_autotune(dd_plan *p, int32_t dir, const void *src, float *dst,
     p->bound = false;
     return fail(status, msg);
   }
-  if (best_ms > 0.99 * default_ms) {  // within timing noise of the current choice: keep it
+  // Within the timing noise of the current choice, keep it: on the headline plan the
+  // three workgroup orders measure within 1% of each other on the tuning span and
+  // rank differently on the whole job.
+  if (best_ms > 0.98 * default_ms) {
     best_shape = orig_shape;
     best_order = orig_order;
     best_ms = default_ms;
