@@ -454,8 +454,8 @@ def bench_survey(args, dd, torch, synth):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="headline")
     ap.add_argument("--adjoint", action="store_true", help="time the adjoint instead of the forward")
     ap.add_argument("--no-cpu-baseline", action="store_true")
