@@ -454,8 +454,9 @@ def bench_survey(args, dd, torch, synth):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 20; 5 for the multi-range workloads, 2 for the 48-beam job)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps first (default 3; 1 for the 48-beam job)")
     ap.add_argument("--workload", default="headline")
     ap.add_argument("--adjoint", action="store_true", help="time the adjoint instead of the forward")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -467,6 +468,11 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first, as a known-size reference for memory counters")
     args = ap.parse_args()
+    long_steps = {"batch48": 2, "tab_plans_8192": 5, "pipeline_high": 5}
+    if args.steps is None:
+        args.steps = long_steps.get(args.workload, 20)
+    if args.warmup is None:
+        args.warmup = 1 if args.workload == "batch48" else 3
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
