@@ -474,7 +474,7 @@ def main():
     if args.warmup is None:
         args.warmup = 1 if args.workload == "batch48" else 3
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+        print("bench.py measures one GPU: there is no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
