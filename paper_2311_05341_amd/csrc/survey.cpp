@@ -157,6 +157,12 @@ dd_status dd_corner_turn(int32_t dtype, const void *d_in, int64_t in_pitch, int3
   if (in_pitch % 16 || out_pitch % 16) return fail(DD_ERR_ALIGN, "pitches must be multiples of 16 bytes");
   if ((double)in_pitch * n_samp > 9.0e18 || (double)out_pitch * n_chan > 9.0e18) return fail(DD_ERR_RANGE, "size overflow");
   if (overlap(d_in, in_pitch * n_samp, d_out, out_pitch * n_chan)) return fail(DD_ERR_ARG, "input and output overlap");
+  {  // one workgroup per tile of (256 bytes of a spectrum) x (128 bytes of a row)
+    const int64_t tc = dtype == DD_U4 ? 256 : 256 / input_row_bytes(dtype, 1);
+    const int64_t tt = dtype == DD_U4 ? 256 : 128 / input_row_bytes(dtype, 1);
+    if (((int64_t)n_chan + tc - 1) / tc * ((n_samp + tt - 1) / tt) > 0x7fffffff)
+      return fail(DD_ERR_RANGE, "too many tiles for one launch");
+  }
   const int e = launch_corner_turn(dtype, d_in, in_pitch, n_chan, n_samp, d_out, out_pitch, stream);
   if (e) return hip_error(e, "corner-turn launch");
   return DD_OK;
