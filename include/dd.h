@@ -90,7 +90,9 @@ typedef struct {
 /* A tile choice for one direction of a plan.  A workgroup computes
  * waves * per_wave output rows (DM rows forward, channels adjoint) over 64 * ns
  * output samples, staging row_block input rows (channels forward, DM rows
- * adjoint) per LDS stage. */
+ * adjoint) per LDS stage.  row_block 0 marks a direct-read shape of an integer
+ * plan: no LDS staging, every (channel, DM) window read from the caches (for
+ * wide delay spreads; 4-bit input covers 2 * 64 * ns samples per workgroup). */
 typedef struct {
   int32_t shape;  /* index of a shape compiled into the library for the plan's dtype */
   int32_t order;  /* workgroup order: 0 = time tiles fastest, 1 = each XCD takes whole time tiles,
