@@ -227,7 +227,8 @@ dd_status dd_plan_autotune(dd_plan *plan, int32_t direction, const void *d_src, 
  *   counter (>= dd_batch_workspace_bytes, 16-byte aligned).  Uploads on
  *   `stream` and records the graph; re-binding re-records it.
  *   Errors: DD_ERR_ARG, DD_ERR_ALIGN, DD_ERR_HIP.
- * dd_execute_batched: replay the graph on `stream`.  Errors: DD_ERR_NOT_BOUND, DD_ERR_HIP.
+ * dd_execute_batched: replay the graph on `stream`.  Errors: DD_ERR_NOT_BOUND, DD_ERR_ARG (the
+ *   current device is not the one the batch was bound on), DD_ERR_HIP.
  * dd_batch_get_tiles: the shared tile shape (order is always 0: work items are claimed dynamically).
  * dd_batch_set_tiles: switch to compiled staged shape `shape` (DD_ERR_RANGE, batch unchanged, if a
  *   beam cannot be staged with it); unbinds the batch, which keeps its workspace size.

@@ -239,6 +239,8 @@ dd_status dd_batch_bind(dd_batch *b, const void *const *d_in, float *const *d_ou
 dd_status dd_execute_batched(dd_batch *b, void *stream) {
   if (!b) return fail(DD_ERR_ARG, "null batch");
   if (!b->bound || !b->exec) return fail(DD_ERR_NOT_BOUND, "batch is not bound");
+  int dev = -1;
+  if (hipGetDevice(&dev) == hipSuccess && dev != b->device) return fail(DD_ERR_ARG, "batch is bound on another device");
   hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
   if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(e));
   return DD_OK;
