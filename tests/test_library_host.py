@@ -277,3 +277,25 @@ def test_batch_tile_choice_host(dd):
         assert ok and ok[0] == first and len(ok) < 13  # the wide beam rules some shapes out
     finally:
         lib.dd_batch_destroy(h)
+
+
+def test_package_without_library_fails_loudly(tmp_path):
+    """A copy of the package without libdd.so must refuse to import: there is no
+    other execution path (no CPU fallback, no route through the oracle)."""
+    import shutil
+    import subprocess
+    import sys
+    src = os.path.join(ROOT, "paper_2311_05341_amd")
+    dst = tmp_path / "paper_2311_05341_amd"
+    shutil.copytree(src, dst, ignore=shutil.ignore_patterns("*.so", "__pycache__", "csrc", "cpu"))
+    assert not list(dst.glob("*.so"))
+    code = ("import sys\n"
+            "try:\n"
+            "    import paper_2311_05341_amd\n"
+            "except ImportError as e:\n"
+            "    print('refused:', e); sys.exit(0)\n"
+            "sys.exit('imported without libdd.so')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=str(tmp_path), capture_output=True, text=True,
+                       timeout=300, env=dict(os.environ, PYTHONPATH=str(tmp_path)))
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "libdd.so is not built" in r.stdout
