@@ -287,3 +287,66 @@ def test_grad_workload_forward_sampled(dd):
     want, ab = oracle.forward_f32(x, cfg["n_samp"], s, rows=rows)
     err = np.abs(got - want)
     assert (err <= F32_TOL * ab).all(), float((err / ab).max())
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u4", "u16", "f32"])
+def test_explicit_unordered_frequencies(dd, dtype):
+    """Channels given by an explicit frequency list in random order (delays no longer grow with
+    the channel index, the staging bases jump between neighbouring channels): the forward, and
+    for float input the adjoint, against the oracle's table built from the same list."""
+    rng = np.random.default_rng({"u8": 51, "u4": 52, "u16": 53, "f32": 54}[dtype])
+    n_chan, n_samp, n_dm = 301, 12000, 45
+    f_high, t_samp = 1450.0, 64e-6
+    freqs = rng.permutation(np.concatenate([[f_high], rng.uniform(1150.0, f_high, n_chan - 1)]))
+    k = 1 / freqs.min() ** 2 - 1 / f_high**2
+    dm_max = 0.6 * n_samp * t_samp / (4.148808e3 * k)
+    start, step = 0.05 * dm_max, 0.95 * dm_max / (n_dm - 1)
+    s = oracle.shift_table(n_chan, f_high, 0.0, t_samp, start, step, n_dm, freqs=freqs)
+    assert (np.diff(s[-1].astype(np.int64)) < 0).any()  # delays are not monotone in the channel index
+    n_out = oracle.n_out_for(s, n_samp)
+    elem = {"f32": 4, "u16": 2}.get(dtype, 1)
+    row = n_samp // 2 if dtype == "u4" else n_samp * elem
+    pitch_bytes = (row + 15) // 16 * 16 + 32
+    pitch = pitch_bytes // elem
+    if dtype in ("u8", "u4"):
+        x = rng.integers(0, 256, (n_chan, pitch)).astype(np.uint8)
+    elif dtype == "u16":
+        x = rng.integers(0, 65536, (n_chan, pitch)).astype(np.uint16)
+    else:
+        x = rng.standard_normal((n_chan, pitch)).astype(np.float32)
+    plan = dd.Plan(n_chan=n_chan, n_samp=n_samp, dtype=dtype, f_high=f_high, chan_bw=0.0, t_samp=t_samp,
+                   dm_start=start, dm_step=step, n_dm=n_dm, chan_freq=freqs, in_pitch_bytes=pitch_bytes)
+    assert np.array_equal(plan.shift, s) and plan.n_out == n_out
+    print("explicit frequencies %s: n_chan=%d n_samp=%d n_dm=%d n_out=%d" % (dtype, n_chan, n_samp, n_dm, n_out),
+          flush=True)
+    got = plan.forward(_to_dev(x))
+    torch.cuda.synchronize()
+    got = got.cpu().numpy()
+    if dtype != "f32":
+        want = oracle.forward(np.ascontiguousarray(x), dtype, n_samp, s)
+        assert np.array_equal(got, want)
+        # the other kernel family on the same plan: direct reads if staged, a staged shape if direct
+        other = [13] if plan.tiles(0)["row_block"] > 0 else [5, 6, 7]
+        for shape in other:
+            try:
+                plan.set_tiles(0, shape, 2)
+            except dd.DDError:
+                continue
+            print("  shape %d" % shape, flush=True)
+            got = plan.forward(_to_dev(x))
+            torch.cuda.synchronize()
+            assert np.array_equal(got.cpu().numpy(), want), shape
+            break
+        else:
+            raise AssertionError("no second kernel family fits this plan")
+        return
+    want, ab = oracle.forward_f32(np.ascontiguousarray(x), n_samp, s)
+    assert (np.abs(got.astype(np.float64) - want) <= F32_TOL * ab + 1e-30).all()
+    y = rng.standard_normal((n_dm, n_out)).astype(np.float32)
+    g = plan.adjoint(torch.from_numpy(y).cuda())
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    want_g = oracle.adjoint(y, n_chan, n_samp, s)
+    ab_g = oracle.adjoint(np.abs(y), n_chan, n_samp, s)
+    assert (np.abs(g - want_g) <= F32_TOL * ab_g).all()
+    assert (g[ab_g == 0] == 0).all()
