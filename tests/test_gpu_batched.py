@@ -122,3 +122,31 @@ def test_batched_every_shape_and_autotune(dd):
     torch.cuda.synchronize()
     for b in range(len(beams)):
         assert torch.equal(outs[b], plain[b])
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u4", "u16"])
+def test_batched_beam_with_one_output_sample(dd, dtype):
+    """A beam whose input is the shortest its plan accepts (one output sample per DM row)
+    next to an ordinary beam, in one persistent launch: both bit-exact."""
+    base = dict(dtype=dtype, n_chan=150, n_samp=1 << 20, f_high=1400.0, chan_bw=0.9, t_samp=64e-6,
+                dm_start=3.0, dm_step=0.77, n_dm=50)
+    ms = int(oracle_table(base).max())
+    short = dict(base, n_samp=ms + 1 + ((ms + 1) & 1 if dtype == "u4" else 0))
+    normal = dict(base, n_chan=97, n_samp=40000, n_dm=33)
+    rng = np.random.default_rng(12)
+    plans, xs, wants = [], [], []
+    for cfg in (short, normal):
+        s = oracle_table(cfg)
+        elem = 2 if dtype == "u16" else 1
+        pitch_bytes = ((cfg["n_samp"] // 2 if dtype == "u4" else cfg["n_samp"] * elem) + 15) // 16 * 16
+        top, npt = (65536, np.uint16) if dtype == "u16" else (256, np.uint8)
+        x = rng.integers(0, top, (cfg["n_chan"], pitch_bytes // elem)).astype(npt)
+        wants.append(oracle.forward(x, dtype, cfg["n_samp"], s))
+        plans.append(plan_for(dd, cfg, in_pitch_bytes=pitch_bytes))
+        xs.append(torch.from_numpy(x).cuda())
+    assert plans[0].n_out in (1, 2)
+    print("batch with a one-output beam: %s" % dtype, flush=True)
+    outs = dd.Batch(plans, xs).run()
+    torch.cuda.synchronize()
+    for o, w in zip(outs, wants):
+        assert np.array_equal(o.cpu().numpy(), w)

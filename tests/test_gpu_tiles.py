@@ -180,3 +180,57 @@ def test_direct_kernel_large_spread(dd, dtype):
             got = plan.forward(xd)
             torch.cuda.synchronize()
             assert np.array_equal(got.cpu().numpy(), want), (shape, o)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u4", "u16", "f32"])
+def test_shortest_input_every_shape(dd, dtype):
+    """The shortest input a plan accepts: n_samp = largest delay + 1 (+1 more for 4-bit input,
+    whose sample count is even), so one or two output samples per DM row, on every compiled
+    shape and order; float plans also through the adjoint."""
+    base = dict(dtype=dtype, n_chan=203, n_samp=1 << 20, f_high=1400.0, chan_bw=0.9, t_samp=64e-6,
+                dm_start=3.0, dm_step=0.77, n_dm=77)
+    ms = int(oracle_table(base).max())
+    n_samp = ms + 1 + ((ms + 1) & 1 if dtype == "u4" else 0)
+    cfg = dict(base, n_samp=n_samp)
+    s = oracle_table(cfg)
+    n_out = oracle.n_out_for(s, n_samp)
+    assert n_out in (1, 2)
+    rng = np.random.default_rng(77)
+    elem = {"f32": 4, "u16": 2}.get(dtype, 1)
+    pitch_bytes = ((n_samp // 2 if dtype == "u4" else n_samp * elem) + 15) // 16 * 16
+    cols = pitch_bytes // elem
+    if dtype == "f32":
+        x = rng.standard_normal((cfg["n_chan"], cols)).astype(np.float32)
+        want, ab = oracle.forward_f32(x, n_samp, s)
+    else:
+        top = 65536 if dtype == "u16" else 256
+        x = rng.integers(0, top, (cfg["n_chan"], cols)).astype(np.uint16 if dtype == "u16" else np.uint8)
+        want = oracle.forward(x, dtype, n_samp, s)
+    plan = plan_for(dd, cfg, in_pitch_bytes=pitch_bytes)
+    assert plan.n_out == n_out
+    xd = torch.from_numpy(x).cuda()
+    choices = _choices(dd, plan, 0)
+    assert choices
+    for s_, o in choices:
+        plan.set_tiles(0, s_, o)
+        print("shortest %s: n_samp=%d n_out=%d shape %d order %d" % (dtype, n_samp, n_out, s_, o), flush=True)
+        got = plan.forward(xd)
+        torch.cuda.synchronize()
+        got = got.cpu().numpy()
+        if dtype == "f32":
+            assert (np.abs(got.astype(np.float64) - want) <= 1e-5 * ab + 1e-30).all(), (s_, o)
+        else:
+            assert np.array_equal(got, want), (s_, o)
+    if dtype != "f32":
+        return
+    y = rng.standard_normal((cfg["n_dm"], n_out)).astype(np.float32)
+    gw = oracle.adjoint(y, cfg["n_chan"], n_samp, s)
+    ga = oracle.adjoint(np.abs(y), cfg["n_chan"], n_samp, s)
+    for s_, o in _choices(dd, plan, 1):
+        plan.set_tiles(1, s_, o)
+        print("shortest f32 adjoint: shape %d order %d" % (s_, o), flush=True)
+        g = plan.adjoint(torch.from_numpy(y).cuda())
+        torch.cuda.synchronize()
+        g = g.cpu().numpy().astype(np.float64)
+        assert (np.abs(g - gw) <= 1e-5 * ga).all(), (s_, o)
+        assert (g[ga == 0] == 0).all(), (s_, o)
