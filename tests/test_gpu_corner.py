@@ -90,8 +90,11 @@ def _survey_args(cfg, n_samp):
     return (cfg["n_chan"], n_samp, cfg["dtype"], cfg["f_high"], cfg["chan_bw"], cfg["t_samp"], cfg["ranges"])
 
 
-@pytest.mark.parametrize("dtype", ["u8", "u4"])
+@pytest.mark.parametrize("dtype", ["u8", "u4", "u16", "f32"])
 def test_time_major_survey_small_exact(dtype, dd):
+    """Spectra in, every range out: the oracle's corner turn, binning and transform. Integer
+    encodings bit for bit; float spectra (and 16-bit spectra, which bin to float sums) within
+    1e-5 of the sum of |terms|."""
     cfg = dict(synth.SURVEYS["survey_small"], dtype=dtype)
     n_chan, n_samp = cfg["n_chan"], cfg["n_samp"]
     spec = _spectra(dtype, n_chan, n_samp, seed=21)
@@ -101,12 +104,22 @@ def test_time_major_survey_small_exact(dtype, dd):
     torch.cuda.synchronize()
     for r, (start, step, n_dm, b) in enumerate(cfg["ranges"]):
         s = oracle.shift_table(n_chan, cfg["f_high"], cfg["chan_bw"], cfg["t_samp"] * b, start, step, n_dm)
-        if b == 1:
-            want = oracle.forward(rows, dtype, n_samp, s)
-        else:
+        got = outs[r].cpu().numpy()
+        if b == 1 and dtype != "f32":
+            assert np.array_equal(got, oracle.forward(rows, dtype, n_samp, s)), r
+        elif b == 1:
+            want, ab = oracle.forward_f32(rows, n_samp, s)
+            assert np.all(np.abs(got.astype(np.float64) - want) <= 1e-5 * ab + 1e-30), r
+        elif dtype in ("u8", "u4"):
             xb = oracle.bin_time(rows, dtype, n_samp, b).astype(np.uint16)
-            want = oracle.forward(xb, "u16", xb.shape[1], s)
-        assert np.array_equal(outs[r].cpu().numpy(), want), r
+            assert np.array_equal(got, oracle.forward(xb, "u16", xb.shape[1], s)), r
+        else:  # 16-bit and float rows bin to float sums
+            xb = oracle.bin_time(rows, dtype, n_samp, b)
+            ab_b = oracle.bin_time(np.abs(rows.astype(np.float64)).astype(np.float32) if dtype == "f32" else rows,
+                                   dtype, n_samp, b)
+            want, _ = oracle.forward_f32(np.ascontiguousarray(xb.astype(np.float32)), xb.shape[1], s)
+            ab, _ = oracle.forward_f32(np.ascontiguousarray(ab_b.astype(np.float32)), xb.shape[1], s)
+            assert np.all(np.abs(got.astype(np.float64) - want) <= 1e-5 * ab + 1e-30), r
 
 
 def test_time_major_pipeline_full_size(dd):
