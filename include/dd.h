@@ -117,6 +117,11 @@ typedef struct dd_batch dd_batch;
  * table (Eq. 1 per channel and DM, rounded half up), derive N_out and the
  * per-DM-block delay spans that size the LDS staging, and choose a tile shape.
  * *out receives a new plan owned by the caller (free with dd_plan_destroy).
+ * Limits, each refused with DD_ERR_RANGE: n_samp < 2^29; in_pitch_bytes < 2^31;
+ * n_chan <= 65793 (DD_U8), 1118481 (DD_U4) or 65537 (DD_U16), so that integer
+ * sums stay exact (see dd_execute); every shift fits int32; for DD_F32 plans a
+ * delay spread that some compiled staging shape holds (integer plans fall back
+ * to the direct-read shapes, which hold any spread).
  * Errors: DD_ERR_ARG, DD_ERR_RANGE, DD_ERR_TOO_SHORT, DD_ERR_NOMEM.
  */
 dd_status dd_plan_create(const dd_plan_desc *desc, dd_plan **out);
