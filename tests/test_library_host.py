@@ -93,6 +93,11 @@ def test_error_codes(dd):
     assert _status(dd, lambda: _plan(dd, cfg, n_chan=70000, chan_bw=0.001)) == "DD_ERR_RANGE"
     assert _status(dd, lambda: _plan(dd, cfg, dtype="u16", n_chan=65538, chan_bw=0.001)) == "DD_ERR_RANGE"
     _plan(dd, cfg, dtype="u16", n_chan=65537, chan_bw=0.001, n_dm=2)  # the largest exact 16-bit plan
+    assert _status(dd, lambda: _plan(dd, cfg, dtype="u4", n_chan=1118482, chan_bw=1e-5, n_dm=2)) == "DD_ERR_RANGE"
+    assert _status(dd, lambda: _plan(dd, cfg, n_samp=1 << 29)) == "DD_ERR_RANGE"
+    _plan(dd, cfg, n_samp=(1 << 29) - 32, n_dm=2)  # the longest rows
+    assert _status(dd, lambda: _plan(dd, cfg, dtype="f32", n_samp=(1 << 29) - 32, n_dm=2,
+                                     in_pitch_bytes=1 << 31)) == "DD_ERR_RANGE"
     assert _status(dd, lambda: _plan(dd, cfg, chan_freq=np.full(128, 1600.0))) == "DD_ERR_RANGE"  # above f_high
     p = _plan(dd, cfg)
     lib = ctypes.CDLL(dd.LIB_PATH)
