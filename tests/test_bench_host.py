@@ -1,0 +1,46 @@
+"""Host-side checks of bench.py (no GPU): the one-GPU contract and the committed
+counter summaries it reads its memory-traffic figures from."""
+import glob
+import importlib.util
+import os
+import re
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench_module", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
+
+
+def test_traffic_blocks_parse_and_name_sources():
+    blocks = 0
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_counters.md")):
+        for block in re.findall(r"```traffic\n(.*?)```", open(path).read(), re.S):
+            kv = dict(line.split(": ", 1) for line in block.strip().splitlines() if ": " in line)
+            assert {"workload", "kernel", "source", "source_sha256"} <= set(kv)
+            assert os.path.isfile(os.path.join(ROOT, kv["source"])), kv["source"]
+            figures = [k for k in kv if k.startswith("traffic_bytes_per_launch")]  # per factor for binning
+            assert figures and all(int(kv[k]) > 0 for k in figures)
+            blocks += 1
+    assert blocks >= 4
+
+
+def test_headline_traffic_matches_the_current_kernel():
+    """The headline's default tiles have counters taken on the kernel source as committed;
+    after a change to that source the counters must be taken again (bench.py then reports
+    the traffic as unknown)."""
+    traffic, src = _bench().measured_traffic("headline", {"shape": 0, "order": 2})
+    assert traffic is not None and src.startswith("profiles" + os.sep)
+    assert traffic > 24.85e9  # at least the algorithmic bytes (input once + output once)
