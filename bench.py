@@ -11,8 +11,8 @@ forward kernel, and the CPU oracle timed on a bounded sample of the same
 workload.
 
   python bench.py [--steps K] [--warmup W]
-                  [--workload headline|lowfreq_u4|lowfreq_wide|headline_u16|grad_f32|small|batch48|
-                              tab_plans_8192|pipeline_high]
+                  [--workload headline|headline_shard8|lowfreq_u4|lowfreq_wide|headline_u16|grad_f32|small|
+                              batch48|tab_plans_8192|pipeline_high]
                   [--adjoint] [--time-major] [--tiles SHAPE,ORDER] [--no-cpu-baseline] [--no-autotune]
                   [--copy-calibration]
 

@@ -220,6 +220,11 @@ CONFIGS = {
                      t_samp=64e-6, dm_start=0.0, dm_step=0.5, n_dm=4000, seed=2,
                      pulses=[(100, 1, 100_000), (600, 2, 280_000), (1600, 4, 460_000),
                              (3000, 8, 640_000), (3800, 16, 820_000)], amp=40),
+    # One GPU's share of the headline under 8-way DM sharding: the last of eight
+    # 500-DM slices (the largest delays), with the headline's DM-1900 pulse.
+    "headline_shard8": dict(dtype="u8", n_chan=8192, n_samp=1 << 20, f_high=1500.0, chan_bw=300.0 / 8192,
+                            t_samp=64e-6, dm_start=1750.0, dm_step=0.5, n_dm=500, seed=2,
+                            pulses=[(300, 16, 820_000)], amp=40),
     "lowfreq_u4": dict(dtype="u4", n_chan=4096, n_samp=1 << 19, f_high=190.0, chan_bw=70.0 / 4096,
                        t_samp=327.68e-6, dm_start=0.0, dm_step=0.1, n_dm=2048, seed=3,
                        pulses=[], amp=0),

@@ -188,6 +188,23 @@ def test_headline_workload_sampled(dd):
             assert int(np.argmax(col)) == dp, (dp, int(np.argmax(col)))
 
 
+def test_headline_shard8_workload_sampled(dd):
+    """One GPU's share of the headline under 8-way DM sharding (DMs 1750..1999.5), as the
+    benchmark times it: sampled rows, the pulse row among them, bit-exact; every row by the
+    row-sum identity."""
+    cfg = synth.CONFIGS["headline_shard8"]
+    s = oracle_table(cfg)
+    xd, xh, applied = _device_u8(cfg, s)
+    plan = plan_for(dd, cfg)
+    out = plan.forward(xd)
+    torch.cuda.synchronize()
+    rows = sample_rows(cfg["n_dm"], cfg["pulses"], extra=3, seed=8)
+    assert np.array_equal(out[rows].cpu().numpy(), oracle.forward(xh, "u8", cfg["n_samp"], s, rows=rows))
+    gpu_rowsum = out.double().sum(dim=1).cpu().numpy().astype(np.int64)
+    assert np.array_equal(gpu_rowsum, row_sums_by_prefix(lambda c: xh[c], s, plan.n_out))
+    assert applied[0].sum() > 0
+
+
 def test_lowfreq_wide_workload_sampled(dd):
     """4096 channels at 120-190 MHz, 2^20 samples, 1024 DMs in steps of 0.5 (264 samples of extra
     delay per step): the direct-read kernel, as the benchmark runs it.  Sampled rows bit-exact,
