@@ -48,8 +48,11 @@ LDS_BYTES_PER_ADD = {"u8": 1, "u4": 1, "u16": 2, "f32": 4}
 # the even/odd byte lanes): 8 sample-adds per 4 VALU ops, so twice the one-add-per-lane peak.
 INT_FORM = "SWAR bytes in 32-bit words, v_perm_b32 + v_add3_u32 (2 sample-adds per VALU lane-op)"
 F32_FORM = "v_add_f32 (1 add per VALU lane-op)"
-U16_FORM = "two 16-bit samples per word, one SDWA v_add_u32 per sample (1 sample-add per VALU lane-op)"
-FORMS = {"u8": (INT_FORM, 2), "u4": (INT_FORM, 2), "u16": (U16_FORM, 1), "f32": (F32_FORM, 1)}
+# 16-bit: per two channel-words (4 sample-adds) one v_add3_u32 for the low halves and
+# one SDWA v_add_u32 per word for the high halves: 3 VALU ops.
+U16_FORM = ("two 16-bit samples per word, v_add3_u32 over two channels + one SDWA v_add_u32 per word "
+            "(4 sample-adds per 3 VALU lane-ops)")
+FORMS = {"u8": (INT_FORM, 2), "u4": (INT_FORM, 2), "u16": (U16_FORM, 4.0 / 3.0), "f32": (F32_FORM, 1)}
 
 
 def log(msg):

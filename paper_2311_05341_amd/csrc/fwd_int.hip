@@ -31,10 +31,11 @@
 // byte, so two copies (shifted by 0 and 2 bytes) align every window.  Per word
 // w = [lo hi] a lane adds
 //     mix += w          (the low half carries into the high half)
-//     odd += w >> 16    (the high samples alone)
+//     odd += w >> 16    (the high samples alone; one SDWA add)
 // and at the end lo_total = mix - (odd << 16) (mod 2^32): exact while every
-// total stays below 2^32, i.e. for up to 65537 channels.  Two channels' adds
-// fuse into one v_add3, so a sample costs one VALU lane-operation.  The float
+// total stays below 2^32, i.e. for up to 65537 channels.  Two channels' mix
+// adds fuse into one v_add3, so two channel-words cost three instructions
+// (0.75 VALU lane-operations per sample).  The float
 // conversion rounds to nearest even above 2^24, as the host's int64-to-float
 // conversion does.
 //
@@ -69,6 +70,18 @@ __device__ __forceinline__ uint4 unpack_u4(uint2 p) {
   r.y = __builtin_amdgcn_perm(hi0, lo0, 0x07030602u);
   r.z = __builtin_amdgcn_perm(hi1, lo1, 0x05010400u);
   r.w = __builtin_amdgcn_perm(hi1, lo1, 0x07030602u);
+  return r;
+}
+
+// acc + (w >> 16) as one SDWA add (the high half of w selected as the
+// operand).  The compiler otherwise emits a shift per word and fuses two
+// channels' shifted words into a v_add3: three instructions per two
+// channel-words here against four.
+__device__ __forceinline__ uint32_t add_high_half(uint32_t acc, uint32_t w) {
+  uint32_t r;
+  asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:WORD_1"
+      : "=v"(r)
+      : "v"(acc), "v"(w));
   return r;
 }
 
@@ -427,7 +440,7 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
               const uint32_t w = wp[pc & 1][h][r][k];
               if constexpr (BITS == 16) {
                 mix[r][k] += w;
-                odd[r][k] += w >> 16;
+                odd[r][k] = add_high_half(odd[r][k], w);
               } else {
                 mix[r][k] += w;
                 odd[r][k] += __builtin_amdgcn_perm(w, w, kOddSel);
@@ -451,7 +464,7 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
             const uint32_t w = wv[cc & 1][r][k];
             if constexpr (BITS == 16) {
               mix[r][k] += w;
-              odd[r][k] += w >> 16;
+              odd[r][k] = add_high_half(odd[r][k], w);
             } else {
               mix[r][k] += w;
               odd[r][k] += __builtin_amdgcn_perm(w, w, kOddSel);
