@@ -180,8 +180,10 @@ dd_status dd_execute_adjoint(const dd_plan *plan, const float *d_y, int64_t y_pi
  * samples per lane, input rows per LDS stage) and the workgroup order decide
  * speed only: results are bitwise identical for every choice (exact integer
  * sums; fixed-order float sums).  dd_plan_create picks the first compiled
- * shape that holds the plan's delay spread, or the choice recorded for an
- * identical plan in the tuning cache (below).
+ * shape that holds the plan's delay spread (integer plans that only fit 1- or
+ * 2-channel stages take a direct-read shape; 16-bit plans take the 8-wave,
+ * 4-rows-per-wave shape when two of its workgroups fit in one CU's LDS), or the
+ * choice recorded for an identical plan in the tuning cache (below).
  *
  * direction: 0 = forward; 1 = adjoint (DD_F32 plans only).
  *

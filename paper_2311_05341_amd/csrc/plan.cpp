@@ -311,6 +311,22 @@ dd_status choose_forward_tiles(dd_plan &p) {
   }
   if (p.desc.dtype != DD_F32 && !is_direct(p.fwd) && p.fwd.chan_block <= 2)
     return set_tiles(p, 0, kNumIntShapes + (p.desc.dtype == DD_U4 ? 1 : 0), kOrderDmGroups);  // 4-bit: 2 rows per wave (registers)
+  // 16-bit plans: the 8-wave shape with 4 rows per wave and 4 channels per stage
+  // beats the 16-wave default when two of its workgroups fit in a CU's LDS, so
+  // that one's barrier waits overlap the other's adds (measured 13-16% faster on
+  // 8192 x 2^20 and on binned 4096-channel ranges; 11% slower on a plan with
+  // ~1000 samples of spread per 32 DMs, where only one fits).
+  if (p.desc.dtype == DD_U16 && !is_direct(p.fwd)) {
+    const int keep_shape = p.fwd.shape, keep_order = p.fwd.order;
+    for (int i = 0; i < kNumIntShapes; ++i) {
+      const int *k = kIntShapes[i];
+      if (k[0] != 16 || k[1] != 4 || k[2] != 8 || k[3] != 4 || i == keep_shape) continue;
+      const dd_status st = set_tiles(p, 0, i, kOrderDmGroups);
+      if (st == DD_ERR_NOMEM) return st;
+      if (st == DD_OK && 2 * p.fwd.lds_bytes > kLdsLimit) return set_tiles(p, 0, keep_shape, keep_order);
+      break;
+    }
+  }
   return DD_OK;
 }
 
