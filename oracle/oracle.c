@@ -77,6 +77,14 @@ static inline int64_t x_u16(const uint8_t *x, int64_t pitch_bytes, int c, int64_
   return (int64_t)p[0] | ((int64_t)p[1] << 8);
 }
 
+/* 32-bit: little-endian unsigned samples, four bytes each (pitch in bytes).
+ * Time-binned 16-bit data holds sums of up to 256 such samples, which need
+ * 24 bits. */
+static inline int64_t x_u32(const uint8_t *x, int64_t pitch_bytes, int c, int64_t t) {
+  const uint8_t *p = x + (int64_t)c * pitch_bytes + 4 * t;
+  return (int64_t)p[0] | ((int64_t)p[1] << 8) | ((int64_t)p[2] << 16) | ((int64_t)p[3] << 24);
+}
+
 /* Every read x(c, t + shift) with t < n_out must stay inside [0, n_samp). */
 static int shifts_in_range(const int32_t *shift, int n_chan, int n_dm, int64_t n_samp,
                            int64_t n_out) {
@@ -91,12 +99,12 @@ static int shifts_in_range(const int32_t *shift, int n_chan, int n_dm, int64_t n
  * rows in order; otherwise out row r holds DM row rows[r].  out is
  * [n_rows][n_out] float, each int64 sum converted once to float (round to
  * nearest even; exact below 2^24).  dtype: 1 = u8, 2 = u4 (pitch in bytes),
- * 4 = u16 (pitch in bytes); 3 = f32 uses oracle_forward_f32 instead.
+ * 4 = u16, 5 = u32 (pitch in bytes); 3 = f32 uses oracle_forward_f32 instead.
  */
 int oracle_forward_int(int dtype, const uint8_t *x, int64_t pitch, int n_chan, int64_t n_samp,
                        const int32_t *shift, int n_dm, int64_t n_out,
                        const int32_t *rows, int n_rows, float *out) {
-  if (dtype != 1 && dtype != 2 && dtype != 4) return -1;
+  if (dtype != 1 && dtype != 2 && dtype != 4 && dtype != 5) return -1;
   if (!shifts_in_range(shift, n_chan, n_dm, n_samp, n_out)) return -1;
   int bad = 0;
 #pragma omp parallel
@@ -122,8 +130,10 @@ int oracle_forward_int(int dtype, const uint8_t *x, int64_t pitch, int n_chan, i
           for (int64_t t = 0; t < n_out; ++t) acc[t] += x_u8(x, pitch, c, t + s);
         } else if (dtype == 2) {
           for (int64_t t = 0; t < n_out; ++t) acc[t] += x_u4(x, pitch, c, t + s);
-        } else {
+        } else if (dtype == 4) {
           for (int64_t t = 0; t < n_out; ++t) acc[t] += x_u16(x, pitch, c, t + s);
+        } else {
+          for (int64_t t = 0; t < n_out; ++t) acc[t] += x_u32(x, pitch, c, t + s);
         }
       }
       for (int64_t t = 0; t < n_out; ++t) out[(int64_t)r * n_out + t] = (float)acc[t];

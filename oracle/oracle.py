@@ -138,16 +138,20 @@ def forward(x: np.ndarray, dtype: str, n_samp: int, shift: np.ndarray, rows=None
 
     x is uint8 [n_chan][pitch]; for dtype "u4" the pitch is in bytes and holds
     two samples per byte, the even sample in the low nibble.  For dtype "u16"
-    x is uint16 [n_chan][pitch] (little-endian samples).
+    x is uint16 [n_chan][pitch] (little-endian samples), for "u32" uint32
+    (time-binned 16-bit data).
     """
     lib = _load()
     assert x.ndim == 2 and x.flags.c_contiguous
     n_dm, n_chan = shift.shape
     assert x.shape[0] == n_chan
-    code = {"u8": 1, "u4": 2, "u16": 4}[dtype]
+    code = {"u8": 1, "u4": 2, "u16": 4, "u32": 5}[dtype]
     if code == 4:
         assert x.dtype == np.uint16 and x.shape[1] >= n_samp
         x = x.astype("<u2", copy=False).view(np.uint8)
+    elif code == 5:
+        assert x.dtype == np.uint32 and x.shape[1] >= n_samp
+        x = x.astype("<u4", copy=False).view(np.uint8)
     else:
         assert x.dtype == np.uint8
     if code == 1:
@@ -173,8 +177,9 @@ def forward_f32(x: np.ndarray, n_samp: int, shift: np.ndarray, rows=None, with_a
     assert x.shape[0] == n_chan and x.shape[1] >= n_samp
     n_out = n_out_for(shift, n_samp)
     r, nr = _rows_arg(rows, n_dm)
-    out = np.empty((nr, max(n_out, 0)), dtype=np.float64)
-    ab = np.empty_like(out) if with_abs else None
+    # NaN-filled, so that a sum the C code fails to start from zero cannot pass for one
+    out = np.full((nr, max(n_out, 0)), np.nan, dtype=np.float64)
+    ab = np.full_like(out, np.nan) if with_abs else None
     sh = np.ascontiguousarray(shift, dtype=np.int32)
     rc = lib.oracle_forward_f32(_ptr(x), x.shape[1], n_chan, n_samp, _ptr(sh), n_dm, n_out,
                                 None if r is None else _ptr(r), nr, _ptr(out),

@@ -152,6 +152,10 @@ def _tiny_case(rng, dtype):
         x = rng.integers(0, 65536, (n_chan, n_samp)).astype(np.uint16)
         x[:, ::7] = 0
         x[:, 3::11] = 65535
+    elif dtype == "u32":  # binned 16-bit sums: up to 256 * 65535 < 2^24
+        x = rng.integers(0, 256 * 65535 + 1, (n_chan, n_samp)).astype(np.uint32)
+        x[:, ::7] = 0
+        x[:, 3::11] = 256 * 65535
     else:
         x = rng.standard_normal((n_chan, n_samp)).astype(np.float32)
         x[:, ::5] = 0.0
@@ -163,10 +167,10 @@ def _pack_u4(v):
     return (v[:, 0::2] | (v[:, 1::2] << 4)).astype(np.uint8)
 
 
-@pytest.mark.parametrize("dtype", ["u8", "u4", "u16", "f32"])
+@pytest.mark.parametrize("dtype", ["u8", "u4", "u16", "u32", "f32"])
 def test_forward_equals_literal_eq3(dtype):
     """Brute-force Eq. 3 (oracle/eq3_literal.py, independent code) on tiny random inputs."""
-    rng = np.random.default_rng({"u8": 11, "u4": 12, "f32": 13, "u16": 14}[dtype])
+    rng = np.random.default_rng({"u8": 11, "u4": 12, "f32": 13, "u16": 14, "u32": 15}[dtype])
     for _ in range(12):
         k = _tiny_case(rng, dtype)
         dms = [k["start"] + d * k["step"] for d in range(k["n_dm"])]
@@ -187,6 +191,9 @@ def test_forward_equals_literal_eq3(dtype):
         elif dtype == "u16":  # at most 8 channels: every sum is below 2^24, so float32 is exact
             got = oracle.forward(k["x"], "u16", k["n_samp"], s)
             assert got.tolist() == ref
+        elif dtype == "u32":  # sums up to 2^27: the exact integer (a double here) rounded once to float32
+            got = oracle.forward(k["x"], "u32", k["n_samp"], s)
+            assert got.tolist() == [[float(np.float32(v)) for v in row] for row in ref]
         else:
             got, _ = oracle.forward_f32(k["x"], k["n_samp"], s)
             np.testing.assert_allclose(got, np.array(ref), rtol=0, atol=1e-12)
@@ -305,6 +312,31 @@ def test_forward_u16_little_endian_samples():
     assert np.array_equal(out[0], want)
 
 
+def test_forward_u32_little_endian_samples_and_u16_agreement():
+    """A 32-bit sample is its bytes in little-endian order; 32-bit data of 16-bit values gives
+    the 16-bit transform, and a value above 2^16 adds its high part on top of it."""
+    raw = np.zeros((1, 4 * 64), dtype=np.uint8)
+    raw[0, 4 * 5: 4 * 5 + 4] = [0x01, 0x02, 0x03, 0x00]  # sample 5 = 0x030201 = 197121
+    raw[0, 4 * 9 + 2] = 0xFF                            # sample 9 = 0xFF0000 = 16711680
+    raw[0, 4 * 12 + 3] = 0x02                           # sample 12 = 0x02000000 = 2^25
+    s0 = np.zeros((1, 1), dtype=np.int32)
+    out = oracle.forward(np.ascontiguousarray(raw.view("<u4")), "u32", 64, s0)
+    want = np.zeros(64, dtype=np.float32)
+    want[5], want[9], want[12] = 197121.0, 16711680.0, 2.0 ** 25
+    assert np.array_equal(out[0], want)
+    rng = np.random.default_rng(44)
+    cfg, s, _ = _small()
+    x16 = rng.integers(0, 65536, (cfg["n_chan"], 4000)).astype(np.uint16)
+    s = s[:: 16, :]
+    s = s[:, :] // 4  # small delays that fit 4000 samples
+    assert np.array_equal(oracle.forward(x16.astype(np.uint32), "u32", 4000, s), oracle.forward(x16, "u16", 4000, s))
+    hi = rng.integers(0, 256, (cfg["n_chan"], 4000)).astype(np.uint32)
+    got = oracle.forward(x16.astype(np.uint32) + (hi << 16), "u32", 4000, s)
+    lo_sum = oracle.forward(x16, "u16", 4000, s).astype(np.float64)     # exact: 128 * 65535 < 2^24
+    hi_sum = oracle.forward(hi.astype(np.uint8), "u8", 4000, s).astype(np.float64)
+    assert np.array_equal(got, (lo_sum + 65536.0 * hi_sum).astype(np.float32))
+
+
 def test_forward_u16_sums_round_to_float32_nearest_even():
     """Sums above 2^24 are converted once to float32, rounding to nearest even."""
     n_chan, n_samp = 257, 32
@@ -341,6 +373,28 @@ def test_forward_and_adjoint_against_dense_matrix():
     y = rng.standard_normal((s.shape[0], n_out)).astype(np.float32)
     g = oracle.adjoint(y, n_chan, n_samp, s)
     np.testing.assert_allclose(g.reshape(-1), a.T @ y.reshape(-1).astype(np.float64), rtol=0, atol=1e-12)
+
+
+def test_forward_f32_abs_sum_against_dense_matrix():
+    """The second output of the float forward, the sum of |terms| that scales every
+    float tolerance, is |A| |x| for the 0/1 matrix of Eq. 3 and equals the forward of
+    |x|; with signed terms it is strictly larger than |sum| where signs cancel."""
+    rng = np.random.default_rng(15)
+    n_chan, n_samp = 7, 90
+    s = oracle.shift_table(n_chan, 400.0, 20.0, 1e-3, 0.1, 0.4, 6)
+    a, n_out = _dense_matrix(s, n_samp)
+    # small integers and halves: every FP64 sum below is exact, so equality is exact
+    x = (rng.integers(-16, 17, (n_chan, n_samp)) * 0.5).astype(np.float32)
+    out, ab = oracle.forward_f32(x, n_samp, s)
+    assert np.array_equal(out.reshape(-1), a @ x.reshape(-1).astype(np.float64))
+    assert np.array_equal(ab.reshape(-1), a @ np.abs(x.reshape(-1)).astype(np.float64))
+    out_abs, _ = oracle.forward_f32(np.abs(x), n_samp, s)
+    assert np.array_equal(ab, out_abs)
+    assert np.all(ab >= np.abs(out)) and np.any(ab > np.abs(out))
+    # a row subset returns the same rows of both outputs, each started from zero
+    rows = [5, 0, 3]
+    out_r, ab_r = oracle.forward_f32(x, n_samp, s, rows=rows)
+    assert np.array_equal(out_r, out[rows]) and np.array_equal(ab_r, ab[rows])
 
 
 # --------------------------------------------------------------------------------------

@@ -40,6 +40,13 @@ MUTANTS = {
     "corner turn reads the next spectrum": ("out[(int64_t)c * out_pitch + t * es + b] = in[t * in_pitch + (int64_t)c * es + b];", "out[(int64_t)c * out_pitch + t * es + b] = in[(t + 1 < n_samp ? t + 1 : t) * in_pitch + (int64_t)c * es + b];"),
     "corner turn reverses element bytes": ("out[(int64_t)c * out_pitch + t * es + b] = in[t * in_pitch + (int64_t)c * es + b];", "out[(int64_t)c * out_pitch + t * es + b] = in[t * in_pitch + (int64_t)c * es + (es - 1 - b)];"),
     "normalised by channel count": ("out[(int64_t)r * n_out + t] = (float)acc[t];", "out[(int64_t)r * n_out + t] = (float)(acc[t] / n_chan);"),
+    "32-bit top byte dropped": ("((int64_t)p[2] << 16) | ((int64_t)p[3] << 24);", "((int64_t)p[2] << 16);"),
+    "32-bit sample stride of two bytes": ("const uint8_t *p = x + (int64_t)c * pitch_bytes + 4 * t;", "const uint8_t *p = x + (int64_t)c * pitch_bytes + 2 * t;"),
+    "32-bit bytes 1 and 2 swapped": ("(int64_t)p[0] | ((int64_t)p[1] << 8) | ((int64_t)p[2] << 16)", "(int64_t)p[0] | ((int64_t)p[2] << 8) | ((int64_t)p[1] << 16)"),
+    "abs sum counts each term twice": ("a[t] += fabs((double)row[t]);", "a[t] += 2.0 * fabs((double)row[t]);"),
+    "abs sum without the absolute value": ("a[t] += fabs((double)row[t]);", "a[t] += (double)row[t];"),
+    "abs sum over the unshifted window": ("a[t] += fabs((double)row[t]);", "a[t] += fabs((double)x[(int64_t)c * pitch + t]);"),
+    "abs sum not cleared per row": ("    if (a)\n      for (int64_t t = 0; t < n_out; ++t) a[t] = 0.0;\n", ""),
 }
 
 PIN_CALLS = [
@@ -55,10 +62,13 @@ PIN_CALLS = [
     ("literal u16", pins.test_forward_equals_literal_eq3, ("u16",)),
     ("u16 little-endian", pins.test_forward_u16_little_endian_samples, ()),
     ("u16 == u8", pins.test_forward_u16_small_values_equal_u8, ()),
+    ("literal u32", pins.test_forward_equals_literal_eq3, ("u32",)),
+    ("u32 little-endian", pins.test_forward_u32_little_endian_samples_and_u16_agreement, ()),
     ("dm0", pins.test_forward_dm0_is_channel_sum, ()),
     ("pulse", pins.test_forward_injected_pulse, ()),
     ("u4 == u8 == f32", pins.test_forward_u4_equals_u8_equals_f32, ()),
     ("dense", pins.test_forward_and_adjoint_against_dense_matrix, ()),
+    ("dense abs sum", pins.test_forward_f32_abs_sum_against_dense_matrix, ()),
     ("dot exact", pins.test_adjoint_exact_dot_test_small_integers, ()),
     ("unread zero", pins.test_adjoint_unread_entries_are_zero, ()),
     ("bin reshape u8", pins.test_bin_equals_reshape_sum, ("u8",)),
