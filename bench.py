@@ -7,14 +7,22 @@ transform of that filterbank, input already resident in HBM.
 
 Prints one JSON line with Tadds/s (adds = N_dm * N_out * N_ch), the
 x-real-time factor (N_t * t_samp / t_step), the VALU roofline fraction of the
-forward kernel, and the CPU oracle timed on a bounded sample of the same
-workload.
+forward kernel, the GPU clocks sampled during the timed steps, and the CPU
+oracle timed on a bounded sample of the same workload.  The headline line also
+carries the rest of the metric, each form against the plain forward on the
+same GPU: the float adjoint against the float forward (1024 ch x 2^17 x 1024
+DMs, and one autograd forward + backward step) and the 48-beam batched launch
+against the same work as plain calls.
 
   python bench.py [--steps K] [--warmup W]
                   [--workload headline|headline_shard8|lowfreq_u4|lowfreq_wide|headline_u16|grad_f32|small|
                               batch48|tab_plans_8192|pipeline_high]
                   [--adjoint] [--time-major] [--tiles SHAPE,ORDER] [--no-cpu-baseline] [--no-autotune]
-                  [--copy-calibration]
+                  [--autotune] [--no-extras] [--copy-calibration]
+
+The headline plan runs its default tiles unless --autotune is given (the
+autotuner's pick on that plan); the other workloads autotune unless
+--no-autotune or --tiles is given.
 
 The multi-range workloads (tab_plans_8192, pipeline_high) time one step as the
 whole survey: binning of the input once per factor plus every range's transform.
@@ -57,6 +65,105 @@ FORMS = {"u8": (INT_FORM, 2), "u4": (INT_FORM, 2), "u16": (U16_FORM, 4.0 / 3.0),
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def host_cpu():
+    """CPU model and thread counts of the host, read from /proc (no program is started)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"cpu_model": model, "nproc": usable, "os_cpu_count": os.cpu_count()}
+
+
+class SysfsClocks:
+    """Samples the GPU's current shader (sclk) and memory (mclk) clocks during a timed region.
+
+    Plain reads of the amdgpu hwmon files (freq1_input = sclk, freq2_input = mclk,
+    in Hz) every `period` seconds from a thread of this process: no program is
+    started, so nothing is exec'd from a process that holds the GPU.  Falls back
+    to the DPM table's current level (pp_dpm_sclk / pp_dpm_mclk, the line marked
+    '*') when hwmon has no frequency files.  Reports the median and range per card."""
+
+    def __init__(self, period=0.05):
+        import threading
+        self.period = period
+        self.samples = {}
+        self._stop = threading.Event()
+        self._thread = threading.Thread(target=self._run, daemon=True)
+        self.sources = self._find()
+
+    @staticmethod
+    def _find():
+        out = {}
+        for dev in sorted(glob.glob("/sys/class/drm/card[0-9]*/device")):
+            card = dev.split("/")[-2]
+            srcs = {}
+            for hw in sorted(glob.glob(os.path.join(dev, "hwmon", "hwmon*"))):
+                for key, fn in (("sclk_mhz", "freq1_input"), ("mclk_mhz", "freq2_input")):
+                    f = os.path.join(hw, fn)
+                    if os.path.isfile(f) and key not in srcs:
+                        srcs[key] = ("hz", f)
+            for key, fn in (("sclk_mhz", "pp_dpm_sclk"), ("mclk_mhz", "pp_dpm_mclk")):
+                f = os.path.join(dev, fn)
+                if key not in srcs and os.path.isfile(f):
+                    srcs[key] = ("dpm", f)
+            if srcs:
+                out[card] = srcs
+        return out
+
+    @staticmethod
+    def _read(kind, path):
+        try:
+            with open(path) as fh:
+                text = fh.read()
+        except OSError:
+            return None
+        if kind == "hz":
+            try:
+                return int(text.strip()) / 1e6
+            except ValueError:
+                return None
+        for line in text.splitlines():
+            if line.rstrip().endswith("*"):
+                m = re.search(r"(\d+)\s*Mhz", line, re.I)
+                return float(m.group(1)) if m else None
+        return None
+
+    def _run(self):
+        while not self._stop.is_set():
+            for card, srcs in self.sources.items():
+                for key, (kind, path) in srcs.items():
+                    v = self._read(kind, path)
+                    if v is not None:
+                        self.samples.setdefault(card, {}).setdefault(key, []).append(v)
+            self._stop.wait(self.period)
+
+    def __enter__(self):
+        if self.sources:
+            self._thread.start()
+        return self
+
+    def __exit__(self, *exc):
+        self._stop.set()
+        if self._thread.is_alive():
+            self._thread.join()
+
+    def report(self):
+        rep = {}
+        for card, keys in self.samples.items():
+            rep[card] = {k: {"median": float(np.median(v)), "min": float(min(v)), "max": float(max(v)), "n": len(v),
+                             "source": self.sources[card][k][0]} for k, v in keys.items()}
+        return rep or None
 
 
 def measured_traffic(workload, tiles):
@@ -155,9 +262,9 @@ def cpu_baseline(cfg, seconds_target=15.0):
     run(rows)
     dt = time.perf_counter() - t
     adds = float(len(rows)) * n_out * cfg["n_chan"]
-    return {"value": adds / dt / 1e12, "unit": "Tadds/s", "cores": threads, "kind": "oracle",
-            "sample": "%d of %d DM rows, all %d channels x %d output samples (%.2e adds, %.1f s)"
-                      % (len(rows), cfg["n_dm"], cfg["n_chan"], n_out, adds, dt)}
+    return dict({"value": adds / dt / 1e12, "unit": "Tadds/s", "cores": threads, "kind": "oracle",
+                 "sample": "%d of %d DM rows, all %d channels x %d output samples (%.2e adds, %.1f s)"
+                           % (len(rows), cfg["n_dm"], cfg["n_chan"], n_out, adds, dt)}, **host_cpu())
 
 
 def cpu_tiled_baseline(cfg, seconds_target=15.0):
@@ -246,6 +353,87 @@ def setup_batch48(dd, torch, synth, n_chunks=BATCH_CHUNKS, log=log):
     torch.cuda.synchronize()
     log("batch: %d batches bound in %.1f s" % (len(batches), time.perf_counter() - t))
     return beams, chunkers, inputs, outputs, batches
+
+
+def timed_events(torch, fn, steps, warmup):
+    """Mean and median kernel time (ms) of fn() over `steps` calls, each bracketed by HIP events on
+    the current stream (the stream every call here launches on)."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for e0, e1 in ev:
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+    return float(np.mean(ms)), float(np.median(ms))
+
+
+def adjoint_vs_forward(dd, torch, synth, steps=10):
+    """The float differentiation workload (1024 ch f32 x 2^17 x 1024 DMs): the forward and the
+    adjoint (gather form) of one plan, each timed alone, and one forward + backward step through
+    DedisperseFn (the backward being the adjoint; the incoming gradient has row pitch n_out).
+    Both directions run in float32 with the same fixed-order sums and the same stated bound
+    (1e-5 of the sum of |terms|)."""
+    cfg = synth.CONFIGS["grad_f32"]
+    plan = dd.Plan(cfg["n_chan"], cfg["n_samp"], "f32", cfg["f_high"], cfg["chan_bw"], cfg["t_samp"],
+                   cfg["dm_start"], cfg["dm_step"], cfg["n_dm"])
+    x = torch.from_numpy(synth.normal_f32(cfg["n_chan"], cfg["n_samp"], cfg["seed"])).cuda()
+    gen = torch.Generator(device="cpu").manual_seed(cfg["target_seed"])
+    y = torch.randn((cfg["n_dm"], plan.n_out), generator=gen).cuda()
+    out = torch.empty((plan.n_dm, plan.out_pitch), device="cuda")
+    g = torch.empty((plan.n_chan, plan.in_row_elems), device="cuda")
+    adds = float(plan.n_dm) * plan.n_out * plan.n_chan
+    f_ms, f_med = timed_events(torch, lambda: plan.forward(x, out=out), steps, 3)
+    a_ms, a_med = timed_events(torch, lambda: plan.adjoint(y, out=g), steps, 3)
+    xg = x.clone().requires_grad_(True)
+
+    def fwd_bwd():
+        xg.grad = None
+        dd.DedisperseFn.apply(xg, plan).backward(y)
+    s_ms, _ = timed_events(torch, fwd_bwd, steps, 2)
+    rec = {"workload": "grad_f32", "n_chan": cfg["n_chan"], "n_samp": cfg["n_samp"], "n_dm": cfg["n_dm"],
+           "adds": adds, "forward": {"ms": f_ms, "ms_median": f_med, "Tadds_s": adds / f_ms / 1e9,
+                                     "tiles": plan.tiles(0)},
+           "adjoint": {"ms": a_ms, "ms_median": a_med, "Tadds_s": adds / a_ms / 1e9, "tiles": plan.tiles(1)},
+           "adjoint_over_forward_throughput": f_ms / a_ms,
+           "autograd_step": {"ms": s_ms, "what": "DedisperseFn forward + backward (adjoint), incoming gradient "
+                                                 "[n_dm][n_out] passed to the adjoint without a copy"},
+           "accuracy": "both float32, fixed-order sums, |err| <= 1e-5 * sum|terms| (tests)"}
+    del x, y, out, g, xg, plan
+    torch.cuda.empty_cache()
+    return rec
+
+
+def batched_vs_plain(dd, torch, synth):
+    """The 48-beam job (2 time chunks per beam), batched persistent graph-replayed launches against
+    the same work as plain dd_execute calls, both bit-exact; one warm-up and one timed pass each,
+    the plan's default tile shape (no tuning inside the benchmark)."""
+    beams, chunkers, inputs, outputs, batches = setup_batch48(dd, torch, synth)
+    adds = float(sum(b["n_dm"] * c.n_out * b["n_chan"] for b, c in zip(beams, chunkers)))
+
+    def batched():
+        for _, bt in batches:
+            bt.run()
+
+    def plain():
+        for k in range(len(batches)):
+            for i, c in enumerate(chunkers):
+                if k < len(c):
+                    c.plans[k].forward(c.input_view(inputs[i], k), out=outputs[i])
+    b_ms, _ = timed_events(torch, batched, 1, 1)
+    p_ms, _ = timed_events(torch, plain, 1, 1)
+    rec = {"workload": "batch48", "beams": len(beams), "time_chunks": len(batches), "adds": adds,
+           "batched": {"ms": b_ms, "Tadds_s": adds / b_ms / 1e9, "tiles": batches[0][1].tiles()},
+           "plain": {"ms": p_ms, "Tadds_s": adds / p_ms / 1e9, "calls": sum(len(c) for c in chunkers)},
+           "batched_over_plain_throughput": p_ms / b_ms,
+           "accuracy": "both bit-exact (integer input; tests compare every beam)"}
+    del beams, chunkers, inputs, outputs, batches
+    torch.cuda.empty_cache()
+    return rec
 
 
 def bench_batch48(args, dd, torch, synth):
@@ -472,6 +660,10 @@ def main():
                     help="multi-range workloads: time-major spectra in, corner turn inside every step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first, as a known-size reference for memory counters")
+    ap.add_argument("--autotune", action="store_true",
+                    help="headline: autotune the tiles first (its default shape is the tuner's pick there)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline: skip the adjoint-vs-forward and batched-vs-plain records")
     args = ap.parse_args()
     long_steps = {"batch48": 2, "tab_plans_8192": 5, "pipeline_high": 5}
     if args.steps is None:
@@ -520,7 +712,7 @@ def main():
     if args.tiles:
         shape, order = (int(v) for v in args.tiles.split(","))
         plan.set_tiles(direction, shape, order)
-    elif not args.no_autotune:
+    elif not args.no_autotune and (args.autotune or args.workload != "headline"):
         t = time.perf_counter()
         tune = plan.autotune(y, g, direction=1) if args.adjoint else plan.autotune(x, out)
         tune["seconds"] = time.perf_counter() - t
@@ -533,13 +725,14 @@ def main():
     stream = torch.cuda.current_stream()
     events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for e0, e1 in events:
-        e0.record(stream)
-        step()
-        e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    with SysfsClocks() as clocks:
+        t0 = time.perf_counter()
+        for e0, e1 in events:
+            e0.record(stream)
+            step()
+            e1.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
     kernel_ms = [e0.elapsed_time(e1) for e0, e1 in events]
     ms_step = wall * 1e3 / args.steps
     adds = float(plan.n_dm) * plan.n_out * plan.n_chan
@@ -583,6 +776,8 @@ def main():
                          "bytes_per_add": LDS_BYTES_PER_ADD[cfg["dtype"]]},
         "tiles": tiles,
         "autotune": tune,
+        "clocks": clocks.report(),
+        "host": host_cpu(),
     }
     if tiles["row_block"] == 0 and cfg["dtype"] != "f32":
         # The direct-read kernel loads 16 + 4 bytes per 16 samples of 8-bit (or 32 of 4-bit) input
@@ -595,6 +790,16 @@ def main():
         if cfg["dtype"] == "u8":
             log("tiled cpu baseline ...")
             rec["cpu_tiled"] = cpu_tiled_baseline(cfg)
+    if args.workload == "headline" and not args.adjoint and not args.no_extras:
+        # the rest of the metric: the adjoint and the batched form against the plain forward, same GPU
+        del x, out
+        torch.cuda.empty_cache()
+        log("adjoint vs forward (grad_f32) ...")
+        rec["adjoint_vs_forward"] = adjoint_vs_forward(dd, torch, synth)
+        log("adjoint vs forward: %s" % rec["adjoint_vs_forward"])
+        log("batched vs plain (batch48) ...")
+        rec["batched_vs_plain"] = batched_vs_plain(dd, torch, synth)
+        log("batched vs plain: %s" % rec["batched_vs_plain"])
     print(json.dumps(rec), flush=True)
 
 

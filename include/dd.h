@@ -98,6 +98,9 @@ typedef struct {
   int32_t order;  /* workgroup order: 0 = time tiles fastest, 1 = each XCD takes whole time tiles,
                      2 = each XCD takes its time tiles for 4 output blocks at a time */
   int32_t ns, per_wave, waves, row_block; /* the shape (output of dd_plan_get_tiles) */
+  int32_t segs;   /* staging form of an integer shape (output): 0 = raw rows staged once, the
+                     byte-phase copies built in LDS; > 0 = 8-bit shapes whose four byte-phase
+                     copies are loaded directly, each copy row in at most segs 1 KiB loads */
 } dd_tiles;
 
 /* Result of dd_plan_autotune.  Times are per launch over the timed span. */
@@ -163,14 +166,16 @@ dd_status dd_execute(const dd_plan *plan, const void *d_in, float *d_out, int64_
 /*
  * Adjoint (transpose of Eq. 3, "re-dispersion") for DD_F32 plans, in gather form:
  *     g(c, tau) = sum_d [0 <= tau - shift(c,d) < n_out] * y(d, tau - shift(c,d)).
- *   d_y        device pointer, float32 [n_dm][y_pitch], columns 0..n_out-1 read.
- *   y_pitch    elements, >= n_out, multiple of 4.
+ *   d_y        device pointer, float32 [n_dm][y_pitch], columns 0..n_out-1 read;
+ *              4-byte aligned (a gradient tensor of any row length can be passed as is).
+ *   y_pitch    elements, >= n_out (any value).
  *   d_grad_in  device pointer, float32 [n_chan] rows of in_pitch_bytes; columns
  *              0..n_samp-1 of every row are overwritten (exact zeros where no
  *              output reads the sample).
  * No atomics; DMs are summed in a fixed order (groups of 32 in order), so the
  * result is deterministic and independent of the tile shape.
- * Errors: DD_ERR_DTYPE (integer plan), DD_ERR_ARG, DD_ERR_ALIGN, DD_ERR_NOT_BOUND, DD_ERR_HIP.
+ * Errors: DD_ERR_DTYPE (integer plan), DD_ERR_ARG, DD_ERR_ALIGN (d_y not 4-byte or d_grad
+ * not 16-byte aligned), DD_ERR_NOT_BOUND, DD_ERR_HIP.
  */
 dd_status dd_execute_adjoint(const dd_plan *plan, const float *d_y, int64_t y_pitch,
                              float *d_grad_in, void *stream);
@@ -266,9 +271,10 @@ void dd_batch_destroy(dd_batch *batch);
  * sums without normalisation; a trailing partial bin is dropped.
  *   dtype      input encoding (a dd_dtype); the output encoding is
  *              dd_bin_out_dtype(dtype): DD_U8 and DD_U4 give exact uint16 sums,
- *              DD_U16 gives float32 holding the exact integer sums, DD_F32 gives
- *              float32 sums (float32 arithmetic, an order that depends only on
- *              `factor`).
+ *              DD_U16 gives float32 holding the exact integer sums (below 2^24),
+ *              DD_F32 gives float32 sums (float32 arithmetic, an order that
+ *              depends only on `factor`).  (Surveys bin 16-bit input into
+ *              split uint16 planes instead; see dd_survey_create.)
  *   d_in       device pointer, [n_chan] rows of in_pitch_bytes (>= one packed row,
  *              multiple of 16); samples 0..n_bins*factor-1 of each row are read.
  *   factor     1..256 (keeps every integer sum exact in its output type).
@@ -312,7 +318,13 @@ dd_status dd_corner_turn(int32_t dtype, const void *d_in, int64_t in_pitch_bytes
  * samples of t_samp * bin_r seconds in encoding dd_bin_out_dtype(dtype) (the
  * input itself when bin_r == 1), with DM_d = dm_start_r + d * dm_step_r.  Its
  * output is that plan's S(d, t), t counted in binned samples.  Ranges that
- * share a factor share one binned copy.
+ * share a factor share one binned copy.  For DD_U16 input the binned copy
+ * instead holds the exact bin sums (below 2^24) as two uint16 planes per row,
+ * their low and their high halves, and the range's plan is a DD_U16 plan over
+ * the low plane: dd_survey_execute sums both planes exactly in 32-bit integers
+ * and writes the float32 of low + 2^16 * high, so every output of an integer
+ * survey is the float32 of its exact integer sum (rounded once, to nearest
+ * even, above 2^24).
  *
  * dd_survey_create: `base` gives the filterbank (n_chan, n_samp, dtype, band,
  *   t_samp_s, in_pitch_bytes); its DM fields are ignored.  ranges[0..n-1]:

@@ -11,6 +11,7 @@ from .binding import (  # noqa: F401
     DD_U8,
     LIB_PATH,
     BIN_OUT,
+    SURVEY_BIN_DTYPE,
     Batch,
     DDError,
     DedisperseFn,

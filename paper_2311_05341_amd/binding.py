@@ -48,7 +48,8 @@ class PlanInfo(ctypes.Structure):
 
 class Tiles(ctypes.Structure):
     _fields_ = [("shape", ctypes.c_int32), ("order", ctypes.c_int32), ("ns", ctypes.c_int32),
-                ("per_wave", ctypes.c_int32), ("waves", ctypes.c_int32), ("row_block", ctypes.c_int32)]
+                ("per_wave", ctypes.c_int32), ("waves", ctypes.c_int32), ("row_block", ctypes.c_int32),
+                ("segs", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -278,7 +279,7 @@ class Plan:
 
     def _check_y(self, y):
         if (y.dtype != torch.float32 or y.device != self.device or y.dim() != 2 or y.shape[0] != self.n_dm
-                or y.shape[1] < self.n_out or y.stride(1) != 1):
+                or y.shape[1] < self.n_out or y.stride(1) != 1 or y.stride(0) < self.n_out):
             raise ValueError("y must be float32 [n_dm][>= n_out] with contiguous rows on %s" % self.device)
 
     def _check_grad(self, g):
@@ -297,10 +298,10 @@ class Plan:
         return out[:, : self.n_out]
 
     def adjoint(self, y, out=None, stream=None):
-        """g = A^T y for float32 plans: float32 [n_chan][n_samp] (view of a pitched buffer)."""
+        """g = A^T y for float32 plans: float32 [n_chan][n_samp] (view of a pitched buffer).
+
+        y may have any row pitch >= n_out (a gradient tensor is passed as is)."""
         self._check_y(y)
-        if y.stride(0) % 4 or y.data_ptr() % 16:
-            y = _pad_rows(y, self.n_out)
         if out is None:
             out = torch.empty((self.n_chan, self.in_row_elems), dtype=torch.float32, device=self.device)
         self._check_grad(out)
@@ -315,37 +316,42 @@ class Plan:
             self._h = None
 
 
-def _pad_rows(y, n):
-    p = torch.zeros((y.shape[0], _round_up(n, 4)), dtype=y.dtype, device=y.device)
-    p[:, :n] = y[:, :n]
-    return p
-
-
 def dedisperse(x, plan: Plan, out=None):
     """Forward transform of ``x`` with ``plan`` on the current stream."""
     return plan.forward(x, out=out)
 
 
 class DedisperseFn(torch.autograd.Function):
-    """Differentiable forward transform for float32 plans; backward is dd_execute_adjoint."""
+    """Differentiable forward transform for float32 plans; backward is dd_execute_adjoint.
+
+    x is float32 [n_chan][m] with the plan's row pitch, m >= n_samp (the plan's
+    whole pitched buffer or a view of its first columns).  The forward returns
+    an [n_dm][n_out] view of a pitched output buffer.  The backward passes the
+    incoming gradient to the adjoint as it is (any row pitch; only a gradient
+    without contiguous rows, such as the expanded ones of a plain sum, is
+    materialised first) and writes the input gradient straight into a buffer of
+    the plan's pitch; columns n_samp..m-1, which no output reads, are zeroed only
+    when x has them."""
 
     @staticmethod
     def forward(ctx, x, plan):
         if plan.dtype != "f32":
             raise TypeError("autograd needs a float32 plan")
         ctx.plan = plan
-        return plan.forward(x.contiguous() if x.stride(1) != 1 else x)
+        ctx.x_cols = int(x.shape[1])
+        return plan.forward(x)
 
     @staticmethod
     def backward(ctx, grad_out):
         plan = ctx.plan
         g = grad_out
-        if g.stride(1) != 1 or g.stride(0) % 4 or g.data_ptr() % 16:
-            g = _pad_rows(g, plan.n_out)
-        gx = plan.adjoint(g)
-        full = torch.zeros((plan.n_chan, plan.in_row_elems), dtype=torch.float32, device=plan.device)
-        full[:, : plan.n_samp] = gx
-        return full, None
+        if g.stride(1) != 1 or g.stride(0) < plan.n_out or g.data_ptr() % 4:
+            g = g.contiguous()
+        gx = torch.empty((plan.n_chan, plan.in_row_elems), dtype=torch.float32, device=plan.device)
+        plan.adjoint(g, out=gx)
+        if ctx.x_cols > plan.n_samp:
+            gx[:, plan.n_samp: ctx.x_cols].zero_()
+        return gx[:, : ctx.x_cols], None
 
 
 class Batch:
@@ -413,6 +419,9 @@ class Batch:
 
 #: Output encoding of time binning per input encoding (dd_bin_out_dtype).
 BIN_OUT = {"u8": "u16", "u4": "u16", "u16": "f32", "f32": "f32"}
+#: Encoding a survey's binned range is dedispersed in: binned 16-bit input is kept as two
+#: exact uint16 planes (low and high halves of the sums) and runs the 16-bit kernel on each.
+SURVEY_BIN_DTYPE = {"u8": "u16", "u4": "u16", "u16": "u16", "f32": "f32"}
 
 
 def _row_bytes(dtype, n_samp):
@@ -516,7 +525,8 @@ class Survey:
             n_out = int(info.n_out)
             self.range_info.append({"n_dm": int(n_dm), "bin": int(b), "n_out": n_out, "out_pitch": _round_up(n_out, 4),
                                     "n_samp": self.n_samp // int(b), "t_samp": float(t_samp) * int(b),
-                                    "dtype": dtype if int(b) == 1 else BIN_OUT[dtype],
+                                    "dtype": dtype if int(b) == 1 else SURVEY_BIN_DTYPE[dtype],
+                                    "split_planes": dtype == "u16" and int(b) > 1,
                                     "max_shift": int(info.max_shift)})
         nbytes = _sz()
         _check(_lib.dd_survey_workspace_bytes(h, ctypes.byref(nbytes)), "dd_survey_workspace_bytes")

@@ -33,41 +33,37 @@ static int64_t packed_row_bytes(int dtype, int64_t n_samp) {
 
 dd_status hip_error(int e, const char *what) { return hip_fail(e, what); }
 
+int copy_tables(const dd_plan &p, void *dst, void *stream) {
+  hipStream_t st = (hipStream_t)stream;
+  uint8_t *base = (uint8_t *)dst;
+  const TableLayout L = table_layout(p);
+  hipError_t e = hipSuccess;
+  if (p.desc.dtype != DD_F32 && is_direct(p.fwd)) {  // the direct kernel reads the plain shift table
+    e = hipMemcpyAsync(base + L.int_offs, p.shift.data(), p.shift.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
+  } else if (p.desc.dtype != DD_F32) {
+    e = hipMemcpyAsync(base + L.int_offs, p.itab.offs.data(), p.itab.offs.size() * 2, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(base + L.int_sbase, p.itab.sbase.data(), p.itab.sbase.size() * 4, hipMemcpyHostToDevice, st);
+  } else {
+    const FloatTables *tabs[2] = {&p.ftab_fwd, &p.ftab_adj};
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+      e = hipMemcpyAsync(base + L.f_offs[k], tabs[k]->offs.data(), tabs[k]->offs.size() * 2, hipMemcpyHostToDevice, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(base + L.f_sbase[k], tabs[k]->sbase.data(), tabs[k]->sbase.size() * 4,
+                           hipMemcpyHostToDevice, st);
+    }
+  }
+  return (int)e;
+}
+
 // Enqueue the upload of the plan's current tables into `ws` and mark the plan
 // bound to it on the current device.
 dd_status upload_tables(dd_plan &p, void *ws, void *stream) {
   int dev = -1;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-  hipStream_t st = (hipStream_t)stream;
-  uint8_t *base = (uint8_t *)ws;
-  if (p.desc.dtype != DD_F32 && is_direct(p.fwd)) {
-    p.int_offs_off = 0;  // the direct kernel reads the plain shift table
-    p.int_sbase_off = 0;
-    e = hipMemcpyAsync(base, p.shift.data(), p.shift.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "table upload");
-  } else if (p.desc.dtype != DD_F32) {
-    const size_t ob = p.itab.offs.size() * sizeof(uint16_t);
-    p.int_offs_off = 0;
-    p.int_sbase_off = (ob + 255) / 256 * 256;
-    e = hipMemcpyAsync(base, p.itab.offs.data(), ob, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(base + p.int_sbase_off, p.itab.sbase.data(), p.itab.sbase.size() * 4, hipMemcpyHostToDevice,
-                         st);
-    if (e != hipSuccess) return hip_fail(e, "table upload");
-  } else {
-    size_t off = 0;
-    FloatTables *tabs[2] = {&p.ftab_fwd, &p.ftab_adj};
-    for (FloatTables *t : tabs) {
-      t->offs_off = off;
-      if (e == hipSuccess) e = hipMemcpyAsync(base + off, t->offs.data(), t->offs.size() * 2, hipMemcpyHostToDevice, st);
-      off += (t->offs.size() * 2 + 255) / 256 * 256;
-      t->sbase_off = off;
-      if (e == hipSuccess) e = hipMemcpyAsync(base + off, t->sbase.data(), t->sbase.size() * 4, hipMemcpyHostToDevice, st);
-      off += (t->sbase.size() * 4 + 255) / 256 * 256;
-    }
-    if (e != hipSuccess) return hip_fail(e, "table upload");
-  }
+  const int ce = copy_tables(p, ws, stream);
+  if (ce) return hip_fail(ce, "table upload");
   p.d_tables = ws;
   p.device = dev;
   p.bound = true;
@@ -175,8 +171,8 @@ dd_status dd_execute(const dd_plan *p, const void *d_in, float *d_out, int64_t o
   if (!aligned16(d_in) || !aligned16(d_out)) return fail(DD_ERR_ALIGN, "buffers must be 16-byte aligned");
   if (out_pitch < p->n_out) return fail(DD_ERR_ARG, "out_pitch < n_out");
   if (out_pitch % 4) return fail(DD_ERR_ALIGN, "out_pitch must be a multiple of 4 elements");
-  int e = p->desc.dtype == DD_F32 ? launch_forward_f32(*p, d_in, d_out, out_pitch, stream)
-                                  : launch_forward_int(*p, d_in, d_out, out_pitch, stream);
+  int e = p->desc.dtype == DD_F32 ? launch_forward_f32(*p, p->d_tables, d_in, d_out, out_pitch, stream)
+                                  : launch_forward_int(*p, p->d_tables, d_in, d_out, out_pitch, stream);
   if (e) return hip_fail(e, "forward launch");
   return DD_OK;
 }
@@ -186,10 +182,12 @@ dd_status dd_execute_adjoint(const dd_plan *p, const float *d_y, int64_t y_pitch
   dd_status st = check_exec(p);
   if (st != DD_OK) return st;
   if (!d_y || !d_grad) return fail(DD_ERR_ARG, "null buffer");
-  if (!aligned16(d_y) || !aligned16(d_grad)) return fail(DD_ERR_ALIGN, "buffers must be 16-byte aligned");
+  // y rows are staged by 16-byte loads from 4-byte-aligned row starts (every
+  // dword range-checked against the row), so y only needs float alignment
+  if (((uintptr_t)d_y & 3u) || !aligned16(d_grad))
+    return fail(DD_ERR_ALIGN, "d_y must be 4-byte and d_grad 16-byte aligned");
   if (y_pitch < p->n_out) return fail(DD_ERR_ARG, "y_pitch < n_out");
-  if (y_pitch % 4) return fail(DD_ERR_ALIGN, "y_pitch must be a multiple of 4 elements");
-  int e = launch_adjoint(*p, d_y, y_pitch, d_grad, stream);
+  int e = launch_adjoint(*p, p->d_tables, d_y, y_pitch, d_grad, stream);
   if (e) return hip_fail(e, "adjoint launch");
   return DD_OK;
 }

@@ -60,7 +60,7 @@ static dd_status batch_set_shape(dd_batch *b, int s) {
   std::vector<IntTables> tabs(n);
   int lds = 0;
   for (int i = 0; i < n; ++i) {
-    const dd_status st = build_int_tables(*b->plans[i], k[0], k[1], k[2], k[3], kBatchLdsLimit, &tabs[i]);
+    const dd_status st = build_int_tables(*b->plans[i], k[0], k[1], k[2], k[3], k[4], kBatchLdsLimit, &tabs[i]);
     if (st != DD_OK) return st;
     lds = std::max(lds, tabs[i].lds_bytes);
   }
@@ -70,6 +70,7 @@ static dd_status batch_set_shape(dd_batch *b, int s) {
   b->tile.dm_per_wave = k[1];
   b->tile.waves = k[2];
   b->tile.chan_block = k[3];
+  b->tile.segs = k[4];
   b->lds_bytes = lds;
   const int dm_tile = k[1] * k[2], t_tile = 64 * k[0];
   b->descs.resize(n);
@@ -140,12 +141,15 @@ dd_status dd_batch_create(const dd_plan *const *plans, int32_t n, dd_batch **out
   }
   b->ws_bytes = off;
   // One tile shape for all beams: the first compiled shape every beam can stage
-  // (two workgroups' worth of LDS is not required: the kernel runs one per CU).
+  // (two workgroups' worth of LDS is not required: the kernel runs one per CU),
+  // phase-load shapes first for 8-bit beams.
   dd_status st = DD_ERR_RANGE;
-  for (int s = 0; s < kNumIntShapes && st != DD_OK; ++s) {
-    st = batch_set_shape(b, s);
-    if (st == DD_ERR_NOMEM) { delete b; return st; }
-  }
+  for (int pass = 0; pass < 2 && st != DD_OK; ++pass)
+    for (int s = 0; s < kNumIntShapes && st != DD_OK; ++s) {
+      if ((kIntShapes[s][4] > 0) != (pass == 0)) continue;
+      st = batch_set_shape(b, s);
+      if (st == DD_ERR_NOMEM) { delete b; return st; }
+    }
   if (st != DD_OK) { delete b; return fail(DD_ERR_RANGE, "a beam's delay spread exceeds the LDS staging capacity"); }
   *out = b;
   return DD_OK;
@@ -194,7 +198,7 @@ dd_status dd_batch_bind(dd_batch *b, const void *const *d_in, float *const *d_ou
   if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("batch upload: ") + hipGetErrorString(e));
 
   BatchLaunch L = {};
-  int le = batch_kernels(b->tile.ns, b->tile.dm_per_wave, b->tile.waves, b->tile.chan_block, b->dtype,
+  int le = batch_kernels(b->tile.ns, b->tile.dm_per_wave, b->tile.waves, b->tile.chan_block, b->tile.segs, b->dtype,
                          b->lds_bytes, &L);
   if (le) return fail(DD_ERR_HIP, std::string("batch kernel setup: ") + hipGetErrorString((hipError_t)le));
   if (!L.reset_fn || !L.main_fn) return fail(DD_ERR_HIP, "batch kernel setup: missing kernel entry");
@@ -255,6 +259,7 @@ dd_status dd_batch_get_tiles(const dd_batch *b, dd_tiles *t) {
   t->per_wave = k[1];
   t->waves = k[2];
   t->row_block = k[3];
+  t->segs = k[4];
   return DD_OK;
 }
 

@@ -294,6 +294,45 @@ __global__ __launch_bounds__(kBinThreads) void bin_any_kernel(BinArgs a) {
   }
 }
 
+// 16-bit input binned into two uint16 planes: the low and high halves of
+// every exact bin sum (below 2^24 for F <= 256, so the high half is at most
+// 255).  The transform then sums each plane exactly in 32-bit integers and
+// combines them once (OutMode in dd_internal.h).  Row c of the low plane is at
+// out + c * out_pitch, of the high plane `hi_off` bytes further.  One lane per
+// bin; the bin's 2F bytes are read as whole words where F allows.
+__global__ __launch_bounds__(kBinThreads) void bin_u16_split_kernel(BinArgs a, int64_t hi_off) {
+  const int f = a.factor;
+  for (int c = blockIdx.y; c < a.n_chan; c += gridDim.y) {
+    const uint8_t *row = a.in + (int64_t)c * a.in_pitch;
+    uint16_t *lo = (uint16_t *)(a.out + (int64_t)c * a.out_pitch);
+    uint16_t *hi = (uint16_t *)(a.out + (int64_t)c * a.out_pitch + hi_off);
+    const int64_t j0 = (int64_t)blockIdx.x * (kBinThreads * kBinUnits) + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < kBinUnits; ++u) {
+      const int64_t j = j0 + u * kBinThreads;
+      if (j >= a.n_bins) break;
+      const uint8_t *b = row + 2 * j * f;  // 16-byte aligned when f % 8 == 0, 4-byte when f is even
+      uint32_t s = 0;
+      if (f % 8 == 0) {
+        for (int i = 0; i < f; i += 8) {
+          const uint4 w = *(const uint4 *)(b + 2 * i);
+          s += (w.x & 0xFFFFu) + (w.x >> 16) + (w.y & 0xFFFFu) + (w.y >> 16) + (w.z & 0xFFFFu) + (w.z >> 16) +
+               (w.w & 0xFFFFu) + (w.w >> 16);
+        }
+      } else if (f % 2 == 0) {
+        for (int i = 0; i < f; i += 2) {
+          const uint32_t w = *(const uint32_t *)(b + 2 * i);
+          s += (w & 0xFFFFu) + (w >> 16);
+        }
+      } else {
+        for (int i = 0; i < f; ++i) s += ((const uint16_t *)b)[i];
+      }
+      lo[j] = (uint16_t)s;
+      hi[j] = (uint16_t)(s >> 16);
+    }
+  }
+}
+
 using BinKernel = void (*)(BinArgs);
 
 template <int DT, int F>
@@ -361,6 +400,23 @@ int launch_bin(int dtype, const void *in, int64_t in_pitch, int n_chan, int64_t 
   const int64_t per_block = (int64_t)kBinThreads * kBinUnits;
   const dim3 grid((unsigned)((a.n_units + per_block - 1) / per_block), (unsigned)(n_chan < 65535 ? n_chan : 65535));
   hipLaunchKernelGGL(k, grid, dim3(kBinThreads), 0, (hipStream_t)stream, a);
+  return (int)hipGetLastError();
+}
+
+int launch_bin_u16_split(const void *in, int64_t in_pitch, int n_chan, int64_t n_samp, int factor, void *out,
+                         int64_t out_pitch, int64_t hi_off, void *stream) {
+  BinArgs a;
+  a.in = (const uint8_t *)in;
+  a.in_pitch = in_pitch;
+  a.out = (uint8_t *)out;
+  a.out_pitch = out_pitch;
+  a.n_chan = n_chan;
+  a.n_bins = n_samp / factor;
+  a.n_units = a.n_bins;
+  a.factor = factor;
+  const int64_t per_block = (int64_t)kBinThreads * kBinUnits;
+  const dim3 grid((unsigned)((a.n_bins + per_block - 1) / per_block), (unsigned)(n_chan < 65535 ? n_chan : 65535));
+  hipLaunchKernelGGL(bin_u16_split_kernel, grid, dim3(kBinThreads), 0, (hipStream_t)stream, a, hi_off);
   return (int)hipGetLastError();
 }
 

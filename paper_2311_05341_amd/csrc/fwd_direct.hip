@@ -14,12 +14,15 @@
 // Windows start at any sample, but the loads stay 4-byte aligned: a lane
 // loads the aligned words covering its 16-byte (8-bit input; 32-byte for
 // 16-bit) window plus one more, and funnel-shifts them (v_alignbit, by a
-// wave-uniform bit count) into the window's words.  Raw buffer loads with the
-// channel row's pitch as the record bound return zeros past the row, so no
-// read can leave the input.  In the last time tile, where a lane's window may
-// run past the row, the words are loaded one by one: a 4-byte-aligned word
-// lies wholly inside or wholly outside the 16-byte-multiple pitch, so the
-// bound check never drops bytes a valid output needs.
+// wave-uniform bit count) into the window's words.  Each (channel, DM) pair
+// gets its own raw buffer descriptor based at the window's first aligned word,
+// with the rest of the channel's row pitch as its record bound, and the loads
+// pass no scalar offset: the bound is checked against the per-lane offset, so
+// every byte past the row pitch reads as zero and no read can leave the input.  In the last time tile,
+// where a lane's window may run past the row, the words are loaded one by one:
+// a 4-byte-aligned word lies wholly inside or wholly outside the bound (both
+// the pitch and the delay offset are multiples of 4 bytes), so the bound check
+// never drops bytes a valid output needs.
 //
 // Accumulation is the same exact SIMD-in-word arithmetic as the LDS kernel:
 // 8-bit words as mix/odd pairs flushed every 256 channels, 4-bit words first
@@ -46,7 +49,19 @@ struct DirectArgs {
   float *out;            // [n_dm][out_pitch]
   int64_t pitch, n_out, out_pitch;
   int32_t n_chan, n_dm;
+  int32_t out_mode;  // an OutMode; other than kOutFloat for 16-bit input only
 };
+
+// Output of one exact total by OutMode (see fwd_int.hip): float32, the raw
+// 32-bit total, or low (read back) + 2^16 * this total converted once.
+__device__ __forceinline__ void store_total(float *o, uint32_t v, int mode) {
+  if (mode == kOutRawTotals)
+    *(uint32_t *)o = v;
+  else if (mode == kOutCombineHigh)
+    *o = (float)((double)*(const uint32_t *)o + 65536.0 * (double)v);
+  else
+    *o = (float)v;
+}
 
 template <typename T>
 __device__ __forceinline__ T scalar_load(const T *p, int64_t i) {
@@ -101,18 +116,20 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int cc = min(c + u, ce - 1);
-        const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(a.x + (int64_t)cc * a.pitch), (short)0, (int)a.pitch, kRsrcWord3);
+        const uint8_t *row = a.x + (int64_t)cc * a.pitch;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int s = scalar_load(a.shift, (int64_t)drow[r] * a.n_chan + cc);
           const int64_t bit = (int64_t)s * BITS;           // bit offset of the delay
-          const int soff = (int)(bit >> 5) * 4;            // aligned byte offset, wave-uniform
+          const int soff = (int)(bit >> 5) * 4;            // aligned byte offset, wave-uniform, < pitch
           sh[u][r] = (int)(bit & 31);
+          // descriptor over [row + soff, row + pitch): the lane offsets are range-checked against it
+          const __amdgpu_buffer_rsrc_t rs =
+              __builtin_amdgcn_make_buffer_rsrc((void *)(row + soff), (short)0, (int)a.pitch - soff, kRsrcWord3);
           if (!last_tile) {
 #pragma unroll
             for (int q = 0; q < WORDS / 4; ++q) {
-              const v4i v = __builtin_amdgcn_raw_buffer_load_b128(rs, vo + 16 * q, soff, 0);
+              const v4i v = __builtin_amdgcn_raw_buffer_load_b128(rs, vo + 16 * q, 0, 0);
               raw[u][r][4 * q] = v.x;
               raw[u][r][4 * q + 1] = v.y;
               raw[u][r][4 * q + 2] = v.z;
@@ -120,9 +137,9 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
             }
           } else {
 #pragma unroll
-            for (int q = 0; q < WORDS; ++q) raw[u][r][q] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo + 4 * q, soff, 0);
+            for (int q = 0; q < WORDS; ++q) raw[u][r][q] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo + 4 * q, 0, 0);
           }
-          raw[u][r][WORDS] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo + 4 * WORDS, soff, 0);
+          raw[u][r][WORDS] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo + 4 * WORDS, 0, 0);
         }
       }
 #pragma unroll
@@ -198,7 +215,9 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
   for (int r = 0; r < R; ++r) {
     if (d0 + r >= a.n_dm) break;
     float *o = a.out + (int64_t)(d0 + r) * a.out_pitch + tl;
-    if (tl + NS <= a.n_out) {
+    if (BITS == 16 && a.out_mode != kOutFloat) {
+      for (int k = 0; k < NS && tl + k < a.n_out; ++k) store_total(o + k, tot[r][k], a.out_mode);
+    } else if (tl + NS <= a.n_out) {
 #pragma unroll
       for (int k = 0; k < NS; k += 4)
         *(float4 *)(o + k) = make_float4((float)tot[r][k], (float)tot[r][k + 1], (float)tot[r][k + 2], (float)tot[r][k + 3]);
@@ -212,18 +231,21 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
 #define DD_DIRECT_SHAPES(X) X(4, 4) X(2, 8)
 
 template <int R, int NW>
-int launch_direct_shape(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, hipStream_t st,
-                        int64_t out_limit) {
+int launch_direct_shape(const dd_plan &p, const void *tables, const void *d_in, float *d_out, int64_t out_pitch,
+                        hipStream_t st, int64_t out_limit, int out_mode) {
   DirectArgs a;
   a.x = (const uint8_t *)d_in;
-  a.shift = (const int32_t *)((const uint8_t *)p.d_tables + p.int_offs_off);
+  a.shift = (const int32_t *)((const uint8_t *)tables + table_layout(p).int_offs);
   a.out = d_out;
   a.pitch = p.in_pitch_bytes;
   a.n_out = out_limit > 0 && out_limit < p.n_out ? out_limit : p.n_out;
   a.out_pitch = out_pitch;
   a.n_chan = p.desc.n_chan;
   a.n_dm = p.desc.n_dm;
+  a.out_mode = out_mode;
   const int bits = p.desc.dtype == DD_U4 ? 4 : p.desc.dtype == DD_U16 ? 16 : 8;
+  // every descriptor base row + (delay bytes rounded down to 4) must lie inside the row pitch
+  if ((int64_t)p.max_shift * bits / 8 >= p.in_pitch_bytes) return (int)hipErrorInvalidValue;
   const int ns = bits == 4 ? 32 : 16;
   const int64_t tiles_t = (a.n_out + 64 * ns - 1) / (64 * ns);
   const int64_t n_dblk = (a.n_dm + NW * R - 1) / (NW * R);
@@ -245,11 +267,12 @@ const int kDirectShapes[][4] = {DD_DIRECT_SHAPES(DD_ROW)};
 #undef DD_ROW
 const int kNumDirectShapes = (int)(sizeof(kDirectShapes) / sizeof(kDirectShapes[0]));
 
-int launch_forward_direct(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream,
-                          int64_t out_limit) {
+int launch_forward_direct(const dd_plan &p, const void *tables, const void *d_in, float *d_out, int64_t out_pitch,
+                          void *stream, int64_t out_limit, int out_mode) {
   const TileCfg &t = p.fwd;
-#define DD_TRY(R, NW) \
-  if (t.dm_per_wave == R && t.waves == NW) return launch_direct_shape<R, NW>(p, d_in, d_out, out_pitch, (hipStream_t)stream, out_limit);
+#define DD_TRY(R, NW)                     \
+  if (t.dm_per_wave == R && t.waves == NW) \
+    return launch_direct_shape<R, NW>(p, tables, d_in, d_out, out_pitch, (hipStream_t)stream, out_limit, out_mode);
   DD_DIRECT_SHAPES(DD_TRY)
 #undef DD_TRY
   return (int)hipErrorInvalidValue;

@@ -124,6 +124,40 @@ __device__ __forceinline__ void flush(uint32_t (&mix)[R][NS / 4], uint32_t (&odd
   }
 }
 
+// Epilogue of the 16-bit kernels for the two exact 32-bit totals of samples
+// t and t + 1 (v0, v1), by OutMode: plain float32 conversion; the raw totals
+// (the low-half plane of a split sum, kept in the output buffer); or the
+// combination with those raw totals, low + 2^16 * this, converted once.  The
+// combined sum is below 2^49, so its double is exact and the conversion to
+// float rounds once, to nearest even, as the conversion of the exact sum would.
+__device__ __forceinline__ float combine_split(uint32_t lo_total, uint32_t hi_total) {
+  return (float)((double)lo_total + 65536.0 * (double)hi_total);
+}
+
+__device__ __forceinline__ void store_u16_pair(float *orow, int64_t t, int64_t n_out, uint32_t v0, uint32_t v1,
+                                               int mode) {
+  if (t >= n_out) return;
+  const bool both = t + 1 < n_out;
+  if (mode == kOutRawTotals) {
+    if (both)
+      *(uint2 *)(orow + t) = make_uint2(v0, v1);
+    else
+      *(uint32_t *)(orow + t) = v0;
+  } else if (mode == kOutCombineHigh) {
+    if (both) {
+      const uint2 lo = *(const uint2 *)(orow + t);
+      *(float2 *)(orow + t) = make_float2(combine_split(lo.x, v0), combine_split(lo.y, v1));
+    } else {
+      orow[t] = combine_split(*(const uint32_t *)(orow + t), v0);
+    }
+  } else {
+    if (both)
+      *(float2 *)(orow + t) = make_float2((float)v0, (float)v1);
+    else
+      orow[t] = (float)v0;
+  }
+}
+
 // Kernel arguments shared by the plain and the batched kernels.
 struct IntArgs {
   const uint8_t *x;       // [n_chan][pitch] bytes
@@ -132,6 +166,7 @@ struct IntArgs {
   float *out;             // [n_dm][out_pitch]
   int64_t pitch, n_samp, n_out, out_pitch;
   int32_t n_chan, n_dm, row_bytes;
+  int32_t out_mode;       // 16-bit input only: an OutMode (float totals, or one half of a split-plane sum)
 };
 
 // Workgroup barrier for LDS hand-offs.  __syncthreads() also waits for every
@@ -505,10 +540,7 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
       for (int k = 0; k < NWD; ++k) {
         const int64_t t = t0 + 2 * (int64_t)(lane + 64 * k);
         const uint32_t lo = mix[r][k] - (odd[r][k] << 16);
-        if (t + 1 < a.n_out)
-          *(float2 *)(orow + t) = make_float2((float)lo, (float)odd[r][k]);
-        else if (t < a.n_out)
-          orow[t] = (float)lo;
+        store_u16_pair(orow, t, a.n_out, lo, odd[r][k], a.out_mode);
       }
       continue;
     }
@@ -527,13 +559,230 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
   }
 }
 
+// ---------------------------------------------------------------------------
+// 8-bit staging by phase loads.  The four byte-phase copies of a staged row are
+// loaded straight from memory into LDS, copy p from byte p of the row on
+// (16-byte loads at byte offsets that are not multiples of 4; the memory
+// pipeline handles them, and each (channel, block) gets a buffer descriptor
+// based at its first staged byte whose record bound ends at the row's last
+// sample, so bytes past the row read as zero).  No phase-building pass, no raw
+// ring: channel blocks stream through kPhaseRing slots of CB channels x 4
+// copies, kPhaseRing - 1 blocks ahead of the summation, with one barrier per
+// block.  The table entry of a (channel, DM row) is the byte offset of its
+// window's first word from the start of the slot, so the summation needs one
+// address add per (channel, row).
+//
+// Loads per block: each of the CB * SEGS (channel, 1 KiB segment) pairs issues
+// its four phase loads from one wave; pair j goes to wave j % NW, so every wave
+// issues exactly 4 * ceil(CB * SEGS / NW) loads per block (padding loads of
+// zero bytes into a sink keep the count fixed) and one vmcnt wait is exact.
+constexpr int kPhaseRing = 3;
+
+template <int CB, int SEGS, int NW>
+constexpr int phase_pairs_per_wave() { return (CB * SEGS + NW - 1) / NW; }
+
+// This wave's (channel, segment) pairs: channel within the block, segment.
+template <int CB, int SEGS, int NW>
+struct PhasePlan {
+  static constexpr int J = phase_pairs_per_wave<CB, SEGS, NW>();
+  int cc[J];           // channel within the block (0 for padding)
+  bool ok[J];          // a real pair (wave-uniform)
+  uint32_t lds_off[J];  // LDS byte offset of the pair's copy 0 segment inside a slot
+  uint32_t voff[J];    // this lane's byte offset in the staged row, copy 0
+  bool lane_ok[J];     // this lane's 16 bytes lie inside the copy (true for padding)
+};
+
+template <int CB, int SEGS, int NW>
+__device__ __forceinline__ PhasePlan<CB, SEGS, NW> phase_plan(int row_bytes, int wave, int lane) {
+  PhasePlan<CB, SEGS, NW> d;
+#pragma unroll
+  for (int m = 0; m < PhasePlan<CB, SEGS, NW>::J; ++m) {
+    const int j = wave + m * NW;
+    const int cc = j / SEGS, seg = j - cc * SEGS;
+    d.ok[m] = j < CB * SEGS && 1024 * seg < row_bytes;
+    d.cc[m] = d.ok[m] ? cc : 0;
+    d.lds_off[m] = d.ok[m] ? (uint32_t)(cc * 4 * row_bytes + 1024 * seg) : 0u;
+    d.voff[m] = (uint32_t)(1024 * seg + 16 * lane);
+    d.lane_ok[m] = !d.ok[m] || 1024 * seg + 16 * lane < row_bytes;
+  }
+  return d;
+}
+
+// Issue this wave's phase loads of block `cb` (first channel) into ring slot
+// `slot`; `base` holds the stage bases of the wave's channels for that block.
+template <int CB, int SEGS, int NW>
+__device__ __forceinline__ void phase_dma(const IntArgs &a, const PhasePlan<CB, SEGS, NW> &d,
+                                          const int32_t (&base_in)[PhasePlan<CB, SEGS, NW>::J], int64_t t0, int cb,
+                                          uint8_t *lds, int slot_bytes, int slot, uint32_t sink_addr) {
+  const uint32_t slot_addr =
+      __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void_t *)(lds + slot * slot_bytes));
+#pragma unroll
+  for (int m = 0; m < PhasePlan<CB, SEGS, NW>::J; ++m) {
+    const bool chan_ok = d.ok[m] && cb + d.cc[m] < a.n_chan;  // wave-uniform
+    const int c = __builtin_amdgcn_readfirstlane(min(cb + d.cc[m], a.n_chan - 1));
+    // first staged byte of the row (a multiple of 16) and the bytes of the row from there on
+    const int64_t row0 = chan_ok ? t0 + base_in[m] : 0;
+    const int64_t left = a.n_samp - row0;
+    const int bytes = chan_ok && left > 0 ? (int)min(left, (int64_t)0x7fffffff) : 0;
+    const v4i_t rs = make_rsrc(a.x + (int64_t)c * a.pitch + row0, bytes);
+    const uint32_t dst = d.ok[m] ? slot_addr + d.lds_off[m] : sink_addr;
+    const uint32_t copy_step = d.ok[m] ? (uint32_t)a.row_bytes : 0u;  // padding: all four into the sink
+    if (d.lane_ok[m]) {
+#pragma unroll
+      for (int ph = 0; ph < 4; ++ph) dma16(rs, d.voff[m] + ph, dst + ph * copy_step);
+    }
+  }
+}
+
+// Stage bases of this wave's channels of block `cb` (scalar loads, one block early).
+template <int CB, int SEGS, int NW>
+__device__ __forceinline__ void phase_bases(const IntArgs &a, const int32_t *sb, int cb,
+                                            const PhasePlan<CB, SEGS, NW> &d,
+                                            int32_t (&base)[PhasePlan<CB, SEGS, NW>::J]) {
+#pragma unroll
+  for (int m = 0; m < PhasePlan<CB, SEGS, NW>::J; ++m) {
+    const int c = __builtin_amdgcn_readfirstlane(min(cb + d.cc[m], a.n_chan - 1));
+    base[m] = scalar_load(sb, c);
+  }
+}
+
+template <int NS, int R, int NW, int CB, int SEGS>
+__device__ __forceinline__ void fwd_u8_phase_tile(uint8_t *lds, const IntArgs &a, int dblk, int tblk) {
+  constexpr int NWD = NS / 4;
+  constexpr int RP = R < 2 ? 2 : R;
+  constexpr int NOW = RP / 2;
+  constexpr int J = PhasePlan<CB, SEGS, NW>::J;
+  constexpr int LOADS = 4 * J;  // loads per wave and block
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t t0 = (int64_t)tblk * (64 * NS);
+  const int chan_pad = (a.n_chan + CB - 1) / CB * CB;
+  const uint32_t *woffs = a.offs + ((int64_t)dblk * NW + wave) * chan_pad * NOW;
+  const int32_t *sb = a.sbase + (int64_t)dblk * a.n_chan;
+  const int slot_bytes = CB * 4 * a.row_bytes;
+  const uint32_t sink_addr =
+      __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void_t *)(lds + kPhaseRing * slot_bytes));
+
+  uint32_t tot[R][NS], mix[R][NWD], odd[R][NWD];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) tot[r][j] = 0;
+#pragma unroll
+    for (int k = 0; k < NWD; ++k) mix[r][k] = odd[r][k] = 0;
+  }
+
+  const int nblk = chan_pad / CB;
+  const PhasePlan<CB, SEGS, NW> dp = phase_plan<CB, SEGS, NW>(a.row_bytes, wave, lane);
+  int32_t bases[J];
+#pragma unroll
+  for (int k = 0; k < kPhaseRing - 1; ++k) {
+    phase_bases<CB, SEGS, NW>(a, sb, k * CB, dp, bases);
+    phase_dma<CB, SEGS, NW>(a, dp, bases, t0, k * CB, lds, slot_bytes, k, sink_addr);
+  }
+  phase_bases<CB, SEGS, NW>(a, sb, (kPhaseRing - 1) * CB, dp, bases);
+  uint32_t ow[CB * NOW];
+#pragma unroll
+  for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, q);
+
+  const uint8_t *lane_base = lds + 4 * lane;
+  int since_flush = 0;
+  for (int b = 0; b < nblk; ++b) {
+    // This wave's loads of block b have landed; after the barrier every
+    // wave's have, and no wave reads the slot of block b - 1 any more, which
+    // the loads of block b + kPhaseRing - 1 then fill.
+    wait_vmcnt<(kPhaseRing - 2) * LOADS>();
+    lds_barrier();
+    phase_dma<CB, SEGS, NW>(a, dp, bases, t0, (b + kPhaseRing - 1) * CB, lds, slot_bytes,
+                            (b + kPhaseRing - 1) % kPhaseRing, sink_addr);  // zeros past the last channel
+    const uint8_t *blk = lane_base + (b % kPhaseRing) * slot_bytes;
+    // The table entry is the window's byte offset from the slot start; lane i
+    // owns words i, i+64, ... of the window (conflict-free ds_read2st64).
+    auto read_chan = [&](int cc, uint32_t (&dst)[R][NWD]) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t e = (ow[cc * NOW + (r >> 1)] >> (16 * (r & 1))) & 0xFFFFu;
+        const uint32_t *p = (const uint32_t *)(blk + e);
+#pragma unroll
+        for (int k = 0; k < NWD; ++k) dst[r][k] = p[64 * k];
+      }
+    };
+    uint32_t wp[2][2][R][NWD];  // channel pairs: the pair after the one being summed is in flight
+    read_chan(0, wp[0][0]);
+    read_chan(1, wp[0][1]);
+#pragma unroll
+    for (int pc = 0; pc < CB / 2; ++pc) {
+      if (2 * pc + 2 < CB) {
+        read_chan(2 * pc + 2, wp[(pc + 1) & 1][0]);
+        read_chan(2 * pc + 3, wp[(pc + 1) & 1][1]);
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int k = 0; k < NWD; ++k) {
+            const uint32_t w = wp[pc & 1][h][r][k];
+            mix[r][k] += w;
+            odd[r][k] += __builtin_amdgcn_perm(w, w, kOddSel);
+          }
+      if (2 * pc + 2 < CB) {
+        __builtin_amdgcn_sched_group_barrier(0x100, R * NWD, 0);      // DS reads: the next pair
+        __builtin_amdgcn_sched_group_barrier(0x002, 8 * R * NWD, 0);  // VALU: this pair's adds
+      }
+    }
+    since_flush += CB;
+    if (since_flush >= 256 || b + 1 == nblk) {
+      flush<NS, R>(mix, odd, tot);
+      since_flush = 0;
+    }
+    const int oi = __builtin_amdgcn_readfirstlane(min(b + 1, nblk - 1) * CB * NOW);
+#pragma unroll
+    for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, oi + q);
+    phase_bases<CB, SEGS, NW>(a, sb, (b + kPhaseRing) * CB, dp, bases);
+  }
+  wait_vmcnt<0>();  // the trailing loads must land before the LDS is reused
+  lds_barrier();
+
+  const int d0 = dblk * (NW * R) + wave * R;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int d = d0 + r;
+    if (d >= a.n_dm) break;
+    float *orow = a.out + (int64_t)d * a.out_pitch;
+#pragma unroll
+    for (int k = 0; k < NS / 4; ++k) {
+      const int64_t t = t0 + 4 * (int64_t)(lane + 64 * k);
+      if (t + 3 < a.n_out) {
+        *(float4 *)(orow + t) = make_float4((float)tot[r][4 * k], (float)tot[r][4 * k + 1], (float)tot[r][4 * k + 2],
+                                            (float)tot[r][4 * k + 3]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (t + i < a.n_out) orow[t + i] = (float)tot[r][4 * k + i];
+      }
+    }
+  }
+}
+
+// One tile of either staging form: SEGS == 0 is the ring form (fwd_int_tile),
+// SEGS > 0 the phase-load form for 8-bit input with at most SEGS 1 KiB load
+// segments per copy row.
+template <int NS, int R, int NW, int CB, int SEGS, int BITS>
+__device__ __forceinline__ void int_tile(uint8_t *lds, const IntArgs &a, int dblk, int tblk) {
+  if constexpr (SEGS == 0)
+    fwd_int_tile<NS, R, NW, CB, BITS>(lds, a, dblk, tblk);
+  else
+    fwd_u8_phase_tile<NS, R, NW, CB, SEGS>(lds, a, dblk, tblk);
+}
+
 // One workgroup per tile; 1-D grid of n_dblk * n_tiles workgroups.
-template <int NS, int R, int NW, int CB, int BITS>
+template <int NS, int R, int NW, int CB, int SEGS, int BITS>
 __global__ __launch_bounds__(NW * 64) void fwd_int_kernel(IntArgs a, int n_dblk, int n_tiles, int order) {
   extern __shared__ __align__(16) uint8_t lds[];
   int dblk, tblk;
   tile_of(blockIdx.x, n_dblk, n_tiles, order, dblk, tblk);
-  fwd_int_tile<NS, R, NW, CB, BITS>(lds, a, dblk, tblk);
+  int_tile<NS, R, NW, CB, SEGS, BITS>(lds, a, dblk, tblk);
 }
 
 __global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0ull; }
@@ -547,7 +796,7 @@ __global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0
 // A workgroup returns at its first claim past the last item: every wave
 // reaches the exit.  Between items no extra barrier is needed for the LDS: a
 // tile ends with all of its LDS reads complete behind its final barrier.
-template <int NS, int R, int NW, int CB, int BITS>
+template <int NS, int R, int NW, int CB, int SEGS, int BITS>
 __global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc *__restrict__ beams, int n_beams,
                                                                    long long n_items,
                                                                    unsigned long long *__restrict__ counter) {
@@ -580,8 +829,9 @@ __global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc
     a.n_chan = b.n_chan;
     a.n_dm = b.n_dm;
     a.row_bytes = b.row_bytes;
+    a.out_mode = kOutFloat;
 
-    fwd_int_tile<NS, R, NW, CB, BITS>(lds, a, dblk, tblk);
+    int_tile<NS, R, NW, CB, SEGS, BITS>(lds, a, dblk, tblk);
     if (threadIdx.x == 0) claimed = (long long)next;
     lds_barrier();  // publishes the claim; the tile's stores may still be in flight
     item = claimed;  // read before this wave's first barrier of the next tile; rewritten only after it
@@ -589,19 +839,24 @@ __global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc
 }
 
 // Compiled tile shapes (samples per lane, DM rows per wave, waves, channels
-// per LDS stage), in the order the plan tries them.
+// per LDS stage, staging form: 0 = raw ring + phase build, any input; S > 0 =
+// phase loads, 8-bit input, copy rows of at most S KiB), in the order the
+// plan tries them.
 #define DD_INT_SHAPES(X)                                                                                    \
-  X(16, 2, 16, 8) X(16, 4, 8, 8) X(16, 2, 16, 4) X(16, 4, 8, 4) X(16, 1, 16, 8) X(16, 1, 16, 4) X(16, 1, 16, 2) \
-  X(16, 1, 16, 1) X(16, 1, 4, 1) X(16, 1, 1, 1) X(8, 2, 16, 8) X(16, 2, 8, 4) X(8, 4, 16, 8)
+  X(16, 2, 16, 8, 0) X(16, 4, 8, 8, 0) X(16, 2, 16, 4, 0) X(16, 4, 8, 4, 0) X(16, 1, 16, 8, 0)             \
+  X(16, 1, 16, 4, 0) X(16, 1, 16, 2, 0) X(16, 1, 16, 1, 0) X(16, 1, 4, 1, 0) X(16, 1, 1, 1, 0)             \
+  X(8, 2, 16, 8, 0) X(16, 2, 8, 4, 0) X(8, 4, 16, 8, 0)                                                    \
+  X(16, 2, 16, 8, 2) X(16, 2, 16, 4, 2) X(16, 2, 8, 4, 2) X(16, 2, 16, 4, 4)
 
-template <int NS, int R, int NW, int CB>
-int launch_int_shape(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, hipStream_t st,
-                     int64_t out_limit) {
+template <int NS, int R, int NW, int CB, int SEGS>
+int launch_int_shape(const dd_plan &p, const void *tables, const void *d_in, float *d_out, int64_t out_pitch,
+                     hipStream_t st, int64_t out_limit, int out_mode) {
   const TileCfg &t = p.fwd;
+  const TableLayout L = table_layout(p);
   IntArgs a;
   a.x = (const uint8_t *)d_in;
-  a.offs = (const uint32_t *)((const uint8_t *)p.d_tables + p.int_offs_off);
-  a.sbase = (const int32_t *)((const uint8_t *)p.d_tables + p.int_sbase_off);
+  a.offs = (const uint32_t *)((const uint8_t *)tables + L.int_offs);
+  a.sbase = (const int32_t *)((const uint8_t *)tables + L.int_sbase);
   a.out = d_out;
   a.pitch = p.in_pitch_bytes;
   a.n_samp = p.desc.n_samp;
@@ -610,54 +865,69 @@ int launch_int_shape(const dd_plan &p, const void *d_in, float *d_out, int64_t o
   a.n_chan = p.desc.n_chan;
   a.n_dm = p.desc.n_dm;
   a.row_bytes = t.row_bytes;
+  a.out_mode = out_mode;
   const int64_t tiles_t = (a.n_out + 64 * NS - 1) / (64 * NS);
   const int64_t n_dblk = (p.desc.n_dm + NW * R - 1) / (NW * R);
   if (tiles_t * n_dblk >= ((int64_t)1 << 31)) return (int)hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)(tiles_t * n_dblk)), block(NW * 64);
   const int bits = p.desc.dtype == DD_U4 ? 4 : p.desc.dtype == DD_U16 ? 16 : 8;
-  const void *fn = bits == 4    ? (const void *)fwd_int_kernel<NS, R, NW, CB, 4>
-                   : bits == 16 ? (const void *)fwd_int_kernel<NS, R, NW, CB, 16>
-                                : (const void *)fwd_int_kernel<NS, R, NW, CB, 8>;
-  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, t.lds_bytes);
-  if (e != hipSuccess) return (int)e;
-  if (bits == 4)
-    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, 4>), grid, block, t.lds_bytes, st, a, (int)n_dblk, (int)tiles_t,
-                       t.order);
-  else if (bits == 16)
-    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, 16>), grid, block, t.lds_bytes, st, a, (int)n_dblk,
+  if constexpr (SEGS > 0) {  // phase loads: 8-bit input only, copy rows within SEGS KiB
+    if (bits != 8 || t.row_bytes > 1024 * SEGS) return (int)hipErrorInvalidValue;
+    const void *fn = (const void *)fwd_int_kernel<NS, R, NW, CB, SEGS, 8>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, t.lds_bytes);
+    if (e != hipSuccess) return (int)e;
+    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, SEGS, 8>), grid, block, t.lds_bytes, st, a, (int)n_dblk,
                        (int)tiles_t, t.order);
-  else
-    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, 8>), grid, block, t.lds_bytes, st, a, (int)n_dblk, (int)tiles_t,
-                       t.order);
-  return (int)hipGetLastError();
+    return (int)hipGetLastError();
+  } else {
+    const void *fn = bits == 4    ? (const void *)fwd_int_kernel<NS, R, NW, CB, 0, 4>
+                     : bits == 16 ? (const void *)fwd_int_kernel<NS, R, NW, CB, 0, 16>
+                                  : (const void *)fwd_int_kernel<NS, R, NW, CB, 0, 8>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, t.lds_bytes);
+    if (e != hipSuccess) return (int)e;
+    if (bits == 4)
+      hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, 0, 4>), grid, block, t.lds_bytes, st, a, (int)n_dblk,
+                         (int)tiles_t, t.order);
+    else if (bits == 16)
+      hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, 0, 16>), grid, block, t.lds_bytes, st, a, (int)n_dblk,
+                         (int)tiles_t, t.order);
+    else
+      hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, 0, 8>), grid, block, t.lds_bytes, st, a, (int)n_dblk,
+                         (int)tiles_t, t.order);
+    return (int)hipGetLastError();
+  }
 }
 
 }  // namespace
 
-#define DD_ROW(NS, R, NW, CB) {NS, R, NW, CB},
-const int kIntShapes[][4] = {DD_INT_SHAPES(DD_ROW)};
+#define DD_ROW(NS, R, NW, CB, SEGS) {NS, R, NW, CB, SEGS},
+const int kIntShapes[][5] = {DD_INT_SHAPES(DD_ROW)};
 #undef DD_ROW
 const int kNumIntShapes = (int)(sizeof(kIntShapes) / sizeof(kIntShapes[0]));
 
-int launch_forward_int(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream,
-                       int64_t out_limit) {
+int launch_forward_int(const dd_plan &p, const void *tables, const void *d_in, float *d_out, int64_t out_pitch,
+                       void *stream, int64_t out_limit, int out_mode) {
   const TileCfg &t = p.fwd;
-  if (is_direct(t)) return launch_forward_direct(p, d_in, d_out, out_pitch, stream, out_limit);
-#define DD_TRY(NS, R, NW, CB)                                                       \
-  if (t.ns == NS && t.dm_per_wave == R && t.waves == NW && t.chan_block == CB)     \
-    return launch_int_shape<NS, R, NW, CB>(p, d_in, d_out, out_pitch, (hipStream_t)stream, out_limit);
+  if (out_mode != kOutFloat && p.desc.dtype != DD_U16) return (int)hipErrorInvalidValue;
+  if (is_direct(t)) return launch_forward_direct(p, tables, d_in, d_out, out_pitch, stream, out_limit, out_mode);
+#define DD_TRY(NS, R, NW, CB, SEGS)                                                                    \
+  if (t.ns == NS && t.dm_per_wave == R && t.waves == NW && t.chan_block == CB && t.segs == SEGS)       \
+    return launch_int_shape<NS, R, NW, CB, SEGS>(p, tables, d_in, d_out, out_pitch, (hipStream_t)stream, out_limit, \
+                                                 out_mode);
   DD_INT_SHAPES(DD_TRY)
 #undef DD_TRY
   return (int)hipErrorInvalidValue;
 }
 
-int batch_kernels(int ns, int dm_per_wave, int waves, int chan_block, int dtype, int lds_bytes, BatchLaunch *out) {
+int batch_kernels(int ns, int dm_per_wave, int waves, int chan_block, int segs, int dtype, int lds_bytes,
+                  BatchLaunch *out) {
   const void *fn = nullptr;
-#define DD_TRY(NS, R, NW, CB)                                                                    \
-  if (ns == NS && dm_per_wave == R && waves == NW && chan_block == CB)                           \
-    fn = dtype == DD_U4    ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, 4>               \
-         : dtype == DD_U16 ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, 16>              \
-                           : (const void *)fwd_int_batched_kernel<NS, R, NW, CB, 8>;
+#define DD_TRY(NS, R, NW, CB, SEGS)                                                                        \
+  if (ns == NS && dm_per_wave == R && waves == NW && chan_block == CB && segs == SEGS)                     \
+    fn = SEGS > 0 ? (dtype == DD_U8 ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, SEGS, 8> : nullptr) \
+         : dtype == DD_U4  ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, 0, 4>                     \
+         : dtype == DD_U16 ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, 0, 16>                    \
+                           : (const void *)fwd_int_batched_kernel<NS, R, NW, CB, 0, 8>;
   DD_INT_SHAPES(DD_TRY)
 #undef DD_TRY
   if (!fn) return (int)hipErrorInvalidValue;

@@ -289,13 +289,14 @@ const int kF32Shapes[][4] = {DD_F32_SHAPES(DD_ROW)};
 #undef DD_ROW
 const int kNumF32Shapes = (int)(sizeof(kF32Shapes) / sizeof(kF32Shapes[0]));
 
-int launch_forward_f32(const dd_plan &p, const void *d_in, float *d_out, int64_t out_pitch, void *stream,
-                       int64_t out_limit) {
+int launch_forward_f32(const dd_plan &p, const void *tables, const void *d_in, float *d_out, int64_t out_pitch,
+                       void *stream, int64_t out_limit) {
   const FloatTables &t = p.ftab_fwd;
+  const TableLayout L = table_layout(p);
   FArgs a;
   a.x = (const float *)d_in;
-  a.offs = (const uint32_t *)((const uint8_t *)p.d_tables + t.offs_off);
-  a.sbase = (const int32_t *)((const uint8_t *)p.d_tables + t.sbase_off);
+  a.offs = (const uint32_t *)((const uint8_t *)tables + L.f_offs[0]);
+  a.sbase = (const int32_t *)((const uint8_t *)tables + L.f_sbase[0]);
   a.out = d_out;
   a.row_pitch = p.in_pitch_bytes / 4;
   a.out_pitch = out_pitch;
@@ -307,13 +308,14 @@ int launch_forward_f32(const dd_plan &p, const void *d_in, float *d_out, int64_t
   return launch_f32(t, a, out_limit, (hipStream_t)stream);
 }
 
-int launch_adjoint(const dd_plan &p, const float *d_y, int64_t y_pitch, float *d_grad, void *stream,
-                   int64_t out_limit) {
+int launch_adjoint(const dd_plan &p, const void *tables, const float *d_y, int64_t y_pitch, float *d_grad,
+                   void *stream, int64_t out_limit) {
   const FloatTables &t = p.ftab_adj;
+  const TableLayout L = table_layout(p);
   FArgs a;
   a.x = d_y;
-  a.offs = (const uint32_t *)((const uint8_t *)p.d_tables + t.offs_off);
-  a.sbase = (const int32_t *)((const uint8_t *)p.d_tables + t.sbase_off);
+  a.offs = (const uint32_t *)((const uint8_t *)tables + L.f_offs[1]);
+  a.sbase = (const int32_t *)((const uint8_t *)tables + L.f_sbase[1]);
   a.out = d_grad;
   a.row_pitch = y_pitch;
   a.out_pitch = p.in_pitch_bytes / 4;

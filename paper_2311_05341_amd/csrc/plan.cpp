@@ -119,26 +119,40 @@ static int round_up(int64_t v, int a) { return (int)((v + a - 1) / a * a); }
 // for 16-bit samples (byte offset 2v) two copies,
 // (v % 2) * row_bytes + 2 * (v - v % 2).
 // Fails with DD_ERR_RANGE if even one channel per LDS stage does not fit.
-dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves, int chan_block, int lds_limit,
-                           IntTables *t) {
+dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves, int chan_block, int segs,
+                           int lds_limit, IntTables *t) {
   const int nc = p.desc.n_chan, nd = p.desc.n_dm;
   const int dblk = waves * dm_per_wave;
   const bool u16 = p.desc.dtype == DD_U16;
   const int unit = p.desc.dtype == DD_U4 ? 32 : u16 ? 8 : 16;
   const int copies = u16 ? 2 : 4;
+  const bool phase = segs > 0;  // 8-bit phase-load staging
+  if (phase && p.desc.dtype != DD_U8) return fail(DD_ERR_RANGE, "phase-load staging is for 8-bit input");
   const int span = max_dm_block_span(p, dblk);
-  const int64_t rs = (int64_t)64 * ns + span + unit + 16;  // samples of a staged row
+  // samples of a staged row: the tile, the spread, the rounding of the stage base
+  // (ring form: and the extra word the phase build reads past a chunk)
+  const int64_t rs = (int64_t)64 * ns + span + unit + (phase ? 0 : 16);
   if (rs > (1 << 23)) return fail(DD_ERR_RANGE, "delay spread too large");
   t->row_bytes = u16 ? round_up(2 * rs, 16) : round_up(rs, unit);
-  // LDS: two buffers of the shifted copies, a ring of 3 raw slots (rows of raw
-  // bytes + 16), 1 KB of scratch.  Loads per block: 1 KB segments of raw rows.
-  const int raw = p.desc.dtype == DD_U4 ? t->row_bytes / 2 : t->row_bytes;
-  const int64_t lds =
-      (int64_t)2 * chan_block * copies * t->row_bytes + (int64_t)3 * chan_block * (raw + 16) + 1024;
+  int64_t lds;
+  if (phase) {
+    // LDS: kPhaseSlots slots of chan_block x 4 copies, 1 KB load sink; a copy row
+    // is loaded in at most `segs` 1 KB segments; entries are slot offsets
+    lds = (int64_t)kPhaseSlots * chan_block * 4 * t->row_bytes + 1024;
+    if ((t->row_bytes + 1023) / 1024 > segs) return fail(DD_ERR_RANGE, "staged rows longer than the shape's loads");
+    if ((int64_t)chan_block * 4 * t->row_bytes > 65536)
+      return fail(DD_ERR_RANGE, "staging slot too large for 16-bit LDS offsets");
+  } else {
+    // LDS: two buffers of the shifted copies, a ring of 3 raw slots (rows of raw
+    // bytes + 16), 1 KB of scratch.  Loads per block: 1 KB segments of raw rows.
+    const int raw = p.desc.dtype == DD_U4 ? t->row_bytes / 2 : t->row_bytes;
+    lds = (int64_t)2 * chan_block * copies * t->row_bytes + (int64_t)3 * chan_block * (raw + 16) + 1024;
+    if (chan_block * ((raw + 1023) / 1024) > 16) return fail(DD_ERR_RANGE, "too many staging segments");  // kStageSegs
+    if ((int64_t)copies * t->row_bytes > 65536) return fail(DD_ERR_RANGE, "staged rows too long for 16-bit LDS offsets");
+  }
   if (lds > lds_limit) return fail(DD_ERR_RANGE, "staged channel block exceeds LDS");
-  if (chan_block * ((raw + 1023) / 1024) > 16) return fail(DD_ERR_RANGE, "too many staging segments");  // kStageSegs
-  if ((int64_t)copies * t->row_bytes > 65536) return fail(DD_ERR_RANGE, "staged rows too long for 16-bit LDS offsets");
   t->chan_block = chan_block;
+  t->segs = segs;
   t->lds_bytes = (int)lds;
   const int n_dblk = (nd + dblk - 1) / dblk;
   const int rp = dm_per_wave < 2 ? 2 : dm_per_wave;  // uint16 slots per channel (whole 32-bit words)
@@ -162,8 +176,9 @@ dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves,
           // window offset v (samples) inside the staged row -> byte offset of
           // its first word inside the channel's shifted copies
           const int32_t v = sd[c] - sb[c];
+          const int32_t slot = phase ? (c % chan_block) * 4 * t->row_bytes : 0;  // channel's copies in the slot
           o[(size_t)c * rp] = u16 ? (uint16_t)((v & 1) * t->row_bytes + 2 * (v & ~1))
-                                  : (uint16_t)((v & 3) * t->row_bytes + (v & ~3));
+                                  : (uint16_t)(slot + (v & 3) * t->row_bytes + (v & ~3));
         }
       }
   }
@@ -278,12 +293,13 @@ dd_status set_tiles(dd_plan &p, int direction, int shape, int order) {
     p.itab = IntTables();
     return DD_OK;
   }
-  const dd_status st = build_int_tables(p, k[0], k[1], k[2], k[3], kLdsLimit, &tab);
+  const dd_status st = build_int_tables(p, k[0], k[1], k[2], k[3], int_shape_segs(shape), kLdsLimit, &tab);
   if (st != DD_OK) return st;
   t.ns = k[0];
   t.dm_per_wave = k[1];
   t.waves = k[2];
   t.chan_block = k[3];
+  t.segs = tab.segs;
   t.row_bytes = tab.row_bytes;
   t.lds_bytes = tab.lds_bytes;
   p.fwd = t;
@@ -292,9 +308,10 @@ dd_status set_tiles(dd_plan &p, int direction, int shape, int order) {
   return DD_OK;
 }
 
-// Default tiles: the first compiled shape (they are listed fastest first) that
-// holds the plan's delay spread, in the grouped workgroup order (as fast as
-// time tiles fastest on the headline plan, with a third of its L2 fetch traffic).
+// Default tiles: the first compiled shape (they are listed fastest first; for
+// 8-bit plans the phase-load shapes before the others) that holds the plan's
+// delay spread, in the grouped workgroup order (as fast as time tiles fastest
+// on the headline plan, with a third of its L2 fetch traffic).
 // For an integer plan whose spread leaves only LDS shapes staging 1 or 2
 // channels at a time, the direct-read kernel is faster (measured: 12.7 against
 // 8.5-10 Tadds/s at 264-395 samples of delay per DM step) and is chosen.
@@ -302,10 +319,13 @@ dd_status choose_forward_tiles(dd_plan &p) {
   const int dirs = p.desc.dtype == DD_F32 ? 2 : 1;
   for (int dir = 0; dir < dirs; ++dir) {
     dd_status last = DD_ERR_RANGE;
-    for (int i = 0; i < num_shapes(p); ++i) {
-      last = set_tiles(p, dir, i, kOrderDmGroups);
-      if (last == DD_OK || last == DD_ERR_NOMEM) break;
-    }
+    for (int pass = 0; pass < 2 && last != DD_OK && last != DD_ERR_NOMEM; ++pass)
+      for (int i = 0; i < num_shapes(p); ++i) {
+        const bool phase = p.desc.dtype == DD_U8 && int_shape_segs(i) > 0;
+        if (phase != (pass == 0)) continue;
+        last = set_tiles(p, dir, i, kOrderDmGroups);
+        if (last == DD_OK || last == DD_ERR_NOMEM) break;
+      }
     if (last == DD_ERR_NOMEM) return last;
     if (last != DD_OK) return fail(DD_ERR_RANGE, "delay spread exceeds every compiled staging shape");
   }
@@ -334,6 +354,23 @@ static size_t up256(size_t v) { return (v + 255) / 256 * 256; }
 
 // Device workspace layout.  Integer plans: [offs uint16][sbase int32].
 // Float plans: [forward offs][forward sbase][adjoint offs][adjoint sbase].
+TableLayout table_layout(const dd_plan &p) {
+  TableLayout L;
+  if (p.desc.dtype != DD_F32) {
+    if (!is_direct(p.fwd)) L.int_sbase = up256(p.itab.offs.size() * sizeof(uint16_t));
+    return L;
+  }
+  size_t off = 0;
+  const FloatTables *tabs[2] = {&p.ftab_fwd, &p.ftab_adj};
+  for (int k = 0; k < 2; ++k) {
+    L.f_offs[k] = off;
+    off += up256(tabs[k]->offs.size() * 2);
+    L.f_sbase[k] = off;
+    off += up256(tabs[k]->sbase.size() * 4);
+  }
+  return L;
+}
+
 size_t table_bytes(const dd_plan &p) {
   if (p.desc.dtype != DD_F32 && is_direct(p.fwd)) return up256(p.shift.size() * sizeof(int32_t));
   if (p.desc.dtype != DD_F32)

@@ -23,6 +23,11 @@ struct dd_survey {
   std::vector<dd_plan *> plans;     // one per range, owned
   std::vector<int> slot_factor;     // distinct binning factors > 1, in first-use order
   std::vector<int64_t> slot_pitch;  // bytes per binned row
+  // 16-bit input: every binned copy holds two uint16 planes per row, the low
+  // and the high halves of the exact bin sums, the high one split_off[k] bytes
+  // after the low one; the range's plan is a 16-bit plan over the low plane
+  bool split16 = false;
+  std::vector<int64_t> split_off;
   std::vector<size_t> slot_off;     // workspace offset of each binned copy
   std::vector<int> range_slot;      // per range: its binned copy, or -1 for the input itself
   std::vector<size_t> tab_off, tab_bytes;  // per range: its tables in the workspace
@@ -104,10 +109,26 @@ dd_status prepare_inputs(const dd_survey &s, const void *d_in, void *stream) {
   }
   const void *rows = rows_input(s, d_in);
   for (size_t k = 0; k < s.slot_factor.size(); ++k) {
-    const int e = launch_bin(s.dtype, rows, s.in_pitch, s.n_chan, s.n_samp, s.slot_factor[k], s.ws + s.slot_off[k],
-                             s.slot_pitch[k], stream);
+    const int e = s.split16 ? launch_bin_u16_split(rows, s.in_pitch, s.n_chan, s.n_samp, s.slot_factor[k],
+                                                   s.ws + s.slot_off[k], s.slot_pitch[k], s.split_off[k], stream)
+                            : launch_bin(s.dtype, rows, s.in_pitch, s.n_chan, s.n_samp, s.slot_factor[k],
+                                         s.ws + s.slot_off[k], s.slot_pitch[k], stream);
     if (e) return hip_error(e, "binning launch");
   }
+  return DD_OK;
+}
+
+// Forward transform of range r into d_out.  A binned range of 16-bit input
+// sums its low-half plane exactly into raw 32-bit totals, then its high-half
+// plane, combining both into the float32 of the exact sum.
+dd_status range_forward(const dd_survey &s, int r, const void *d_in, float *d_out, int64_t out_pitch, void *stream) {
+  const int slot = s.range_slot[r];
+  if (!s.split16 || slot < 0) return dd_execute(s.plans[r], range_input(s, r, d_in), d_out, out_pitch, stream);
+  const uint8_t *lo = s.ws + s.slot_off[slot];
+  const dd_plan &p = *s.plans[r];
+  int e = launch_forward_int(p, p.d_tables, lo, d_out, out_pitch, stream, 0, kOutRawTotals);
+  if (!e) e = launch_forward_int(p, p.d_tables, lo + s.split_off[slot], d_out, out_pitch, stream, 0, kOutCombineHigh);
+  if (e) return hip_error(e, "forward launch");
   return DD_OK;
 }
 
@@ -207,7 +228,8 @@ dd_status dd_survey_create(const dd_plan_desc *base, const dd_range *ranges, int
     s->time_major = time_major;
     s->spectrum_pitch = spitch;
     s->ranges.assign(ranges, ranges + n_ranges);
-    const int ob = bin_out_bytes(base->dtype);
+    s->split16 = base->dtype == DD_U16;
+    const int ob = s->split16 ? 2 : bin_out_bytes(base->dtype);
     size_t off = 0;
     if (time_major) {
       s->turn_off = 0;
@@ -221,9 +243,11 @@ dd_status dd_survey_create(const dd_plan_desc *base, const dd_range *ranges, int
           if (s->slot_factor[k] == f) slot = (int)k;
         if (slot < 0) {
           slot = (int)s->slot_factor.size();
-          const int64_t bp = (int64_t)round_up((size_t)(base->n_samp / f) * ob, 256);
+          const int64_t plane = (int64_t)round_up((size_t)(base->n_samp / f) * ob, 256);
+          const int64_t bp = s->split16 ? 2 * plane : plane;  // split rows: low plane, then high plane
           s->slot_factor.push_back(f);
           s->slot_pitch.push_back(bp);
+          s->split_off.push_back(s->split16 ? plane : 0);
           s->slot_off.push_back(off);
           off += round_up((size_t)bp * (size_t)base->n_chan, 256);
         }
@@ -234,7 +258,7 @@ dd_status dd_survey_create(const dd_plan_desc *base, const dd_range *ranges, int
       d.dm_step = ranges[r].dm_step;
       d.n_dm = ranges[r].n_dm;
       if (f > 1) {
-        d.dtype = dd_bin_out_dtype(base->dtype);
+        d.dtype = s->split16 ? DD_U16 : dd_bin_out_dtype(base->dtype);
         d.n_samp = base->n_samp / f;
         d.t_samp_s = base->t_samp_s * f;
         d.in_pitch_bytes = s->slot_pitch[slot];
@@ -313,7 +337,7 @@ dd_status dd_survey_execute(const dd_survey *s, const void *d_in, float *const *
   if (st != DD_OK) return st;
   st = prepare_inputs(*s, d_in, stream);
   for (size_t r = 0; r < s->plans.size() && st == DD_OK; ++r)
-    st = dd_execute(s->plans[r], range_input(*s, (int)r, d_in), d_out[r], out_pitch[r], stream);
+    st = range_forward(*s, (int)r, d_in, d_out[r], out_pitch[r], stream);
   return st;
 }
 

@@ -16,7 +16,7 @@
 
 namespace dd {
 
-static const char kCacheTag[] = "dd-tune-v1";
+static const char kCacheTag[] = "dd-tune-v2";
 static std::mutex g_cache_mutex;
 
 static const int *shape_params(const dd_plan &p, int shape) {
@@ -124,6 +124,7 @@ dd_status dd_plan_get_tiles(const dd_plan *p, int32_t dir, dd_tiles *t) {
   t->per_wave = s[1];
   t->waves = s[2];
   t->row_block = s[3];
+  t->segs = p->desc.dtype == DD_F32 ? 0 : int_shape_segs(shape);
   return DD_OK;
 }
 
@@ -169,9 +170,9 @@ dd_status dd_plan_autotune(dd_plan *p, int32_t dir, const void *src, float *dst,
     return hip_error(he, "hipEventCreate");
   }
   auto run = [&]() -> int {
-    if (dir == 1) return launch_adjoint(*p, (const float *)src, pitch, dst, stream, lim);
-    if (p->desc.dtype == DD_F32) return launch_forward_f32(*p, src, dst, pitch, stream, lim);
-    return launch_forward_int(*p, src, dst, pitch, stream, lim);
+    if (dir == 1) return launch_adjoint(*p, p->d_tables, (const float *)src, pitch, dst, stream, lim);
+    if (p->desc.dtype == DD_F32) return launch_forward_f32(*p, p->d_tables, src, dst, pitch, stream, lim);
+    return launch_forward_int(*p, p->d_tables, src, dst, pitch, stream, lim);
   };
   // Upload the current tables, warm up, then time two launches.
   auto time_current = [&](double *ms) -> dd_status {

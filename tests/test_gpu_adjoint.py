@@ -170,3 +170,67 @@ def test_autograd_exact_small_integers(dd):
         lp = ((op[dd_, uu_].double() - target[dd_, uu_].double()) ** 2).sum()
         lm = ((om[dd_, uu_].double() - target[dd_, uu_].double()) ** 2).sum()
         assert ((lp - lm) / 2.0).item() == grad[c, t].item(), (c, t)
+
+
+def test_adjoint_full_workload_sampled_channels(dd):
+    """The adjoint at the full differentiation size (1024 ch x 2^17 x 1024 DMs) against the
+    oracle's scatter form, element by element on sampled channels (every time sample of each):
+    the oracle runs on the shift sub-table of those channels, which includes the lowest channel,
+    so its N_out is the plan's.  y is N(0,1) and passed with row pitch n_out (not a multiple of 4),
+    the layout a gradient tensor arrives in."""
+    cfg = synth.CONFIGS["grad_f32"]
+    plan = plan_for(dd, cfg)
+    n_chan, n_samp = cfg["n_chan"], cfg["n_samp"]
+    assert plan.n_out % 4 != 0
+    gen = torch.Generator(device="cpu").manual_seed(cfg["target_seed"] + 1)
+    y = torch.randn((cfg["n_dm"], plan.n_out), generator=gen)
+    g = plan.adjoint(y.cuda())
+    torch.cuda.synchronize()
+    s = plan.shift
+    rng = np.random.default_rng(23)
+    chans = sorted({0, 1, n_chan // 2, n_chan - 2, n_chan - 1} | {int(c) for c in rng.integers(0, n_chan, 11)})
+    sub = np.ascontiguousarray(s[:, chans])
+    yn = y.numpy()
+    want = oracle.adjoint(yn, len(chans), n_samp, sub)
+    ab = oracle.adjoint(np.abs(yn), len(chans), n_samp, sub)
+    got = g[chans].cpu().numpy().astype(np.float64)
+    err = np.abs(got - want)
+    assert (err <= 1e-5 * ab).all(), float((err / np.maximum(ab, 1e-30)).max())
+    assert (got[ab == 0] == 0).all()
+
+
+def test_autograd_pitched_view_and_no_gradient_copy(dd):
+    """DedisperseFn on a view of the first n_samp columns of a pitched buffer and on the whole
+    buffer: the gradient has the input's shape, equals the adjoint of 2 (A x - target), is zero
+    on columns past n_samp, and the incoming gradient reaches the adjoint without a copy."""
+    n_chan, n_samp, n_dm = 96, 6001, 40
+    cfg = dict(dtype="f32", n_chan=n_chan, n_samp=n_samp, f_high=1500.0, chan_bw=300.0 / n_chan, t_samp=128e-6,
+               dm_start=0.0, dm_step=3.0, n_dm=n_dm)
+    pitch = 6016  # floats; 64 bytes of row padding past the last whole 16-byte chunk
+    plan = plan_for(dd, cfg, in_pitch_bytes=4 * pitch)
+    assert plan.n_out % 4 != 0
+    rng = np.random.default_rng(31)
+    base = torch.from_numpy(rng.integers(-8, 9, (n_chan, pitch)).astype(np.float32)).cuda()
+    target = torch.from_numpy(rng.integers(-8, 9, (n_dm, plan.n_out)).astype(np.float32)).cuda()
+    seen = {}
+    orig = plan.adjoint
+
+    def spy(y, out=None, stream=None):
+        seen["y"] = y.data_ptr()
+        return orig(y, out=out, stream=stream)
+    plan.adjoint = spy
+    try:
+        for cols in (n_samp, pitch):
+            leaf = base.clone().requires_grad_(True)
+            x = leaf[:, :cols]
+            out = dd.DedisperseFn.apply(x, plan)
+            out.register_hook(lambda g: seen.__setitem__("grad_out", g.data_ptr()))
+            ((out - target) ** 2).sum().backward()
+            assert seen["y"] == seen["grad_out"], "the incoming gradient was copied"
+            want = orig(2.0 * (plan.forward(base) - target)).cpu()  # exact: small integers
+            got = leaf.grad.cpu()
+            assert got.shape == (n_chan, pitch)
+            assert torch.equal(got[:, :n_samp], want)
+            assert (got[:, n_samp:] == 0).all()
+    finally:
+        plan.adjoint = orig

@@ -102,7 +102,7 @@ def test_batched_every_shape_and_autotune(dd):
     plain = [p.forward(x).clone() for p, x in zip(plans, xs)]
     batch = dd.Batch(plans, xs)
     n_ok = 0
-    for shape in range(13):
+    for shape in range(plans[0].n_shapes - 2):  # every staged shape (the two direct-read shapes come last)
         try:
             batch.set_tiles(shape)
         except dd.DDError as e:

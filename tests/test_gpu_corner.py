@@ -93,8 +93,8 @@ def _survey_args(cfg, n_samp):
 @pytest.mark.parametrize("dtype", ["u8", "u4", "u16", "f32"])
 def test_time_major_survey_small_exact(dtype, dd):
     """Spectra in, every range out: the oracle's corner turn, binning and transform. Integer
-    encodings bit for bit; float spectra (and 16-bit spectra, which bin to float sums) within
-    1e-5 of the sum of |terms|."""
+    encodings bit for bit (binned 16-bit ranges too: the oracle sums the exact 32-bit bin sums);
+    float spectra within 1e-5 of the sum of |terms|."""
     cfg = dict(synth.SURVEYS["survey_small"], dtype=dtype)
     n_chan, n_samp = cfg["n_chan"], cfg["n_samp"]
     spec = _spectra(dtype, n_chan, n_samp, seed=21)
@@ -113,10 +113,12 @@ def test_time_major_survey_small_exact(dtype, dd):
         elif dtype in ("u8", "u4"):
             xb = oracle.bin_time(rows, dtype, n_samp, b).astype(np.uint16)
             assert np.array_equal(got, oracle.forward(xb, "u16", xb.shape[1], s)), r
-        else:  # 16-bit and float rows bin to float sums
+        elif dtype == "u16":
+            xb = oracle.bin_time(rows, dtype, n_samp, b).astype(np.uint32)
+            assert np.array_equal(got, oracle.forward(xb, "u32", xb.shape[1], s)), r
+        else:  # float rows bin to float sums
             xb = oracle.bin_time(rows, dtype, n_samp, b)
-            ab_b = oracle.bin_time(np.abs(rows.astype(np.float64)).astype(np.float32) if dtype == "f32" else rows,
-                                   dtype, n_samp, b)
+            ab_b = oracle.bin_time(np.abs(rows.astype(np.float64)).astype(np.float32), dtype, n_samp, b)
             want, _ = oracle.forward_f32(np.ascontiguousarray(xb.astype(np.float32)), xb.shape[1], s)
             ab, _ = oracle.forward_f32(np.ascontiguousarray(ab_b.astype(np.float32)), xb.shape[1], s)
             assert np.all(np.abs(got.astype(np.float64) - want) <= 1e-5 * ab + 1e-30), r

@@ -342,8 +342,9 @@ def test_explicit_unordered_frequencies(dd, dtype):
     if dtype != "f32":
         want = oracle.forward(np.ascontiguousarray(x), dtype, n_samp, s)
         assert np.array_equal(got, want)
-        # the other kernel family on the same plan: direct reads if staged, a staged shape if direct
-        other = [13] if plan.tiles(0)["row_block"] > 0 else [5, 6, 7]
+        # the other kernel families on the same plan: direct reads and the ring-staged form if staged
+        # (8-bit plans stage by phase loads by default), staged shapes if direct
+        other = [plan.n_shapes - 2, 0] if plan.tiles(0)["row_block"] > 0 else [5, 6, 7]
         for shape in other:
             try:
                 plan.set_tiles(0, shape, 2)

@@ -109,19 +109,18 @@ def test_bin_zero_bins_rejected(dd):
 
 
 def _oracle_range(xh, dtype, n_samp, cfg, rng_):
-    """Oracle result of one range of an integer-input survey: (table, values, exact?).
+    """Oracle result of one range of an integer-input survey: (table, values).
 
-    Binned 16-bit input feeds the float kernel (float32 sums of exact integer
-    bins), so that range is compared within 1e-5 of its (non-negative) sum."""
+    The oracle bins exactly (int64) and sums the bins of 8- and 4-bit input as
+    16-bit samples, of 16-bit input as 32-bit samples (bin sums reach 2^24)."""
     start, step, n_dm, b = rng_
     s = oracle.shift_table(cfg["n_chan"], cfg["f_high"], cfg["chan_bw"], cfg["t_samp"] * b, start, step, n_dm)
     if b == 1:
-        return s, oracle.forward(xh, dtype, n_samp, s), True
+        return s, oracle.forward(xh, dtype, n_samp, s)
     xb = oracle.bin_time(xh, dtype, n_samp, b)
-    if dtype in ("u8", "u4"):
-        return s, oracle.forward(np.ascontiguousarray(xb.astype(np.uint16)), "u16", xb.shape[1], s), True
-    want, _ = oracle.forward_f32(np.ascontiguousarray(xb.astype(np.float32)), xb.shape[1], s)
-    return s, want, False
+    wide = "u16" if dtype in ("u8", "u4") else "u32"
+    return s, oracle.forward(np.ascontiguousarray(xb.astype(np.uint16 if wide == "u16" else np.uint32)), wide,
+                             xb.shape[1], s)
 
 
 def _survey(dd, cfg, dtype, n_samp, pitch_bytes=0):
@@ -132,7 +131,8 @@ def _survey(dd, cfg, dtype, n_samp, pitch_bytes=0):
 @pytest.mark.parametrize("dtype", ["u8", "u4", "u16"])
 def test_survey_small_exact(dtype, dd):
     """Every output of every range bit-exact: binned ranges run the 16-bit kernel on exact uint16 sums
-    (8- and 4-bit input) or the float kernel on exact float sums (16-bit input)."""
+    (8- and 4-bit input), or on the low and high uint16 halves of the exact bin sums (16-bit input)
+    combined once into the float32 of the exact total."""
     cfg = synth.SURVEYS["survey_small"]
     n_samp = cfg["n_samp"]
     row = {"u8": n_samp, "u4": n_samp // 2, "u16": 2 * n_samp}[dtype]
@@ -147,13 +147,36 @@ def test_survey_small_exact(dtype, dd):
     outs = sv.run(_to_dev(xh))
     torch.cuda.synchronize()
     for r, rg in enumerate(cfg["ranges"]):
-        s, want, exact = _oracle_range(xh, dtype, n_samp, cfg, rg)
+        s, want = _oracle_range(xh, dtype, n_samp, cfg, rg)
         assert np.array_equal(sv.shift(r), s)
-        got = outs[r].cpu().numpy()
-        if exact:
-            assert np.array_equal(got, want), r
-        else:
-            assert np.all(np.abs(got.astype(np.float64) - want) <= 1e-5 * want), r
+        assert np.array_equal(outs[r].cpu().numpy(), want), r
+
+
+def test_survey_u16_binned_exact_large_sums(dd):
+    """Binned 16-bit ranges for factors whose sums need the high plane (8, 16, 256; and 6, an even
+    factor that is not a multiple of 8), on uniform data and on all-65535 data: with bin sums up to
+    256 * 65535 and channel sums up to 72 * 256 * 65535 (far past 2^24), every output equals the
+    oracle's exact sum rounded once to float32."""
+    n_chan, n_samp = 72, 1 << 16
+    cfg = dict(n_chan=n_chan, f_high=1500.0, chan_bw=300.0 / n_chan, t_samp=64e-6)
+    ranges = [(0.0, 1.0, 16, 8), (10.0, 2.0, 16, 16), (50.0, 4.0, 8, 256), (5.0, 1.5, 12, 6)]
+    pitch = 2 * n_samp + 32
+    for seed, fill in ((41, None), (42, 65535)):
+        xh = _host("u16", n_chan, n_samp, pitch // 2, seed=seed)
+        if fill is not None:
+            xh[:, :n_samp] = fill
+        sv = dd.Survey(n_chan, n_samp, "u16", cfg["f_high"], cfg["chan_bw"], cfg["t_samp"], ranges,
+                       in_pitch_bytes=pitch)
+        assert all(ri["split_planes"] for ri in sv.range_info)
+        outs = sv.run(_to_dev(xh))
+        torch.cuda.synchronize()
+        for r, rg in enumerate(ranges):
+            s, want = _oracle_range(xh, "u16", n_samp, cfg, rg)
+            got = outs[r].cpu().numpy()
+            assert np.array_equal(got, want), (seed, r)
+        if fill is not None:  # every output is the float32 of n_chan * factor * 65535
+            for r, (_, _, _, b) in enumerate(ranges):
+                assert (outs[r] == float(np.float32(n_chan * b * 65535))).all(), r
 
 
 def test_survey_small_f32(dd):

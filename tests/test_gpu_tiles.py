@@ -109,7 +109,7 @@ def test_autotune_forward_and_cache(dd, tmp_path, monkeypatch):
     torch.cuda.synchronize()
     assert np.array_equal(got.cpu().numpy(), want)
     line = cache.read_text().strip().splitlines()[-1].split()
-    assert line[0] == "dd-tune-v1" and int(line[2]) == t["shape"] and int(line[3]) == t["order"]
+    assert line[0] == "dd-tune-v2" and int(line[2]) == t["shape"] and int(line[3]) == t["order"]
     again = plan_for(dd, cfg)
     assert again.tiles(0) == t
 

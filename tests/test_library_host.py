@@ -167,8 +167,9 @@ def test_survey_range_plans_equal_oracle(dd, dtype):
         assert np.array_equal(s.shift(r), want)
         ri = s.range_info[r]
         assert ri["n_out"] == oracle.n_out_for(want, n_samp // b) and ri["n_samp"] == n_samp // b
-        assert ri["dtype"] == (dtype if b == 1 else dd.BIN_OUT[dtype])
-        if b > 1:
+        assert ri["dtype"] == (dtype if b == 1 else dd.SURVEY_BIN_DTYPE[dtype])
+        assert ri["split_planes"] == (dtype == "u16" and b > 1)
+        if b > 1:  # binned sums: uint16 for 8/4-bit input, two uint16 planes for 16-bit, float32 for float
             need += cfg["n_chan"] * (n_samp // b) * (2 if dd.BIN_OUT[dtype] == "u16" else 4)
     assert s.workspace_bytes >= need
 
@@ -237,7 +238,7 @@ def test_large_spread_plan_uses_direct_kernel(dd):
     cfg = synth.CONFIGS["lowfreq_wide"]
     p = _plan(dd, cfg)
     t = p.tiles(0)
-    assert t["row_block"] == 0 and t["shape"] >= 13
+    assert t["row_block"] == 0 and t["shape"] >= p.n_shapes - 2  # the two direct-read shapes come last
     assert p.info.dev_table_bytes >= cfg["n_dm"] * cfg["n_chan"] * 4
     assert p.info.tune_ws_bytes >= p.info.dev_table_bytes
     for name in ["small", "headline", "lowfreq_u4", "headline_u16"]:  # narrow spreads keep LDS staging
@@ -267,19 +268,24 @@ def test_batch_tile_choice_host(dd):
         ws0 = ctypes.c_size_t()
         lib.dd_batch_workspace_bytes(h, ctypes.byref(ws0))
         first = t.shape
-        assert lib.dd_batch_set_tiles(h, 13) == -1 and lib.dd_batch_set_tiles(h, -1) == -1
-        ok = []
-        for s in range(13):
+        n_staged = plans[0].n_shapes - 2  # the staged shapes; the two direct-read shapes follow them
+        assert lib.dd_batch_set_tiles(h, n_staged) == -1 and lib.dd_batch_set_tiles(h, -1) == -1
+        ok, segs = [], {}
+        for s in range(n_staged):
             rc = lib.dd_batch_set_tiles(h, s)
             assert rc in (0, -3), rc
             lib.dd_batch_get_tiles(h, ctypes.byref(t))
             if rc == 0:
                 ok.append(s)
+                segs[s] = t.segs
                 assert t.shape == s
             ws = ctypes.c_size_t()
             lib.dd_batch_workspace_bytes(h, ctypes.byref(ws))
             assert ws.value == ws0.value
-        assert ok and ok[0] == first and len(ok) < 13  # the wide beam rules some shapes out
+        assert ok and len(ok) < n_staged  # the wide beam rules some shapes out
+        # the default: the first phase-load shape that stages every (8-bit) beam, else the first shape
+        phase_ok = [s for s in ok if segs[s] > 0]
+        assert first == (phase_ok[0] if phase_ok else ok[0])
     finally:
         lib.dd_batch_destroy(h)
 

@@ -110,18 +110,18 @@ def test_tune_cache_applied(dd, tmp_path, monkeypatch):
     path = tmp_path / "tune.txt"
     other_key = key.replace("ndm=%d" % cfg["n_dm"], "ndm=%d" % (cfg["n_dm"] + 1))
     params = "%d %d %d %d" % (t["ns"], t["per_wave"], t["waves"], t["row_block"])
-    path.write_text("dd-tune-v1 %s %d 1 %s 1.0\n" % (key, shape, params) +
-                    "dd-tune-v1 %s 0 0 %s 1.0\n" % (other_key, params) +
+    path.write_text("dd-tune-v2 %s %d 1 %s 1.0\n" % (key, shape, params) +
+                    "dd-tune-v2 %s 0 0 %s 1.0\n" % (other_key, params) +
                     "garbage line\n")
     monkeypatch.setenv("DD_TUNE_CACHE", str(path))
     p = _plan(dd, cfg)
     assert (p.tiles(0)["shape"], p.tiles(0)["order"]) == (shape, 1)
     # a line whose shape parameters disagree with the compiled shape is ignored
-    path.write_text("dd-tune-v1 %s %d 1 %d %s 1.0\n" % (key, shape, t["ns"] + 1, params.split(" ", 1)[1]))
+    path.write_text("dd-tune-v2 %s %d 1 %d %s 1.0\n" % (key, shape, t["ns"] + 1, params.split(" ", 1)[1]))
     p = _plan(dd, cfg)
     assert p.tiles(0)["order"] == 2
     # a different plan does not pick up the line
-    path.write_text("dd-tune-v1 %s %d 1 %s 1.0\n" % (key, shape, params))
+    path.write_text("dd-tune-v2 %s %d 1 %s 1.0\n" % (key, shape, params))
     p = _plan(dd, cfg, n_dm=cfg["n_dm"] - 1)
     assert p.tiles(0)["order"] == 2
     monkeypatch.delenv("DD_TUNE_CACHE")
