@@ -166,6 +166,44 @@ class SysfsClocks:
         return rep or None
 
 
+# Which microbenchmarked rate prices each input type's accumulate loop: the VALU
+# form it issues and the LDS read instruction it reads windows with.
+# (Float input adds with v_add_f32, priced at the measured v_add_u32 issue rate: both
+# are single-rate 32-bit VALU operations.)
+MEASURED_FORM = {"u8": "swar_pair_8bit", "u4": "swar_pair_8bit", "u16": "v_add3_u32", "f32": "v_add_u32"}
+MEASURED_LDS = "ds_read2st64_b32"
+
+
+def attach_measured_peaks(rec, dd, torch, dtype):
+    """Run the microbenchmarks (libddmb.so) and put the measured rates beside the datasheet
+    denominators: the VALU rate of the accumulate loop's own instruction form (sample-adds per
+    second) and the LDS read bandwidth of the read instruction it uses."""
+    from paper_2311_05341_amd import microbench
+    clocks = rec.get("clocks") or {}
+    sclk = None
+    for card in clocks.values():
+        if "sclk_mhz" in card:
+            sclk = card["sclk_mhz"]["median"] * 1e6
+            break
+    mb = microbench.measure(torch, sclk_hz=sclk)
+    rec["microbench"] = mb
+    achieved = rec["roofline"]["achieved"]
+    form = mb["valu"][MEASURED_FORM[dtype]]
+    if dtype == "u16":
+        # 4 sample-adds per one v_add3_u32 and two SDWA adds, each at its own measured rate
+        r_a = mb["valu"]["v_add3_u32"]["lane_ops_per_s"]
+        r_s = mb["valu"]["v_add_u32_sdwa"]["lane_ops_per_s"]
+        peak = 4.0 / (1.0 / r_a + 2.0 / r_s) / 1e12
+    else:
+        peak = form["sample_adds_per_s"] / 1e12
+    rec["roofline"]["peak_measured_instruction_form"] = peak
+    rec["roofline"]["frac_measured_instruction_form"] = achieved / peak
+    lds = mb["lds"][MEASURED_LDS]["bytes_per_s"] / 1e12
+    rec["lds_roofline"]["peak_measured"] = lds
+    rec["lds_roofline"]["peak_measured_instruction"] = MEASURED_LDS
+    rec["lds_roofline"]["frac_measured"] = rec["lds_roofline"]["achieved"] / lds
+
+
 def measured_traffic(workload, tiles):
     """Memory traffic per launch from a committed rocprofv3 counter summary.
 
@@ -662,6 +700,8 @@ def main():
                     help="run one 1 GiB device copy first, as a known-size reference for memory counters")
     ap.add_argument("--autotune", action="store_true",
                     help="headline: autotune the tiles first (its default shape is the tuner's pick there)")
+    ap.add_argument("--no-microbench", action="store_true",
+                    help="skip the measured VALU/LDS/HBM rates reported beside the datasheet peaks")
     ap.add_argument("--no-extras", action="store_true",
                     help="headline: skip the adjoint-vs-forward and batched-vs-plain records")
     args = ap.parse_args()
@@ -790,6 +830,9 @@ def main():
         if cfg["dtype"] == "u8":
             log("tiled cpu baseline ...")
             rec["cpu_tiled"] = cpu_tiled_baseline(cfg)
+    if not args.no_microbench:
+        log("microbenchmarks (measured VALU, LDS and HBM rates) ...")
+        attach_measured_peaks(rec, dd, torch, cfg["dtype"])
     if args.workload == "headline" and not args.adjoint and not args.no_extras:
         # the rest of the metric: the adjoint and the batched form against the plain forward, same GPU
         del x, out

@@ -194,12 +194,15 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 typedef int v4i_t __attribute__((ext_vector_type(4)));
 
 // Raw buffer descriptor over [base, base + bytes): reads past the end return 0.
+// The arguments are wave-uniform; readfirstlane keeps the descriptor in SGPRs
+// (the inline-asm loads take it as an "s" operand) even where the compiler
+// computed a part of it with vector instructions.
 __device__ __forceinline__ v4i_t make_rsrc(const void *base, int bytes) {
   const uint64_t a = (uint64_t)base;
   v4i_t r;
-  r.x = (int)(uint32_t)a;
-  r.y = (int)(uint32_t)(a >> 32);  // stride 0
-  r.z = bytes;
+  r.x = __builtin_amdgcn_readfirstlane((int)(uint32_t)a);
+  r.y = __builtin_amdgcn_readfirstlane((int)(uint32_t)(a >> 32));  // stride 0
+  r.z = __builtin_amdgcn_readfirstlane(bytes);
   r.w = kBufferRsrcFlags;
   return r;
 }
@@ -563,14 +566,20 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
 // 8-bit staging by phase loads.  The four byte-phase copies of a staged row are
 // loaded straight from memory into LDS, copy p from byte p of the row on
 // (16-byte loads at byte offsets that are not multiples of 4; the memory
-// pipeline handles them, and each (channel, block) gets a buffer descriptor
-// based at its first staged byte whose record bound ends at the row's last
-// sample, so bytes past the row read as zero).  No phase-building pass, no raw
-// ring: channel blocks stream through kPhaseRing slots of CB channels x 4
-// copies, kPhaseRing - 1 blocks ahead of the summation, with one barrier per
-// block.  The table entry of a (channel, DM row) is the byte offset of its
-// window's first word from the start of the slot, so the summation needs one
-// address add per (channel, row).
+// pipeline handles them).  Each (channel, block) gets a buffer descriptor
+// based at its first staged byte whose record bound ends at the row length
+// rounded up to 16 bytes (inside the row pitch), so nothing past the pitch is
+// read.  The bound is checked per 32-bit word of a load: copy 0's words are
+// aligned and all arrive, but in copies 1..3 the one word that straddles the
+// bound reads as zero although its first 4 - p bytes lie inside it.  Where a
+// staged row reaches that far (the last time tiles), the wave that loaded the
+// word rebuilds it from copy 0's last word (a byte shift) before the block's
+// barrier.  No phase-building pass, no raw ring: channel blocks stream through
+// kPhaseRing slots of CB channels x 4 copies, kPhaseRing - 1 blocks ahead of
+// the summation, with one barrier per block.  The table entry of a (channel, DM
+// row) is the byte offset of its window's first word from the start of the
+// slot (padding channels past the last: their own zero row), so the summation
+// needs one address add per (channel, row).
 //
 // Loads per block: each of the CB * SEGS (channel, 1 KiB segment) pairs issues
 // its four phase loads from one wave; pair j goes to wave j % NW, so every wave
@@ -589,6 +598,7 @@ struct PhasePlan {
   bool ok[J];          // a real pair (wave-uniform)
   uint32_t lds_off[J];  // LDS byte offset of the pair's copy 0 segment inside a slot
   uint32_t voff[J];    // this lane's byte offset in the staged row, copy 0
+  int seg0[J];         // first byte of the pair's segment in the staged row
   bool lane_ok[J];     // this lane's 16 bytes lie inside the copy (true for padding)
 };
 
@@ -603,6 +613,7 @@ __device__ __forceinline__ PhasePlan<CB, SEGS, NW> phase_plan(int row_bytes, int
     d.cc[m] = d.ok[m] ? cc : 0;
     d.lds_off[m] = d.ok[m] ? (uint32_t)(cc * 4 * row_bytes + 1024 * seg) : 0u;
     d.voff[m] = (uint32_t)(1024 * seg + 16 * lane);
+    d.seg0[m] = 1024 * seg;
     d.lane_ok[m] = !d.ok[m] || 1024 * seg + 16 * lane < row_bytes;
   }
   return d;
@@ -620,9 +631,10 @@ __device__ __forceinline__ void phase_dma(const IntArgs &a, const PhasePlan<CB, 
   for (int m = 0; m < PhasePlan<CB, SEGS, NW>::J; ++m) {
     const bool chan_ok = d.ok[m] && cb + d.cc[m] < a.n_chan;  // wave-uniform
     const int c = __builtin_amdgcn_readfirstlane(min(cb + d.cc[m], a.n_chan - 1));
-    // first staged byte of the row (a multiple of 16) and the bytes of the row from there on
+    // first staged byte of the row (a multiple of 16) and the bytes from there to the
+    // row length rounded up to 16 (<= the pitch)
     const int64_t row0 = chan_ok ? t0 + base_in[m] : 0;
-    const int64_t left = a.n_samp - row0;
+    const int64_t left = ((a.n_samp + 15) & ~(int64_t)15) - row0;
     const int bytes = chan_ok && left > 0 ? (int)min(left, (int64_t)0x7fffffff) : 0;
     const v4i_t rs = make_rsrc(a.x + (int64_t)c * a.pitch + row0, bytes);
     const uint32_t dst = d.ok[m] ? slot_addr + d.lds_off[m] : sink_addr;
@@ -643,6 +655,30 @@ __device__ __forceinline__ void phase_bases(const IntArgs &a, const int32_t *sb,
   for (int m = 0; m < PhasePlan<CB, SEGS, NW>::J; ++m) {
     const int c = __builtin_amdgcn_readfirstlane(min(cb + d.cc[m], a.n_chan - 1));
     base[m] = scalar_load(sb, c);
+  }
+}
+
+// Rebuild, in copies 1..3 of this wave's channels of block `cb` (ring slot
+// `slot`), the word that straddles the load bound (see above).  Copy p's word
+// at copy position k = bound - 4 holds row bytes k + p .. k + p + 3, of which
+// those below the bound are copy 0's word at k shifted down by p bytes; the
+// rest lie past the row and feed no output.  Call after this wave's loads of
+// the block have landed and before the block's barrier.
+template <int CB, int SEGS, int NW>
+__device__ __forceinline__ void phase_fix_tail(const IntArgs &a, const PhasePlan<CB, SEGS, NW> &d, const int32_t *sb,
+                                               int64_t t0, int cb, uint8_t *lds, int slot_bytes, int slot, int lane) {
+  const int64_t bound = (a.n_samp + 15) & ~(int64_t)15;
+#pragma unroll
+  for (int m = 0; m < PhasePlan<CB, SEGS, NW>::J; ++m) {
+    const int c = cb + d.cc[m];
+    if (!d.ok[m] || c >= a.n_chan) continue;  // wave-uniform
+    const int64_t k = bound - (t0 + scalar_load(sb, c)) - 4;
+    if (k < d.seg0[m] || k >= d.seg0[m] + 1024 || k >= a.row_bytes) continue;  // not in this wave's segment
+    if (lane < 3) {
+      uint8_t *row = lds + slot * slot_bytes + d.cc[m] * 4 * a.row_bytes + k;
+      const uint32_t w0 = *(const uint32_t *)row;
+      *(uint32_t *)(row + (lane + 1) * a.row_bytes) = w0 >> (8 * (lane + 1));
+    }
   }
 }
 
@@ -686,12 +722,17 @@ __device__ __forceinline__ void fwd_u8_phase_tile(uint8_t *lds, const IntArgs &a
   for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, q);
 
   const uint8_t *lane_base = lds + 4 * lane;
+  // Does any staged row of this tile reach the word that straddles the load
+  // bound?  (Stage bases are at most the largest shift, n_samp - n_out.)
+  const bool near_end =
+      t0 + (a.n_samp - a.n_out) + a.row_bytes + 4 > ((a.n_samp + 15) & ~(int64_t)15);  // wave-uniform
   int since_flush = 0;
   for (int b = 0; b < nblk; ++b) {
     // This wave's loads of block b have landed; after the barrier every
     // wave's have, and no wave reads the slot of block b - 1 any more, which
     // the loads of block b + kPhaseRing - 1 then fill.
     wait_vmcnt<(kPhaseRing - 2) * LOADS>();
+    if (near_end) phase_fix_tail<CB, SEGS, NW>(a, dp, sb, t0, b * CB, lds, slot_bytes, b % kPhaseRing, lane);
     lds_barrier();
     phase_dma<CB, SEGS, NW>(a, dp, bases, t0, (b + kPhaseRing - 1) * CB, lds, slot_bytes,
                             (b + kPhaseRing - 1) % kPhaseRing, sink_addr);  // zeros past the last channel

@@ -156,7 +156,7 @@ dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves,
   t->lds_bytes = (int)lds;
   const int n_dblk = (nd + dblk - 1) / dblk;
   const int rp = dm_per_wave < 2 ? 2 : dm_per_wave;  // uint16 slots per channel (whole 32-bit words)
-  const int ncp = (nc + chan_block - 1) / chan_block * chan_block;  // padding channels read offset 0
+  const int ncp = (nc + chan_block - 1) / chan_block * chan_block;  // channels rounded up to whole blocks
   try {
     t->offs.assign((size_t)n_dblk * waves * ncp * rp, 0);
     t->sbase.assign((size_t)n_dblk * nc, 0);
@@ -172,10 +172,11 @@ dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves,
         const int d = std::min(b * dblk + w * dm_per_wave + r, nd - 1);
         const int32_t *sd = p.shift.data() + (size_t)d * nc;
         uint16_t *o = t->offs.data() + (((size_t)b * waves + w) * ncp) * rp + r;
-        for (int c = 0; c < nc; ++c) {
+        for (int c = 0; c < ncp; ++c) {
           // window offset v (samples) inside the staged row -> byte offset of
-          // its first word inside the channel's shifted copies
-          const int32_t v = sd[c] - sb[c];
+          // its first word inside the channel's shifted copies; padding
+          // channels (c >= nc, staged as zero rows) read their own row at 0
+          const int32_t v = c < nc ? sd[c] - sb[c] : 0;
           const int32_t slot = phase ? (c % chan_block) * 4 * t->row_bytes : 0;  // channel's copies in the slot
           o[(size_t)c * rp] = u16 ? (uint16_t)((v & 1) * t->row_bytes + 2 * (v & ~1))
                                   : (uint16_t)(slot + (v & 3) * t->row_bytes + (v & ~3));

@@ -41,6 +41,18 @@ def test_header_symbols_exported(dd):
         assert hasattr(lib, n), "missing export " + n
 
 
+def test_microbench_header_symbols_exported():
+    from paper_2311_05341_amd import microbench
+    with open(os.path.join(ROOT, "include", "ddmb.h")) as fh:
+        text = fh.read()
+    names = sorted(set(re.findall(r"\b(ddmb_[a-z_]+)\s*\(", text)))
+    assert len(names) == 5
+    lib = ctypes.CDLL(microbench.LIB)
+    for n in names:
+        assert hasattr(lib, n), "missing export " + n
+    assert lib.ddmb_valu_instructions_per_lane(5, 3) == 2 * lib.ddmb_valu_instructions_per_lane(1, 3)
+
+
 @pytest.mark.parametrize("name", ["small", "headline", "lowfreq_u4", "headline_u16", "grad_f32"])
 def test_library_table_equals_oracle(dd, name):
     cfg = synth.CONFIGS[name]
