@@ -15,7 +15,7 @@ DMs, and one autograd forward + backward step) and the 48-beam batched launch
 against the same work as plain calls.
 
   python bench.py [--steps K] [--warmup W]
-                  [--workload headline|headline_shard8|lowfreq_u4|lowfreq_wide|headline_u16|grad_f32|small|
+                  [--workload headline|headline_shard8|lowfreq_u4|headline_u4|lowfreq_wide|headline_u16|grad_f32|small|
                               batch48|tab_plans_8192|pipeline_high]
                   [--adjoint] [--time-major] [--tiles SHAPE,ORDER] [--no-cpu-baseline] [--no-autotune]
                   [--autotune] [--no-extras] [--copy-calibration]
@@ -61,6 +61,17 @@ F32_FORM = "v_add_f32 (1 add per VALU lane-op)"
 U16_FORM = ("two 16-bit samples per word, v_add3_u32 over two channels + one SDWA v_add_u32 per word "
             "(4 sample-adds per 3 VALU lane-ops)")
 FORMS = {"u8": (INT_FORM, 2), "u4": (INT_FORM, 2), "u16": (U16_FORM, 4.0 / 3.0), "f32": (F32_FORM, 1)}
+# Packed 4-bit phase-load shapes add nibbles in place: per two channel words (16 samples) two
+# v_and_b32, two v_lshrrev_b32 and two v_add3_u32; their windows are read packed (half a byte per add).
+U4_NIBBLE_FORM = ("SWAR nibbles in 32-bit words, v_and_b32 + v_lshrrev_b32 + v_add3_u32 "
+                  "(16 sample-adds per 6 VALU lane-ops)")
+
+
+def accumulate_form(dtype, tiles):
+    """(instruction form, sample-adds per VALU lane-op, LDS bytes read per add) of a kernel choice."""
+    if dtype == "u4" and tiles.get("segs", 0) > 0 and tiles.get("row_block", 0) > 0:
+        return U4_NIBBLE_FORM, 16.0 / 6.0, 0.5
+    return FORMS[dtype][0], FORMS[dtype][1], LDS_BYTES_PER_ADD[dtype]
 
 
 def log(msg):
@@ -189,7 +200,13 @@ def attach_measured_peaks(rec, dd, torch, dtype):
     rec["microbench"] = mb
     achieved = rec["roofline"]["achieved"]
     form = mb["valu"][MEASURED_FORM[dtype]]
-    if dtype == "u16":
+    if dtype == "u4" and rec["roofline"]["instruction_form"] == U4_NIBBLE_FORM:
+        # 16 sample-adds per two v_and_b32, two v_lshrrev_b32 (priced at the v_add_u32 rate: single-
+        # rate VOP2) and two v_add3_u32, each at its own measured rate
+        r_a = mb["valu"]["v_add3_u32"]["lane_ops_per_s"]
+        r_1 = mb["valu"]["v_add_u32"]["lane_ops_per_s"]
+        peak = 16.0 / (2.0 / r_a + 4.0 / r_1) / 1e12
+    elif dtype == "u16":
         # 4 sample-adds per one v_add3_u32 and two SDWA adds, each at its own measured rate
         r_a = mb["valu"]["v_add3_u32"]["lane_ops_per_s"]
         r_s = mb["valu"]["v_add_u32_sdwa"]["lane_ops_per_s"]
@@ -393,6 +410,15 @@ def setup_batch48(dd, torch, synth, n_chunks=BATCH_CHUNKS, log=log):
     return beams, chunkers, inputs, outputs, batches
 
 
+def batch_shapes(batch):
+    """Tile shapes a batch's beams run: {shape index: number of beams}."""
+    counts = {}
+    for b in range(len(batch.plans)):
+        s = batch.beam_tiles(b)["shape"]
+        counts[s] = counts.get(s, 0) + 1
+    return {str(k): v for k, v in sorted(counts.items())}
+
+
 def timed_events(torch, fn, steps, warmup):
     """Mean and median kernel time (ms) of fn() over `steps` calls, each bracketed by HIP events on
     the current stream (the stream every call here launches on)."""
@@ -465,7 +491,8 @@ def batched_vs_plain(dd, torch, synth):
     b_ms, _ = timed_events(torch, batched, 1, 1)
     p_ms, _ = timed_events(torch, plain, 1, 1)
     rec = {"workload": "batch48", "beams": len(beams), "time_chunks": len(batches), "adds": adds,
-           "batched": {"ms": b_ms, "Tadds_s": adds / b_ms / 1e9, "tiles": batches[0][1].tiles()},
+           "batched": {"ms": b_ms, "Tadds_s": adds / b_ms / 1e9, "tiles": batches[0][1].tiles(),
+                       "beams_per_shape": batch_shapes(batches[0][1])},
            "plain": {"ms": p_ms, "Tadds_s": adds / p_ms / 1e9, "calls": sum(len(c) for c in chunkers)},
            "batched_over_plain_throughput": p_ms / b_ms,
            "accuracy": "both bit-exact (integer input; tests compare every beam)"}
@@ -560,6 +587,7 @@ def bench_batch48(args, dd, torch, synth):
         "lds_roofline": {"achieved": achieved, "peak": LDS_PEAK_TBS, "unit": "TB/s", "frac": achieved / LDS_PEAK_TBS,
                          "bytes_per_add": 1},
         "batch_tiles": batches[0][1].tiles(),
+        "beams_per_shape": batch_shapes(batches[0][1]),
         "batch_autotune": tune,
     }
     if not args.no_cpu_baseline:
@@ -781,6 +809,7 @@ def main():
     k_med = float(np.median(kernel_ms))
     achieved = adds / (k_avg * 1e-3) / 1e12
     traffic, traffic_src = (None, None) if args.adjoint else measured_traffic(args.workload, tiles)
+    form = accumulate_form(cfg["dtype"], tiles)
     log("steps: kernel ms %s, wall ms/step %.3f" % (["%.3f" % v for v in kernel_ms], ms_step))
     rec = {
         "metric": "Tadds/s" + (" (adjoint)" if args.adjoint else ""),
@@ -808,12 +837,12 @@ def main():
                      "kernel": ("f32_kernel" if cfg["dtype"] == "f32" else
                                 "fwd_direct_kernel" if tiles["row_block"] == 0 else "fwd_int_kernel"),
                      "kernel_ms": k_avg, "kernel_ms_median": k_med,
-                     "instruction_form": FORMS[cfg["dtype"]][0],
-                     "peak_instruction_form": VALU_PEAK_TOPS * FORMS[cfg["dtype"]][1],
-                     "frac_instruction_form": achieved / (VALU_PEAK_TOPS * FORMS[cfg["dtype"]][1])},
-        "lds_roofline": {"achieved": achieved * LDS_BYTES_PER_ADD[cfg["dtype"]], "peak": LDS_PEAK_TBS,
-                         "unit": "TB/s", "frac": achieved * LDS_BYTES_PER_ADD[cfg["dtype"]] / LDS_PEAK_TBS,
-                         "bytes_per_add": LDS_BYTES_PER_ADD[cfg["dtype"]]},
+                     "instruction_form": form[0],
+                     "peak_instruction_form": VALU_PEAK_TOPS * form[1],
+                     "frac_instruction_form": achieved / (VALU_PEAK_TOPS * form[1])},
+        "lds_roofline": {"achieved": achieved * form[2], "peak": LDS_PEAK_TBS,
+                         "unit": "TB/s", "frac": achieved * form[2] / LDS_PEAK_TBS,
+                         "bytes_per_add": form[2]},
         "tiles": tiles,
         "autotune": tune,
         "clocks": clocks.report(),

@@ -225,30 +225,39 @@ dd_status dd_plan_autotune(dd_plan *plan, int32_t direction, const void *d_src, 
 
 /*
  * Batch of independent forward transforms ("beams"), each with its own plan
- * (channel count, length, DM plan), run as ONE persistent kernel launch that
- * pulls (beam, DM block, time tile) work items from a device counter, largest
- * items first.  The launch sequence is recorded once as a HIP graph and
- * replayed by every dd_execute_batched call.  All beams share one staged tile
- * shape: the first that stages every beam, or the one dd_batch_autotune picks.
+ * (channel count, length, DM plan), run by persistent kernel launches that pull
+ * (beam, DM block, time tile) work items from a device counter, largest items
+ * first.  Every beam has a staged tile shape of its own; the beams of one shape
+ * form a group, one persistent launch per group, the groups one after another.
+ * The launch sequence is recorded once as a HIP graph and replayed by every
+ * dd_execute_batched call.  By default a beam runs its plan's own forward tile
+ * shape (the plan's default, or what the plan was set or tuned to) when that is
+ * a staged shape, else the first staged shape that holds the beam (8-bit
+ * plans: the phase-load shapes first); dd_batch_set_tiles puts every beam on
+ * one shape and dd_batch_autotune chooses between these assignments.
  *
  * dd_batch_create: plans[0..n-1] must be integer plans (DD_U8, DD_U4 or DD_U16),
- *   all of one dtype, and outlive the batch.  Errors: DD_ERR_ARG, DD_ERR_DTYPE, DD_ERR_NOMEM.
- * dd_batch_workspace_bytes: device workspace dd_batch_bind needs.
+ *   all of one dtype, and outlive the batch.  Errors: DD_ERR_ARG, DD_ERR_DTYPE, DD_ERR_NOMEM,
+ *   DD_ERR_RANGE (a beam that no staged shape holds).
+ * dd_batch_workspace_bytes: device workspace dd_batch_bind needs (it does not depend on the shapes).
  * dd_batch_bind: d_in[b], d_out[b], out_pitch[b] as for dd_execute of plan b;
- *   d_workspace holds the work list, descriptors, the beams' tables and the
- *   counter (>= dd_batch_workspace_bytes, 16-byte aligned).  Uploads on
+ *   d_workspace holds the group counters, the beam descriptors and the beams'
+ *   tables (>= dd_batch_workspace_bytes, 16-byte aligned).  Uploads on
  *   `stream` and records the graph; re-binding re-records it.
  *   Errors: DD_ERR_ARG, DD_ERR_ALIGN, DD_ERR_HIP.
  * dd_execute_batched: replay the graph on `stream`.  Errors: DD_ERR_NOT_BOUND, DD_ERR_ARG (the
  *   current device is not the one the batch was bound on), DD_ERR_HIP.
- * dd_batch_get_tiles: the shared tile shape (order is always 0: work items are claimed dynamically).
- * dd_batch_set_tiles: switch to compiled staged shape `shape` (DD_ERR_RANGE, batch unchanged, if a
- *   beam cannot be staged with it); unbinds the batch, which keeps its workspace size.
- * dd_batch_autotune: with the arguments of dd_batch_bind, time the default shape and every staged
- *   shape with at least 32 DM rows per workgroup on the whole batch (one warm-up replay, one timed
- *   replay with HIP events on `stream`), keep the fastest (the default stays unless another is at
- *   least 2% faster) and leave the batch bound with it.  Outputs are overwritten.  Synchronises
- *   `stream`.  *report may be NULL (timed_out_samples is 0: whole replays are timed).
+ * dd_batch_get_tiles: the shape every beam runs (order is always 0: work items are claimed
+ *   dynamically), or shape = -1 and all other fields 0 when the beams run different shapes.
+ * dd_batch_get_beam_tiles: the shape beam `beam` (0..n-1, the order of dd_batch_create) runs.
+ * dd_batch_set_tiles: put every beam on compiled staged shape `shape` (DD_ERR_RANGE, batch
+ *   unchanged, if a beam cannot be staged with it); unbinds the batch, which keeps its workspace size.
+ * dd_batch_autotune: with the arguments of dd_batch_bind, time the current assignment, every
+ *   beam at its default shape, and every staged shape with at least 32 DM rows per workgroup for
+ *   all beams, each on the whole batch (one warm-up replay, one timed replay with HIP events on
+ *   `stream`); keep the fastest (the current one stays unless another is at least 2% faster) and
+ *   leave the batch bound with it.  Outputs are overwritten.  Synchronises `stream`.  *report may
+ *   be NULL (best is as dd_batch_get_tiles; timed_out_samples is 0: whole replays are timed).
  *   Errors: as dd_batch_bind.
  */
 dd_status dd_batch_create(const dd_plan *const *plans, int32_t n, dd_batch **out);
@@ -257,6 +266,7 @@ dd_status dd_batch_bind(dd_batch *batch, const void *const *d_in, float *const *
                         const int64_t *out_pitch, void *d_workspace, size_t bytes, void *stream);
 dd_status dd_execute_batched(dd_batch *batch, void *stream);
 dd_status dd_batch_get_tiles(const dd_batch *batch, dd_tiles *tiles);
+dd_status dd_batch_get_beam_tiles(const dd_batch *batch, int32_t beam, dd_tiles *tiles);
 dd_status dd_batch_set_tiles(dd_batch *batch, int32_t shape);
 dd_status dd_batch_autotune(dd_batch *batch, const void *const *d_in, float *const *d_out, const int64_t *out_pitch,
                             void *d_workspace, size_t bytes, void *stream, dd_tune_report *report);

@@ -91,6 +91,8 @@ _lib.dd_execute_batched.argtypes = [_vp, _vp]
 _lib.dd_execute_batched.restype = _i32
 _lib.dd_batch_get_tiles.argtypes = [_vp, ctypes.POINTER(Tiles)]
 _lib.dd_batch_get_tiles.restype = _i32
+_lib.dd_batch_get_beam_tiles.argtypes = [_vp, _i32, ctypes.POINTER(Tiles)]
+_lib.dd_batch_get_beam_tiles.restype = _i32
 _lib.dd_batch_set_tiles.argtypes = [_vp, _i32]
 _lib.dd_batch_set_tiles.restype = _i32
 _lib.dd_batch_autotune.argtypes = [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_i64), _vp, _sz, _vp,
@@ -355,7 +357,7 @@ class DedisperseFn(torch.autograd.Function):
 
 
 class Batch:
-    """Many beams (one plan each) in one persistent, graph-replayed launch."""
+    """Many beams (one plan each) in persistent, graph-replayed launches (one per tile shape in use)."""
 
     def __init__(self, plans, inputs, outputs=None, stream=None):
         n = len(plans)
@@ -387,18 +389,25 @@ class Batch:
                                   _stream_handle(stream)), "dd_batch_bind")
 
     def tiles(self) -> dict:
+        """The shape every beam runs (shape -1 when the beams run different shapes)."""
         t = Tiles()
         _check(_lib.dd_batch_get_tiles(self._h, ctypes.byref(t)), "dd_batch_get_tiles")
         return t.as_dict()
 
+    def beam_tiles(self, beam) -> dict:
+        """The shape beam `beam` runs."""
+        t = Tiles()
+        _check(_lib.dd_batch_get_beam_tiles(self._h, int(beam), ctypes.byref(t)), "dd_batch_get_beam_tiles")
+        return t.as_dict()
+
     def set_tiles(self, shape, stream=None):
-        """Switch every beam to compiled staged shape `shape` and re-bind."""
+        """Put every beam on compiled staged shape `shape` and re-bind."""
         _check(_lib.dd_batch_set_tiles(self._h, int(shape)), "dd_batch_set_tiles")
         self.bind(stream)
 
     def autotune(self, stream=None) -> dict:
-        """Time the staged shapes on the whole batch and keep the fastest (dd_batch_autotune); outputs are
-        overwritten."""
+        """Time the per-beam default shapes and the shared staged shapes on the whole batch and keep the
+        fastest (dd_batch_autotune); outputs are overwritten."""
         ins, outs, pitches = self._bind_args()
         rep = TuneReport()
         _check(_lib.dd_batch_autotune(self._h, ins, outs, pitches, self.workspace.data_ptr(), self.workspace.numel(),

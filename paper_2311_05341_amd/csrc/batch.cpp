@@ -1,6 +1,9 @@
-// Batched forward: many beams, each with its own plan, in one persistent
-// kernel launch recorded once as a HIP graph (counter reset, then the
-// persistent kernel) and replayed by dd_execute_batched.
+// Batched forward: many beams, each with its own plan, run by persistent
+// kernel launches recorded once as a HIP graph and replayed by
+// dd_execute_batched.  Each beam has a staged tile shape of its own; beams of
+// one shape form a group, and each group is one persistent launch (counter
+// reset, then the kernel claiming that group's work items), the groups one
+// after another in the graph.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -14,17 +17,32 @@
 
 using namespace dd;
 
+namespace {
+
+// Beams sharing one staged tile shape and as many workgroups per CU as their
+// LDS allows: one persistent launch.  (The launch's LDS is the largest of its
+// beams', so beams of one shape whose LDS needs allow different numbers of
+// resident workgroups are kept apart.)
+struct BatchGroup {
+  int shape = 0;                // index in kIntShapes
+  int per_cu = 0;               // workgroups per CU its beams' LDS allows
+  int lds_bytes = 0;            // largest of its beams' LDS needs
+  std::vector<int> beams;       // original beam indices, in decreasing per-item cost
+  size_t desc_first = 0;        // index of its first descriptor in the workspace's descriptor array
+  long long n_items = 0;
+};
+
+}  // namespace
+
 struct dd_batch {
   std::vector<const dd_plan *> plans;
   int dtype = 0;
-  int shape = 0;                // index of the shared LDS shape in kIntShapes
-  TileCfg tile;                 // shared tile shape (ns, dm_per_wave, waves)
-  std::vector<IntTables> tables;  // per beam (original index), for the shared shape
-  int lds_bytes = 0;
-  std::vector<int> order;       // beams in decreasing per-item cost
-  std::vector<BeamDesc> descs;  // in `order`
-  long long n_items = 0;
-  size_t table_off = 0, ws_bytes = 0;
+  std::vector<int> shape;         // per beam (original index): its staged shape
+  std::vector<IntTables> tables;  // per beam (original index), for its shape
+  std::vector<int> order;         // beams in decreasing per-item cost
+  std::vector<BatchGroup> groups;
+  std::vector<BeamDesc> descs;    // group after group, each group's beams in cost order
+  size_t ws_bytes = 0;
   std::vector<size_t> table_offs, sbase_offs;  // per beam (original index)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -33,6 +51,7 @@ struct dd_batch {
 };
 
 static const int kBatchLdsLimit = 160 * 1024 - 64;  // leaves room for the claimed-item slot
+static const int kMaxGroups = 64;
 
 static size_t up256(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -52,49 +71,100 @@ static void int_table_bytes(const dd_plan &p, const int *k, size_t *offs, size_t
   *sbase = up256((size_t)(n_dblk * nc) * sizeof(int32_t));
 }
 
-// Switch the batch to LDS shape s: every beam's tables, the launch geometry and
-// the work list.  DD_ERR_RANGE (batch unchanged) if a beam cannot be staged.
-static dd_status batch_set_shape(dd_batch *b, int s) {
+// Workspace layout: one 256-byte counter slot per group (at most one per
+// compiled shape and LDS occupancy class), the beam
+// descriptors, then per beam room for its tables under the largest compiled
+// shape, so that no assignment of shapes moves anything.
+static size_t counters_bytes() { return (size_t)kMaxGroups * 256; }
+static size_t descs_offset() { return counters_bytes(); }
+
+// Give beam i staged shape shapes[i], for every beam: tables, groups, work
+// items.  DD_ERR_RANGE (batch unchanged) if a beam cannot be staged with its shape.
+static dd_status batch_assign(dd_batch *b, const std::vector<int> &shapes) {
   const int n = (int)b->plans.size();
-  const int *k = kIntShapes[s];
   std::vector<IntTables> tabs(n);
-  int lds = 0;
   for (int i = 0; i < n; ++i) {
+    const int *k = kIntShapes[shapes[i]];
     const dd_status st = build_int_tables(*b->plans[i], k[0], k[1], k[2], k[3], k[4], kBatchLdsLimit, &tabs[i]);
     if (st != DD_OK) return st;
-    lds = std::max(lds, tabs[i].lds_bytes);
+  }
+  std::vector<BatchGroup> groups;
+  for (int q = 0; q < n; ++q) {  // groups in order of their costliest beam
+    const int i = b->order[q];
+    const int per_cu = (kBatchLdsLimit + 64) / (tabs[i].lds_bytes + 64);  // the kernel keeps 64 bytes of its own
+    auto g = std::find_if(groups.begin(), groups.end(),
+                          [&](const BatchGroup &x) { return x.shape == shapes[i] && x.per_cu == per_cu; });
+    if (g == groups.end()) {
+      groups.emplace_back();
+      g = groups.end() - 1;
+      g->shape = shapes[i];
+      g->per_cu = per_cu;
+    }
+    g->beams.push_back(i);
+    g->lds_bytes = std::max(g->lds_bytes, tabs[i].lds_bytes);
+  }
+  if ((int)groups.size() > kMaxGroups) return fail(DD_ERR_RANGE, "too many distinct beam shapes in one batch");
+  std::vector<BeamDesc> descs(n);
+  size_t q = 0;
+  for (BatchGroup &g : groups) {
+    const int *k = kIntShapes[g.shape];
+    const int dm_tile = k[1] * k[2], t_tile = 64 * k[0];
+    g.desc_first = q;
+    long long items = 0;
+    for (int i : g.beams) {
+      const dd_plan &p = *b->plans[i];
+      BeamDesc &d = descs[q++];
+      memset(&d, 0, sizeof(d));
+      d.n_chan = p.desc.n_chan;
+      d.n_dm = p.desc.n_dm;
+      d.n_samp = p.desc.n_samp;
+      d.n_out = p.n_out;
+      d.pitch = p.in_pitch_bytes;
+      d.row_bytes = tabs[i].row_bytes;
+      d.chan_block = tabs[i].chan_block;
+      d.tiles_t = (int)((p.n_out + t_tile - 1) / t_tile);
+      d.tiles_d = (p.desc.n_dm + dm_tile - 1) / dm_tile;
+      d.item_begin = items;
+      items += (long long)d.tiles_t * d.tiles_d;
+    }
+    g.n_items = items;
   }
   b->tables = std::move(tabs);
-  b->shape = s;
-  b->tile.ns = k[0];
-  b->tile.dm_per_wave = k[1];
-  b->tile.waves = k[2];
-  b->tile.chan_block = k[3];
-  b->tile.segs = k[4];
-  b->lds_bytes = lds;
-  const int dm_tile = k[1] * k[2], t_tile = 64 * k[0];
-  b->descs.resize(n);
-  long long items = 0;
-  for (int q = 0; q < n; ++q) {
-    const int i = b->order[q];
-    const dd_plan &p = *b->plans[i];
-    BeamDesc &d = b->descs[q];
-    memset(&d, 0, sizeof(d));
-    d.n_chan = p.desc.n_chan;
-    d.n_dm = p.desc.n_dm;
-    d.n_samp = p.desc.n_samp;
-    d.n_out = p.n_out;
-    d.pitch = p.in_pitch_bytes;
-    d.row_bytes = b->tables[i].row_bytes;
-    d.chan_block = b->tables[i].chan_block;
-    d.tiles_t = (int)((p.n_out + t_tile - 1) / t_tile);
-    d.tiles_d = (p.desc.n_dm + dm_tile - 1) / dm_tile;
-    d.item_begin = items;
-    items += (long long)d.tiles_t * d.tiles_d;
-  }
-  b->n_items = items;
+  b->groups = std::move(groups);
+  b->descs = std::move(descs);
+  b->shape = shapes;
   b->bound = false;
   return DD_OK;
+}
+
+// The shape a beam runs by default: its plan's own staged forward shape (its
+// default, or what the plan was set or tuned to), else the first staged shape
+// that holds it (phase-load shapes first for 8-bit input).
+static int default_shape(const dd_plan &p) {
+  if (!is_direct(p.fwd) && p.fwd.shape < kNumIntShapes) {
+    IntTables t;
+    const int *k = kIntShapes[p.fwd.shape];
+    if (build_int_tables(p, k[0], k[1], k[2], k[3], k[4], kBatchLdsLimit, &t, false) == DD_OK) return p.fwd.shape;
+  }
+  for (int pass = 0; pass < 2; ++pass)
+    for (int s = 0; s < kNumIntShapes; ++s) {
+      if ((kIntShapes[s][4] > 0) != (pass == 0)) continue;
+      IntTables t;
+      const int *k = kIntShapes[s];
+      if (build_int_tables(p, k[0], k[1], k[2], k[3], k[4], kBatchLdsLimit, &t, false) == DD_OK) return s;
+    }
+  return -1;
+}
+
+static void fill_tiles(int s, dd_tiles *t) {
+  const int *k = kIntShapes[s];
+  t->shape = s;
+  t->order = 0;
+  t->ns = k[0];
+  t->per_wave = k[1];
+  t->waves = k[2];
+  t->row_block = k[3];
+  t->segs = k[4];
 }
 
 extern "C" {
@@ -120,10 +190,7 @@ dd_status dd_batch_create(const dd_plan *const *plans, int32_t n, dd_batch **out
   std::stable_sort(b->order.begin(), b->order.end(), [&](int a, int c) {
     return b->plans[a]->desc.n_chan > b->plans[c]->desc.n_chan;
   });
-  // Workspace layout: counter, descriptors, then per beam room for its tables
-  // under the largest compiled shape, so changing the shape never moves them.
-  size_t off = up256(sizeof(unsigned long long)) + up256(sizeof(BeamDesc) * (size_t)n);
-  b->table_off = off;
+  size_t off = descs_offset() + up256(sizeof(BeamDesc) * (size_t)n);
   b->table_offs.assign(n, 0);
   b->sbase_offs.assign(n, 0);
   for (int i = 0; i < n; ++i) {
@@ -140,17 +207,16 @@ dd_status dd_batch_create(const dd_plan *const *plans, int32_t n, dd_batch **out
     off += sbb;
   }
   b->ws_bytes = off;
-  // One tile shape for all beams: the first compiled shape every beam can stage
-  // (two workgroups' worth of LDS is not required: the kernel runs one per CU),
-  // phase-load shapes first for 8-bit beams.
-  dd_status st = DD_ERR_RANGE;
-  for (int pass = 0; pass < 2 && st != DD_OK; ++pass)
-    for (int s = 0; s < kNumIntShapes && st != DD_OK; ++s) {
-      if ((kIntShapes[s][4] > 0) != (pass == 0)) continue;
-      st = batch_set_shape(b, s);
-      if (st == DD_ERR_NOMEM) { delete b; return st; }
+  std::vector<int> shapes(n);
+  for (int i = 0; i < n; ++i) {
+    shapes[i] = default_shape(*b->plans[i]);
+    if (shapes[i] < 0) {
+      delete b;
+      return fail(DD_ERR_RANGE, "beam " + std::to_string(i) + "'s delay spread exceeds the LDS staging capacity");
     }
-  if (st != DD_OK) { delete b; return fail(DD_ERR_RANGE, "a beam's delay spread exceeds the LDS staging capacity"); }
+  }
+  const dd_status st = batch_assign(b, shapes);
+  if (st != DD_OK) { delete b; return st; }
   *out = b;
   return DD_OK;
 }
@@ -176,18 +242,18 @@ dd_status dd_batch_bind(dd_batch *b, const void *const *d_in, float *const *d_ou
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
   uint8_t *base = (uint8_t *)ws;
-  for (int k = 0; k < n; ++k) {
-    const int i = b->order[k];
-    BeamDesc &d = b->descs[k];
-    d.x = (const uint8_t *)d_in[i];
-    d.out = d_out[i];
-    d.out_pitch = out_pitch[i];
-    d.offs = (const uint32_t *)(base + b->table_offs[i]);
-    d.sbase = (const int32_t *)(base + b->sbase_offs[i]);
-  }
+  for (const BatchGroup &g : b->groups)
+    for (size_t k = 0; k < g.beams.size(); ++k) {
+      const int i = g.beams[k];
+      BeamDesc &d = b->descs[g.desc_first + k];
+      d.x = (const uint8_t *)d_in[i];
+      d.out = d_out[i];
+      d.out_pitch = out_pitch[i];
+      d.offs = (const uint32_t *)(base + b->table_offs[i]);
+      d.sbase = (const int32_t *)(base + b->sbase_offs[i]);
+    }
   hipStream_t st = (hipStream_t)stream;
-  e = hipMemcpyAsync(base + up256(sizeof(unsigned long long)), b->descs.data(), sizeof(BeamDesc) * n,
-                     hipMemcpyHostToDevice, st);
+  e = hipMemcpyAsync(base + descs_offset(), b->descs.data(), sizeof(BeamDesc) * n, hipMemcpyHostToDevice, st);
   for (int i = 0; i < n && e == hipSuccess; ++i) {
     e = hipMemcpyAsync(base + b->table_offs[i], b->tables[i].offs.data(), b->tables[i].offs.size() * 2,
                        hipMemcpyHostToDevice, st);
@@ -197,31 +263,42 @@ dd_status dd_batch_bind(dd_batch *b, const void *const *d_in, float *const *d_ou
   }
   if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("batch upload: ") + hipGetErrorString(e));
 
-  BatchLaunch L = {};
-  int le = batch_kernels(b->tile.ns, b->tile.dm_per_wave, b->tile.waves, b->tile.chan_block, b->tile.segs, b->dtype,
-                         b->lds_bytes, &L);
-  if (le) return fail(DD_ERR_HIP, std::string("batch kernel setup: ") + hipGetErrorString((hipError_t)le));
-  if (!L.reset_fn || !L.main_fn) return fail(DD_ERR_HIP, "batch kernel setup: missing kernel entry");
+  // The graph: per group, a counter reset and then the group's persistent
+  // kernel, the groups chained one after another.  The node parameters are
+  // copied when the nodes are added, so per-group argument storage only has to
+  // live until then.
   release_graph(b);
-  unsigned long long *counter = (unsigned long long *)base;
-  const BeamDesc *descs = (const BeamDesc *)(base + up256(sizeof(unsigned long long)));
-  int nb = n;
-  long long items = b->n_items;
-  void *reset_args[] = {&counter};
-  void *main_args[] = {&descs, &nb, &items, &counter};
-  hipGraphNode_t n_reset = nullptr, n_main = nullptr;
-  hipKernelNodeParams kp;
   e = hipGraphCreate(&b->graph, 0);
-  if (e == hipSuccess) {
+  hipGraphNode_t prev = nullptr;
+  for (size_t gi = 0; gi < b->groups.size() && e == hipSuccess; ++gi) {
+    const BatchGroup &g = b->groups[gi];
+    const int *k = kIntShapes[g.shape];
+    BatchLaunch L = {};
+    const int le = batch_kernels(k[0], k[1], k[2], k[3], k[4], b->dtype, g.lds_bytes, &L);
+    if (le) {
+      release_graph(b);
+      return fail(DD_ERR_HIP, std::string("batch kernel setup: ") + hipGetErrorString((hipError_t)le));
+    }
+    if (!L.reset_fn || !L.main_fn) {
+      release_graph(b);
+      return fail(DD_ERR_HIP, "batch kernel setup: missing kernel entry");
+    }
+    unsigned long long *counter = (unsigned long long *)(base + 256 * gi);
+    const BeamDesc *descs = (const BeamDesc *)(base + descs_offset()) + g.desc_first;
+    int nb = (int)g.beams.size();
+    long long items = g.n_items;
+    void *reset_args[] = {&counter};
+    void *main_args[] = {&descs, &nb, &items, &counter};
+    hipGraphNode_t n_reset = nullptr, n_main = nullptr;
+    hipKernelNodeParams kp;
     memset(&kp, 0, sizeof(kp));
     kp.func = (void *)L.reset_fn;
     kp.gridDim = dim3(1);
     kp.blockDim = dim3(1);
     kp.sharedMemBytes = 0;
     kp.kernelParams = reset_args;
-    e = hipGraphAddKernelNode(&n_reset, b->graph, nullptr, 0, &kp);
-  }
-  if (e == hipSuccess) {
+    e = hipGraphAddKernelNode(&n_reset, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    if (e != hipSuccess) break;
     memset(&kp, 0, sizeof(kp));
     kp.func = (void *)L.main_fn;
     kp.gridDim = dim3(L.grid);
@@ -229,6 +306,7 @@ dd_status dd_batch_bind(dd_batch *b, const void *const *d_in, float *const *d_ou
     kp.sharedMemBytes = L.lds_bytes;
     kp.kernelParams = main_args;
     e = hipGraphAddKernelNode(&n_main, b->graph, &n_reset, 1, &kp);
+    prev = n_main;
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) {
@@ -252,21 +330,26 @@ dd_status dd_execute_batched(dd_batch *b, void *stream) {
 
 dd_status dd_batch_get_tiles(const dd_batch *b, dd_tiles *t) {
   if (!b || !t) return fail(DD_ERR_ARG, "null argument");
-  const int *k = kIntShapes[b->shape];
-  t->shape = b->shape;
-  t->order = 0;
-  t->ns = k[0];
-  t->per_wave = k[1];
-  t->waves = k[2];
-  t->row_block = k[3];
-  t->segs = k[4];
+  memset(t, 0, sizeof(*t));
+  if (std::all_of(b->shape.begin(), b->shape.end(), [&](int s) { return s == b->shape[0]; })) {
+    fill_tiles(b->shape[0], t);
+  } else {
+    t->shape = -1;  // the beams run different shapes: see dd_batch_get_beam_tiles
+  }
+  return DD_OK;
+}
+
+dd_status dd_batch_get_beam_tiles(const dd_batch *b, int32_t beam, dd_tiles *t) {
+  if (!b || !t) return fail(DD_ERR_ARG, "null argument");
+  if (beam < 0 || beam >= (int)b->plans.size()) return fail(DD_ERR_ARG, "no such beam");
+  fill_tiles(b->shape[beam], t);
   return DD_OK;
 }
 
 dd_status dd_batch_set_tiles(dd_batch *b, int32_t shape) {
   if (!b) return fail(DD_ERR_ARG, "null batch");
   if (shape < 0 || shape >= kNumIntShapes) return fail(DD_ERR_ARG, "no such staged tile shape");
-  const dd_status st = batch_set_shape(b, shape);
+  const dd_status st = batch_assign(b, std::vector<int>(b->plans.size(), shape));
   if (st == DD_ERR_RANGE) return fail(st, "a beam's delay spread does not fit this shape");
   return st;
 }
@@ -274,7 +357,7 @@ dd_status dd_batch_set_tiles(dd_batch *b, int32_t shape) {
 dd_status dd_batch_autotune(dd_batch *b, const void *const *d_in, float *const *d_out, const int64_t *out_pitch,
                             void *ws, size_t bytes, void *stream, dd_tune_report *rep) {
   if (!b) return fail(DD_ERR_ARG, "null batch");
-  const int orig = b->shape;
+  const std::vector<int> orig = b->shape;
   hipStream_t st = (hipStream_t)stream;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t he = hipEventCreate(&e0);
@@ -283,9 +366,9 @@ dd_status dd_batch_autotune(dd_batch *b, const void *const *d_in, float *const *
     if (e0) (void)hipEventDestroy(e0);
     return hip_error(he, "hipEventCreate");
   }
-  // Bind shape s, replay once to warm up, then time one replay.
-  auto time_shape = [&](int s, double *ms) -> dd_status {
-    dd_status r = batch_set_shape(b, s);
+  // Bind an assignment, replay once to warm up, then time one replay.
+  auto time_assign = [&](const std::vector<int> &shapes, double *ms) -> dd_status {
+    dd_status r = batch_assign(b, shapes);
     if (r != DD_OK) return r;
     r = dd_batch_bind(b, d_in, d_out, out_pitch, ws, bytes, stream);
     if (r != DD_OK) return r;
@@ -300,28 +383,37 @@ dd_status dd_batch_autotune(dd_batch *b, const void *const *d_in, float *const *
     *ms = t;
     return DD_OK;
   };
+  // Candidates: the current assignment, every beam at its default shape, and
+  // every staged shape with at least 32 DM rows per workgroup shared by all
+  // beams (smaller ones only pay where a beam's default had to fall back to them).
+  std::vector<std::vector<int>> cands;
+  cands.push_back(orig);
+  std::vector<int> defaults(orig.size());
+  for (size_t i = 0; i < orig.size(); ++i) defaults[i] = default_shape(*b->plans[i]);
+  if (defaults != orig) cands.push_back(defaults);
+  for (int s = 0; s < kNumIntShapes; ++s) {
+    if (kIntShapes[s][1] * kIntShapes[s][2] < 32) continue;
+    std::vector<int> all(orig.size(), s);
+    if (all != orig && all != defaults) cands.push_back(all);
+  }
   double default_ms = 0.0, best_ms = 0.0;
-  int best = orig, tried = 0;
-  dd_status status = time_shape(orig, &default_ms);
-  if (status == DD_OK) {
-    best_ms = default_ms;
-    tried = 1;
-    // Candidates: shapes with at least 32 DM rows per workgroup (the smaller ones
-    // only pay where the batch's own default already had to fall back to them).
-    for (int s = 0; s < kNumIntShapes && status == DD_OK; ++s) {
-      if (s == orig || kIntShapes[s][1] * kIntShapes[s][2] < 32) continue;
-      double ms = 0.0;
-      const dd_status ts = time_shape(s, &ms);
-      if (ts == DD_ERR_RANGE) continue;
-      if (ts != DD_OK) {
-        status = ts;
-        break;
-      }
-      ++tried;
-      if (ms < best_ms) {
-        best_ms = ms;
-        best = s;
-      }
+  size_t best = 0;
+  int tried = 0;
+  dd_status status = DD_OK;
+  for (size_t c = 0; c < cands.size() && status == DD_OK; ++c) {
+    double ms = 0.0;
+    const dd_status ts = time_assign(cands[c], &ms);
+    if (ts == DD_ERR_RANGE && c > 0) continue;
+    if (ts != DD_OK) {
+      status = ts;
+      break;
+    }
+    ++tried;
+    if (c == 0) {
+      default_ms = best_ms = ms;
+    } else if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
     }
   }
   (void)hipEventDestroy(e0);
@@ -329,14 +421,14 @@ dd_status dd_batch_autotune(dd_batch *b, const void *const *d_in, float *const *
   if (status != DD_OK) {
     const std::string msg = dd_last_error();
     (void)hipStreamSynchronize(st);
-    (void)batch_set_shape(b, orig);
+    (void)batch_assign(b, orig);
     return fail(status, msg);
   }
-  if (best_ms > 0.98 * default_ms) {  // within timing noise of the default: keep it
-    best = orig;
+  if (best_ms > 0.98 * default_ms) {  // within timing noise of the current choice: keep it
+    best = 0;
     best_ms = default_ms;
   }
-  status = batch_set_shape(b, best);
+  status = batch_assign(b, cands[best]);
   if (status == DD_OK) status = dd_batch_bind(b, d_in, d_out, out_pitch, ws, bytes, stream);
   if (status == DD_OK) {
     const hipError_t se = hipStreamSynchronize(st);

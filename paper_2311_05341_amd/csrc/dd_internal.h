@@ -125,8 +125,10 @@ struct BeamDesc {
   int32_t n_chan, n_dm, row_bytes, chan_block, tiles_t, tiles_d;
 };
 
+// Tables of the integer forward kernel for one staged shape; with fill false
+// only the size checks run and t gets row_bytes / lds_bytes (no tables).
 dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves, int chan_block, int segs,
-                           int lds_limit, IntTables *t);
+                           int lds_limit, IntTables *t, bool fill = true);
 
 // Epilogue modes of the integer forward kernels for 16-bit input.  A sum of
 // values up to 2^24 (binned 16-bit samples) is computed exactly from two

@@ -590,6 +590,17 @@ constexpr int kPhaseRing = 3;
 template <int CB, int SEGS, int NW>
 constexpr int phase_pairs_per_wave() { return (CB * SEGS + NW - 1) / NW; }
 
+// Copies of a staged row in the phase-load forms: the four byte phases for
+// 8-bit samples; for packed 4-bit samples the eight nibble phases, of which
+// the byte phases are the even ones (copy 2p = byte phase p).
+template <int BITS>
+constexpr int phase_copies() { return BITS == 4 ? 8 : 4; }
+
+// Bytes of row from sample s on (4-bit rows hold two samples per byte; every
+// staged row starts on a multiple of 32 samples).
+template <int BITS>
+__device__ __forceinline__ int64_t phase_bytes(int64_t s) { return BITS == 4 ? s >> 1 : s; }
+
 // This wave's (channel, segment) pairs: channel within the block, segment.
 template <int CB, int SEGS, int NW>
 struct PhasePlan {
@@ -602,7 +613,7 @@ struct PhasePlan {
   bool lane_ok[J];     // this lane's 16 bytes lie inside the copy (true for padding)
 };
 
-template <int CB, int SEGS, int NW>
+template <int CB, int SEGS, int NW, int BITS>
 __device__ __forceinline__ PhasePlan<CB, SEGS, NW> phase_plan(int row_bytes, int wave, int lane) {
   PhasePlan<CB, SEGS, NW> d;
 #pragma unroll
@@ -611,7 +622,7 @@ __device__ __forceinline__ PhasePlan<CB, SEGS, NW> phase_plan(int row_bytes, int
     const int cc = j / SEGS, seg = j - cc * SEGS;
     d.ok[m] = j < CB * SEGS && 1024 * seg < row_bytes;
     d.cc[m] = d.ok[m] ? cc : 0;
-    d.lds_off[m] = d.ok[m] ? (uint32_t)(cc * 4 * row_bytes + 1024 * seg) : 0u;
+    d.lds_off[m] = d.ok[m] ? (uint32_t)(cc * phase_copies<BITS>() * row_bytes + 1024 * seg) : 0u;
     d.voff[m] = (uint32_t)(1024 * seg + 16 * lane);
     d.seg0[m] = 1024 * seg;
     d.lane_ok[m] = !d.ok[m] || 1024 * seg + 16 * lane < row_bytes;
@@ -621,24 +632,26 @@ __device__ __forceinline__ PhasePlan<CB, SEGS, NW> phase_plan(int row_bytes, int
 
 // Issue this wave's phase loads of block `cb` (first channel) into ring slot
 // `slot`; `base` holds the stage bases of the wave's channels for that block.
-template <int CB, int SEGS, int NW>
+// Byte phase p goes to copy p (8-bit) or copy 2p (4-bit).
+template <int CB, int SEGS, int NW, int BITS>
 __device__ __forceinline__ void phase_dma(const IntArgs &a, const PhasePlan<CB, SEGS, NW> &d,
                                           const int32_t (&base_in)[PhasePlan<CB, SEGS, NW>::J], int64_t t0, int cb,
                                           uint8_t *lds, int slot_bytes, int slot, uint32_t sink_addr) {
   const uint32_t slot_addr =
       __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void_t *)(lds + slot * slot_bytes));
+  const int64_t bound = (phase_bytes<BITS>(a.n_samp) + 15) & ~(int64_t)15;  // row bytes rounded up to 16 (<= pitch)
 #pragma unroll
   for (int m = 0; m < PhasePlan<CB, SEGS, NW>::J; ++m) {
     const bool chan_ok = d.ok[m] && cb + d.cc[m] < a.n_chan;  // wave-uniform
     const int c = __builtin_amdgcn_readfirstlane(min(cb + d.cc[m], a.n_chan - 1));
-    // first staged byte of the row (a multiple of 16) and the bytes from there to the
-    // row length rounded up to 16 (<= the pitch)
-    const int64_t row0 = chan_ok ? t0 + base_in[m] : 0;
-    const int64_t left = ((a.n_samp + 15) & ~(int64_t)15) - row0;
+    // first staged byte of the row (a multiple of 16) and the bytes from there to the bound
+    const int64_t row0 = chan_ok ? phase_bytes<BITS>(t0 + base_in[m]) : 0;
+    const int64_t left = bound - row0;
     const int bytes = chan_ok && left > 0 ? (int)min(left, (int64_t)0x7fffffff) : 0;
     const v4i_t rs = make_rsrc(a.x + (int64_t)c * a.pitch + row0, bytes);
     const uint32_t dst = d.ok[m] ? slot_addr + d.lds_off[m] : sink_addr;
-    const uint32_t copy_step = d.ok[m] ? (uint32_t)a.row_bytes : 0u;  // padding: all four into the sink
+    // padding: all four into the sink
+    const uint32_t copy_step = d.ok[m] ? (uint32_t)(phase_copies<BITS>() / 4 * a.row_bytes) : 0u;
     if (d.lane_ok[m]) {
 #pragma unroll
       for (int ph = 0; ph < 4; ++ph) dma16(rs, d.voff[m] + ph, dst + ph * copy_step);
@@ -664,22 +677,31 @@ __device__ __forceinline__ void phase_bases(const IntArgs &a, const int32_t *sb,
 // those below the bound are copy 0's word at k shifted down by p bytes; the
 // rest lie past the row and feed no output.  Call after this wave's loads of
 // the block have landed and before the block's barrier.
-template <int CB, int SEGS, int NW>
+template <int CB, int SEGS, int NW, int BITS>
 __device__ __forceinline__ void phase_fix_tail(const IntArgs &a, const PhasePlan<CB, SEGS, NW> &d, const int32_t *sb,
                                                int64_t t0, int cb, uint8_t *lds, int slot_bytes, int slot, int lane) {
-  const int64_t bound = (a.n_samp + 15) & ~(int64_t)15;
+  const int64_t bound = (phase_bytes<BITS>(a.n_samp) + 15) & ~(int64_t)15;
+  const int step = phase_copies<BITS>() / 4 * a.row_bytes;  // byte phase p is at p * step
 #pragma unroll
   for (int m = 0; m < PhasePlan<CB, SEGS, NW>::J; ++m) {
     const int c = cb + d.cc[m];
     if (!d.ok[m] || c >= a.n_chan) continue;  // wave-uniform
-    const int64_t k = bound - (t0 + scalar_load(sb, c)) - 4;
+    const int64_t k = bound - phase_bytes<BITS>(t0 + scalar_load(sb, c)) - 4;
     if (k < d.seg0[m] || k >= d.seg0[m] + 1024 || k >= a.row_bytes) continue;  // not in this wave's segment
     if (lane < 3) {
-      uint8_t *row = lds + slot * slot_bytes + d.cc[m] * 4 * a.row_bytes + k;
+      uint8_t *row = lds + slot * slot_bytes + d.cc[m] * phase_copies<BITS>() * a.row_bytes + k;
       const uint32_t w0 = *(const uint32_t *)row;
-      *(uint32_t *)(row + (lane + 1) * a.row_bytes) = w0 >> (8 * (lane + 1));
+      *(uint32_t *)(row + (lane + 1) * step) = w0 >> (8 * (lane + 1));
     }
   }
+}
+
+// Does any staged row of tile t0 reach the word that straddles the load bound?
+// (Stage bases are at most the largest shift, n_samp - n_out.)
+template <int BITS>
+__device__ __forceinline__ bool phase_near_end(const IntArgs &a, int64_t t0) {
+  const int64_t bound = (phase_bytes<BITS>(a.n_samp) + 15) & ~(int64_t)15;
+  return phase_bytes<BITS>(t0 + (a.n_samp - a.n_out)) + a.row_bytes + 4 > bound;
 }
 
 template <int NS, int R, int NW, int CB, int SEGS>
@@ -709,12 +731,12 @@ __device__ __forceinline__ void fwd_u8_phase_tile(uint8_t *lds, const IntArgs &a
   }
 
   const int nblk = chan_pad / CB;
-  const PhasePlan<CB, SEGS, NW> dp = phase_plan<CB, SEGS, NW>(a.row_bytes, wave, lane);
+  const PhasePlan<CB, SEGS, NW> dp = phase_plan<CB, SEGS, NW, 8>(a.row_bytes, wave, lane);
   int32_t bases[J];
 #pragma unroll
   for (int k = 0; k < kPhaseRing - 1; ++k) {
     phase_bases<CB, SEGS, NW>(a, sb, k * CB, dp, bases);
-    phase_dma<CB, SEGS, NW>(a, dp, bases, t0, k * CB, lds, slot_bytes, k, sink_addr);
+    phase_dma<CB, SEGS, NW, 8>(a, dp, bases, t0, k * CB, lds, slot_bytes, k, sink_addr);
   }
   phase_bases<CB, SEGS, NW>(a, sb, (kPhaseRing - 1) * CB, dp, bases);
   uint32_t ow[CB * NOW];
@@ -722,19 +744,16 @@ __device__ __forceinline__ void fwd_u8_phase_tile(uint8_t *lds, const IntArgs &a
   for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, q);
 
   const uint8_t *lane_base = lds + 4 * lane;
-  // Does any staged row of this tile reach the word that straddles the load
-  // bound?  (Stage bases are at most the largest shift, n_samp - n_out.)
-  const bool near_end =
-      t0 + (a.n_samp - a.n_out) + a.row_bytes + 4 > ((a.n_samp + 15) & ~(int64_t)15);  // wave-uniform
+  const bool near_end = phase_near_end<8>(a, t0);  // wave-uniform
   int since_flush = 0;
   for (int b = 0; b < nblk; ++b) {
     // This wave's loads of block b have landed; after the barrier every
     // wave's have, and no wave reads the slot of block b - 1 any more, which
     // the loads of block b + kPhaseRing - 1 then fill.
     wait_vmcnt<(kPhaseRing - 2) * LOADS>();
-    if (near_end) phase_fix_tail<CB, SEGS, NW>(a, dp, sb, t0, b * CB, lds, slot_bytes, b % kPhaseRing, lane);
+    if (near_end) phase_fix_tail<CB, SEGS, NW, 8>(a, dp, sb, t0, b * CB, lds, slot_bytes, b % kPhaseRing, lane);
     lds_barrier();
-    phase_dma<CB, SEGS, NW>(a, dp, bases, t0, (b + kPhaseRing - 1) * CB, lds, slot_bytes,
+    phase_dma<CB, SEGS, NW, 8>(a, dp, bases, t0, (b + kPhaseRing - 1) * CB, lds, slot_bytes,
                             (b + kPhaseRing - 1) % kPhaseRing, sink_addr);  // zeros past the last channel
     const uint8_t *blk = lane_base + (b % kPhaseRing) * slot_bytes;
     // The table entry is the window's byte offset from the slot start; lane i
@@ -806,20 +825,246 @@ __device__ __forceinline__ void fwd_u8_phase_tile(uint8_t *lds, const IntArgs &a
   }
 }
 
+// ---------------------------------------------------------------------------
+// Packed 4-bit staging by phase loads.  A staged row stays packed (two samples
+// per byte) in eight nibble-phase copies: copy q holds the row from nibble q
+// on, so every window starts on a whole 32-bit word of the copy of its phase
+// (v mod 8 for a window at nibble v).  The even copies are the byte phases and
+// are loaded straight into LDS as in the 8-bit form (copy 2p from byte p; the
+// word straddling the load bound is rebuilt the same way); the odd copies are
+// built in LDS one block ahead of the summation: word k of copy 2p + 1 is words
+// k and k + 1 of copy 2p funnel-shifted by one nibble.  LDS holds 4 bytes per
+// staged sample, as the unpacked byte-phase form does, but the summation reads
+// half the bytes (8 samples per word) and needs fewer instructions per sample:
+//
+// Exact SIMD-within-a-word sums of nibbles.  Per word w (nibbles n0..n7, n0 the
+// earliest sample) a lane adds
+//     E += w & 0x0F0F0F0F      (the even nibbles, one per byte lane)
+//     S += w >> 4
+// and two channels' words fuse into one v_add3 each: six instructions per 16
+// samples.  w >> 4 is the odd nibbles in the byte lanes plus 16 times the even
+// nibbles moved down one byte, so with no byte lane of E above 255 (at most 17
+// channels) the odd-nibble sums are O = S - 16 * (E >> 8), S stays below 2^32.
+// Every 16 channels the byte lanes of E and O are added into per-sample
+// 32-bit totals with SDWA byte-select adds (eight per word).
+//
+// Block schedule: at iteration b this wave waits for its loads of block b + 1,
+// the workgroup meets at the block barrier (block b + 1's even copies have all
+// landed, block b's odd copies are complete, block b - 1's slot is free), the
+// loads of block b + 2 go out, block b + 1's odd copies are built and block b
+// is summed.  Three slots: the summation slot, the one being built, the one
+// being loaded.
+
+// acc + byte M of w (zero-extended): one SDWA add.
+template <int M>
+__device__ __forceinline__ uint32_t add_byte(uint32_t acc, uint32_t w) {
+  uint32_t r;
+  if constexpr (M == 0)
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+        : "=v"(r) : "v"(acc), "v"(w));
+  else if constexpr (M == 1)
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+        : "=v"(r) : "v"(acc), "v"(w));
+  else if constexpr (M == 2)
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
+        : "=v"(r) : "v"(acc), "v"(w));
+  else
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
+        : "=v"(r) : "v"(acc), "v"(w));
+  return r;
+}
+
+// Flush the nibble sums of R rows x NWD words into the per-sample totals
+// (sample 8k + j of the lane's word k at tot[r][8k + j]) and clear them.
+template <int NWD, int R>
+__device__ __forceinline__ void flush_u4(uint32_t (&ev)[R][NWD], uint32_t (&sh)[R][NWD], uint32_t (&tot)[R][8 * NWD]) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int k = 0; k < NWD; ++k) {
+      const uint32_t e = ev[r][k];
+      const uint32_t o = sh[r][k] - ((e >> 4) & 0x0FFFFFF0u);  // S - 16 * (E >> 8)
+      uint32_t *t = tot[r] + 8 * k;
+      t[0] = add_byte<0>(t[0], e);
+      t[2] = add_byte<1>(t[2], e);
+      t[4] = add_byte<2>(t[4], e);
+      t[6] = add_byte<3>(t[6], e);
+      t[1] = add_byte<0>(t[1], o);
+      t[3] = add_byte<1>(t[3], o);
+      t[5] = add_byte<2>(t[5], o);
+      t[7] = add_byte<3>(t[7], o);
+      ev[r][k] = 0;
+      sh[r][k] = 0;
+    }
+  }
+}
+
+// Build the odd nibble-phase copies of the CB channels of ring slot `slot`
+// from the even ones: 16-byte chunks, each thread a strided set of (channel,
+// byte phase, chunk).  The last word of each odd copy is left as it is (no
+// window reads it: rows carry a spare word).
+template <int NT, int CB>
+__device__ __forceinline__ void build_odd_nibbles(uint8_t *lds, int slot_bytes, int slot, int row_bytes) {
+  const int chunks = row_bytes >> 4;
+  uint8_t *base = lds + slot * slot_bytes;
+  for (int i = (int)threadIdx.x; i < CB * 4 * chunks; i += NT) {
+    const int cp = i / chunks, j = i - cp * chunks;  // cp = cc * 4 + p
+    const uint8_t *src = base + (2 * cp) * row_bytes + 16 * j;  // copy 2p of channel cc
+    const uint4 v = *(const uint4 *)src;
+    const uint32_t nx = j + 1 < chunks ? *(const uint32_t *)(src + 16) : 0u;
+    uint4 o;
+    o.x = __builtin_amdgcn_alignbit(v.y, v.x, 4);
+    o.y = __builtin_amdgcn_alignbit(v.z, v.y, 4);
+    o.z = __builtin_amdgcn_alignbit(v.w, v.z, 4);
+    o.w = __builtin_amdgcn_alignbit(nx, v.w, 4);
+    *(uint4 *)(src + row_bytes) = o;  // copy 2p + 1
+  }
+}
+
+template <int NS, int R, int NW, int CB, int SEGS>
+__device__ __forceinline__ void fwd_u4_phase_tile(uint8_t *lds, const IntArgs &a, int dblk, int tblk) {
+  static_assert(NS % 8 == 0, "4-bit phase tiles take whole 8-sample words per lane");
+  constexpr int NT = NW * 64;
+  constexpr int NWD = NS / 8;
+  constexpr int RP = R < 2 ? 2 : R;
+  constexpr int NOW = RP / 2;
+  constexpr int J = PhasePlan<CB, SEGS, NW>::J;
+  constexpr int LOADS = 4 * J;  // loads per wave and block
+  constexpr int kFlushChans = 16;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t t0 = (int64_t)tblk * (64 * NS);
+  const int chan_pad = (a.n_chan + CB - 1) / CB * CB;
+  const uint32_t *woffs = a.offs + ((int64_t)dblk * NW + wave) * chan_pad * NOW;
+  const int32_t *sb = a.sbase + (int64_t)dblk * a.n_chan;
+  const int slot_bytes = CB * 8 * a.row_bytes;
+  const uint32_t sink_addr =
+      __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void_t *)(lds + kPhaseRing * slot_bytes));
+
+  uint32_t tot[R][NS], ev[R][NWD], sh[R][NWD];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j) tot[r][j] = 0;
+#pragma unroll
+    for (int k = 0; k < NWD; ++k) ev[r][k] = sh[r][k] = 0;
+  }
+
+  const int nblk = chan_pad / CB;
+  const PhasePlan<CB, SEGS, NW> dp = phase_plan<CB, SEGS, NW, 4>(a.row_bytes, wave, lane);
+  const bool near_end = phase_near_end<4>(a, t0);  // wave-uniform
+  int32_t bases[J];
+  // Prologue: blocks 0 and 1 in flight; block 0's odd copies built.
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    phase_bases<CB, SEGS, NW>(a, sb, k * CB, dp, bases);
+    phase_dma<CB, SEGS, NW, 4>(a, dp, bases, t0, k * CB, lds, slot_bytes, k, sink_addr);
+  }
+  phase_bases<CB, SEGS, NW>(a, sb, 2 * CB, dp, bases);
+  uint32_t ow[CB * NOW];
+#pragma unroll
+  for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, q);
+  wait_vmcnt<LOADS>();
+  if (near_end) phase_fix_tail<CB, SEGS, NW, 4>(a, dp, sb, t0, 0, lds, slot_bytes, 0, lane);
+  lds_barrier();
+  build_odd_nibbles<NT, CB>(lds, slot_bytes, 0, a.row_bytes);
+
+  const uint8_t *lane_base = lds + 4 * lane;
+  int since_flush = 0;
+  for (int b = 0; b < nblk; ++b) {
+    wait_vmcnt<0>();  // this wave's loads of block b + 1
+    if (near_end) phase_fix_tail<CB, SEGS, NW, 4>(a, dp, sb, t0, (b + 1) * CB, lds, slot_bytes, (b + 1) % kPhaseRing, lane);
+    lds_barrier();
+    phase_dma<CB, SEGS, NW, 4>(a, dp, bases, t0, (b + 2) * CB, lds, slot_bytes, (b + 2) % kPhaseRing,
+                               sink_addr);  // zeros past the last channel
+    if (b + 1 < nblk) build_odd_nibbles<NT, CB>(lds, slot_bytes, (b + 1) % kPhaseRing, a.row_bytes);
+    const uint8_t *blk = lane_base + (b % kPhaseRing) * slot_bytes;
+    auto read_chan = [&](int cc, uint32_t (&dst)[R][NWD]) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const uint32_t e = (ow[cc * NOW + (r >> 1)] >> (16 * (r & 1))) & 0xFFFFu;
+        const uint32_t *p = (const uint32_t *)(blk + e);
+#pragma unroll
+        for (int k = 0; k < NWD; ++k) dst[r][k] = p[64 * k];
+      }
+    };
+    uint32_t wp[2][2][R][NWD];  // channel pairs: the pair after the one being summed is in flight
+    read_chan(0, wp[0][0]);
+    read_chan(1, wp[0][1]);
+#pragma unroll
+    for (int pc = 0; pc < CB / 2; ++pc) {
+      if (2 * pc + 2 < CB) {
+        read_chan(2 * pc + 2, wp[(pc + 1) & 1][0]);
+        read_chan(2 * pc + 3, wp[(pc + 1) & 1][1]);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int k = 0; k < NWD; ++k) {
+          const uint32_t w1 = wp[pc & 1][0][r][k], w2 = wp[pc & 1][1][r][k];
+          ev[r][k] += (w1 & 0x0F0F0F0Fu) + (w2 & 0x0F0F0F0Fu);
+          sh[r][k] += (w1 >> 4) + (w2 >> 4);
+        }
+    }
+    since_flush += CB;
+    if (since_flush + CB > kFlushChans || b + 1 == nblk) {
+      flush_u4<NWD, R>(ev, sh, tot);
+      since_flush = 0;
+    }
+    const int oi = __builtin_amdgcn_readfirstlane(min(b + 1, nblk - 1) * CB * NOW);
+#pragma unroll
+    for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, oi + q);
+    phase_bases<CB, SEGS, NW>(a, sb, (b + 3) * CB, dp, bases);
+  }
+  wait_vmcnt<0>();  // the trailing loads must land before the LDS is reused
+  lds_barrier();
+
+  // Word k of lane i holds samples t0 + 8 * (i + 64k) + 0..7.
+  const int d0 = dblk * (NW * R) + wave * R;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int d = d0 + r;
+    if (d >= a.n_dm) break;
+    float *orow = a.out + (int64_t)d * a.out_pitch;
+#pragma unroll
+    for (int k = 0; k < NWD; ++k) {
+      const int64_t t = t0 + 8 * (int64_t)(lane + 64 * k);
+      const uint32_t *v = tot[r] + 8 * k;
+      if (t + 7 < a.n_out) {
+        *(float4 *)(orow + t) = make_float4((float)v[0], (float)v[1], (float)v[2], (float)v[3]);
+        *(float4 *)(orow + t + 4) = make_float4((float)v[4], (float)v[5], (float)v[6], (float)v[7]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (t + i < a.n_out) orow[t + i] = (float)v[i];
+      }
+    }
+  }
+}
+
 // One tile of either staging form: SEGS == 0 is the ring form (fwd_int_tile),
-// SEGS > 0 the phase-load form for 8-bit input with at most SEGS 1 KiB load
-// segments per copy row.
+// SEGS > 0 the phase-load form for 8-bit or packed 4-bit input with at most
+// SEGS 1 KiB load segments per copy row.
 template <int NS, int R, int NW, int CB, int SEGS, int BITS>
 __device__ __forceinline__ void int_tile(uint8_t *lds, const IntArgs &a, int dblk, int tblk) {
   if constexpr (SEGS == 0)
     fwd_int_tile<NS, R, NW, CB, BITS>(lds, a, dblk, tblk);
+  else if constexpr (BITS == 4)
+    fwd_u4_phase_tile<NS, R, NW, CB, SEGS>(lds, a, dblk, tblk);
   else
     fwd_u8_phase_tile<NS, R, NW, CB, SEGS>(lds, a, dblk, tblk);
 }
 
+// Waves per SIMD the compiler must leave room for: 8-wave shapes with at most
+// 32 accumulated samples per lane are held to 128 VGPRs, so that two of their
+// workgroups share a CU (4 waves per SIMD) when their LDS fits twice; wider
+// shapes get no such limit (it would make them spill).
+template <int NS, int R, int NW>
+constexpr int min_waves_per_simd() { return NW == 8 && NS * R <= 32 ? 4 : 1; }
+
 // One workgroup per tile; 1-D grid of n_dblk * n_tiles workgroups.
 template <int NS, int R, int NW, int CB, int SEGS, int BITS>
-__global__ __launch_bounds__(NW * 64) void fwd_int_kernel(IntArgs a, int n_dblk, int n_tiles, int order) {
+__global__ __launch_bounds__(NW * 64, (min_waves_per_simd<NS, R, NW>())) void fwd_int_kernel(IntArgs a, int n_dblk, int n_tiles, int order) {
   extern __shared__ __align__(16) uint8_t lds[];
   int dblk, tblk;
   tile_of(blockIdx.x, n_dblk, n_tiles, order, dblk, tblk);
@@ -838,7 +1083,7 @@ __global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0
 // reaches the exit.  Between items no extra barrier is needed for the LDS: a
 // tile ends with all of its LDS reads complete behind its final barrier.
 template <int NS, int R, int NW, int CB, int SEGS, int BITS>
-__global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc *__restrict__ beams, int n_beams,
+__global__ __launch_bounds__(NW * 64, (min_waves_per_simd<NS, R, NW>())) void fwd_int_batched_kernel(const BeamDesc *__restrict__ beams, int n_beams,
                                                                    long long n_items,
                                                                    unsigned long long *__restrict__ counter) {
   extern __shared__ __align__(16) uint8_t lds[];
@@ -887,7 +1132,7 @@ __global__ __launch_bounds__(NW * 64) void fwd_int_batched_kernel(const BeamDesc
   X(16, 2, 16, 8, 0) X(16, 4, 8, 8, 0) X(16, 2, 16, 4, 0) X(16, 4, 8, 4, 0) X(16, 1, 16, 8, 0)             \
   X(16, 1, 16, 4, 0) X(16, 1, 16, 2, 0) X(16, 1, 16, 1, 0) X(16, 1, 4, 1, 0) X(16, 1, 1, 1, 0)             \
   X(8, 2, 16, 8, 0) X(16, 2, 8, 4, 0) X(8, 4, 16, 8, 0)                                                    \
-  X(16, 2, 16, 8, 2) X(16, 2, 16, 4, 2) X(16, 2, 8, 4, 2) X(16, 2, 16, 4, 4)
+  X(8, 4, 8, 8, 1) X(16, 2, 16, 8, 2) X(8, 4, 16, 8, 2) X(16, 2, 16, 4, 2) X(16, 2, 8, 4, 2) X(16, 2, 16, 4, 4)
 
 template <int NS, int R, int NW, int CB, int SEGS>
 int launch_int_shape(const dd_plan &p, const void *tables, const void *d_in, float *d_out, int64_t out_pitch,
@@ -912,13 +1157,18 @@ int launch_int_shape(const dd_plan &p, const void *tables, const void *d_in, flo
   if (tiles_t * n_dblk >= ((int64_t)1 << 31)) return (int)hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)(tiles_t * n_dblk)), block(NW * 64);
   const int bits = p.desc.dtype == DD_U4 ? 4 : p.desc.dtype == DD_U16 ? 16 : 8;
-  if constexpr (SEGS > 0) {  // phase loads: 8-bit input only, copy rows within SEGS KiB
-    if (bits != 8 || t.row_bytes > 1024 * SEGS) return (int)hipErrorInvalidValue;
-    const void *fn = (const void *)fwd_int_kernel<NS, R, NW, CB, SEGS, 8>;
+  if constexpr (SEGS > 0) {  // phase loads: 8-bit or packed 4-bit input, copy rows within SEGS KiB
+    if ((bits != 8 && bits != 4) || t.row_bytes > 1024 * SEGS) return (int)hipErrorInvalidValue;
+    const void *fn = bits == 4 ? (const void *)fwd_int_kernel<NS, R, NW, CB, SEGS, 4>
+                               : (const void *)fwd_int_kernel<NS, R, NW, CB, SEGS, 8>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, t.lds_bytes);
     if (e != hipSuccess) return (int)e;
-    hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, SEGS, 8>), grid, block, t.lds_bytes, st, a, (int)n_dblk,
-                       (int)tiles_t, t.order);
+    if (bits == 4)
+      hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, SEGS, 4>), grid, block, t.lds_bytes, st, a, (int)n_dblk,
+                         (int)tiles_t, t.order);
+    else
+      hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, SEGS, 8>), grid, block, t.lds_bytes, st, a, (int)n_dblk,
+                         (int)tiles_t, t.order);
     return (int)hipGetLastError();
   } else {
     const void *fn = bits == 4    ? (const void *)fwd_int_kernel<NS, R, NW, CB, 0, 4>
@@ -965,7 +1215,9 @@ int batch_kernels(int ns, int dm_per_wave, int waves, int chan_block, int segs, 
   const void *fn = nullptr;
 #define DD_TRY(NS, R, NW, CB, SEGS)                                                                        \
   if (ns == NS && dm_per_wave == R && waves == NW && chan_block == CB && segs == SEGS)                     \
-    fn = SEGS > 0 ? (dtype == DD_U8 ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, SEGS, 8> : nullptr) \
+    fn = SEGS > 0 ? (dtype == DD_U8   ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, SEGS, 8>         \
+                     : dtype == DD_U4 ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, SEGS, 4>         \
+                                      : nullptr)                                                             \
          : dtype == DD_U4  ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, 0, 4>                     \
          : dtype == DD_U16 ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, 0, 16>                    \
                            : (const void *)fwd_int_batched_kernel<NS, R, NW, CB, 0, 8>;

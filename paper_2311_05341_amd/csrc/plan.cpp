@@ -117,30 +117,38 @@ static int round_up(int64_t v, int a) { return (int)((v + a - 1) / a * a); }
 // the channel's shifted copies (each row_bytes long): for 8- and 4-bit samples
 // (one byte each once staged) four copies, (v % 4) * row_bytes + (v - v % 4);
 // for 16-bit samples (byte offset 2v) two copies,
-// (v % 2) * row_bytes + 2 * (v - v % 2).
+// (v % 2) * row_bytes + 2 * (v - v % 2).  Phase-load shapes (segs > 0) add
+// the channel's place in the staging slot; for packed 4-bit samples the copies
+// are the eight nibble phases of the packed row and the entry is
+// (v % 8) * row_bytes + 4 * (v / 8).
 // Fails with DD_ERR_RANGE if even one channel per LDS stage does not fit.
 dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves, int chan_block, int segs,
-                           int lds_limit, IntTables *t) {
+                           int lds_limit, IntTables *t, bool fill) {
   const int nc = p.desc.n_chan, nd = p.desc.n_dm;
   const int dblk = waves * dm_per_wave;
   const bool u16 = p.desc.dtype == DD_U16;
-  const int unit = p.desc.dtype == DD_U4 ? 32 : u16 ? 8 : 16;
-  const int copies = u16 ? 2 : 4;
-  const bool phase = segs > 0;  // 8-bit phase-load staging
-  if (phase && p.desc.dtype != DD_U8) return fail(DD_ERR_RANGE, "phase-load staging is for 8-bit input");
+  const bool u4 = p.desc.dtype == DD_U4;
+  const int unit = u4 ? 32 : u16 ? 8 : 16;
+  const bool phase = segs > 0;  // phase-load staging (8-bit, packed 4-bit)
+  if (phase && p.desc.dtype != DD_U8 && !u4) return fail(DD_ERR_RANGE, "phase-load staging is for 8- and 4-bit input");
+  if (phase && u4 && (ns % 8 || chan_block > 16)) return fail(DD_ERR_RANGE, "shape not compiled for 4-bit phase loads");
+  // copies of a staged row: byte phases (4, or 2 for 16-bit samples); packed
+  // 4-bit phase loads keep the eight nibble phases of the packed row
+  const int copies = phase && u4 ? 8 : u16 ? 2 : 4;
   const int span = max_dm_block_span(p, dblk);
   // samples of a staged row: the tile, the spread, the rounding of the stage base
-  // (ring form: and the extra word the phase build reads past a chunk)
-  const int64_t rs = (int64_t)64 * ns + span + unit + (phase ? 0 : 16);
+  // (ring form: and the extra word the phase build reads past a chunk; packed
+  // 4-bit phase loads: a spare word, which the odd nibble copies never fill)
+  const int64_t rs = (int64_t)64 * ns + span + unit + (phase ? (u4 ? 8 : 0) : 16);
   if (rs > (1 << 23)) return fail(DD_ERR_RANGE, "delay spread too large");
-  t->row_bytes = u16 ? round_up(2 * rs, 16) : round_up(rs, unit);
+  t->row_bytes = u16 ? round_up(2 * rs, 16) : phase && u4 ? round_up((rs + 1) / 2, 16) : round_up(rs, unit);
   int64_t lds;
   if (phase) {
-    // LDS: kPhaseSlots slots of chan_block x 4 copies, 1 KB load sink; a copy row
+    // LDS: kPhaseSlots slots of chan_block x copies, 1 KB load sink; a copy row
     // is loaded in at most `segs` 1 KB segments; entries are slot offsets
-    lds = (int64_t)kPhaseSlots * chan_block * 4 * t->row_bytes + 1024;
+    lds = (int64_t)kPhaseSlots * chan_block * copies * t->row_bytes + 1024;
     if ((t->row_bytes + 1023) / 1024 > segs) return fail(DD_ERR_RANGE, "staged rows longer than the shape's loads");
-    if ((int64_t)chan_block * 4 * t->row_bytes > 65536)
+    if ((int64_t)chan_block * copies * t->row_bytes > 65536)
       return fail(DD_ERR_RANGE, "staging slot too large for 16-bit LDS offsets");
   } else {
     // LDS: two buffers of the shifted copies, a ring of 3 raw slots (rows of raw
@@ -154,6 +162,7 @@ dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves,
   t->chan_block = chan_block;
   t->segs = segs;
   t->lds_bytes = (int)lds;
+  if (!fill) return DD_OK;
   const int n_dblk = (nd + dblk - 1) / dblk;
   const int rp = dm_per_wave < 2 ? 2 : dm_per_wave;  // uint16 slots per channel (whole 32-bit words)
   const int ncp = (nc + chan_block - 1) / chan_block * chan_block;  // channels rounded up to whole blocks
@@ -177,9 +186,10 @@ dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves,
           // its first word inside the channel's shifted copies; padding
           // channels (c >= nc, staged as zero rows) read their own row at 0
           const int32_t v = c < nc ? sd[c] - sb[c] : 0;
-          const int32_t slot = phase ? (c % chan_block) * 4 * t->row_bytes : 0;  // channel's copies in the slot
-          o[(size_t)c * rp] = u16 ? (uint16_t)((v & 1) * t->row_bytes + 2 * (v & ~1))
-                                  : (uint16_t)(slot + (v & 3) * t->row_bytes + (v & ~3));
+          const int32_t slot = phase ? (c % chan_block) * copies * t->row_bytes : 0;  // channel's copies in the slot
+          o[(size_t)c * rp] = u16             ? (uint16_t)((v & 1) * t->row_bytes + 2 * (v & ~1))
+                              : phase && u4 ? (uint16_t)(slot + (v & 7) * t->row_bytes + 4 * (v >> 3))
+                                            : (uint16_t)(slot + (v & 3) * t->row_bytes + (v & ~3));
         }
       }
   }
@@ -310,7 +320,8 @@ dd_status set_tiles(dd_plan &p, int direction, int shape, int order) {
 }
 
 // Default tiles: the first compiled shape (they are listed fastest first; for
-// 8-bit plans the phase-load shapes before the others) that holds the plan's
+// 8- and 4-bit plans the phase-load shapes before the others, an 8-wave one
+// only where two of its workgroups fit in a CU's LDS) that holds the plan's
 // delay spread, in the grouped workgroup order (as fast as time tiles fastest
 // on the headline plan, with a third of its L2 fetch traffic).
 // For an integer plan whose spread leaves only LDS shapes staging 1 or 2
@@ -322,9 +333,11 @@ dd_status choose_forward_tiles(dd_plan &p) {
     dd_status last = DD_ERR_RANGE;
     for (int pass = 0; pass < 2 && last != DD_OK && last != DD_ERR_NOMEM; ++pass)
       for (int i = 0; i < num_shapes(p); ++i) {
-        const bool phase = p.desc.dtype == DD_U8 && int_shape_segs(i) > 0;
+        const bool phase = (p.desc.dtype == DD_U8 || p.desc.dtype == DD_U4) && int_shape_segs(i) > 0;
         if (phase != (pass == 0)) continue;
         last = set_tiles(p, dir, i, kOrderDmGroups);
+        // an 8-wave phase-load shape pays only when two of its workgroups share a CU
+        if (last == DD_OK && phase && p.fwd.waves == 8 && 2 * p.fwd.lds_bytes > kLdsLimit) last = DD_ERR_RANGE;
         if (last == DD_OK || last == DD_ERR_NOMEM) break;
       }
     if (last == DD_ERR_NOMEM) return last;

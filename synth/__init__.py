@@ -228,6 +228,11 @@ CONFIGS = {
     "lowfreq_u4": dict(dtype="u4", n_chan=4096, n_samp=1 << 19, f_high=190.0, chan_bw=70.0 / 4096,
                        t_samp=327.68e-6, dm_start=0.0, dm_step=0.1, n_dm=2048, seed=3,
                        pulses=[], amp=0),
+    # The headline plan on packed 4-bit input (two samples per byte), for the
+    # 4-bit against 8-bit comparison on one plan.
+    "headline_u4": dict(dtype="u4", n_chan=8192, n_samp=1 << 20, f_high=1500.0, chan_bw=300.0 / 8192,
+                        t_samp=64e-6, dm_start=0.0, dm_step=0.5, n_dm=4000, seed=7,
+                        pulses=[], amp=0),
     "headline_u16": dict(dtype="u16", n_chan=8192, n_samp=1 << 20, f_high=1500.0, chan_bw=300.0 / 8192,
                          t_samp=64e-6, dm_start=0.0, dm_step=0.5, n_dm=4000, seed=6,
                          pulses=[(100, 1, 100_000), (1600, 4, 460_000), (3800, 16, 820_000)], amp=2560),

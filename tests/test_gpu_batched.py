@@ -54,6 +54,37 @@ def test_batched_matches_oracle_and_plain(dd):
         assert np.array_equal(outs[b][rows].cpu().numpy(), want)
 
 
+def test_batched_mixed_shapes_and_tuned_plan(dd):
+    """Beams whose plans run different staged shapes (a narrow and a wide delay spread, and a
+    plan set to a third shape) run in one batch as several groups, each beam on its plan's own
+    shape: bit-exact against plain calls and the oracle, over two replays."""
+    base = dict(dtype="u8", f_high=1500.0, t_samp=64e-6, dm_start=0.0)
+    beams = [dict(base, n_chan=256, chan_bw=300.0 / 256, n_samp=70016, dm_step=0.25, n_dm=150, seed=951),
+             dict(base, n_chan=300, chan_bw=1.0, n_samp=60032, dm_step=1.0, n_dm=97, seed=952),
+             dict(base, n_chan=96, chan_bw=3.0, n_samp=50048, dm_step=0.5, n_dm=64, seed=953)]
+    plans, xs, hosts, tables = [], [], [], []
+    for cfg in beams:
+        tables.append(oracle_table(cfg))
+        x = synth.gaussian_u8(cfg["n_chan"], cfg["n_samp"], cfg["seed"])
+        plans.append(plan_for(dd, cfg))
+        xs.append(torch.from_numpy(x).cuda())
+        hosts.append(x)
+    plans[2].set_tiles(0, 0, 2)  # a ring-staged shape for the third beam
+    shapes = [p.tiles(0)["shape"] for p in plans]
+    batch = dd.Batch(plans, xs)
+    assert [batch.beam_tiles(b)["shape"] for b in range(3)] == shapes
+    assert len(set(shapes)) >= 2 and batch.tiles()["shape"] == -1
+    outs = [o.clone() for o in batch.run()]
+    outs2 = batch.run()
+    torch.cuda.synchronize()
+    for b, cfg in enumerate(beams):
+        assert torch.equal(outs[b], outs2[b])
+        assert torch.equal(outs[b], plans[b].forward(xs[b]))
+        rows = sample_rows(cfg["n_dm"], every=17)
+        want = oracle.forward(hosts[b], "u8", cfg["n_samp"], tables[b], rows=rows)
+        assert np.array_equal(outs[b][rows].cpu().numpy(), want), b
+
+
 def test_batched_single_beam_and_u4(dd):
     cfg = dict(dtype="u4", n_chan=200, n_samp=50016, f_high=400.0, chan_bw=0.5, t_samp=256e-6,
                dm_start=0.0, dm_step=0.3, n_dm=70)

@@ -295,9 +295,28 @@ def test_batch_tile_choice_host(dd):
             lib.dd_batch_workspace_bytes(h, ctypes.byref(ws))
             assert ws.value == ws0.value
         assert ok and len(ok) < n_staged  # the wide beam rules some shapes out
-        # the default: the first phase-load shape that stages every (8-bit) beam, else the first shape
-        phase_ok = [s for s in ok if segs[s] > 0]
-        assert first == (phase_ok[0] if phase_ok else ok[0])
+        # the default: every beam on its plan's own shape when that is staged, else on the first
+        # staged shape that holds it (phase-load shapes first); here the two beams differ
+        assert first == -1
+    finally:
+        lib.dd_batch_destroy(h)
+    # a fresh batch reports each beam's default
+    lib.dd_batch_get_beam_tiles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(dd.binding.Tiles)]
+    h = ctypes.c_void_p()
+    assert lib.dd_batch_create(arr, 2, ctypes.byref(h)) == 0
+    try:
+        for b, p in enumerate(plans):
+            t = dd.binding.Tiles()
+            assert lib.dd_batch_get_beam_tiles(h, b, ctypes.byref(t)) == 0
+            own = p.tiles(0)
+            assert t.row_block > 0
+            if own["row_block"] > 0:
+                # the plan's own shape, unless its LDS need falls in the 64 bytes the persistent
+                # kernel keeps for itself: then a later staged shape
+                assert t.shape >= own["shape"]
+                if b == 0:
+                    assert t.shape == own["shape"]
+        assert lib.dd_batch_get_beam_tiles(h, 2, ctypes.byref(t)) == -1
     finally:
         lib.dd_batch_destroy(h)
 
