@@ -164,6 +164,26 @@ dd_status dd_execute(const dd_plan *plan, const void *d_in, float *d_out, int64_
                      void *stream);
 
 /*
+ * dd_execute without a workspace, for callers that cannot allocate device
+ * memory or bind one (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, result and errors as
+ * dd_execute, but the plan need not be bound: on every call the plan's device
+ * tables are copied (hipMemcpyAsync on `stream`) into a static device array of
+ * DD_NOALLOC_TABLE_BYTES bytes inside the library, which every device the
+ * library runs on holds until the process ends, and the forward kernels read
+ * them there.  Nothing is allocated or freed.  Plans whose tables
+ * (dev_table_bytes of dd_plan_query) exceed the array are refused with
+ * DD_ERR_RANGE before anything is enqueued.  All calls on one device share the
+ * array and it keeps only the last call's tables: calls on one device must not
+ * overlap in time (one stream, or an explicit ordering between streams);
+ * overlapping calls race on the tables.  Errors: those of dd_execute except
+ * DD_ERR_NOT_BOUND, plus DD_ERR_RANGE.
+ */
+#define DD_NOALLOC_TABLE_BYTES ((size_t)32 << 20)
+dd_status dd_execute_noalloc(const dd_plan *plan, const void *d_in, float *d_out, int64_t out_pitch,
+                             void *stream);
+
+/*
  * Adjoint (transpose of Eq. 3, "re-dispersion") for DD_F32 plans, in gather form:
  *     g(c, tau) = sum_d [0 <= tau - shift(c,d) < n_out] * y(d, tau - shift(c,d)).
  *   d_y        device pointer, float32 [n_dm][y_pitch], columns 0..n_out-1 read;

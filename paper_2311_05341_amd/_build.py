@@ -7,7 +7,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdd.so")
-SOURCES = ["plan.cpp", "api.cpp", "tune.cpp", "batch.cpp", "survey.cpp", "fwd_int.hip", "fwd_direct.hip", "kernels_f32.hip", "bin.hip", "corner.hip"]
+SOURCES = ["plan.cpp", "api.cpp", "tune.cpp", "batch.cpp", "survey.cpp", "fwd_int.hip", "fwd_direct.hip", "kernels_f32.hip", "bin.hip", "corner.hip", "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -71,6 +71,8 @@ _lib.dd_plan_bind.argtypes = [_vp, _vp, _sz, _vp]
 _lib.dd_plan_bind.restype = _i32
 _lib.dd_execute.argtypes = [_vp, _vp, _vp, _i64, _vp]
 _lib.dd_execute.restype = _i32
+_lib.dd_execute_noalloc.argtypes = [_vp, _vp, _vp, _i64, _vp]
+_lib.dd_execute_noalloc.restype = _i32
 _lib.dd_execute_adjoint.argtypes = [_vp, _vp, _i64, _vp, _vp]
 _lib.dd_execute_adjoint.restype = _i32
 _lib.dd_plan_shape_count.argtypes = [_vp, ctypes.POINTER(_i32)]
@@ -297,6 +299,18 @@ class Plan:
         self._check_output(out)
         _check(_lib.dd_execute(self._h, x.data_ptr(), out.data_ptr(), out.stride(0), _stream_handle(stream)),
                "dd_execute")
+        return out[:, : self.n_out]
+
+    def forward_noalloc(self, x, out, stream=None):
+        """dd_execute_noalloc: the forward transform with the plan's tables in the library's
+        static device area instead of a bound workspace; allocates nothing (`out` is required).
+        Works on an unbound plan (bind=False), which then takes x's device for its checks."""
+        if self.device is None:
+            self.device = x.device
+        self._check_input(x)
+        self._check_output(out)
+        _check(_lib.dd_execute_noalloc(self._h, x.data_ptr(), out.data_ptr(), out.stride(0), _stream_handle(stream)),
+               "dd_execute_noalloc")
         return out[:, : self.n_out]
 
     def adjoint(self, y, out=None, stream=None):
