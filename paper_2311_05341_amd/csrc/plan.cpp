@@ -335,6 +335,10 @@ dd_status choose_forward_tiles(dd_plan &p) {
       for (int i = 0; i < num_shapes(p); ++i) {
         const bool phase = (p.desc.dtype == DD_U8 || p.desc.dtype == DD_U4) && int_shape_segs(i) > 0;
         if (phase != (pass == 0)) continue;
+        // 4-bit phase loads build half their copies in LDS every block: with fewer than 8
+        // channels per stage that costs more than it saves (measured on 4096 ch x 2^19,
+        // 120-190 MHz: 19.6-21.7 Tadds/s against 25.3 for the raw ring)
+        if (phase && p.desc.dtype == DD_U4 && int_shape(i)[3] < 8) continue;
         last = set_tiles(p, dir, i, kOrderDmGroups);
         // an 8-wave phase-load shape pays only when two of its workgroups share a CU
         if (last == DD_OK && phase && p.fwd.waves == 8 && 2 * p.fwd.lds_bytes > kLdsLimit) last = DD_ERR_RANGE;

@@ -41,6 +41,11 @@ def test_headline_traffic_matches_the_current_kernel():
     """The headline's default tiles have counters taken on the kernel source as committed;
     after a change to that source the counters must be taken again (bench.py then reports
     the traffic as unknown)."""
-    traffic, src = _bench().measured_traffic("headline", {"shape": 0, "order": 2})
+    import paper_2311_05341_amd as dd
+    import synth
+    c = synth.CONFIGS["headline"]
+    plan = dd.Plan(c["n_chan"], c["n_samp"], c["dtype"], c["f_high"], c["chan_bw"], c["t_samp"], c["dm_start"],
+                   c["dm_step"], c["n_dm"], bind=False)
+    traffic, src = _bench().measured_traffic("headline", plan.tiles(0))
     assert traffic is not None and src.startswith("profiles" + os.sep)
     assert traffic > 24.85e9  # at least the algorithmic bytes (input once + output once)
