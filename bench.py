@@ -849,9 +849,10 @@ def main():
         "host": host_cpu(),
     }
     if tiles["row_block"] == 0 and cfg["dtype"] != "f32":
-        # The direct-read kernel loads 16 + 4 bytes per 16 samples of 8-bit (or 32 of 4-bit) input
-        # from L1/L2 for every (channel, DM) pair: that load stream, not the VALU, bounds it.
-        per_add = {"u8": 20 / 16, "u4": 20 / 32, "u16": 36 / 16}[cfg["dtype"]]
+        # The direct-read kernel loads 16 bytes per 16 samples of 8-bit (or 32 of 4-bit) input from
+        # L1/L2 for every (channel, DM) pair (the word after them comes from the next lane): that
+        # load stream, not the VALU, bounds it.
+        per_add = {"u8": 16 / 16, "u4": 16 / 32, "u16": 32 / 16}[cfg["dtype"]]
         rec["load_path"] = {"bytes_per_add": per_add, "achieved_TB_s": achieved * per_add}
     if not args.no_cpu_baseline:
         log("cpu baseline ...")

@@ -248,7 +248,7 @@ dd_status dd_plan_autotune(dd_plan *plan, int32_t direction, const void *d_src, 
  * (channel count, length, DM plan), run by persistent kernel launches that pull
  * (beam, DM block, time tile) work items from a device counter, largest items
  * first.  Every beam has a staged tile shape of its own; the beams of one shape
- * form a group, one persistent launch per group, the groups one after another.
+ * form a group, one persistent launch per group, the groups independent of each other.
  * The launch sequence is recorded once as a HIP graph and replayed by every
  * dd_execute_batched call.  By default a beam runs its plan's own forward tile
  * shape (the plan's default, or what the plan was set or tuned to) when that is

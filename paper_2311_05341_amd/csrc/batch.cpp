@@ -2,8 +2,8 @@
 // kernel launches recorded once as a HIP graph and replayed by
 // dd_execute_batched.  Each beam has a staged tile shape of its own; beams of
 // one shape form a group, and each group is one persistent launch (counter
-// reset, then the kernel claiming that group's work items), the groups one
-// after another in the graph.
+// reset, then the kernel claiming that group's work items), the groups
+// independent nodes of the graph.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -264,12 +264,12 @@ dd_status dd_batch_bind(dd_batch *b, const void *const *d_in, float *const *d_ou
   if (e != hipSuccess) return fail(DD_ERR_HIP, std::string("batch upload: ") + hipGetErrorString(e));
 
   // The graph: per group, a counter reset and then the group's persistent
-  // kernel, the groups chained one after another.  The node parameters are
-  // copied when the nodes are added, so per-group argument storage only has to
-  // live until then.
+  // kernel.  The groups do not depend on each other, so the runtime may run
+  // them side by side (a group's workgroups then fill the CUs that another
+  // group's tail leaves idle).  The node parameters are copied when the nodes
+  // are added, so per-group argument storage only has to live until then.
   release_graph(b);
   e = hipGraphCreate(&b->graph, 0);
-  hipGraphNode_t prev = nullptr;
   for (size_t gi = 0; gi < b->groups.size() && e == hipSuccess; ++gi) {
     const BatchGroup &g = b->groups[gi];
     const int *k = kIntShapes[g.shape];
@@ -297,7 +297,7 @@ dd_status dd_batch_bind(dd_batch *b, const void *const *d_in, float *const *d_ou
     kp.blockDim = dim3(1);
     kp.sharedMemBytes = 0;
     kp.kernelParams = reset_args;
-    e = hipGraphAddKernelNode(&n_reset, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    e = hipGraphAddKernelNode(&n_reset, b->graph, nullptr, 0, &kp);
     if (e != hipSuccess) break;
     memset(&kp, 0, sizeof(kp));
     kp.func = (void *)L.main_fn;
@@ -306,7 +306,6 @@ dd_status dd_batch_bind(dd_batch *b, const void *const *d_in, float *const *d_ou
     kp.sharedMemBytes = L.lds_bytes;
     kp.kernelParams = main_args;
     e = hipGraphAddKernelNode(&n_main, b->graph, &n_reset, 1, &kp);
-    prev = n_main;
   }
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
   if (e != hipSuccess) {

@@ -13,7 +13,8 @@
 //
 // Windows start at any sample, but the loads stay 4-byte aligned: a lane
 // loads the aligned words covering its 16-byte (8-bit input; 32-byte for
-// 16-bit) window plus one more, and funnel-shifts them (v_alignbit, by a
+// 16-bit) window, takes the word after them from the next lane (a wave shift,
+// DPP; lane 63 loads its own), and funnel-shifts them (v_alignbit, by a
 // wave-uniform bit count) into the window's words.  Each (channel, DM) pair
 // gets its own raw buffer descriptor based at the window's first aligned word,
 // with the rest of the channel's row pitch as its record bound, and the loads
@@ -113,6 +114,7 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
     for (int c = cb; c < ce; c += kUnroll) {
       uint32_t raw[kUnroll][R][WORDS + 1];
       int sh[kUnroll][R];
+      __amdgpu_buffer_rsrc_t rsr[kUnroll][R];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int cc = min(c + u, ce - 1);
@@ -139,9 +141,28 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
 #pragma unroll
             for (int q = 0; q < WORDS; ++q) raw[u][r][q] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo + 4 * q, 0, 0);
           }
-          raw[u][r][WORDS] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo + 4 * WORDS, 0, 0);
+          rsr[u][r] = rs;
         }
       }
+      // The word after a lane's window is the next lane's first word: lanes 0..62 take it from
+      // their neighbour (a wave shift, DPP), and only lane 63 loads it, all in one branch.
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int r = 0; r < R; ++r) raw[u][r][WORDS] = 0;
+      if (lane == 63) {
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+            raw[u][r][WORDS] = __builtin_amdgcn_raw_buffer_load_b32(rsr[u][r], vo + 4 * WORDS, 0, 0);
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+        for (int r = 0; r < R; ++r)  // wave_shl:1; lane 63 keeps its own load (no source lane)
+          raw[u][r][WORDS] = (uint32_t)__builtin_amdgcn_update_dpp((int)raw[u][r][WORDS], (int)raw[u][r][0], 0x130,
+                                                                   0xF, 0xF, false);
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const uint32_t live = c + u < ce ? 0xFFFFFFFFu : 0u;  // the unrolled tail repeats a channel
