@@ -41,7 +41,7 @@ int copy_tables(const dd_plan &p, void *dst, void *stream) {
   if (p.desc.dtype != DD_F32 && is_direct(p.fwd)) {  // the direct kernel reads the plain shift table
     e = hipMemcpyAsync(base + L.int_offs, p.shift.data(), p.shift.size() * sizeof(int32_t), hipMemcpyHostToDevice, st);
   } else if (p.desc.dtype != DD_F32) {
-    e = hipMemcpyAsync(base + L.int_offs, p.itab.offs.data(), p.itab.offs.size() * 2, hipMemcpyHostToDevice, st);
+    e = hipMemcpyAsync(base + L.int_offs, p.itab.offs.data(), p.itab.offs.size() * 4, hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
       e = hipMemcpyAsync(base + L.int_sbase, p.itab.sbase.data(), p.itab.sbase.size() * 4, hipMemcpyHostToDevice, st);
   } else {

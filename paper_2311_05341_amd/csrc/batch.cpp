@@ -66,8 +66,8 @@ static void release_graph(dd_batch *b) {
 // rounded up to 256 bytes.
 static void int_table_bytes(const dd_plan &p, const int *k, size_t *offs, size_t *sbase) {
   const int64_t nd = p.desc.n_dm, nc = p.desc.n_chan, dblk = (int64_t)k[1] * k[2];
-  const int64_t n_dblk = (nd + dblk - 1) / dblk, rp = k[1] < 2 ? 2 : k[1], ncp = (nc + k[3] - 1) / k[3] * k[3];
-  *offs = up256((size_t)(n_dblk * k[2] * ncp * rp) * sizeof(uint16_t));
+  const int64_t n_dblk = (nd + dblk - 1) / dblk, ew = int_entry_words(k[1], k[4]), ncp = (nc + k[3] - 1) / k[3] * k[3];
+  *offs = up256((size_t)(n_dblk * k[2] * ncp * ew) * sizeof(uint32_t));
   *sbase = up256((size_t)(n_dblk * nc) * sizeof(int32_t));
 }
 
@@ -255,7 +255,7 @@ dd_status dd_batch_bind(dd_batch *b, const void *const *d_in, float *const *d_ou
   hipStream_t st = (hipStream_t)stream;
   e = hipMemcpyAsync(base + descs_offset(), b->descs.data(), sizeof(BeamDesc) * n, hipMemcpyHostToDevice, st);
   for (int i = 0; i < n && e == hipSuccess; ++i) {
-    e = hipMemcpyAsync(base + b->table_offs[i], b->tables[i].offs.data(), b->tables[i].offs.size() * 2,
+    e = hipMemcpyAsync(base + b->table_offs[i], b->tables[i].offs.data(), b->tables[i].offs.size() * 4,
                        hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
       e = hipMemcpyAsync(base + b->sbase_offs[i], b->tables[i].sbase.data(), b->tables[i].sbase.size() * 4,

@@ -43,8 +43,14 @@ enum TileOrder {
 // the staging unit) and, per (block, wave, channel, row), the LDS byte offset
 // of the window's first word as uint16 (inside the channel's shifted copies
 // for the ring form, from the start of the staging slot for the phase-load form).
+// Entries are 32-bit words: raw-ring shapes pack two uint16 entries per word
+// (row r at bits 16 * (r % 2) of word r / 2); phase-load shapes hold one
+// entry per word (the byte offset from the staging slot's start).
+inline int int_entry_words(int dm_per_wave, int segs) {
+  return segs > 0 ? dm_per_wave : (dm_per_wave < 2 ? 2 : dm_per_wave) / 2;
+}
 struct IntTables {
-  std::vector<uint16_t> offs;  // [n_dblk][waves][n_chan rounded up to chan_block][max(dm_per_wave, 2)]
+  std::vector<uint32_t> offs;  // [n_dblk][waves][n_chan rounded up to chan_block][int_entry_words]
   std::vector<int32_t> sbase;  // [n_dblk][n_chan]
   int row_bytes = 0, chan_block = 0, segs = 0, lds_bytes = 0;
 };
@@ -95,7 +101,7 @@ dd_status set_tiles(dd_plan &p, int direction, int shape, int order);
 int num_shapes(const dd_plan &p);
 size_t table_bytes(const dd_plan &p);
 // Byte offsets of the plan's current tables inside a table workspace of
-// table_bytes(p) bytes.  Integer plans: [offs uint16][sbase int32] (direct-read
+// table_bytes(p) bytes.  Integer plans: [offs words][sbase int32] (direct-read
 // shapes: the plain int32 shift table at 0).  Float plans: [forward offs]
 // [forward sbase][adjoint offs][adjoint sbase].  Each part starts on 256 bytes.
 struct TableLayout {

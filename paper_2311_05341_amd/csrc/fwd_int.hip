@@ -161,7 +161,7 @@ __device__ __forceinline__ void store_u16_pair(float *orow, int64_t t, int64_t n
 // Kernel arguments shared by the plain and the batched kernels.
 struct IntArgs {
   const uint8_t *x;       // [n_chan][pitch] bytes
-  const uint32_t *offs;   // [n_dblk][NW][n_chan][max(R,2)/2]: pairs of uint16 LDS offsets (see build_int_tables)
+  const uint32_t *offs;   // [n_dblk][NW][n_chan][words]: LDS offsets (see build_int_tables, int_entry_words)
   const int32_t *sbase;   // [n_dblk][n_chan]: stage base (first-DM shift rounded down to the unit)
   float *out;             // [n_dm][out_pitch]
   int64_t pitch, n_samp, n_out, out_pitch;
@@ -707,8 +707,7 @@ __device__ __forceinline__ bool phase_near_end(const IntArgs &a, int64_t t0) {
 template <int NS, int R, int NW, int CB, int SEGS>
 __device__ __forceinline__ void fwd_u8_phase_tile(uint8_t *lds, const IntArgs &a, int dblk, int tblk) {
   constexpr int NWD = NS / 4;
-  constexpr int RP = R < 2 ? 2 : R;
-  constexpr int NOW = RP / 2;
+  constexpr int NOW = R;  // one 32-bit table entry per (channel, row)
   constexpr int J = PhasePlan<CB, SEGS, NW>::J;
   constexpr int LOADS = 4 * J;  // loads per wave and block
   const int lane = threadIdx.x & 63;
@@ -761,7 +760,7 @@ __device__ __forceinline__ void fwd_u8_phase_tile(uint8_t *lds, const IntArgs &a
     auto read_chan = [&](int cc, uint32_t (&dst)[R][NWD]) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const uint32_t e = (ow[cc * NOW + (r >> 1)] >> (16 * (r & 1))) & 0xFFFFu;
+        const uint32_t e = ow[cc * NOW + r];
         const uint32_t *p = (const uint32_t *)(blk + e);
 #pragma unroll
         for (int k = 0; k < NWD; ++k) dst[r][k] = p[64 * k];
@@ -786,7 +785,7 @@ __device__ __forceinline__ void fwd_u8_phase_tile(uint8_t *lds, const IntArgs &a
             mix[r][k] += w;
             odd[r][k] += __builtin_amdgcn_perm(w, w, kOddSel);
           }
-      if (2 * pc + 2 < CB) {
+      if (NWD > 2 && 2 * pc + 2 < CB) {  // pinned for wider windows; 8-sample windows run 1.4% faster unpinned
         __builtin_amdgcn_sched_group_barrier(0x100, R * NWD, 0);      // DS reads: the next pair
         __builtin_amdgcn_sched_group_barrier(0x002, 8 * R * NWD, 0);  // VALU: this pair's adds
       }
@@ -926,8 +925,7 @@ __device__ __forceinline__ void fwd_u4_phase_tile(uint8_t *lds, const IntArgs &a
   static_assert(NS % 8 == 0, "4-bit phase tiles take whole 8-sample words per lane");
   constexpr int NT = NW * 64;
   constexpr int NWD = NS / 8;
-  constexpr int RP = R < 2 ? 2 : R;
-  constexpr int NOW = RP / 2;
+  constexpr int NOW = R;  // one 32-bit table entry per (channel, row)
   constexpr int J = PhasePlan<CB, SEGS, NW>::J;
   constexpr int LOADS = 4 * J;  // loads per wave and block
   constexpr int kFlushChans = 16;
@@ -982,7 +980,7 @@ __device__ __forceinline__ void fwd_u4_phase_tile(uint8_t *lds, const IntArgs &a
     auto read_chan = [&](int cc, uint32_t (&dst)[R][NWD]) {
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const uint32_t e = (ow[cc * NOW + (r >> 1)] >> (16 * (r & 1))) & 0xFFFFu;
+        const uint32_t e = ow[cc * NOW + r];
         const uint32_t *p = (const uint32_t *)(blk + e);
 #pragma unroll
         for (int k = 0; k < NWD; ++k) dst[r][k] = p[64 * k];

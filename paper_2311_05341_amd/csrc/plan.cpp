@@ -164,10 +164,10 @@ dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves,
   t->lds_bytes = (int)lds;
   if (!fill) return DD_OK;
   const int n_dblk = (nd + dblk - 1) / dblk;
-  const int rp = dm_per_wave < 2 ? 2 : dm_per_wave;  // uint16 slots per channel (whole 32-bit words)
+  const int ew = int_entry_words(dm_per_wave, segs);  // 32-bit words per channel
   const int ncp = (nc + chan_block - 1) / chan_block * chan_block;  // channels rounded up to whole blocks
   try {
-    t->offs.assign((size_t)n_dblk * waves * ncp * rp, 0);
+    t->offs.assign((size_t)n_dblk * waves * ncp * ew, 0);
     t->sbase.assign((size_t)n_dblk * nc, 0);
   } catch (const std::bad_alloc &) {
     return fail(DD_ERR_NOMEM, "table allocation failed");
@@ -180,16 +180,20 @@ dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves,
       for (int r = 0; r < dm_per_wave; ++r) {
         const int d = std::min(b * dblk + w * dm_per_wave + r, nd - 1);
         const int32_t *sd = p.shift.data() + (size_t)d * nc;
-        uint16_t *o = t->offs.data() + (((size_t)b * waves + w) * ncp) * rp + r;
+        uint32_t *o = t->offs.data() + (((size_t)b * waves + w) * ncp) * ew;
         for (int c = 0; c < ncp; ++c) {
           // window offset v (samples) inside the staged row -> byte offset of
           // its first word inside the channel's shifted copies; padding
           // channels (c >= nc, staged as zero rows) read their own row at 0
           const int32_t v = c < nc ? sd[c] - sb[c] : 0;
           const int32_t slot = phase ? (c % chan_block) * copies * t->row_bytes : 0;  // channel's copies in the slot
-          o[(size_t)c * rp] = u16             ? (uint16_t)((v & 1) * t->row_bytes + 2 * (v & ~1))
-                              : phase && u4 ? (uint16_t)(slot + (v & 7) * t->row_bytes + 4 * (v >> 3))
-                                            : (uint16_t)(slot + (v & 3) * t->row_bytes + (v & ~3));
+          const uint32_t e = u16             ? (uint32_t)((v & 1) * t->row_bytes + 2 * (v & ~1))
+                             : phase && u4 ? (uint32_t)(slot + (v & 7) * t->row_bytes + 4 * (v >> 3))
+                                           : (uint32_t)(slot + (v & 3) * t->row_bytes + (v & ~3));
+          if (phase)
+            o[(size_t)c * ew + r] = e;
+          else
+            o[(size_t)c * ew + (r >> 1)] |= e << (16 * (r & 1));
         }
       }
   }
@@ -370,12 +374,12 @@ dd_status choose_forward_tiles(dd_plan &p) {
 
 static size_t up256(size_t v) { return (v + 255) / 256 * 256; }
 
-// Device workspace layout.  Integer plans: [offs uint16][sbase int32].
+// Device workspace layout.  Integer plans: [offs words][sbase int32].
 // Float plans: [forward offs][forward sbase][adjoint offs][adjoint sbase].
 TableLayout table_layout(const dd_plan &p) {
   TableLayout L;
   if (p.desc.dtype != DD_F32) {
-    if (!is_direct(p.fwd)) L.int_sbase = up256(p.itab.offs.size() * sizeof(uint16_t));
+    if (!is_direct(p.fwd)) L.int_sbase = up256(p.itab.offs.size() * sizeof(uint32_t));
     return L;
   }
   size_t off = 0;
@@ -392,32 +396,33 @@ TableLayout table_layout(const dd_plan &p) {
 size_t table_bytes(const dd_plan &p) {
   if (p.desc.dtype != DD_F32 && is_direct(p.fwd)) return up256(p.shift.size() * sizeof(int32_t));
   if (p.desc.dtype != DD_F32)
-    return up256(p.itab.offs.size() * sizeof(uint16_t)) + up256(p.itab.sbase.size() * sizeof(int32_t));
+    return up256(p.itab.offs.size() * sizeof(uint32_t)) + up256(p.itab.sbase.size() * sizeof(int32_t));
   return up256(p.ftab_fwd.offs.size() * 2) + up256(p.ftab_fwd.sbase.size() * 4) + up256(p.ftab_adj.offs.size() * 2) +
          up256(p.ftab_adj.sbase.size() * 4);
 }
 
 // Table sizes follow the layouts of build_int_tables / build_float_tables
-// (offs: per output block, wave and padded row, max(per_wave, 2) uint16
+// (offs: per output block, wave and padded row, `entry_bytes` bytes of
 // entries; sbase: per output block and row, one int32).
-static size_t shape_table_bytes(int64_t n_out, int64_t n_rows, const int *k) {
+static size_t shape_table_bytes(int64_t n_out, int64_t n_rows, const int *k, int64_t entry_bytes) {
   const int64_t per_wave = k[1], waves = k[2], rb = k[3];
   const int64_t n_oblk = (n_out + waves * per_wave - 1) / (waves * per_wave);
   const int64_t rows_pad = (n_rows + rb - 1) / rb * rb;
-  return up256((size_t)(n_oblk * waves * rows_pad * std::max<int64_t>(per_wave, 2) * 2)) +
-         up256((size_t)(n_oblk * n_rows * 4));
+  return up256((size_t)(n_oblk * waves * rows_pad * entry_bytes)) + up256((size_t)(n_oblk * n_rows * 4));
 }
 
 size_t tune_table_bytes(const dd_plan &p) {
   const int64_t nc = p.desc.n_chan, nd = p.desc.n_dm;
   size_t fwd = 0, adj = 0;
   if (p.desc.dtype != DD_F32) {
-    for (int i = 0; i < kNumIntShapes; ++i) fwd = std::max(fwd, shape_table_bytes(nd, nc, kIntShapes[i]));
+    for (int i = 0; i < kNumIntShapes; ++i)
+      fwd = std::max(fwd, shape_table_bytes(nd, nc, kIntShapes[i], 4 * int_entry_words(kIntShapes[i][1], kIntShapes[i][4])));
     return std::max(fwd, up256((size_t)nd * (size_t)nc * sizeof(int32_t)));  // direct shapes: the shift table
   }
   for (int i = 0; i < kNumF32Shapes; ++i) {
-    fwd = std::max(fwd, shape_table_bytes(nd, nc, kF32Shapes[i]));
-    adj = std::max(adj, shape_table_bytes(nc, nd, kF32Shapes[i]));
+    const int64_t eb = 2 * std::max(kF32Shapes[i][1], 2);  // max(per_wave, 2) uint16 entries
+    fwd = std::max(fwd, shape_table_bytes(nd, nc, kF32Shapes[i], eb));
+    adj = std::max(adj, shape_table_bytes(nc, nd, kF32Shapes[i], eb));
   }
   return fwd + adj;
 }
