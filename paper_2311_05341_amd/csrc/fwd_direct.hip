@@ -25,9 +25,10 @@
 // the pitch and the delay offset are multiples of 4 bytes), so the bound check
 // never drops bytes a valid output needs.
 //
-// Accumulation is the same exact SIMD-in-word arithmetic as the LDS kernel:
-// 8-bit words as mix/odd pairs flushed every 256 channels, 4-bit words first
-// split into their even and odd nibbles, 16-bit words as mix and high halves.
+// Accumulation is the same exact SIMD-in-word arithmetic as the LDS kernels:
+// 8-bit words as mix/odd pairs flushed every 256 channels, 4-bit words as even
+// nibbles (E) and the word shifted down a nibble (S) flushed every 16 channels,
+// 16-bit words as mix and high halves.
 //
 // A workgroup covers NW * R DM rows x 64 * NS samples; wave w owns R rows, lane
 // i samples NS*i .. NS*i + NS-1 of the tile (NS = 16, or 32 for 4-bit input).
@@ -62,6 +63,25 @@ __device__ __forceinline__ void store_total(float *o, uint32_t v, int mode) {
     *o = (float)((double)*(const uint32_t *)o + 65536.0 * (double)v);
   else
     *o = (float)v;
+}
+
+// acc + byte M of w (zero-extended): one SDWA add.
+template <int M>
+__device__ __forceinline__ uint32_t add_byte(uint32_t acc, uint32_t w) {
+  uint32_t r;
+  if constexpr (M == 0)
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_0"
+        : "=v"(r) : "v"(acc), "v"(w));
+  else if constexpr (M == 1)
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_1"
+        : "=v"(r) : "v"(acc), "v"(w));
+  else if constexpr (M == 2)
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_2"
+        : "=v"(r) : "v"(acc), "v"(w));
+  else
+    asm("v_add_u32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:DWORD src1_sel:BYTE_3"
+        : "=v"(r) : "v"(acc), "v"(w));
+  return r;
 }
 
 template <typename T>
@@ -101,16 +121,10 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
 #pragma unroll
     for (int k = 0; k < WORDS; ++k) mix[r][k] = odd[r][k] = 0;
   }
-  constexpr int kFlush = BITS == 16 ? (1 << 30) : 256;  // channels between exact flushes
+  // channels between exact flushes: 256 for bytes, 16 for nibbles (no byte lane of E above 255)
+  constexpr int kFlush = BITS == 16 ? (1 << 30) : BITS == 4 ? 16 : 256;
   for (int cb = 0; cb < a.n_chan; cb += kFlush) {
     const int ce = min(cb + kFlush, a.n_chan);
-    uint32_t me[R][WORDS], mo[R][WORDS], oe[R][WORDS], oo[R][WORDS];  // 4-bit: even / odd nibble words
-    if constexpr (BITS == 4) {
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int k = 0; k < WORDS; ++k) me[r][k] = mo[r][k] = oe[r][k] = oo[r][k] = 0;
-    }
     for (int c = cb; c < ce; c += kUnroll) {
       uint32_t raw[kUnroll][R][WORDS + 1];
       int sh[kUnroll][R];
@@ -177,18 +191,15 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
             } else if constexpr (BITS == 16) {
               mix[r][k] += v;
               odd[r][k] += v >> 16;
-            } else {
-              const uint32_t e = v & 0x0F0F0F0Fu, o = (v >> 4) & 0x0F0F0F0Fu;
-              me[r][k] += e;
-              oe[r][k] += __builtin_amdgcn_perm(e, e, kOdd);
-              mo[r][k] += o;
-              oo[r][k] += __builtin_amdgcn_perm(o, o, kOdd);
+            } else {  // nibbles: E = even nibbles in the byte lanes, S = the word shifted down a nibble
+              mix[r][k] += v & 0x0F0F0F0Fu;
+              odd[r][k] += v >> 4;
             }
           }
         }
       }
     }
-    // Flush the block of at most 256 channels into the int32 totals.
+    // Flush the block of channels into the int32 totals.  Bytes:
     // mix - (odd << 8) = sum of bytes 0 + 2^16 * sum of bytes 2 (each sum < 2^16).
     if constexpr (BITS == 8) {
 #pragma unroll
@@ -203,21 +214,23 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
           mix[r][k] = odd[r][k] = 0;
         }
     } else if constexpr (BITS == 4) {
-      // word k holds samples 8k .. 8k+7; even nibbles are samples 8k, 8k+2, 8k+4, 8k+6
+      // word k holds samples 8k .. 8k+7: byte m of E is sample 8k + 2m, byte m of the odd-nibble
+      // sums O = S - 16 * (E >> 8) is sample 8k + 2m + 1 (no byte lane above 255 after 16 channels)
 #pragma unroll
       for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int k = 0; k < WORDS; ++k) {
-          const uint32_t ee = me[r][k] - (oe[r][k] << 8), eo = oe[r][k];
-          const uint32_t oe2 = mo[r][k] - (oo[r][k] << 8), oo2 = oo[r][k];
-          tot[r][8 * k + 0] += ee & 0xFFFFu;
-          tot[r][8 * k + 2] += eo & 0xFFFFu;
-          tot[r][8 * k + 4] += ee >> 16;
-          tot[r][8 * k + 6] += eo >> 16;
-          tot[r][8 * k + 1] += oe2 & 0xFFFFu;
-          tot[r][8 * k + 3] += oo2 & 0xFFFFu;
-          tot[r][8 * k + 5] += oe2 >> 16;
-          tot[r][8 * k + 7] += oo2 >> 16;
+          const uint32_t e = mix[r][k], o = odd[r][k] - ((e >> 4) & 0x0FFFFFF0u);
+          uint32_t *t = tot[r] + 8 * k;
+          t[0] = add_byte<0>(t[0], e);
+          t[2] = add_byte<1>(t[2], e);
+          t[4] = add_byte<2>(t[4], e);
+          t[6] = add_byte<3>(t[6], e);
+          t[1] = add_byte<0>(t[1], o);
+          t[3] = add_byte<1>(t[3], o);
+          t[5] = add_byte<2>(t[5], o);
+          t[7] = add_byte<3>(t[7], o);
+          mix[r][k] = odd[r][k] = 0;
         }
     }
   }

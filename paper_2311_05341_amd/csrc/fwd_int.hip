@@ -134,16 +134,18 @@ __device__ __forceinline__ float combine_split(uint32_t lo_total, uint32_t hi_to
   return (float)((double)lo_total + 65536.0 * (double)hi_total);
 }
 
-__device__ __forceinline__ void store_u16_pair(float *orow, int64_t t, int64_t n_out, uint32_t v0, uint32_t v1,
-                                               int mode) {
+// The mode is a template parameter: a run-time choice here raised the 16-bit
+// kernels' register use from 116 to 138 VGPRs, below two workgroups per CU.
+template <int MODE>
+__device__ __forceinline__ void store_u16_pair(float *orow, int64_t t, int64_t n_out, uint32_t v0, uint32_t v1) {
   if (t >= n_out) return;
   const bool both = t + 1 < n_out;
-  if (mode == kOutRawTotals) {
+  if constexpr (MODE == kOutRawTotals) {
     if (both)
       *(uint2 *)(orow + t) = make_uint2(v0, v1);
     else
       *(uint32_t *)(orow + t) = v0;
-  } else if (mode == kOutCombineHigh) {
+  } else if constexpr (MODE == kOutCombineHigh) {
     if (both) {
       const uint2 lo = *(const uint2 *)(orow + t);
       *(float2 *)(orow + t) = make_float2(combine_split(lo.x, v0), combine_split(lo.y, v1));
@@ -166,7 +168,6 @@ struct IntArgs {
   float *out;             // [n_dm][out_pitch]
   int64_t pitch, n_samp, n_out, out_pitch;
   int32_t n_chan, n_dm, row_bytes;
-  int32_t out_mode;       // 16-bit input only: an OutMode (float totals, or one half of a split-plane sum)
 };
 
 // Workgroup barrier for LDS hand-offs.  __syncthreads() also waits for every
@@ -381,8 +382,9 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
 }
 
-// One tile: DM block `dblk`, time tile `tblk`.
-template <int NS, int R, int NW, int CB, int BITS>
+// One tile: DM block `dblk`, time tile `tblk`.  OM: the OutMode of the
+// 16-bit epilogue (kOutFloat for other inputs).
+template <int NS, int R, int NW, int CB, int BITS, int OM>
 __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int dblk, int tblk) {
   constexpr int NT = NW * 64;
   constexpr int NPH = num_phases<BITS>();
@@ -543,7 +545,7 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
       for (int k = 0; k < NWD; ++k) {
         const int64_t t = t0 + 2 * (int64_t)(lane + 64 * k);
         const uint32_t lo = mix[r][k] - (odd[r][k] << 16);
-        store_u16_pair(orow, t, a.n_out, lo, odd[r][k], a.out_mode);
+        store_u16_pair<OM>(orow, t, a.n_out, lo, odd[r][k]);
       }
       continue;
     }
@@ -1043,10 +1045,10 @@ __device__ __forceinline__ void fwd_u4_phase_tile(uint8_t *lds, const IntArgs &a
 // One tile of either staging form: SEGS == 0 is the ring form (fwd_int_tile),
 // SEGS > 0 the phase-load form for 8-bit or packed 4-bit input with at most
 // SEGS 1 KiB load segments per copy row.
-template <int NS, int R, int NW, int CB, int SEGS, int BITS>
+template <int NS, int R, int NW, int CB, int SEGS, int BITS, int OM = kOutFloat>
 __device__ __forceinline__ void int_tile(uint8_t *lds, const IntArgs &a, int dblk, int tblk) {
   if constexpr (SEGS == 0)
-    fwd_int_tile<NS, R, NW, CB, BITS>(lds, a, dblk, tblk);
+    fwd_int_tile<NS, R, NW, CB, BITS, OM>(lds, a, dblk, tblk);
   else if constexpr (BITS == 4)
     fwd_u4_phase_tile<NS, R, NW, CB, SEGS>(lds, a, dblk, tblk);
   else
@@ -1061,20 +1063,23 @@ template <int NS, int R, int NW>
 constexpr int min_waves_per_simd() { return NW == 8 && NS * R <= 32 ? 4 : 1; }
 
 // One workgroup per tile; 1-D grid of n_dblk * n_tiles workgroups.
-template <int NS, int R, int NW, int CB, int SEGS, int BITS>
+template <int NS, int R, int NW, int CB, int SEGS, int BITS, int OM = kOutFloat>
 __global__ __launch_bounds__(NW * 64, (min_waves_per_simd<NS, R, NW>())) void fwd_int_kernel(IntArgs a, int n_dblk, int n_tiles, int order) {
   extern __shared__ __align__(16) uint8_t lds[];
   int dblk, tblk;
   tile_of(blockIdx.x, n_dblk, n_tiles, order, dblk, tblk);
-  int_tile<NS, R, NW, CB, SEGS, BITS>(lds, a, dblk, tblk);
+  int_tile<NS, R, NW, CB, SEGS, BITS, OM>(lds, a, dblk, tblk);
 }
 
 __global__ void reset_counter_kernel(unsigned long long *counter) { *counter = 0ull; }
 
 // Persistent batched forward kernel.  Workgroups claim work items (beam, DM
 // block, time tile) from a device counter; items are numbered beam by beam
-// with the beams in decreasing cost order and, inside a beam, time tile
-// fastest (as the plain launch's default order).  The claim of the next item
+// with the beams in decreasing cost order and, inside a beam, DM block
+// fastest: the items claimed at about the same time stage the same input rows
+// (one time tile), which the XCDs' L2 caches then share, as in the XCD-aware
+// orders of the plain launch (time tile fastest measured 2.3% slower than plain
+// launches on the 48-beam job).  The claim of the next item
 // is issued when an item starts and read when it ends, so its latency hides
 // behind the tile.  Claims only grow, so the beam index only moves forward.
 // A workgroup returns at its first claim past the last item: every wave
@@ -1100,7 +1105,7 @@ __global__ __launch_bounds__(NW * 64, (min_waves_per_simd<NS, R, NW>())) void fw
     while (lo + 1 < n_beams && scalar_load(&beams[lo + 1].item_begin, 0) <= item) ++lo;
     const BeamDesc &b = beams[lo];
     const long long k = item - b.item_begin;
-    const int dblk = (int)(k / b.tiles_t), tblk = (int)(k - (long long)dblk * b.tiles_t);
+    const int tblk = (int)(k / b.tiles_d), dblk = (int)(k - (long long)tblk * b.tiles_d);
     IntArgs a;
     a.x = b.x;
     a.offs = b.offs;
@@ -1113,7 +1118,6 @@ __global__ __launch_bounds__(NW * 64, (min_waves_per_simd<NS, R, NW>())) void fw
     a.n_chan = b.n_chan;
     a.n_dm = b.n_dm;
     a.row_bytes = b.row_bytes;
-    a.out_mode = kOutFloat;
 
     int_tile<NS, R, NW, CB, SEGS, BITS>(lds, a, dblk, tblk);
     if (threadIdx.x == 0) claimed = (long long)next;
@@ -1149,7 +1153,6 @@ int launch_int_shape(const dd_plan &p, const void *tables, const void *d_in, flo
   a.n_chan = p.desc.n_chan;
   a.n_dm = p.desc.n_dm;
   a.row_bytes = t.row_bytes;
-  a.out_mode = out_mode;
   const int64_t tiles_t = (a.n_out + 64 * NS - 1) / (64 * NS);
   const int64_t n_dblk = (p.desc.n_dm + NW * R - 1) / (NW * R);
   if (tiles_t * n_dblk >= ((int64_t)1 << 31)) return (int)hipErrorInvalidConfiguration;
@@ -1169,14 +1172,23 @@ int launch_int_shape(const dd_plan &p, const void *tables, const void *d_in, flo
                          (int)tiles_t, t.order);
     return (int)hipGetLastError();
   } else {
-    const void *fn = bits == 4    ? (const void *)fwd_int_kernel<NS, R, NW, CB, 0, 4>
-                     : bits == 16 ? (const void *)fwd_int_kernel<NS, R, NW, CB, 0, 16>
-                                  : (const void *)fwd_int_kernel<NS, R, NW, CB, 0, 8>;
+    const void *fn = bits == 4 ? (const void *)fwd_int_kernel<NS, R, NW, CB, 0, 4>
+                     : bits == 16
+                         ? (out_mode == kOutRawTotals     ? (const void *)fwd_int_kernel<NS, R, NW, CB, 0, 16, kOutRawTotals>
+                            : out_mode == kOutCombineHigh ? (const void *)fwd_int_kernel<NS, R, NW, CB, 0, 16, kOutCombineHigh>
+                                                          : (const void *)fwd_int_kernel<NS, R, NW, CB, 0, 16>)
+                         : (const void *)fwd_int_kernel<NS, R, NW, CB, 0, 8>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, t.lds_bytes);
     if (e != hipSuccess) return (int)e;
     if (bits == 4)
       hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, 0, 4>), grid, block, t.lds_bytes, st, a, (int)n_dblk,
                          (int)tiles_t, t.order);
+    else if (bits == 16 && out_mode == kOutRawTotals)
+      hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, 0, 16, kOutRawTotals>), grid, block, t.lds_bytes, st, a,
+                         (int)n_dblk, (int)tiles_t, t.order);
+    else if (bits == 16 && out_mode == kOutCombineHigh)
+      hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, 0, 16, kOutCombineHigh>), grid, block, t.lds_bytes, st, a,
+                         (int)n_dblk, (int)tiles_t, t.order);
     else if (bits == 16)
       hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, 0, 16>), grid, block, t.lds_bytes, st, a, (int)n_dblk,
                          (int)tiles_t, t.order);

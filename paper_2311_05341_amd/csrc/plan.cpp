@@ -351,8 +351,14 @@ dd_status choose_forward_tiles(dd_plan &p) {
     if (last == DD_ERR_NOMEM) return last;
     if (last != DD_OK) return fail(DD_ERR_RANGE, "delay spread exceeds every compiled staging shape");
   }
-  if (p.desc.dtype != DD_F32 && !is_direct(p.fwd) && p.fwd.chan_block <= 2)
-    return set_tiles(p, 0, kNumIntShapes + (p.desc.dtype == DD_U4 ? 1 : 0), kOrderDmGroups);  // 4-bit: 2 rows per wave (registers)
+  // 4-bit plans whose staged default holds at most 4 channels per raw-ring stage
+  // take the direct kernel too: it reads 32 packed samples per 16-byte load and
+  // adds nibbles in place (4096 ch x 2^19 at 120-190 MHz: 29.8 against 25.2
+  // Tadds/s for the 4-channel raw ring)
+  const int direct_below = p.desc.dtype == DD_U4 && !is_direct(p.fwd) && p.fwd.segs == 0 ? 4 : 2;
+  if (p.desc.dtype != DD_F32 && !is_direct(p.fwd) && p.fwd.chan_block <= direct_below)
+    return set_tiles(p, 0, kNumIntShapes + 1, kOrderDmGroups);  // 2 rows x 8 waves (20.5 against 18.0 Tadds/s
+                                                                 // for 4 x 4 on 4096 ch u8 x 2^20, 120-190 MHz)
   // 16-bit plans: the 8-wave shape with 4 rows per wave and 4 channels per stage
   // beats the 16-wave default when two of its workgroups fit in a CU's LDS, so
   // that one's barrier waits overlap the other's adds (measured 13-16% faster on

@@ -126,7 +126,7 @@ def test_plan_tile_shapes(dd):
         p = _plan(dd, synth.CONFIGS[name])
         i = p.info
         assert i.kernel_ns in (8, 16, 32) and i.kernel_waves >= 1 and i.kernel_dm_per_wave >= 1
-        assert 256 % i.kernel_chan_block == 0
+        assert i.kernel_chan_block == 0 or 256 % i.kernel_chan_block == 0  # 0: a direct-read shape
 
 
 def _bin_lib(dd):
@@ -245,16 +245,19 @@ def test_survey_time_major_layout(dd):
 
 
 def test_large_spread_plan_uses_direct_kernel(dd):
-    """Plans whose delay spread leaves only 1- or 2-channel LDS stages default to the direct-read
-    kernel (no staging: row_block 0), whose table is the plain shift table."""
+    """Plans whose delay spread leaves only 1- or 2-channel LDS stages (4-bit plans: raw-ring
+    stages of at most 4 channels) default to the direct-read kernel with 2 rows x 8 waves (no
+    staging: row_block 0), whose table is the plain shift table."""
     cfg = synth.CONFIGS["lowfreq_wide"]
     p = _plan(dd, cfg)
     t = p.tiles(0)
     assert t["row_block"] == 0 and t["shape"] >= p.n_shapes - 2  # the two direct-read shapes come last
+    assert t["per_wave"] == 2 and t["waves"] == 8
     assert p.info.dev_table_bytes >= cfg["n_dm"] * cfg["n_chan"] * 4
     assert p.info.tune_ws_bytes >= p.info.dev_table_bytes
-    for name in ["small", "headline", "lowfreq_u4", "headline_u16"]:  # narrow spreads keep LDS staging
+    for name in ["small", "headline", "headline_u4", "headline_u16"]:  # narrow spreads keep LDS staging
         assert _plan(dd, synth.CONFIGS[name]).tiles(0)["row_block"] > 0
+    assert _plan(dd, synth.CONFIGS["lowfreq_u4"]).tiles(0)["row_block"] == 0  # 4-bit, 4-channel ring stages
     p4 = _plan(dd, dict(cfg, dtype="u4"))
     assert p4.tiles(0)["row_block"] == 0 and p4.tiles(0)["per_wave"] == 2
 
