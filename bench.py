@@ -65,11 +65,28 @@ FORMS = {"u8": (INT_FORM, 2), "u4": (INT_FORM, 2), "u16": (U16_FORM, 4.0 / 3.0),
 # v_and_b32, two v_lshrrev_b32 and two v_add3_u32; their windows are read packed (half a byte per add).
 U4_NIBBLE_FORM = ("SWAR nibbles in 32-bit words, v_and_b32 + v_lshrrev_b32 + v_add3_u32 "
                   "(16 sample-adds per 6 VALU lane-ops)")
+# The direct-read kernel first aligns each window word with one v_alignbit_b32, then adds it in
+# the same SWAR forms (two channels per v_add3_u32): per two channel words 2 v_alignbit_b32 plus
+# 2 v_perm_b32 + 2 v_add3_u32 (8-bit, 8 sample-adds), 2 v_and_b32 + 2 v_lshrrev_b32 + 2
+# v_add3_u32 (4-bit, 16) or 2 v_lshrrev_b32 + 2 v_add3_u32 (16-bit, 4).  No LDS.
+DIRECT_FORMS = {
+    "u8": ("direct reads: v_alignbit_b32 per word, SWAR bytes v_perm_b32 + v_add3_u32 "
+           "(8 sample-adds per 6 VALU lane-ops)", 8.0 / 6.0),
+    "u4": ("direct reads: v_alignbit_b32 per word, SWAR nibbles v_and_b32 + v_lshrrev_b32 + v_add3_u32 "
+           "(16 sample-adds per 8 VALU lane-ops)", 2.0),
+    "u16": ("direct reads: v_alignbit_b32 per word, 16-bit halves v_lshrrev_b32 + v_add3_u32 "
+            "(4 sample-adds per 6 VALU lane-ops)", 4.0 / 6.0),
+}
+# (v_alignbit_b32, v_perm_b32, single-rate VOP2 (v_and/v_lshrrev), v_add3_u32) per two channel
+# words, and the sample-adds they make, for pricing the direct forms at measured rates.
+DIRECT_OPS = {"u8": (2, 2, 0, 2, 8), "u4": (2, 0, 4, 2, 16), "u16": (2, 0, 2, 2, 4)}
 
 
 def accumulate_form(dtype, tiles):
     """(instruction form, sample-adds per VALU lane-op, LDS bytes read per add) of a kernel choice."""
-    if dtype == "u4" and tiles.get("segs", 0) > 0 and tiles.get("row_block", 0) > 0:
+    if dtype != "f32" and tiles.get("row_block", 0) == 0:
+        return DIRECT_FORMS[dtype][0], DIRECT_FORMS[dtype][1], 0
+    if dtype == "u4" and tiles.get("segs", 0) > 0:
         return U4_NIBBLE_FORM, 16.0 / 6.0, 0.5
     return FORMS[dtype][0], FORMS[dtype][1], LDS_BYTES_PER_ADD[dtype]
 
@@ -200,7 +217,15 @@ def attach_measured_peaks(rec, dd, torch, dtype):
     rec["microbench"] = mb
     achieved = rec["roofline"]["achieved"]
     form = mb["valu"][MEASURED_FORM[dtype]]
-    if dtype == "u4" and rec["roofline"]["instruction_form"] == U4_NIBBLE_FORM:
+    direct = [k for k, v in DIRECT_FORMS.items() if v[0] == rec["roofline"]["instruction_form"]]
+    if direct:
+        # each op priced at its measured rate: v_alignbit_b32 as v_perm_b32 (both single-rate VOP3)
+        n_align, n_perm, n_vop2, n_add3, adds = DIRECT_OPS[direct[0]]
+        v = mb["valu"]
+        t = ((n_align + n_perm) / v["v_perm_b32"]["lane_ops_per_s"] + n_vop2 / v["v_add_u32"]["lane_ops_per_s"]
+             + n_add3 / v["v_add3_u32"]["lane_ops_per_s"])
+        peak = adds / t / 1e12
+    elif dtype == "u4" and rec["roofline"]["instruction_form"] == U4_NIBBLE_FORM:
         # 16 sample-adds per two v_and_b32, two v_lshrrev_b32 (priced at the v_add_u32 rate: single-
         # rate VOP2) and two v_add3_u32, each at its own measured rate
         r_a = mb["valu"]["v_add3_u32"]["lane_ops_per_s"]
@@ -215,6 +240,8 @@ def attach_measured_peaks(rec, dd, torch, dtype):
         peak = form["sample_adds_per_s"] / 1e12
     rec["roofline"]["peak_measured_instruction_form"] = peak
     rec["roofline"]["frac_measured_instruction_form"] = achieved / peak
+    if rec.get("lds_roofline") is None:
+        return
     lds = mb["lds"][MEASURED_LDS]["bytes_per_s"] / 1e12
     rec["lds_roofline"]["peak_measured"] = lds
     rec["lds_roofline"]["peak_measured_instruction"] = MEASURED_LDS
@@ -840,9 +867,9 @@ def main():
                      "instruction_form": form[0],
                      "peak_instruction_form": VALU_PEAK_TOPS * form[1],
                      "frac_instruction_form": achieved / (VALU_PEAK_TOPS * form[1])},
-        "lds_roofline": {"achieved": achieved * form[2], "peak": LDS_PEAK_TBS,
-                         "unit": "TB/s", "frac": achieved * form[2] / LDS_PEAK_TBS,
-                         "bytes_per_add": form[2]},
+        "lds_roofline": None if form[2] == 0 else {
+            "achieved": achieved * form[2], "peak": LDS_PEAK_TBS, "unit": "TB/s",
+            "frac": achieved * form[2] / LDS_PEAK_TBS, "bytes_per_add": form[2]},
         "tiles": tiles,
         "autotune": tune,
         "clocks": clocks.report(),

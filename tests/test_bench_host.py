@@ -49,3 +49,22 @@ def test_headline_traffic_matches_the_current_kernel():
     traffic, src = _bench().measured_traffic("headline", plan.tiles(0))
     assert traffic is not None and src.startswith("profiles" + os.sep)
     assert traffic > 24.85e9  # at least the algorithmic bytes (input once + output once)
+
+
+def test_accumulate_forms_follow_the_kernel():
+    """The instruction form (and LDS bytes per add) the bench line prices a run against is the
+    one its tile choice runs: direct-read shapes read no LDS, packed 4-bit phase loads add
+    nibbles in place, the raw ring adds unpacked bytes."""
+    b = _bench()
+    direct = {"row_block": 0, "segs": 0}
+    phase = {"row_block": 8, "segs": 1}
+    ring = {"row_block": 4, "segs": 0}
+    assert b.accumulate_form("u4", direct)[1:] == (2.0, 0)
+    assert b.accumulate_form("u8", direct)[1:] == (8.0 / 6.0, 0)
+    assert b.accumulate_form("u16", direct)[1:] == (4.0 / 6.0, 0)
+    assert b.accumulate_form("u4", phase) == (b.U4_NIBBLE_FORM, 16.0 / 6.0, 0.5)
+    assert b.accumulate_form("u4", ring)[1:] == (2, 1)
+    assert b.accumulate_form("u8", phase)[1:] == (2, 1)
+    assert b.accumulate_form("f32", {"row_block": 8, "segs": 0})[1:] == (1, 4)
+    for dtype, ops in b.DIRECT_OPS.items():  # the op counts and the stated rate agree
+        assert ops[4] / sum(ops[:4]) == b.DIRECT_FORMS[dtype][1]
