@@ -877,9 +877,9 @@ def main():
     }
     if tiles["row_block"] == 0 and cfg["dtype"] != "f32":
         # The direct-read kernel loads 16 bytes per 16 samples of 8-bit (or 32 of 4-bit) input from
-        # L1/L2 for every (channel, DM) pair (the word after them comes from the next lane): that
-        # load stream, not the VALU, bounds it.
-        per_add = {"u8": 16 / 16, "u4": 16 / 32, "u16": 32 / 16}[cfg["dtype"]]
+        # L1/L2 for every (channel, DM) pair (the word after them comes from the next lane); lane 63
+        # of each wave loads a window only for lane 62 and outputs nothing, so 64 loads per 63.
+        per_add = {"u8": 16 / 16, "u4": 16 / 32, "u16": 32 / 16}[cfg["dtype"]] * 64 / 63
         rec["load_path"] = {"bytes_per_add": per_add, "achieved_TB_s": achieved * per_add}
     if not args.no_cpu_baseline:
         log("cpu baseline ...")

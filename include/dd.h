@@ -92,11 +92,13 @@ typedef struct {
  * output samples, staging row_block input rows (channels forward, DM rows
  * adjoint) per LDS stage.  row_block 0 marks a direct-read shape of an integer
  * plan: no LDS staging, every (channel, DM) window read from the caches (for
- * wide delay spreads; 4-bit input covers 2 * 64 * ns samples per workgroup). */
+ * wide delay spreads; a workgroup covers 63 * ns samples, 2 * 63 * ns for 4-bit
+ * input). */
 typedef struct {
   int32_t shape;  /* index of a shape compiled into the library for the plan's dtype */
   int32_t order;  /* workgroup order: 0 = time tiles fastest, 1 = each XCD takes whole time tiles,
-                     2 = each XCD takes its time tiles for 4 output blocks at a time */
+                     2 = each XCD takes its time tiles for 4 output blocks at a time, 3 = each XCD
+                     takes a contiguous run of time tiles, time tiles fastest */
   int32_t ns, per_wave, waves, row_block; /* the shape (output of dd_plan_get_tiles) */
   int32_t segs;   /* staging form of an integer shape (output): 0 = raw rows staged once, the
                      byte-phase copies built in LDS; > 0 = 8-bit shapes whose four byte-phase
@@ -215,7 +217,7 @@ dd_status dd_execute_adjoint(const dd_plan *plan, const float *d_y, int64_t y_pi
  * dd_plan_shape_count: number of compiled shapes for the plan's dtype.
  * dd_plan_get_tiles: current choice for `direction`.
  * dd_plan_set_tiles: rebuild the plan's tables for compiled shape `shape` and
- *   workgroup order `order` (0, 1 or 2).  DD_ERR_RANGE (plan unchanged) if the shape
+ *   workgroup order `order` (0 to 3).  DD_ERR_RANGE (plan unchanged) if the shape
  *   cannot stage the plan's delay spread.  On success the plan is unbound:
  *   query dev_table_bytes again and call dd_plan_bind before executing.
  * dd_plan_autotune: time every (shape, order) that holds the plan's spread and

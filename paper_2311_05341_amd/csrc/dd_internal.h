@@ -35,7 +35,8 @@ enum TileOrder {
   kOrderTimeFirst = 0,  // consecutive workgroups take consecutive time tiles of one output block
   kOrderXcdTiles = 1,   // each XCD takes whole time tiles, every output block of a tile in turn
   kOrderDmGroups = 2,   // each XCD takes its time tiles for 4 output blocks at a time (tile_order.h)
-  kNumOrders = 3
+  kOrderXcdRuns = 3,    // each XCD takes a contiguous run of time tiles, time tiles fastest
+  kNumOrders = 4
 };
 
 // Device tables of the integer forward kernel for one tile shape: per DM

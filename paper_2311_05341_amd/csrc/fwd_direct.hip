@@ -14,8 +14,10 @@
 // Windows start at any sample, but the loads stay 4-byte aligned: a lane
 // loads the aligned words covering its 16-byte (8-bit input; 32-byte for
 // 16-bit) window, takes the word after them from the next lane (a wave shift,
-// DPP; lane 63 loads its own), and funnel-shifts them (v_alignbit, by a
-// wave-uniform bit count) into the window's words.  Each (channel, DM) pair
+// DPP), and funnel-shifts them (v_alignbit, by a wave-uniform bit count) into
+// the window's words.  Lane 63 has no next lane: it loads its window only for
+// lane 62 and produces no output, so a wave covers 63 lanes' samples and every
+// (channel, DM) window costs one vector load instruction per 16 bytes.  Each (channel, DM) pair
 // gets its own raw buffer descriptor based at the window's first aligned word,
 // with the rest of the channel's row pitch as its record bound, and the loads
 // pass no scalar offset: the bound is checked against the per-lane offset, so
@@ -30,8 +32,8 @@
 // nibbles (E) and the word shifted down a nibble (S) flushed every 16 channels,
 // 16-bit words as mix and high halves.
 //
-// A workgroup covers NW * R DM rows x 64 * NS samples; wave w owns R rows, lane
-// i samples NS*i .. NS*i + NS-1 of the tile (NS = 16, or 32 for 4-bit input).
+// A workgroup covers NW * R DM rows x 63 * NS samples; wave w owns R rows, lane
+// i < 63 samples NS*i .. NS*i + NS-1 of the tile (NS = 16, or 32 for 4-bit input).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -44,6 +46,7 @@ namespace {
 constexpr uint32_t kOdd = 0x0C030C01u;  // v_perm: bytes 1 and 3 into bytes 0 and 2
 constexpr int kRsrcWord3 = 0x00020000;  // raw (untyped) buffer access
 constexpr int kUnroll = 2;              // channels whose loads are issued together
+constexpr int kOutLanes = 63;           // lanes of a wave that produce output (lane 63 only loads)
 
 struct DirectArgs {
   const uint8_t *x;      // [n_chan][pitch] bytes
@@ -103,9 +106,9 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   const int d0 = (dblk * NW + w) * R;
-  const int64_t t0 = (int64_t)tblk * 64 * NS;
+  const int64_t t0 = (int64_t)tblk * kOutLanes * NS;
   const uint32_t vo = (uint32_t)((t0 + NS * lane) * BITS / 8);  // byte of the lane's first sample
-  const bool last_tile = t0 + 64 * NS > a.n_out;                 // wave-uniform
+  const bool last_tile = t0 + 64 * NS > a.n_out;                 // wave-uniform; lane 63's window too
   int drow[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) drow[r] = min(d0 + r, a.n_dm - 1);
@@ -128,7 +131,6 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
     for (int c = cb; c < ce; c += kUnroll) {
       uint32_t raw[kUnroll][R][WORDS + 1];
       int sh[kUnroll][R];
-      __amdgpu_buffer_rsrc_t rsr[kUnroll][R];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int cc = min(c + u, ce - 1);
@@ -139,9 +141,11 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
           const int64_t bit = (int64_t)s * BITS;           // bit offset of the delay
           const int soff = (int)(bit >> 5) * 4;            // aligned byte offset, wave-uniform, < pitch
           sh[u][r] = (int)(bit & 31);
-          // descriptor over [row + soff, row + pitch): the lane offsets are range-checked against it
+          // descriptor over [row + soff, row + pitch): the lane offsets are range-checked against
+          // it; the unrolled tail past the block's last channel gets an empty one (reads zeros)
+          const int records = c + u < ce ? (int)a.pitch - soff : 0;
           const __amdgpu_buffer_rsrc_t rs =
-              __builtin_amdgcn_make_buffer_rsrc((void *)(row + soff), (short)0, (int)a.pitch - soff, kRsrcWord3);
+              __builtin_amdgcn_make_buffer_rsrc((void *)(row + soff), (short)0, records, kRsrcWord3);
           if (!last_tile) {
 #pragma unroll
             for (int q = 0; q < WORDS / 4; ++q) {
@@ -155,36 +159,22 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
 #pragma unroll
             for (int q = 0; q < WORDS; ++q) raw[u][r][q] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo + 4 * q, 0, 0);
           }
-          rsr[u][r] = rs;
         }
       }
-      // The word after a lane's window is the next lane's first word: lanes 0..62 take it from
-      // their neighbour (a wave shift, DPP), and only lane 63 loads it, all in one branch.
+      // The word after a lane's window is the next lane's first word (a wave shift, DPP);
+      // lane 63 gets zero and its sums are never stored.
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
-        for (int r = 0; r < R; ++r) raw[u][r][WORDS] = 0;
-      if (lane == 63) {
-#pragma unroll
-        for (int u = 0; u < kUnroll; ++u)
-#pragma unroll
-          for (int r = 0; r < R; ++r)
-            raw[u][r][WORDS] = __builtin_amdgcn_raw_buffer_load_b32(rsr[u][r], vo + 4 * WORDS, 0, 0);
-      }
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-#pragma unroll
-        for (int r = 0; r < R; ++r)  // wave_shl:1; lane 63 keeps its own load (no source lane)
-          raw[u][r][WORDS] = (uint32_t)__builtin_amdgcn_update_dpp((int)raw[u][r][WORDS], (int)raw[u][r][0], 0x130,
-                                                                   0xF, 0xF, false);
+        for (int r = 0; r < R; ++r)  // wave_shl:1
+          raw[u][r][WORDS] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)raw[u][r][0], 0x130, 0xF, 0xF, false);
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        const uint32_t live = c + u < ce ? 0xFFFFFFFFu : 0u;  // the unrolled tail repeats a channel
 #pragma unroll
         for (int r = 0; r < R; ++r) {
 #pragma unroll
           for (int k = 0; k < WORDS; ++k) {
-            const uint32_t v = __builtin_amdgcn_alignbit(raw[u][r][k + 1], raw[u][r][k], sh[u][r]) & live;
+            const uint32_t v = __builtin_amdgcn_alignbit(raw[u][r][k + 1], raw[u][r][k], sh[u][r]);
             if constexpr (BITS == 8) {
               mix[r][k] += v;
               odd[r][k] += __builtin_amdgcn_perm(v, v, kOdd);
@@ -245,6 +235,7 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
       }
   }
   const int64_t tl = t0 + NS * lane;
+  if (lane >= kOutLanes) return;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (d0 + r >= a.n_dm) break;
@@ -281,7 +272,7 @@ int launch_direct_shape(const dd_plan &p, const void *tables, const void *d_in, 
   // every descriptor base row + (delay bytes rounded down to 4) must lie inside the row pitch
   if ((int64_t)p.max_shift * bits / 8 >= p.in_pitch_bytes) return (int)hipErrorInvalidValue;
   const int ns = bits == 4 ? 32 : 16;
-  const int64_t tiles_t = (a.n_out + 64 * ns - 1) / (64 * ns);
+  const int64_t tiles_t = (a.n_out + kOutLanes * ns - 1) / (kOutLanes * ns);
   const int64_t n_dblk = (a.n_dm + NW * R - 1) / (NW * R);
   if (tiles_t * n_dblk >= ((int64_t)1 << 31)) return (int)hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)(tiles_t * n_dblk)), block(NW * 64);

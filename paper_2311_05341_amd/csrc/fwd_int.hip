@@ -900,32 +900,68 @@ __device__ __forceinline__ void flush_u4(uint32_t (&ev)[R][NWD], uint32_t (&sh)[
   }
 }
 
-// Build the odd nibble-phase copies of the CB channels of ring slot `slot`
-// from the even ones: 16-byte chunks, each thread a strided set of (channel,
-// byte phase, chunk).  The last word of each odd copy is left as it is (no
-// window reads it: rows carry a spare word).
-template <int NT, int CB>
-__device__ __forceinline__ void build_odd_nibbles(uint8_t *lds, int slot_bytes, int slot, int row_bytes) {
+// The odd-copy build's work split: the 16-byte chunks of a slot's even copies,
+// numbered (channel, byte phase, chunk) and dealt round-robin over the
+// workgroup's threads.  A thread's chunks sit at the same offsets from the
+// slot start in every block, so they are worked out once per tile (rows of at
+// most SEGS KiB give each thread at most N of them).
+template <int CB, int SEGS, int NW>
+struct OddPlan {
+  static constexpr int N = (CB * 4 * SEGS * 64 + NW * 64 - 1) / (NW * 64);
+  uint32_t off[N];  // byte offset of the chunk (in copy 2p) from the slot start; 0 past n
+  int n;            // chunks of this thread
+};
+
+template <int CB, int SEGS, int NW>
+__device__ __forceinline__ OddPlan<CB, SEGS, NW> odd_plan(int row_bytes) {
+  constexpr int NT = NW * 64;
+  OddPlan<CB, SEGS, NW> o;
   const int chunks = row_bytes >> 4;
+  const int total = CB * 4 * chunks;
+  const int tid = (int)threadIdx.x;
+  o.n = tid < total ? (total - 1 - tid) / NT + 1 : 0;
+#pragma unroll
+  for (int m = 0; m < OddPlan<CB, SEGS, NW>::N; ++m) {
+    const int i = tid + m * NT;
+    const int cp = i / chunks, j = i - cp * chunks;  // cp = channel * 4 + byte phase
+    o.off[m] = m < o.n ? (uint32_t)(2 * cp * row_bytes + 16 * j) : 0u;
+  }
+  return o;
+}
+
+// Build the odd nibble-phase copies of the CB channels of ring slot `slot`
+// from the even ones: word k of copy 2p + 1 is words k and k + 1 of copy 2p
+// shifted down by one nibble.  The last word of an odd copy takes its upper
+// nibble from whatever follows copy 2p's row (the odd copy's first word, being
+// written meanwhile): no window reads that word (rows carry a spare word).
+template <int CB, int SEGS, int NW>
+__device__ __forceinline__ void build_odd_nibbles(uint8_t *lds, int slot_bytes, int slot, int row_bytes,
+                                                  const OddPlan<CB, SEGS, NW> &op) {
+  constexpr int N = OddPlan<CB, SEGS, NW>::N;
   uint8_t *base = lds + slot * slot_bytes;
-  for (int i = (int)threadIdx.x; i < CB * 4 * chunks; i += NT) {
-    const int cp = i / chunks, j = i - cp * chunks;  // cp = cc * 4 + p
-    const uint8_t *src = base + (2 * cp) * row_bytes + 16 * j;  // copy 2p of channel cc
-    const uint4 v = *(const uint4 *)src;
-    const uint32_t nx = j + 1 < chunks ? *(const uint32_t *)(src + 16) : 0u;
+  // all reads first (chunks past this thread's count read chunk 0 and are not written back)
+  uint4 v[N];
+  uint32_t nx[N];
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
+    const uint8_t *src = base + op.off[m];
+    v[m] = *(const uint4 *)src;
+    nx[m] = *(const uint32_t *)(src + 16);
+  }
+#pragma unroll
+  for (int m = 0; m < N; ++m) {
     uint4 o;
-    o.x = __builtin_amdgcn_alignbit(v.y, v.x, 4);
-    o.y = __builtin_amdgcn_alignbit(v.z, v.y, 4);
-    o.z = __builtin_amdgcn_alignbit(v.w, v.z, 4);
-    o.w = __builtin_amdgcn_alignbit(nx, v.w, 4);
-    *(uint4 *)(src + row_bytes) = o;  // copy 2p + 1
+    o.x = __builtin_amdgcn_alignbit(v[m].y, v[m].x, 4);
+    o.y = __builtin_amdgcn_alignbit(v[m].z, v[m].y, 4);
+    o.z = __builtin_amdgcn_alignbit(v[m].w, v[m].z, 4);
+    o.w = __builtin_amdgcn_alignbit(nx[m], v[m].w, 4);
+    if (m < op.n) *(uint4 *)(base + op.off[m] + row_bytes) = o;  // copy 2p + 1
   }
 }
 
 template <int NS, int R, int NW, int CB, int SEGS>
 __device__ __forceinline__ void fwd_u4_phase_tile(uint8_t *lds, const IntArgs &a, int dblk, int tblk) {
   static_assert(NS % 8 == 0, "4-bit phase tiles take whole 8-sample words per lane");
-  constexpr int NT = NW * 64;
   constexpr int NWD = NS / 8;
   constexpr int NOW = R;  // one 32-bit table entry per (channel, row)
   constexpr int J = PhasePlan<CB, SEGS, NW>::J;
@@ -952,6 +988,7 @@ __device__ __forceinline__ void fwd_u4_phase_tile(uint8_t *lds, const IntArgs &a
 
   const int nblk = chan_pad / CB;
   const PhasePlan<CB, SEGS, NW> dp = phase_plan<CB, SEGS, NW, 4>(a.row_bytes, wave, lane);
+  const OddPlan<CB, SEGS, NW> op = odd_plan<CB, SEGS, NW>(a.row_bytes);
   const bool near_end = phase_near_end<4>(a, t0);  // wave-uniform
   int32_t bases[J];
   // Prologue: blocks 0 and 1 in flight; block 0's odd copies built.
@@ -967,7 +1004,7 @@ __device__ __forceinline__ void fwd_u4_phase_tile(uint8_t *lds, const IntArgs &a
   wait_vmcnt<LOADS>();
   if (near_end) phase_fix_tail<CB, SEGS, NW, 4>(a, dp, sb, t0, 0, lds, slot_bytes, 0, lane);
   lds_barrier();
-  build_odd_nibbles<NT, CB>(lds, slot_bytes, 0, a.row_bytes);
+  build_odd_nibbles<CB, SEGS, NW>(lds, slot_bytes, 0, a.row_bytes, op);
 
   const uint8_t *lane_base = lds + 4 * lane;
   int since_flush = 0;
@@ -977,7 +1014,7 @@ __device__ __forceinline__ void fwd_u4_phase_tile(uint8_t *lds, const IntArgs &a
     lds_barrier();
     phase_dma<CB, SEGS, NW, 4>(a, dp, bases, t0, (b + 2) * CB, lds, slot_bytes, (b + 2) % kPhaseRing,
                                sink_addr);  // zeros past the last channel
-    if (b + 1 < nblk) build_odd_nibbles<NT, CB>(lds, slot_bytes, (b + 1) % kPhaseRing, a.row_bytes);
+    if (b + 1 < nblk) build_odd_nibbles<CB, SEGS, NW>(lds, slot_bytes, (b + 1) % kPhaseRing, a.row_bytes, op);
     const uint8_t *blk = lane_base + (b % kPhaseRing) * slot_bytes;
     auto read_chan = [&](int cc, uint32_t (&dst)[R][NWD]) {
 #pragma unroll

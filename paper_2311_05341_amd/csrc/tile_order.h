@@ -17,6 +17,12 @@ constexpr int kDmGroup = 4;  // output blocks per group in the grouped order
 //   output blocks at a time (the blocks of one tile next to each other), one
 //   group of output blocks after another: kDmGroup blocks share each staged
 //   tile in L2 while the grid still sweeps time.
+// order 3: XCD x takes the contiguous run of time tiles [x * T, (x + 1) * T)
+//   (T = n_tiles / 8 rounded down), time tiles fastest, one output block after
+//   another.  The workgroups resident on one XCD then cover neighbouring tiles
+//   of one output block, whose windows overlap wherever a block's delay spread
+//   is wider than a tile (the direct-read plans), so they share input lines in
+//   that XCD's L2.
 // Tiles or blocks left over from whole rounds go last, in tile order.
 __device__ __forceinline__ void tile_of(int w, int n_oblk, int n_tiles, int order, int &oblk, int &tblk) {
   if (order == 0) {
@@ -34,6 +40,19 @@ __device__ __forceinline__ void tile_of(int w, int n_oblk, int n_tiles, int orde
       const int r = w - n_oblk * full;
       tblk = full + r / n_oblk;
       oblk = r % n_oblk;
+    }
+    return;
+  }
+  if (order == 3) {
+    const int per = n_tiles / kXcds, main = kXcds * per * n_oblk;
+    if (w < main) {
+      const int x = w % kXcds, k = w / kXcds;
+      oblk = k / per;
+      tblk = x * per + (k - oblk * per);
+    } else {
+      const int r = w - main, tail_t = n_tiles - kXcds * per;
+      tblk = kXcds * per + r % tail_t;
+      oblk = r / tail_t;
     }
     return;
   }

@@ -34,7 +34,7 @@ def _case(dtype):
 def _choices(dd, plan, direction):
     out = []
     for s in range(plan.n_shapes):
-        for o in (0, 1, 2):
+        for o in (0, 1, 2, 3):
             try:
                 plan.set_tiles(direction, s, o)
             except dd.DDError as e:
@@ -174,7 +174,7 @@ def test_direct_kernel_large_spread(dd, dtype):
             continue
         if plan.tiles(0)["row_block"] != 0:
             continue
-        for o in (0, 1, 2):
+        for o in (0, 1, 2, 3):
             plan.set_tiles(0, shape, o)
             print("direct shape", shape, "order", o, flush=True)
             got = plan.forward(xd)

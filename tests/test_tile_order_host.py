@@ -33,7 +33,7 @@ static int check(int n_oblk, int n_tiles, int order) {
 int main() {
   const int big[][2] = {{125, 993}, {16, 993}, {64, 1024}, {32, 407}, {4, 2}, {1, 1}, {250, 1985}};
   int bad = 0;
-  for (int order = 0; order < 3; ++order) {
+  for (int order = 0; order < 4; ++order) {
     for (int a = 1; a <= 24; ++a)
       for (int b = 1; b <= 40; ++b)
         if (check(a, b, order)) { printf("order %d grid %d x %d\n", order, a, b); ++bad; }

@@ -43,7 +43,7 @@ def test_every_shape_feasible_or_refused(dd, name):
     for direction in dirs:
         ok = 0
         for s in range(p.n_shapes):
-            for o in (0, 1, 2):
+            for o in (0, 1, 2, 3):
                 before = p.tiles(direction)
                 try:
                     p.set_tiles(direction, s, o)
@@ -68,7 +68,7 @@ def test_tiles_argument_errors(dd):
     assert _status(dd, lambda: p.set_tiles(1, 0, 0)) == "DD_ERR_DTYPE"
     assert _status(dd, lambda: p.set_tiles(0, p.n_shapes, 0)) == "DD_ERR_ARG"
     assert _status(dd, lambda: p.set_tiles(0, -1, 0)) == "DD_ERR_ARG"
-    assert _status(dd, lambda: p.set_tiles(0, 0, 3)) == "DD_ERR_ARG"
+    assert _status(dd, lambda: p.set_tiles(0, 0, 4)) == "DD_ERR_ARG"
 
 
 def test_default_tiles_grouped_order(dd):
