@@ -15,7 +15,7 @@ DMs, and one autograd forward + backward step) and the 48-beam batched launch
 against the same work as plain calls.
 
   python bench.py [--steps K] [--warmup W]
-                  [--workload headline|headline_shard8|lowfreq_u4|headline_u4|lowfreq_wide|headline_u16|grad_f32|small|
+                  [--workload headline|headline_shard8|lowfreq_u4|headline_u4|lowfreq_wide|lowfreq_wide_u16|headline_u16|grad_f32|small|
                               batch48|tab_plans_8192|pipeline_high]
                   [--adjoint] [--time-major] [--tiles SHAPE,ORDER] [--no-cpu-baseline] [--no-autotune]
                   [--autotune] [--no-extras] [--copy-calibration]

@@ -101,8 +101,10 @@ typedef struct {
                      takes a contiguous run of time tiles, time tiles fastest */
   int32_t ns, per_wave, waves, row_block; /* the shape (output of dd_plan_get_tiles) */
   int32_t segs;   /* staging form of an integer shape (output): 0 = raw rows staged once, the
-                     byte-phase copies built in LDS; > 0 = 8-bit shapes whose four byte-phase
-                     copies are loaded directly, each copy row in at most segs 1 KiB loads */
+                     byte-phase copies built in LDS; > 0 = the phase copies loaded directly
+                     (8-bit: four byte phases; 4-bit: the four even nibble phases, the odd
+                     ones built in LDS; 16-bit: copies from bytes 0 and 2), each copy row in
+                     at most segs 1 KiB loads */
 } dd_tiles;
 
 /* Result of dd_plan_autotune.  Times are per launch over the timed span. */

@@ -37,6 +37,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "dd_internal.h"
 #include "tile_order.h"
 
@@ -97,97 +99,117 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 template <int BITS>
 constexpr int lane_samples() { return BITS == 4 ? 32 : 16; }
 
-template <int BITS, int R, int NW>
-__global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n_dblk, int n_tiles, int order) {
+typedef int32_t v8i32 __attribute__((ext_vector_type(8)));
+constexpr int kDelayChunk = 8;  // channels whose delays one scalar load per row reads
+
+// The sums of one wave's R rows over every channel (see the file comment): per
+// chunk of 8 channels one scalar load per row reads their delays; per channel
+// one buffer descriptor spans its row pitch (an empty one for the unrolled tail
+// past the block's last channel, which reads zeros), and each window's aligned
+// delay offset goes into the range-checked per-lane offset.  LAST loads the
+// words one by one (the last time tile, where windows may run past the row).
+template <int BITS, int R, bool LAST>
+__device__ __forceinline__ void direct_channels(const DirectArgs &a, const int (&drow)[R], uint32_t vo,
+                                                uint32_t (&tot)[R][lane_samples<BITS>()],
+                                                uint32_t (&mix)[R][lane_samples<BITS>() * BITS / 32],
+                                                uint32_t (&odd)[R][lane_samples<BITS>() * BITS / 32]) {
   constexpr int NS = lane_samples<BITS>();
   constexpr int WORDS = NS * BITS / 32;  // window words per lane (4, or 8 for 16-bit)
-  int dblk, tblk;
-  tile_of((int)blockIdx.x, n_dblk, n_tiles, order, dblk, tblk);
-  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int lane = threadIdx.x & 63;
-  const int d0 = (dblk * NW + w) * R;
-  const int64_t t0 = (int64_t)tblk * kOutLanes * NS;
-  const uint32_t vo = (uint32_t)((t0 + NS * lane) * BITS / 8);  // byte of the lane's first sample
-  const bool last_tile = t0 + 64 * NS > a.n_out;                 // wave-uniform; lane 63's window too
-  int drow[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) drow[r] = min(d0 + r, a.n_dm - 1);
-
-  // Totals per row and sample.  8-bit: exact int32; 4-bit: likewise; 16-bit: the
-  // word sums themselves (mix) and the high-half sums (hi), resolved at the end.
-  uint32_t tot[R][NS];
-  uint32_t mix[R][WORDS], odd[R][WORDS];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-#pragma unroll
-    for (int k = 0; k < NS; ++k) tot[r][k] = 0;
-#pragma unroll
-    for (int k = 0; k < WORDS; ++k) mix[r][k] = odd[r][k] = 0;
-  }
   // channels between exact flushes: 256 for bytes, 16 for nibbles (no byte lane of E above 255)
   constexpr int kFlush = BITS == 16 ? (1 << 30) : BITS == 4 ? 16 : 256;
+  static_assert(kFlush % kDelayChunk == 0, "flush blocks hold whole delay chunks");
+  const int32_t *srow[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) srow[r] = a.shift + (int64_t)drow[r] * a.n_chan;
   for (int cb = 0; cb < a.n_chan; cb += kFlush) {
     const int ce = min(cb + kFlush, a.n_chan);
-    for (int c = cb; c < ce; c += kUnroll) {
-      uint32_t raw[kUnroll][R][WORDS + 1];
-      int sh[kUnroll][R];
+    for (int c0 = cb; c0 < ce; c0 += kDelayChunk) {
+      const int nc = min(kDelayChunk, ce - c0);  // wave-uniform
+      // FULL: a whole chunk in straight-line code, so the next pair's loads can be issued
+      // early.  Only for 2-row waves: with 4 rows the extra registers cost occupancy
+      // (measured on 4096 ch u8 x 2^20, 120-190 MHz: 4 rows x 4 waves 110.2 ms with a
+      // branch per channel pair against 134.8 ms straight; 2 x 8: 155.7 against 127.5).
+      auto chunk = [&](auto full) {
+        constexpr bool FULL = decltype(full)::value;
+        int dl[R][kDelayChunk];
+        if (FULL || nc == kDelayChunk) {
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int cc = min(c + u, ce - 1);
-        const uint8_t *row = a.x + (int64_t)cc * a.pitch;
+          for (int r = 0; r < R; ++r) {
+            const v8i32 v = *(const __attribute__((address_space(4))) v8i32 *)(srow[r] + c0);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int s = scalar_load(a.shift, (int64_t)drow[r] * a.n_chan + cc);
-          const int64_t bit = (int64_t)s * BITS;           // bit offset of the delay
-          const int soff = (int)(bit >> 5) * 4;            // aligned byte offset, wave-uniform, < pitch
-          sh[u][r] = (int)(bit & 31);
-          // descriptor over [row + soff, row + pitch): the lane offsets are range-checked against
-          // it; the unrolled tail past the block's last channel gets an empty one (reads zeros)
-          const int records = c + u < ce ? (int)a.pitch - soff : 0;
-          const __amdgpu_buffer_rsrc_t rs =
-              __builtin_amdgcn_make_buffer_rsrc((void *)(row + soff), (short)0, records, kRsrcWord3);
-          if (!last_tile) {
+            for (int q = 0; q < kDelayChunk; ++q) dl[r][q] = v[q];
+          }
+        } else {
 #pragma unroll
-            for (int q = 0; q < WORDS / 4; ++q) {
-              const v4i v = __builtin_amdgcn_raw_buffer_load_b128(rs, vo + 16 * q, 0, 0);
-              raw[u][r][4 * q] = v.x;
-              raw[u][r][4 * q + 1] = v.y;
-              raw[u][r][4 * q + 2] = v.z;
-              raw[u][r][4 * q + 3] = v.w;
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < kDelayChunk; ++q) dl[r][q] = scalar_load(srow[r], c0 + min(q, nc - 1));
+        }
+        const uint8_t *row = a.x + (int64_t)c0 * a.pitch;
+#pragma unroll
+        for (int q0 = 0; q0 < kDelayChunk; q0 += kUnroll) {
+          if (!FULL && q0 >= nc) break;
+          uint32_t raw[kUnroll][R][WORDS + 1];
+          int sh[kUnroll][R];
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+            const bool live = FULL || q0 + u < nc;  // wave-uniform
+            const __amdgpu_buffer_rsrc_t rs =
+                __builtin_amdgcn_make_buffer_rsrc((void *)row, (short)0, live ? (int)a.pitch : 0, kRsrcWord3);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+              const int64_t bit = (int64_t)dl[r][q0 + u] * BITS;  // bit offset of the delay
+              const uint32_t off = vo + (uint32_t)(bit >> 5) * 4;  // aligned byte offset, range-checked
+              sh[u][r] = (int)(bit & 31);
+              if constexpr (!LAST) {
+#pragma unroll
+                for (int q = 0; q < WORDS / 4; ++q) {
+                  const v4i v = __builtin_amdgcn_raw_buffer_load_b128(rs, off + 16 * q, 0, 0);
+                  raw[u][r][4 * q] = v.x;
+                  raw[u][r][4 * q + 1] = v.y;
+                  raw[u][r][4 * q + 2] = v.z;
+                  raw[u][r][4 * q + 3] = v.w;
+                }
+              } else {
+#pragma unroll
+                for (int q = 0; q < WORDS; ++q) raw[u][r][q] = __builtin_amdgcn_raw_buffer_load_b32(rs, off + 4 * q, 0, 0);
+              }
             }
-          } else {
+            if (live) row += a.pitch;
+          }
+          // The word after a lane's window is the next lane's first word (a wave shift, DPP);
+          // lane 63 gets zero and its sums are never stored.
 #pragma unroll
-            for (int q = 0; q < WORDS; ++q) raw[u][r][q] = __builtin_amdgcn_raw_buffer_load_b32(rs, vo + 4 * q, 0, 0);
+          for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+            for (int r = 0; r < R; ++r)  // wave_shl:1
+              raw[u][r][WORDS] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)raw[u][r][0], 0x130, 0xF, 0xF, false);
+#pragma unroll
+          for (int u = 0; u < kUnroll; ++u) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+#pragma unroll
+              for (int k = 0; k < WORDS; ++k) {
+                const uint32_t v = __builtin_amdgcn_alignbit(raw[u][r][k + 1], raw[u][r][k], sh[u][r]);
+                if constexpr (BITS == 8) {
+                  mix[r][k] += v;
+                  odd[r][k] += __builtin_amdgcn_perm(v, v, kOdd);
+                } else if constexpr (BITS == 16) {
+                  mix[r][k] += v;
+                  odd[r][k] += v >> 16;
+                } else {  // nibbles: E = even nibbles in the byte lanes, S = the word shifted down a nibble
+                  mix[r][k] += v & 0x0F0F0F0Fu;
+                  odd[r][k] += v >> 4;
+                }
+              }
+            }
           }
         }
-      }
-      // The word after a lane's window is the next lane's first word (a wave shift, DPP);
-      // lane 63 gets zero and its sums are never stored.
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u)
-#pragma unroll
-        for (int r = 0; r < R; ++r)  // wave_shl:1
-          raw[u][r][WORDS] = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)raw[u][r][0], 0x130, 0xF, 0xF, false);
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-#pragma unroll
-          for (int k = 0; k < WORDS; ++k) {
-            const uint32_t v = __builtin_amdgcn_alignbit(raw[u][r][k + 1], raw[u][r][k], sh[u][r]);
-            if constexpr (BITS == 8) {
-              mix[r][k] += v;
-              odd[r][k] += __builtin_amdgcn_perm(v, v, kOdd);
-            } else if constexpr (BITS == 16) {
-              mix[r][k] += v;
-              odd[r][k] += v >> 16;
-            } else {  // nibbles: E = even nibbles in the byte lanes, S = the word shifted down a nibble
-              mix[r][k] += v & 0x0F0F0F0Fu;
-              odd[r][k] += v >> 4;
-            }
-          }
-        }
-      }
+      };
+      if (R <= 2 && nc == kDelayChunk)
+        chunk(std::true_type{});
+      else
+        chunk(std::false_type{});
     }
     // Flush the block of channels into the int32 totals.  Bytes:
     // mix - (odd << 8) = sum of bytes 0 + 2^16 * sum of bytes 2 (each sum < 2^16).
@@ -224,6 +246,39 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
         }
     }
   }
+}
+
+template <int BITS, int R, int NW>
+__global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n_dblk, int n_tiles, int order) {
+  constexpr int NS = lane_samples<BITS>();
+  constexpr int WORDS = NS * BITS / 32;  // window words per lane (4, or 8 for 16-bit)
+  int dblk, tblk;
+  tile_of((int)blockIdx.x, n_dblk, n_tiles, order, dblk, tblk);
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63;
+  const int d0 = (dblk * NW + w) * R;
+  const int64_t t0 = (int64_t)tblk * kOutLanes * NS;
+  const uint32_t vo = (uint32_t)((t0 + NS * lane) * BITS / 8);  // byte of the lane's first sample
+  const bool last_tile = t0 + 64 * NS > a.n_out;                 // wave-uniform; lane 63's window too
+  int drow[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) drow[r] = min(d0 + r, a.n_dm - 1);
+
+  // Totals per row and sample.  8-bit: exact int32; 4-bit: likewise; 16-bit: the
+  // word sums themselves (mix) and the high-half sums (hi), resolved at the end.
+  uint32_t tot[R][NS];
+  uint32_t mix[R][WORDS], odd[R][WORDS];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+#pragma unroll
+    for (int k = 0; k < NS; ++k) tot[r][k] = 0;
+#pragma unroll
+    for (int k = 0; k < WORDS; ++k) mix[r][k] = odd[r][k] = 0;
+  }
+  if (last_tile)
+    direct_channels<BITS, R, true>(a, drow, vo, tot, mix, odd);
+  else
+    direct_channels<BITS, R, false>(a, drow, vo, tot, mix, odd);
   if constexpr (BITS == 16) {
     // low samples: mix - (hi << 16) (mod 2^32), exact for up to 65537 channels
 #pragma unroll

@@ -581,12 +581,15 @@ __device__ __forceinline__ void fwd_int_tile(uint8_t *lds, const IntArgs &a, int
 // the summation, with one barrier per block.  The table entry of a (channel, DM
 // row) is the byte offset of its window's first word from the start of the
 // slot (padding channels past the last: their own zero row), so the summation
-// needs one address add per (channel, row).
+// needs one address add per (channel, row).  16-bit rows take two copies, from
+// bytes 0 and 2 (every 16-bit window then starts on a word of one of them),
+// with the same straddling-word rebuild for copy 1.
 //
 // Loads per block: each of the CB * SEGS (channel, 1 KiB segment) pairs issues
-// its four phase loads from one wave; pair j goes to wave j % NW, so every wave
-// issues exactly 4 * ceil(CB * SEGS / NW) loads per block (padding loads of
-// zero bytes into a sink keep the count fixed) and one vmcnt wait is exact.
+// its phase loads (four; two for 16-bit rows) from one wave; pair j goes to
+// wave j % NW, so every wave issues exactly the same number of loads per block
+// (padding loads of zero bytes into a sink keep the count fixed) and one vmcnt
+// wait is exact.
 constexpr int kPhaseRing = 3;
 
 template <int CB, int SEGS, int NW>
@@ -594,14 +597,22 @@ constexpr int phase_pairs_per_wave() { return (CB * SEGS + NW - 1) / NW; }
 
 // Copies of a staged row in the phase-load forms: the four byte phases for
 // 8-bit samples; for packed 4-bit samples the eight nibble phases, of which
-// the byte phases are the even ones (copy 2p = byte phase p).
+// the byte phases are the even ones (copy 2p = byte phase p); for 16-bit
+// samples two, from bytes 0 and 2.
 template <int BITS>
-constexpr int phase_copies() { return BITS == 4 ? 8 : 4; }
+constexpr int phase_copies() { return BITS == 4 ? 8 : BITS == 16 ? 2 : 4; }
+
+// Loads per (channel, segment) pair and their byte step: the copies that come
+// straight from memory (all of them but the odd nibble phases).
+template <int BITS>
+constexpr int phase_loads() { return BITS == 16 ? 2 : 4; }
+template <int BITS>
+constexpr int phase_load_step() { return BITS == 16 ? 2 : 1; }
 
 // Bytes of row from sample s on (4-bit rows hold two samples per byte; every
 // staged row starts on a multiple of 32 samples).
 template <int BITS>
-__device__ __forceinline__ int64_t phase_bytes(int64_t s) { return BITS == 4 ? s >> 1 : s; }
+__device__ __forceinline__ int64_t phase_bytes(int64_t s) { return BITS == 4 ? s >> 1 : BITS == 16 ? 2 * s : s; }
 
 // This wave's (channel, segment) pairs: channel within the block, segment.
 template <int CB, int SEGS, int NW>
@@ -634,7 +645,8 @@ __device__ __forceinline__ PhasePlan<CB, SEGS, NW> phase_plan(int row_bytes, int
 
 // Issue this wave's phase loads of block `cb` (first channel) into ring slot
 // `slot`; `base` holds the stage bases of the wave's channels for that block.
-// Byte phase p goes to copy p (8-bit) or copy 2p (4-bit).
+// Byte phase p goes to copy p (8-bit) or copy 2p (4-bit); 16-bit rows load
+// copies 0 and 1 from bytes 0 and 2.
 template <int CB, int SEGS, int NW, int BITS>
 __device__ __forceinline__ void phase_dma(const IntArgs &a, const PhasePlan<CB, SEGS, NW> &d,
                                           const int32_t (&base_in)[PhasePlan<CB, SEGS, NW>::J], int64_t t0, int cb,
@@ -652,11 +664,12 @@ __device__ __forceinline__ void phase_dma(const IntArgs &a, const PhasePlan<CB, 
     const int bytes = chan_ok && left > 0 ? (int)min(left, (int64_t)0x7fffffff) : 0;
     const v4i_t rs = make_rsrc(a.x + (int64_t)c * a.pitch + row0, bytes);
     const uint32_t dst = d.ok[m] ? slot_addr + d.lds_off[m] : sink_addr;
-    // padding: all four into the sink
-    const uint32_t copy_step = d.ok[m] ? (uint32_t)(phase_copies<BITS>() / 4 * a.row_bytes) : 0u;
+    // padding: all of them into the sink
+    constexpr int NL = phase_loads<BITS>();
+    const uint32_t copy_step = d.ok[m] ? (uint32_t)(phase_copies<BITS>() / NL * a.row_bytes) : 0u;
     if (d.lane_ok[m]) {
 #pragma unroll
-      for (int ph = 0; ph < 4; ++ph) dma16(rs, d.voff[m] + ph, dst + ph * copy_step);
+      for (int ph = 0; ph < NL; ++ph) dma16(rs, d.voff[m] + ph * phase_load_step<BITS>(), dst + ph * copy_step);
     }
   }
 }
@@ -673,27 +686,29 @@ __device__ __forceinline__ void phase_bases(const IntArgs &a, const int32_t *sb,
   }
 }
 
-// Rebuild, in copies 1..3 of this wave's channels of block `cb` (ring slot
-// `slot`), the word that straddles the load bound (see above).  Copy p's word
-// at copy position k = bound - 4 holds row bytes k + p .. k + p + 3, of which
-// those below the bound are copy 0's word at k shifted down by p bytes; the
-// rest lie past the row and feed no output.  Call after this wave's loads of
-// the block have landed and before the block's barrier.
+// Rebuild, in the loaded copies 1.. of this wave's channels of block `cb`
+// (ring slot `slot`), the word that straddles the load bound (see above).  The
+// copy loaded from byte o holds at copy position k = bound - 4 the row bytes
+// k + o .. k + o + 3, of which those below the bound are copy 0's word at k
+// shifted down by o bytes; the rest lie past the row and feed no output.  Call
+// after this wave's loads of the block have landed and before the block's
+// barrier.
 template <int CB, int SEGS, int NW, int BITS>
 __device__ __forceinline__ void phase_fix_tail(const IntArgs &a, const PhasePlan<CB, SEGS, NW> &d, const int32_t *sb,
                                                int64_t t0, int cb, uint8_t *lds, int slot_bytes, int slot, int lane) {
   const int64_t bound = (phase_bytes<BITS>(a.n_samp) + 15) & ~(int64_t)15;
-  const int step = phase_copies<BITS>() / 4 * a.row_bytes;  // byte phase p is at p * step
+  constexpr int NL = phase_loads<BITS>();
+  const int step = phase_copies<BITS>() / NL * a.row_bytes;  // load p's copy is at p * step
 #pragma unroll
   for (int m = 0; m < PhasePlan<CB, SEGS, NW>::J; ++m) {
     const int c = cb + d.cc[m];
     if (!d.ok[m] || c >= a.n_chan) continue;  // wave-uniform
     const int64_t k = bound - phase_bytes<BITS>(t0 + scalar_load(sb, c)) - 4;
     if (k < d.seg0[m] || k >= d.seg0[m] + 1024 || k >= a.row_bytes) continue;  // not in this wave's segment
-    if (lane < 3) {
+    if (lane < NL - 1) {
       uint8_t *row = lds + slot * slot_bytes + d.cc[m] * phase_copies<BITS>() * a.row_bytes + k;
       const uint32_t w0 = *(const uint32_t *)row;
-      *(uint32_t *)(row + (lane + 1) * step) = w0 >> (8 * (lane + 1));
+      *(uint32_t *)(row + (lane + 1) * step) = w0 >> (8 * phase_load_step<BITS>() * (lane + 1));
     }
   }
 }
@@ -706,38 +721,48 @@ __device__ __forceinline__ bool phase_near_end(const IntArgs &a, int64_t t0) {
   return phase_bytes<BITS>(t0 + (a.n_samp - a.n_out)) + a.row_bytes + 4 > bound;
 }
 
-template <int NS, int R, int NW, int CB, int SEGS>
-__device__ __forceinline__ void fwd_u8_phase_tile(uint8_t *lds, const IntArgs &a, int dblk, int tblk) {
-  constexpr int NWD = NS / 4;
+// Phase-load tile for 8-bit and 16-bit input.  8-bit: the four byte-phase
+// copies, SIMD-in-word mix/odd sums flushed every 256 channels, channel pairs
+// read one pair ahead.  16-bit: the copies from bytes 0 and 2, mix/odd sums of
+// whole words and their high halves (exact 32-bit totals, no flush), one
+// channel read ahead; the epilogue by OutMode as in the ring form.
+template <int NS, int R, int NW, int CB, int SEGS, int BITS, int OM>
+__device__ __forceinline__ void fwd_byte_phase_tile(uint8_t *lds, const IntArgs &a, int dblk, int tblk) {
+  static_assert(BITS == 8 || BITS == 16, "byte-phase tiles take 8- or 16-bit samples");
+  constexpr int NWD = BITS == 16 ? NS / 2 : NS / 4;  // 32-bit words per lane and window
   constexpr int NOW = R;  // one 32-bit table entry per (channel, row)
   constexpr int J = PhasePlan<CB, SEGS, NW>::J;
-  constexpr int LOADS = 4 * J;  // loads per wave and block
+  constexpr int LOADS = phase_loads<BITS>() * J;  // loads per wave and block
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int64_t t0 = (int64_t)tblk * (64 * NS);
   const int chan_pad = (a.n_chan + CB - 1) / CB * CB;
   const uint32_t *woffs = a.offs + ((int64_t)dblk * NW + wave) * chan_pad * NOW;
   const int32_t *sb = a.sbase + (int64_t)dblk * a.n_chan;
-  const int slot_bytes = CB * 4 * a.row_bytes;
+  const int slot_bytes = CB * phase_copies<BITS>() * a.row_bytes;
   const uint32_t sink_addr =
       __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)(lds_void_t *)(lds + kPhaseRing * slot_bytes));
 
-  uint32_t tot[R][NS], mix[R][NWD], odd[R][NWD];
+  // 8-bit: mix/odd are the SIMD-in-word accumulators, tot the flushed totals.
+  // 16-bit: mix sums whole words, odd their high halves; no tot.
+  uint32_t tot[R][BITS == 16 ? 1 : NS], mix[R][NWD], odd[R][NWD];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
+    if constexpr (BITS != 16) {
 #pragma unroll
-    for (int j = 0; j < NS; ++j) tot[r][j] = 0;
+      for (int j = 0; j < NS; ++j) tot[r][j] = 0;
+    }
 #pragma unroll
     for (int k = 0; k < NWD; ++k) mix[r][k] = odd[r][k] = 0;
   }
 
   const int nblk = chan_pad / CB;
-  const PhasePlan<CB, SEGS, NW> dp = phase_plan<CB, SEGS, NW, 8>(a.row_bytes, wave, lane);
+  const PhasePlan<CB, SEGS, NW> dp = phase_plan<CB, SEGS, NW, BITS>(a.row_bytes, wave, lane);
   int32_t bases[J];
 #pragma unroll
   for (int k = 0; k < kPhaseRing - 1; ++k) {
     phase_bases<CB, SEGS, NW>(a, sb, k * CB, dp, bases);
-    phase_dma<CB, SEGS, NW, 8>(a, dp, bases, t0, k * CB, lds, slot_bytes, k, sink_addr);
+    phase_dma<CB, SEGS, NW, BITS>(a, dp, bases, t0, k * CB, lds, slot_bytes, k, sink_addr);
   }
   phase_bases<CB, SEGS, NW>(a, sb, (kPhaseRing - 1) * CB, dp, bases);
   uint32_t ow[CB * NOW];
@@ -745,17 +770,17 @@ __device__ __forceinline__ void fwd_u8_phase_tile(uint8_t *lds, const IntArgs &a
   for (int q = 0; q < CB * NOW; ++q) ow[q] = scalar_load(woffs, q);
 
   const uint8_t *lane_base = lds + 4 * lane;
-  const bool near_end = phase_near_end<8>(a, t0);  // wave-uniform
+  const bool near_end = phase_near_end<BITS>(a, t0);  // wave-uniform
   int since_flush = 0;
   for (int b = 0; b < nblk; ++b) {
     // This wave's loads of block b have landed; after the barrier every
     // wave's have, and no wave reads the slot of block b - 1 any more, which
     // the loads of block b + kPhaseRing - 1 then fill.
     wait_vmcnt<(kPhaseRing - 2) * LOADS>();
-    if (near_end) phase_fix_tail<CB, SEGS, NW, 8>(a, dp, sb, t0, b * CB, lds, slot_bytes, b % kPhaseRing, lane);
+    if (near_end) phase_fix_tail<CB, SEGS, NW, BITS>(a, dp, sb, t0, b * CB, lds, slot_bytes, b % kPhaseRing, lane);
     lds_barrier();
-    phase_dma<CB, SEGS, NW, 8>(a, dp, bases, t0, (b + kPhaseRing - 1) * CB, lds, slot_bytes,
-                            (b + kPhaseRing - 1) % kPhaseRing, sink_addr);  // zeros past the last channel
+    phase_dma<CB, SEGS, NW, BITS>(a, dp, bases, t0, (b + kPhaseRing - 1) * CB, lds, slot_bytes,
+                                  (b + kPhaseRing - 1) % kPhaseRing, sink_addr);  // zeros past the last channel
     const uint8_t *blk = lane_base + (b % kPhaseRing) * slot_bytes;
     // The table entry is the window's byte offset from the slot start; lane i
     // owns words i, i+64, ... of the window (conflict-free ds_read2st64).
@@ -768,34 +793,52 @@ __device__ __forceinline__ void fwd_u8_phase_tile(uint8_t *lds, const IntArgs &a
         for (int k = 0; k < NWD; ++k) dst[r][k] = p[64 * k];
       }
     };
-    uint32_t wp[2][2][R][NWD];  // channel pairs: the pair after the one being summed is in flight
-    read_chan(0, wp[0][0]);
-    read_chan(1, wp[0][1]);
+    if constexpr (BITS == 16) {
+      // one channel read ahead (a pair ahead would not fit the registers of 8 words per row)
+      uint32_t wv[2][R][NWD];
+      read_chan(0, wv[0]);
 #pragma unroll
-    for (int pc = 0; pc < CB / 2; ++pc) {
-      if (2 * pc + 2 < CB) {
-        read_chan(2 * pc + 2, wp[(pc + 1) & 1][0]);
-        read_chan(2 * pc + 3, wp[(pc + 1) & 1][1]);
-      }
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int cc = 0; cc < CB; ++cc) {
+        if (cc + 1 < CB) read_chan(cc + 1, wv[(cc + 1) & 1]);
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
           for (int k = 0; k < NWD; ++k) {
-            const uint32_t w = wp[pc & 1][h][r][k];
+            const uint32_t w = wv[cc & 1][r][k];
             mix[r][k] += w;
-            odd[r][k] += __builtin_amdgcn_perm(w, w, kOddSel);
+            odd[r][k] = add_high_half(odd[r][k], w);
           }
-      if (NWD > 2 && 2 * pc + 2 < CB) {  // pinned for wider windows; 8-sample windows run 1.4% faster unpinned
-        __builtin_amdgcn_sched_group_barrier(0x100, R * NWD, 0);      // DS reads: the next pair
-        __builtin_amdgcn_sched_group_barrier(0x002, 8 * R * NWD, 0);  // VALU: this pair's adds
       }
-    }
-    since_flush += CB;
-    if (since_flush >= 256 || b + 1 == nblk) {
-      flush<NS, R>(mix, odd, tot);
-      since_flush = 0;
+    } else {
+      uint32_t wp[2][2][R][NWD];  // channel pairs: the pair after the one being summed is in flight
+      read_chan(0, wp[0][0]);
+      read_chan(1, wp[0][1]);
+#pragma unroll
+      for (int pc = 0; pc < CB / 2; ++pc) {
+        if (2 * pc + 2 < CB) {
+          read_chan(2 * pc + 2, wp[(pc + 1) & 1][0]);
+          read_chan(2 * pc + 3, wp[(pc + 1) & 1][1]);
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < NWD; ++k) {
+              const uint32_t w = wp[pc & 1][h][r][k];
+              mix[r][k] += w;
+              odd[r][k] += __builtin_amdgcn_perm(w, w, kOddSel);
+            }
+        if (NWD > 2 && 2 * pc + 2 < CB) {  // pinned for wider windows; 8-sample windows run 1.4% faster unpinned
+          __builtin_amdgcn_sched_group_barrier(0x100, R * NWD, 0);      // DS reads: the next pair
+          __builtin_amdgcn_sched_group_barrier(0x002, 8 * R * NWD, 0);  // VALU: this pair's adds
+        }
+      }
+      since_flush += CB;
+      if (since_flush >= 256 || b + 1 == nblk) {
+        flush<NS, R>(mix, odd, tot);
+        since_flush = 0;
+      }
     }
     const int oi = __builtin_amdgcn_readfirstlane(min(b + 1, nblk - 1) * CB * NOW);
 #pragma unroll
@@ -805,12 +848,23 @@ __device__ __forceinline__ void fwd_u8_phase_tile(uint8_t *lds, const IntArgs &a
   wait_vmcnt<0>();  // the trailing loads must land before the LDS is reused
   lds_barrier();
 
+  // Word k of lane i holds samples t0 + 4*(i + 64k) + 0..3 (16-bit: t0 +
+  // 2*(i + 64k) + 0..1): stores are contiguous across the wave.
   const int d0 = dblk * (NW * R) + wave * R;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int d = d0 + r;
     if (d >= a.n_dm) break;
     float *orow = a.out + (int64_t)d * a.out_pitch;
+    if constexpr (BITS == 16) {
+#pragma unroll
+      for (int k = 0; k < NWD; ++k) {
+        const int64_t t = t0 + 2 * (int64_t)(lane + 64 * k);
+        const uint32_t lo = mix[r][k] - (odd[r][k] << 16);
+        store_u16_pair<OM>(orow, t, a.n_out, lo, odd[r][k]);
+      }
+      continue;
+    }
 #pragma unroll
     for (int k = 0; k < NS / 4; ++k) {
       const int64_t t = t0 + 4 * (int64_t)(lane + 64 * k);
@@ -1089,7 +1143,7 @@ __device__ __forceinline__ void int_tile(uint8_t *lds, const IntArgs &a, int dbl
   else if constexpr (BITS == 4)
     fwd_u4_phase_tile<NS, R, NW, CB, SEGS>(lds, a, dblk, tblk);
   else
-    fwd_u8_phase_tile<NS, R, NW, CB, SEGS>(lds, a, dblk, tblk);
+    fwd_byte_phase_tile<NS, R, NW, CB, SEGS, BITS, OM>(lds, a, dblk, tblk);
 }
 
 // Waves per SIMD the compiler must leave room for: 8-wave shapes with at most
@@ -1165,13 +1219,13 @@ __global__ __launch_bounds__(NW * 64, (min_waves_per_simd<NS, R, NW>())) void fw
 
 // Compiled tile shapes (samples per lane, DM rows per wave, waves, channels
 // per LDS stage, staging form: 0 = raw ring + phase build, any input; S > 0 =
-// phase loads, 8-bit input, copy rows of at most S KiB), in the order the
-// plan tries them.
+// phase loads, copy rows of at most S KiB), in the order the plan tries them.
 #define DD_INT_SHAPES(X)                                                                                    \
   X(16, 2, 16, 8, 0) X(16, 4, 8, 8, 0) X(16, 2, 16, 4, 0) X(16, 4, 8, 4, 0) X(16, 1, 16, 8, 0)             \
   X(16, 1, 16, 4, 0) X(16, 1, 16, 2, 0) X(16, 1, 16, 1, 0) X(16, 1, 4, 1, 0) X(16, 1, 1, 1, 0)             \
   X(8, 2, 16, 8, 0) X(16, 2, 8, 4, 0) X(8, 4, 16, 8, 0)                                                    \
-  X(8, 4, 8, 8, 1) X(16, 2, 16, 8, 2) X(8, 4, 16, 8, 2) X(16, 2, 16, 4, 2) X(16, 2, 8, 4, 2) X(16, 2, 16, 4, 4)
+  X(8, 4, 8, 8, 1) X(16, 2, 16, 8, 2) X(8, 4, 16, 8, 2) X(16, 2, 16, 4, 2) X(16, 2, 8, 4, 2) X(16, 2, 16, 4, 4) \
+  X(8, 4, 8, 8, 2) X(16, 4, 8, 4, 3)
 
 template <int NS, int R, int NW, int CB, int SEGS>
 int launch_int_shape(const dd_plan &p, const void *tables, const void *d_in, float *d_out, int64_t out_pitch,
@@ -1195,14 +1249,28 @@ int launch_int_shape(const dd_plan &p, const void *tables, const void *d_in, flo
   if (tiles_t * n_dblk >= ((int64_t)1 << 31)) return (int)hipErrorInvalidConfiguration;
   const dim3 grid((unsigned)(tiles_t * n_dblk)), block(NW * 64);
   const int bits = p.desc.dtype == DD_U4 ? 4 : p.desc.dtype == DD_U16 ? 16 : 8;
-  if constexpr (SEGS > 0) {  // phase loads: 8-bit or packed 4-bit input, copy rows within SEGS KiB
-    if ((bits != 8 && bits != 4) || t.row_bytes > 1024 * SEGS) return (int)hipErrorInvalidValue;
+  if constexpr (SEGS > 0) {  // phase loads, copy rows within SEGS KiB
+    if (t.row_bytes > 1024 * SEGS || (bits == 4 && NS % 8)) return (int)hipErrorInvalidValue;
     const void *fn = bits == 4 ? (const void *)fwd_int_kernel<NS, R, NW, CB, SEGS, 4>
-                               : (const void *)fwd_int_kernel<NS, R, NW, CB, SEGS, 8>;
+                     : bits == 16
+                         ? (out_mode == kOutRawTotals ? (const void *)fwd_int_kernel<NS, R, NW, CB, SEGS, 16, kOutRawTotals>
+                            : out_mode == kOutCombineHigh
+                                ? (const void *)fwd_int_kernel<NS, R, NW, CB, SEGS, 16, kOutCombineHigh>
+                                : (const void *)fwd_int_kernel<NS, R, NW, CB, SEGS, 16>)
+                         : (const void *)fwd_int_kernel<NS, R, NW, CB, SEGS, 8>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, t.lds_bytes);
     if (e != hipSuccess) return (int)e;
     if (bits == 4)
       hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, SEGS, 4>), grid, block, t.lds_bytes, st, a, (int)n_dblk,
+                         (int)tiles_t, t.order);
+    else if (bits == 16 && out_mode == kOutRawTotals)
+      hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, SEGS, 16, kOutRawTotals>), grid, block, t.lds_bytes, st, a,
+                         (int)n_dblk, (int)tiles_t, t.order);
+    else if (bits == 16 && out_mode == kOutCombineHigh)
+      hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, SEGS, 16, kOutCombineHigh>), grid, block, t.lds_bytes, st, a,
+                         (int)n_dblk, (int)tiles_t, t.order);
+    else if (bits == 16)
+      hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, SEGS, 16>), grid, block, t.lds_bytes, st, a, (int)n_dblk,
                          (int)tiles_t, t.order);
     else
       hipLaunchKernelGGL((fwd_int_kernel<NS, R, NW, CB, SEGS, 8>), grid, block, t.lds_bytes, st, a, (int)n_dblk,
@@ -1264,7 +1332,7 @@ int batch_kernels(int ns, int dm_per_wave, int waves, int chan_block, int segs, 
   if (ns == NS && dm_per_wave == R && waves == NW && chan_block == CB && segs == SEGS)                     \
     fn = SEGS > 0 ? (dtype == DD_U8   ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, SEGS, 8>         \
                      : dtype == DD_U4 ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, SEGS, 4>         \
-                                      : nullptr)                                                             \
+                                      : (const void *)fwd_int_batched_kernel<NS, R, NW, CB, SEGS, 16>)       \
          : dtype == DD_U4  ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, 0, 4>                     \
          : dtype == DD_U16 ? (const void *)fwd_int_batched_kernel<NS, R, NW, CB, 0, 16>                    \
                            : (const void *)fwd_int_batched_kernel<NS, R, NW, CB, 0, 8>;

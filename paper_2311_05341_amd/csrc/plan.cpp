@@ -130,7 +130,7 @@ dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves,
   const bool u4 = p.desc.dtype == DD_U4;
   const int unit = u4 ? 32 : u16 ? 8 : 16;
   const bool phase = segs > 0;  // phase-load staging (8-bit, packed 4-bit)
-  if (phase && p.desc.dtype != DD_U8 && !u4) return fail(DD_ERR_RANGE, "phase-load staging is for 8- and 4-bit input");
+  if (phase && p.desc.dtype == DD_F32) return fail(DD_ERR_RANGE, "phase-load staging is for integer input");
   if (phase && u4 && (ns % 8 || chan_block > 16)) return fail(DD_ERR_RANGE, "shape not compiled for 4-bit phase loads");
   // copies of a staged row: byte phases (4, or 2 for 16-bit samples); packed
   // 4-bit phase loads keep the eight nibble phases of the packed row
@@ -187,7 +187,7 @@ dd_status build_int_tables(const dd_plan &p, int ns, int dm_per_wave, int waves,
           // channels (c >= nc, staged as zero rows) read their own row at 0
           const int32_t v = c < nc ? sd[c] - sb[c] : 0;
           const int32_t slot = phase ? (c % chan_block) * copies * t->row_bytes : 0;  // channel's copies in the slot
-          const uint32_t e = u16             ? (uint32_t)((v & 1) * t->row_bytes + 2 * (v & ~1))
+          const uint32_t e = u16             ? (uint32_t)(slot + (v & 1) * t->row_bytes + 2 * (v & ~1))
                              : phase && u4 ? (uint32_t)(slot + (v & 7) * t->row_bytes + 4 * (v >> 3))
                                            : (uint32_t)(slot + (v & 3) * t->row_bytes + (v & ~3));
           if (phase)
@@ -355,25 +355,34 @@ dd_status choose_forward_tiles(dd_plan &p) {
   // take the direct kernel too: it reads 32 packed samples per 16-byte load and
   // adds nibbles in place (4096 ch x 2^19 at 120-190 MHz: 29.8 against 25.2
   // Tadds/s for the 4-channel raw ring)
+  // Direct shape: 2 rows x 8 waves for 4-bit input (4096 ch x 2^19 at 120-190 MHz: 46.2
+  // against 38.3 Tadds/s for 4 x 4), 4 rows x 4 waves otherwise (4096 ch x 2^20 at 120-190
+  // MHz, DM step 0.5: 30.0 against 25.9 for 8-bit samples, 11.7 against 8.2 for 16-bit)
   const int direct_below = p.desc.dtype == DD_U4 && !is_direct(p.fwd) && p.fwd.segs == 0 ? 4 : 2;
   if (p.desc.dtype != DD_F32 && !is_direct(p.fwd) && p.fwd.chan_block <= direct_below)
-    return set_tiles(p, 0, kNumIntShapes + 1, kOrderDmGroups);  // 2 rows x 8 waves (20.5 against 18.0 Tadds/s
-                                                                 // for 4 x 4 on 4096 ch u8 x 2^20, 120-190 MHz)
-  // 16-bit plans: the 8-wave shape with 4 rows per wave and 4 channels per stage
-  // beats the 16-wave default when two of its workgroups fit in a CU's LDS, so
-  // that one's barrier waits overlap the other's adds (measured 13-16% faster on
-  // 8192 x 2^20 and on binned 4096-channel ranges; 11% slower on a plan with
-  // ~1000 samples of spread per 32 DMs, where only one fits).
+    return set_tiles(p, 0, kNumIntShapes + (p.desc.dtype == DD_U4 ? 1 : 0), kOrderDmGroups);
+  // 16-bit plans: the 8-wave shape with 4 rows per wave and 4 channels per stage,
+  // where two of its workgroups fit in a CU's LDS, so that one's barrier waits
+  // overlap the other's adds: first in its phase-load form (the two copies loaded
+  // straight into LDS: 1111.5 against 1326.9 ms on 8192 ch x 2^20 x 4000 DMs),
+  // else in its raw-ring form (13-16% faster than the 16-wave default on 8192 x
+  // 2^20 and on binned 4096-channel ranges; 11% slower on a plan with ~1000
+  // samples of spread per 32 DMs, where only one fits).
   if (p.desc.dtype == DD_U16 && !is_direct(p.fwd)) {
     const int keep_shape = p.fwd.shape, keep_order = p.fwd.order;
-    for (int i = 0; i < kNumIntShapes; ++i) {
-      const int *k = kIntShapes[i];
-      if (k[0] != 16 || k[1] != 4 || k[2] != 8 || k[3] != 4 || i == keep_shape) continue;
-      const dd_status st = set_tiles(p, 0, i, kOrderDmGroups);
-      if (st == DD_ERR_NOMEM) return st;
-      if (st == DD_OK && 2 * p.fwd.lds_bytes > kLdsLimit) return set_tiles(p, 0, keep_shape, keep_order);
-      break;
-    }
+    bool moved = false;
+    for (int want_phase = 1; want_phase >= 0; --want_phase)
+      for (int i = 0; i < kNumIntShapes; ++i) {
+        const int *k = kIntShapes[i];
+        if (k[0] != 16 || k[1] != 4 || k[2] != 8 || k[3] != 4 || (k[4] > 0) != (want_phase == 1)) continue;
+        if (i == keep_shape) return moved ? set_tiles(p, 0, keep_shape, keep_order) : DD_OK;
+        const dd_status st = set_tiles(p, 0, i, kOrderDmGroups);
+        if (st == DD_ERR_NOMEM) return st;
+        if (st == DD_OK && 2 * p.fwd.lds_bytes <= kLdsLimit) return DD_OK;
+        moved = moved || st == DD_OK;
+        break;
+      }
+    if (moved) return set_tiles(p, 0, keep_shape, keep_order);
   }
   return DD_OK;
 }

@@ -241,6 +241,10 @@ CONFIGS = {
     "lowfreq_wide": dict(dtype="u8", n_chan=4096, n_samp=1 << 20, f_high=190.0, chan_bw=70.0 / 4096,
                          t_samp=327.68e-6, dm_start=0.0, dm_step=0.5, n_dm=1024, seed=10,
                          pulses=[(200, 2, 100_000), (700, 4, 400_000)], amp=40),
+    # The same plan on 16-bit samples (the direct kernel's 16-bit form).
+    "lowfreq_wide_u16": dict(dtype="u16", n_chan=4096, n_samp=1 << 20, f_high=190.0, chan_bw=70.0 / 4096,
+                             t_samp=327.68e-6, dm_start=0.0, dm_step=0.5, n_dm=1024, seed=11,
+                             pulses=[(200, 2, 100_000), (700, 4, 400_000)], amp=2560),
     "grad_f32": dict(dtype="f32", n_chan=1024, n_samp=1 << 17, f_high=1500.0, chan_bw=300.0 / 1024,
                      t_samp=128e-6, dm_start=0.0, dm_step=1.0, n_dm=1024, seed=4,
                      target_seed=40, fd_seed=41, pulses=[], amp=0),

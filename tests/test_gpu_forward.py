@@ -291,6 +291,36 @@ def test_headline_u16_workload_sampled(dd):
             assert int(np.argmax(out[:, t0].cpu().numpy())) == dp
 
 
+def test_lowfreq_wide_u16_workload_sampled(dd):
+    """The wide-spread low-frequency plan on 16-bit samples (4096 ch x 2^20 x 1024 DMs, 264
+    samples of extra delay per DM step): the direct-read kernel's 16-bit form, as the benchmark
+    runs it.  Sampled rows bit-exact against the oracle, DM 0 against the plain channel sum."""
+    cfg = synth.CONFIGS["lowfreq_wide_u16"]
+    s = oracle_table(cfg)
+    n_chan, n_samp = cfg["n_chan"], cfg["n_samp"]
+    xd = torch.empty((n_chan, n_samp), dtype=torch.uint16, device="cuda")
+    table = torch.from_numpy(synth.gaussian_table16()).cuda()
+    synth.gaussian_u16_device(xd.data_ptr(), n_chan, n_samp, n_samp, cfg["seed"], table.data_ptr(),
+                              torch.cuda.current_stream().cuda_stream)
+    xh = synth.gaussian_u16(n_chan, n_samp, cfg["seed"])
+    for dp, width, t0 in cfg["pulses"]:
+        rows, cols, vals, _ = synth.boxcar_updates(lambda r, c: xh[r, c], s[dp], t0, width, cfg["amp"], 65535)
+        xh[rows, cols] = vals
+        xd.view(torch.int16)[torch.from_numpy(rows).cuda(), torch.from_numpy(cols).cuda()] = \
+            torch.from_numpy(vals.view(np.int16)).cuda()
+    torch.cuda.synchronize()
+    plan = plan_for(dd, cfg)
+    assert plan.tiles(0)["row_block"] == 0, plan.tiles(0)
+    out = plan.forward(xd)
+    torch.cuda.synchronize()
+    rows = sample_rows(cfg["n_dm"], cfg["pulses"], every=128, extra=4, seed=11)
+    assert np.array_equal(out[rows].cpu().numpy(), oracle.forward(xh, "u16", n_samp, s, rows=rows))
+    dm0 = xh[:, :plan.n_out].sum(axis=0, dtype=np.int64).astype(np.float32)
+    assert np.array_equal(out[0].cpu().numpy(), dm0)
+    for dp, width, t0 in cfg["pulses"]:
+        assert int(np.argmax(out[:, t0].cpu().numpy())) == dp
+
+
 def test_grad_workload_forward_sampled(dd):
     """1024 float channels x 2^17 samples x 1024 DMs: sampled rows within the FP32 bound."""
     cfg = synth.CONFIGS["grad_f32"]

@@ -246,13 +246,16 @@ def test_survey_time_major_layout(dd):
 
 def test_large_spread_plan_uses_direct_kernel(dd):
     """Plans whose delay spread leaves only 1- or 2-channel LDS stages (4-bit plans: raw-ring
-    stages of at most 4 channels) default to the direct-read kernel with 2 rows x 8 waves (no
-    staging: row_block 0), whose table is the plain shift table."""
+    stages of at most 4 channels) default to the direct-read kernel (no staging: row_block 0),
+    whose table is the plain shift table: 4 rows x 4 waves for 8- and 16-bit samples, 2 rows x
+    8 waves for 4-bit samples."""
     cfg = synth.CONFIGS["lowfreq_wide"]
     p = _plan(dd, cfg)
     t = p.tiles(0)
     assert t["row_block"] == 0 and t["shape"] >= p.n_shapes - 2  # the two direct-read shapes come last
-    assert t["per_wave"] == 2 and t["waves"] == 8
+    assert t["per_wave"] == 4 and t["waves"] == 4
+    t16 = _plan(dd, synth.CONFIGS["lowfreq_wide_u16"]).tiles(0)
+    assert t16["row_block"] == 0 and t16["per_wave"] == 4 and t16["waves"] == 4
     assert p.info.dev_table_bytes >= cfg["n_dm"] * cfg["n_chan"] * 4
     assert p.info.tune_ws_bytes >= p.info.dev_table_bytes
     for name in ["small", "headline", "headline_u4", "headline_u16"]:  # narrow spreads keep LDS staging

@@ -147,3 +147,25 @@ def test_time_chunks_cover_the_output(dd, dtype, n_chunks):
         assert np.array_equal(p.shift, whole.shift)
         t += n
     assert t == whole.n_out
+
+
+def test_16bit_default_takes_the_phase_load_shape(dd):
+    """16-bit plans take the 8-wave, 4-rows-per-wave, 4-channel shape in its phase-load form
+    when two of its workgroups fit in a CU's LDS (the headline plan), its raw-ring form
+    otherwise when that fits twice, and keep the first staged shape that holds the spread
+    when neither does."""
+    def key(t):
+        return (t["ns"], t["per_wave"], t["waves"], t["row_block"])
+    p = _plan(dd, synth.CONFIGS["headline_u16"])
+    t = p.tiles(0)
+    assert key(t) == (16, 4, 8, 4) and t["segs"] > 0 and t["order"] == 2
+    # the 120-190 MHz plan with 16-bit samples: 32 DMs spread over 1638 samples, rows too
+    # long for two workgroups of either form; the first staged shape that holds it stays
+    p = _plan(dd, dict(synth.CONFIGS["lowfreq_u4"], dtype="u16"))
+    t = p.tiles(0)
+    assert key(t) != (16, 4, 8, 4) and t["row_block"] > 0 and t["segs"] == 0
+    for s in range(p.n_shapes):  # and no earlier compiled shape would have held it
+        if s == t["shape"]:
+            break
+        with pytest.raises(dd.DDError):
+            p.set_tiles(0, s, 2)
