@@ -99,7 +99,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 template <int BITS>
 constexpr int lane_samples() { return BITS == 4 ? 32 : 16; }
 
-typedef int32_t v8i32 __attribute__((ext_vector_type(8)));
+typedef int32_t v8i32 __attribute__((ext_vector_type(8), aligned(4)));  // rows of the delay table are only 4-byte aligned
 constexpr int kDelayChunk = 8;  // channels whose delays one scalar load per row reads
 
 // The sums of one wave's R rows over every channel (see the file comment): per
