@@ -17,15 +17,18 @@
 // DPP), and funnel-shifts them (v_alignbit, by a wave-uniform bit count) into
 // the window's words.  Lane 63 has no next lane: it loads its window only for
 // lane 62 and produces no output, so a wave covers 63 lanes' samples and every
-// (channel, DM) window costs one vector load instruction per 16 bytes.  Each (channel, DM) pair
-// gets its own raw buffer descriptor based at the window's first aligned word,
-// with the rest of the channel's row pitch as its record bound, and the loads
-// pass no scalar offset: the bound is checked against the per-lane offset, so
-// every byte past the row pitch reads as zero and no read can leave the input.  In the last time tile,
-// where a lane's window may run past the row, the words are loaded one by one:
-// a 4-byte-aligned word lies wholly inside or wholly outside the bound (both
-// the pitch and the delay offset are multiples of 4 bytes), so the bound check
-// never drops bytes a valid output needs.
+// (channel, DM) window costs one vector load instruction per 16 bytes.  Each
+// channel gets one raw buffer descriptor spanning its row pitch; a window's
+// aligned delay offset is added to the per-lane offset, and the loads pass no
+// scalar offset (which the hardware would not range-check): the bound is
+// checked against the whole offset, so every byte past the row pitch reads as
+// zero and no read can leave the input.  In the last time tile, where a lane's
+// window may run past the row, the words are loaded one by one: a
+// 4-byte-aligned word lies wholly inside or wholly outside the bound (both the
+// pitch and the delay offset are multiples of 4 bytes), so the bound check
+// never drops bytes a valid output needs.  The delays of 8 channels come with
+// one scalar load per DM row, and the row pointer steps by the pitch: the
+// kernel's scalar work per window is a few instructions.
 //
 // Accumulation is the same exact SIMD-in-word arithmetic as the LDS kernels:
 // 8-bit words as mix/odd pairs flushed every 256 channels, 4-bit words as even
