@@ -209,10 +209,13 @@ dd_status dd_execute_adjoint(const dd_plan *plan, const float *d_y, int64_t y_pi
  * samples per lane, input rows per LDS stage) and the workgroup order decide
  * speed only: results are bitwise identical for every choice (exact integer
  * sums; fixed-order float sums).  dd_plan_create picks the first compiled
- * shape that holds the plan's delay spread (integer plans that only fit 1- or
- * 2-channel stages take a direct-read shape; 16-bit plans take the 8-wave,
- * 4-rows-per-wave shape when two of its workgroups fit in one CU's LDS), or the
- * choice recorded for an identical plan in the tuning cache (below).
+ * shape that holds the plan's delay spread, 8- and 4-bit plans trying the
+ * phase-load shapes first (integer plans that only fit 1- or 2-channel stages,
+ * and 4-bit plans left with 4-channel raw-ring stages, take a direct-read
+ * shape: 2 rows x 8 waves for 4-bit input, 4 rows x 4 waves otherwise; 16-bit
+ * plans take the 8-wave, 4-rows-per-wave, 4-channel shape, phase-load form
+ * first, when two of its workgroups fit in one CU's LDS), or the choice
+ * recorded for an identical plan in the tuning cache (below).
  *
  * direction: 0 = forward; 1 = adjoint (DD_F32 plans only).
  *
@@ -251,22 +254,24 @@ dd_status dd_plan_autotune(dd_plan *plan, int32_t direction, const void *d_src, 
  * Batch of independent forward transforms ("beams"), each with its own plan
  * (channel count, length, DM plan), run by persistent kernel launches that pull
  * (beam, DM block, time tile) work items from a device counter, largest items
- * first.  Every beam has a staged tile shape of its own; the beams of one shape
- * form a group, one persistent launch per group, the groups independent of each other.
- * The launch sequence is recorded once as a HIP graph and replayed by every
- * dd_execute_batched call.  By default a beam runs its plan's own forward tile
- * shape (the plan's default, or what the plan was set or tuned to) when that is
- * a staged shape, else the first staged shape that holds the beam (8-bit
- * plans: the phase-load shapes first); dd_batch_set_tiles puts every beam on
- * one shape and dd_batch_autotune chooses between these assignments.
+ * first.  Every beam has a tile shape of its own, staged or direct-read; the
+ * beams of one shape form a group, one persistent launch per group, the groups
+ * independent of each other.  The launch sequence is recorded once as a HIP
+ * graph and replayed by every dd_execute_batched call.  By default a beam runs
+ * its plan's own forward tile shape (the plan's default, or what the plan was
+ * set or tuned to), else (a staged shape whose LDS need falls in the 64 bytes
+ * the persistent kernel keeps for itself) the first staged shape that holds the
+ * beam (the phase-load shapes first), else the plan's default direct-read
+ * shape; dd_batch_set_tiles puts every beam on one shape and dd_batch_autotune
+ * chooses between these assignments.
  *
  * dd_batch_create: plans[0..n-1] must be integer plans (DD_U8, DD_U4 or DD_U16),
- *   all of one dtype, and outlive the batch.  Errors: DD_ERR_ARG, DD_ERR_DTYPE, DD_ERR_NOMEM,
- *   DD_ERR_RANGE (a beam that no staged shape holds).
+ *   all of one dtype, and outlive the batch.  Errors: DD_ERR_ARG, DD_ERR_DTYPE, DD_ERR_NOMEM.
  * dd_batch_workspace_bytes: device workspace dd_batch_bind needs (it does not depend on the shapes).
  * dd_batch_bind: d_in[b], d_out[b], out_pitch[b] as for dd_execute of plan b;
  *   d_workspace holds the group counters, the beam descriptors and the beams'
- *   tables (>= dd_batch_workspace_bytes, 16-byte aligned).  Uploads on
+ *   tables (staged offsets, or the plain shift table for a direct-read shape;
+ *   >= dd_batch_workspace_bytes, 16-byte aligned).  Uploads on
  *   `stream` and records the graph; re-binding re-records it.
  *   Errors: DD_ERR_ARG, DD_ERR_ALIGN, DD_ERR_HIP.
  * dd_execute_batched: replay the graph on `stream`.  Errors: DD_ERR_NOT_BOUND, DD_ERR_ARG (the
@@ -274,11 +279,12 @@ dd_status dd_plan_autotune(dd_plan *plan, int32_t direction, const void *d_src, 
  * dd_batch_get_tiles: the shape every beam runs (order is always 0: work items are claimed
  *   dynamically), or shape = -1 and all other fields 0 when the beams run different shapes.
  * dd_batch_get_beam_tiles: the shape beam `beam` (0..n-1, the order of dd_batch_create) runs.
- * dd_batch_set_tiles: put every beam on compiled staged shape `shape` (DD_ERR_RANGE, batch
- *   unchanged, if a beam cannot be staged with it); unbinds the batch, which keeps its workspace size.
+ * dd_batch_set_tiles: put every beam on compiled shape `shape` (below dd_plan_shape_count of
+ *   the beams' plans: staged or direct-read; DD_ERR_RANGE, batch unchanged, if a beam cannot
+ *   be staged with it); unbinds the batch, which keeps its workspace size.
  * dd_batch_autotune: with the arguments of dd_batch_bind, time the current assignment, every
- *   beam at its default shape, and every staged shape with at least 32 DM rows per workgroup for
- *   all beams, each on the whole batch (one warm-up replay, one timed replay with HIP events on
+ *   beam at its default shape, and every staged shape with at least 32 DM rows per workgroup and
+ *   every direct-read shape for all beams, each on the whole batch (one warm-up replay, one timed replay with HIP events on
  *   `stream`); keep the fastest (the current one stays unless another is at least 2% faster) and
  *   leave the batch bound with it.  Outputs are overwritten.  Synchronises `stream`.  *report may
  *   be NULL (best is as dd_batch_get_tiles; timed_out_samples is 0: whole replays are timed).

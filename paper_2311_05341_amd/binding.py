@@ -415,13 +415,13 @@ class Batch:
         return t.as_dict()
 
     def set_tiles(self, shape, stream=None):
-        """Put every beam on compiled staged shape `shape` and re-bind."""
+        """Put every beam on compiled shape `shape` (staged or direct-read) and re-bind."""
         _check(_lib.dd_batch_set_tiles(self._h, int(shape)), "dd_batch_set_tiles")
         self.bind(stream)
 
     def autotune(self, stream=None) -> dict:
-        """Time the per-beam default shapes and the shared staged shapes on the whole batch and keep the
-        fastest (dd_batch_autotune); outputs are overwritten."""
+        """Time the per-beam default shapes and the shared staged and direct-read shapes on the whole
+        batch and keep the fastest (dd_batch_autotune); outputs are overwritten."""
         ins, outs, pitches = self._bind_args()
         rep = TuneReport()
         _check(_lib.dd_batch_autotune(self._h, ins, outs, pitches, self.workspace.data_ptr(), self.workspace.numel(),

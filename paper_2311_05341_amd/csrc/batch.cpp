@@ -1,9 +1,9 @@
 // Batched forward: many beams, each with its own plan, run by persistent
 // kernel launches recorded once as a HIP graph and replayed by
-// dd_execute_batched.  Each beam has a staged tile shape of its own; beams of
-// one shape form a group, and each group is one persistent launch (counter
-// reset, then the kernel claiming that group's work items), the groups
-// independent nodes of the graph.
+// dd_execute_batched.  Each beam has a tile shape of its own, staged or
+// direct-read; beams of one shape form a group, and each group is one
+// persistent launch (counter reset, then the kernel claiming that group's work
+// items), the groups independent nodes of the graph.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -19,13 +19,13 @@ using namespace dd;
 
 namespace {
 
-// Beams sharing one staged tile shape and as many workgroups per CU as their
-// LDS allows: one persistent launch.  (The launch's LDS is the largest of its
-// beams', so beams of one shape whose LDS needs allow different numbers of
-// resident workgroups are kept apart.)
+// Beams sharing one tile shape and as many workgroups per CU as their LDS
+// allows: one persistent launch.  (The launch's LDS is the largest of its
+// beams', so beams of one staged shape whose LDS needs allow different numbers
+// of resident workgroups are kept apart.)
 struct BatchGroup {
-  int shape = 0;                // index in kIntShapes
-  int per_cu = 0;               // workgroups per CU its beams' LDS allows
+  int shape = 0;                // plan shape index (staged below kNumIntShapes, direct-read above)
+  int per_cu = 0;               // workgroups per CU its beams' LDS allows (0: direct-read, no LDS)
   int lds_bytes = 0;            // largest of its beams' LDS needs
   std::vector<int> beams;       // original beam indices, in decreasing per-item cost
   size_t desc_first = 0;        // index of its first descriptor in the workspace's descriptor array
@@ -37,8 +37,8 @@ struct BatchGroup {
 struct dd_batch {
   std::vector<const dd_plan *> plans;
   int dtype = 0;
-  std::vector<int> shape;         // per beam (original index): its staged shape
-  std::vector<IntTables> tables;  // per beam (original index), for its shape
+  std::vector<int> shape;         // per beam (original index): its shape
+  std::vector<IntTables> tables;  // per beam (original index), for its shape (empty for direct-read)
   std::vector<int> order;         // beams in decreasing per-item cost
   std::vector<BatchGroup> groups;
   std::vector<BeamDesc> descs;    // group after group, each group's beams in cost order
@@ -54,6 +54,9 @@ static const int kBatchLdsLimit = 160 * 1024 - 64;  // leaves room for the claim
 static const int kMaxGroups = 64;
 
 static size_t up256(size_t v) { return (v + 255) / 256 * 256; }
+
+static bool direct_shape(int s) { return s >= kNumIntShapes; }
+static int num_batch_shapes() { return kNumIntShapes + kNumDirectShapes; }
 
 static void release_graph(dd_batch *b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -72,26 +75,34 @@ static void int_table_bytes(const dd_plan &p, const int *k, size_t *offs, size_t
 }
 
 // Workspace layout: one 256-byte counter slot per group (at most one per
-// compiled shape and LDS occupancy class), the beam
-// descriptors, then per beam room for its tables under the largest compiled
-// shape, so that no assignment of shapes moves anything.
+// compiled shape and LDS occupancy class), the beam descriptors, then per beam
+// room for its tables under the largest compiled staged shape or its plain
+// int32 shift table (what a direct-read shape reads), so that no assignment of
+// shapes moves anything.
 static size_t counters_bytes() { return (size_t)kMaxGroups * 256; }
 static size_t descs_offset() { return counters_bytes(); }
 
-// Give beam i staged shape shapes[i], for every beam: tables, groups, work
-// items.  DD_ERR_RANGE (batch unchanged) if a beam cannot be staged with its shape.
+// Give beam i shape shapes[i], for every beam: tables, groups, work items.
+// DD_ERR_RANGE (batch unchanged) if a beam cannot be staged with its shape.
 static dd_status batch_assign(dd_batch *b, const std::vector<int> &shapes) {
   const int n = (int)b->plans.size();
   std::vector<IntTables> tabs(n);
   for (int i = 0; i < n; ++i) {
+    const dd_plan &p = *b->plans[i];
+    if (direct_shape(shapes[i])) {  // reads the plan's shift table; its descriptors stay inside the row pitch
+      const int bits = p.desc.dtype == DD_U4 ? 4 : p.desc.dtype == DD_U16 ? 16 : 8;
+      if ((int64_t)p.max_shift * bits / 8 >= p.in_pitch_bytes) return fail(DD_ERR_RANGE, "delay exceeds the row pitch");
+      continue;
+    }
     const int *k = kIntShapes[shapes[i]];
-    const dd_status st = build_int_tables(*b->plans[i], k[0], k[1], k[2], k[3], k[4], kBatchLdsLimit, &tabs[i]);
+    const dd_status st = build_int_tables(p, k[0], k[1], k[2], k[3], k[4], kBatchLdsLimit, &tabs[i]);
     if (st != DD_OK) return st;
   }
   std::vector<BatchGroup> groups;
   for (int q = 0; q < n; ++q) {  // groups in order of their costliest beam
     const int i = b->order[q];
-    const int per_cu = (kBatchLdsLimit + 64) / (tabs[i].lds_bytes + 64);  // the kernel keeps 64 bytes of its own
+    // the staged kernel keeps 64 bytes of LDS of its own
+    const int per_cu = direct_shape(shapes[i]) ? 0 : (kBatchLdsLimit + 64) / (tabs[i].lds_bytes + 64);
     auto g = std::find_if(groups.begin(), groups.end(),
                           [&](const BatchGroup &x) { return x.shape == shapes[i] && x.per_cu == per_cu; });
     if (g == groups.end()) {
@@ -107,8 +118,8 @@ static dd_status batch_assign(dd_batch *b, const std::vector<int> &shapes) {
   std::vector<BeamDesc> descs(n);
   size_t q = 0;
   for (BatchGroup &g : groups) {
-    const int *k = kIntShapes[g.shape];
-    const int dm_tile = k[1] * k[2], t_tile = 64 * k[0];
+    const int *k = int_shape(g.shape);
+    const int dm_tile = k[1] * k[2], t_tile = direct_shape(g.shape) ? direct_tile_samples(b->dtype) : 64 * k[0];
     g.desc_first = q;
     long long items = 0;
     for (int i : g.beams) {
@@ -137,10 +148,12 @@ static dd_status batch_assign(dd_batch *b, const std::vector<int> &shapes) {
   return DD_OK;
 }
 
-// The shape a beam runs by default: its plan's own staged forward shape (its
-// default, or what the plan was set or tuned to), else the first staged shape
-// that holds it (phase-load shapes first for 8-bit input).
+// The shape a beam runs by default: its plan's own forward shape (its default,
+// or what the plan was set or tuned to), staged or direct-read, else the first
+// staged shape that holds it (phase-load shapes first), else the plan's
+// default direct-read shape.
 static int default_shape(const dd_plan &p) {
+  if (is_direct(p.fwd) && direct_shape(p.fwd.shape)) return p.fwd.shape;
   if (!is_direct(p.fwd) && p.fwd.shape < kNumIntShapes) {
     IntTables t;
     const int *k = kIntShapes[p.fwd.shape];
@@ -153,11 +166,11 @@ static int default_shape(const dd_plan &p) {
       const int *k = kIntShapes[s];
       if (build_int_tables(p, k[0], k[1], k[2], k[3], k[4], kBatchLdsLimit, &t, false) == DD_OK) return s;
     }
-  return -1;
+  return kNumIntShapes + (p.desc.dtype == DD_U4 ? 1 : 0);
 }
 
 static void fill_tiles(int s, dd_tiles *t) {
-  const int *k = kIntShapes[s];
+  const int *k = int_shape(s);
   t->shape = s;
   t->order = 0;
   t->ns = k[0];
@@ -194,7 +207,7 @@ dd_status dd_batch_create(const dd_plan *const *plans, int32_t n, dd_batch **out
   b->table_offs.assign(n, 0);
   b->sbase_offs.assign(n, 0);
   for (int i = 0; i < n; ++i) {
-    size_t ob = 0, sbb = 0;
+    size_t ob = up256(b->plans[i]->shift.size() * sizeof(int32_t)), sbb = 0;
     for (int s = 0; s < kNumIntShapes; ++s) {
       size_t o, sb;
       int_table_bytes(*b->plans[i], kIntShapes[s], &o, &sb);
@@ -208,13 +221,7 @@ dd_status dd_batch_create(const dd_plan *const *plans, int32_t n, dd_batch **out
   }
   b->ws_bytes = off;
   std::vector<int> shapes(n);
-  for (int i = 0; i < n; ++i) {
-    shapes[i] = default_shape(*b->plans[i]);
-    if (shapes[i] < 0) {
-      delete b;
-      return fail(DD_ERR_RANGE, "beam " + std::to_string(i) + "'s delay spread exceeds the LDS staging capacity");
-    }
-  }
+  for (int i = 0; i < n; ++i) shapes[i] = default_shape(*b->plans[i]);
   const dd_status st = batch_assign(b, shapes);
   if (st != DD_OK) { delete b; return st; }
   *out = b;
@@ -255,6 +262,11 @@ dd_status dd_batch_bind(dd_batch *b, const void *const *d_in, float *const *d_ou
   hipStream_t st = (hipStream_t)stream;
   e = hipMemcpyAsync(base + descs_offset(), b->descs.data(), sizeof(BeamDesc) * n, hipMemcpyHostToDevice, st);
   for (int i = 0; i < n && e == hipSuccess; ++i) {
+    if (direct_shape(b->shape[i])) {
+      const std::vector<int32_t> &sh = b->plans[i]->shift;
+      e = hipMemcpyAsync(base + b->table_offs[i], sh.data(), sh.size() * 4, hipMemcpyHostToDevice, st);
+      continue;
+    }
     e = hipMemcpyAsync(base + b->table_offs[i], b->tables[i].offs.data(), b->tables[i].offs.size() * 4,
                        hipMemcpyHostToDevice, st);
     if (e == hipSuccess)
@@ -272,9 +284,10 @@ dd_status dd_batch_bind(dd_batch *b, const void *const *d_in, float *const *d_ou
   e = hipGraphCreate(&b->graph, 0);
   for (size_t gi = 0; gi < b->groups.size() && e == hipSuccess; ++gi) {
     const BatchGroup &g = b->groups[gi];
-    const int *k = kIntShapes[g.shape];
+    const int *k = int_shape(g.shape);
     BatchLaunch L = {};
-    const int le = batch_kernels(k[0], k[1], k[2], k[3], k[4], b->dtype, g.lds_bytes, &L);
+    const int le = direct_shape(g.shape) ? batch_direct_kernels(k[1], k[2], b->dtype, &L)
+                                         : batch_kernels(k[0], k[1], k[2], k[3], k[4], b->dtype, g.lds_bytes, &L);
     if (le) {
       release_graph(b);
       return fail(DD_ERR_HIP, std::string("batch kernel setup: ") + hipGetErrorString((hipError_t)le));
@@ -347,7 +360,7 @@ dd_status dd_batch_get_beam_tiles(const dd_batch *b, int32_t beam, dd_tiles *t) 
 
 dd_status dd_batch_set_tiles(dd_batch *b, int32_t shape) {
   if (!b) return fail(DD_ERR_ARG, "null batch");
-  if (shape < 0 || shape >= kNumIntShapes) return fail(DD_ERR_ARG, "no such staged tile shape");
+  if (shape < 0 || shape >= num_batch_shapes()) return fail(DD_ERR_ARG, "no such tile shape");
   const dd_status st = batch_assign(b, std::vector<int>(b->plans.size(), shape));
   if (st == DD_ERR_RANGE) return fail(st, "a beam's delay spread does not fit this shape");
   return st;
@@ -383,15 +396,16 @@ dd_status dd_batch_autotune(dd_batch *b, const void *const *d_in, float *const *
     return DD_OK;
   };
   // Candidates: the current assignment, every beam at its default shape, and
-  // every staged shape with at least 32 DM rows per workgroup shared by all
-  // beams (smaller ones only pay where a beam's default had to fall back to them).
+  // every staged shape with at least 32 DM rows per workgroup, and every
+  // direct-read shape, shared by all beams (smaller staged ones only pay where
+  // a beam's default had to fall back to them).
   std::vector<std::vector<int>> cands;
   cands.push_back(orig);
   std::vector<int> defaults(orig.size());
   for (size_t i = 0; i < orig.size(); ++i) defaults[i] = default_shape(*b->plans[i]);
   if (defaults != orig) cands.push_back(defaults);
-  for (int s = 0; s < kNumIntShapes; ++s) {
-    if (kIntShapes[s][1] * kIntShapes[s][2] < 32) continue;
+  for (int s = 0; s < num_batch_shapes(); ++s) {
+    if (!direct_shape(s) && kIntShapes[s][1] * kIntShapes[s][2] < 32) continue;
     std::vector<int> all(orig.size(), s);
     if (all != orig && all != defaults) cands.push_back(all);
   }

@@ -187,6 +187,11 @@ struct BatchLaunch {
 };
 int batch_kernels(int ns, int dm_per_wave, int waves, int chan_block, int segs, int dtype, int lds_bytes,
                   BatchLaunch *out);
+// The same for a direct-read shape (fwd_direct.hip); its work items are time
+// tiles of direct_tile_samples(dtype) outputs by DM blocks of waves x
+// dm_per_wave rows, and a beam's table is its plain int32 shift table.
+int batch_direct_kernels(int dm_per_wave, int waves, int dtype, BatchLaunch *out);
+int direct_tile_samples(int dtype);
 
 // Time binning (bin.hip): bytes per output element, and the launch.  The
 // caller has validated every argument (sizes, alignment, factor 1..256).

@@ -251,12 +251,12 @@ __device__ __forceinline__ void direct_channels(const DirectArgs &a, const int (
   }
 }
 
+// One tile: DM block dblk (NW * R rows) x time tile tblk (63 * NS samples).
+// No LDS and no barrier.
 template <int BITS, int R, int NW>
-__global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n_dblk, int n_tiles, int order) {
+__device__ __forceinline__ void direct_tile(const DirectArgs &a, int dblk, int tblk) {
   constexpr int NS = lane_samples<BITS>();
   constexpr int WORDS = NS * BITS / 32;  // window words per lane (4, or 8 for 16-bit)
-  int dblk, tblk;
-  tile_of((int)blockIdx.x, n_dblk, n_tiles, order, dblk, tblk);
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int lane = threadIdx.x & 63;
   const int d0 = (dblk * NW + w) * R;
@@ -293,20 +293,92 @@ __global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n
       }
   }
   const int64_t tl = t0 + NS * lane;
-  if (lane >= kOutLanes) return;
+  if (lane < kOutLanes) {
 #pragma unroll
-  for (int r = 0; r < R; ++r) {
-    if (d0 + r >= a.n_dm) break;
-    float *o = a.out + (int64_t)(d0 + r) * a.out_pitch + tl;
-    if (BITS == 16 && a.out_mode != kOutFloat) {
-      for (int k = 0; k < NS && tl + k < a.n_out; ++k) store_total(o + k, tot[r][k], a.out_mode);
-    } else if (tl + NS <= a.n_out) {
+    for (int r = 0; r < R; ++r) {
+      if (d0 + r >= a.n_dm) break;
+      float *o = a.out + (int64_t)(d0 + r) * a.out_pitch + tl;
+      if (BITS == 16 && a.out_mode != kOutFloat) {
+        for (int k = 0; k < NS && tl + k < a.n_out; ++k) store_total(o + k, tot[r][k], a.out_mode);
+      } else if (tl + NS <= a.n_out) {
 #pragma unroll
-      for (int k = 0; k < NS; k += 4)
-        *(float4 *)(o + k) = make_float4((float)tot[r][k], (float)tot[r][k + 1], (float)tot[r][k + 2], (float)tot[r][k + 3]);
-    } else {
-      for (int k = 0; k < NS && tl + k < a.n_out; ++k) o[k] = (float)tot[r][k];
+        for (int k = 0; k < NS; k += 4)
+          *(float4 *)(o + k) =
+              make_float4((float)tot[r][k], (float)tot[r][k + 1], (float)tot[r][k + 2], (float)tot[r][k + 3]);
+      } else {
+        for (int k = 0; k < NS && tl + k < a.n_out; ++k) o[k] = (float)tot[r][k];
+      }
     }
+  }
+}
+
+template <int BITS, int R, int NW>
+__global__ __launch_bounds__(NW * 64) void fwd_direct_kernel(DirectArgs a, int n_dblk, int n_tiles, int order) {
+  int dblk, tblk;
+  tile_of((int)blockIdx.x, n_dblk, n_tiles, order, dblk, tblk);
+  direct_tile<BITS, R, NW>(a, dblk, tblk);
+}
+
+__global__ void reset_direct_counter_kernel(unsigned long long *counter) { *counter = 0ull; }
+
+// Workgroup barrier for the claimed-item slot in LDS (the tiles themselves use
+// no LDS; the tile's stores need not have completed).
+__device__ __forceinline__ void claim_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Persistent batched direct-read kernel, the counterpart of the staged one in
+// fwd_int.hip: workgroups claim (beam, DM block, time tile) work items from a
+// device counter (beams in decreasing cost order, DM block fastest inside a
+// beam); a beam's delay table is the plain int32 shift table (BeamDesc.offs).
+// The claim of the next item is issued when an item starts and read when it
+// ends.  A tile has no barrier of its own, so a second barrier after reading
+// the claim keeps thread 0 from overwriting it before every wave has read it.
+// A workgroup returns at its first claim past the last item: every wave
+// reaches the exit.
+// Waves per SIMD the batched kernel is held to.  Its claim state costs 8-12
+// more VGPRs than the one-launch kernel; on the 8-wave shape for 4-bit samples
+// that would leave one resident workgroup per CU instead of two (8 wide-spread
+// beams, 1024-2048 ch x 2^18-2^19 at 120-190 MHz: 33.9 -> 27.2 ms when held to
+// 4 waves).  The other shapes keep their occupancy as they are (16-bit ones
+// held to 4 or 3 waves ran 11% and 8% slower).
+template <int BITS, int NW>
+constexpr int direct_batched_waves() {
+  return NW == 8 && BITS == 4 ? 4 : 1;
+}
+
+template <int BITS, int R, int NW>
+__global__ __launch_bounds__(NW * 64, (direct_batched_waves<BITS, NW>())) void fwd_direct_batched_kernel(
+    const BeamDesc *__restrict__ beams, int n_beams, long long n_items, unsigned long long *__restrict__ counter) {
+  __shared__ long long claimed;
+  if (threadIdx.x == 0) claimed = (long long)atomicAdd(counter, 1ull);
+  claim_barrier();
+  long long item = claimed;
+  int lo = 0;
+  for (;;) {
+    item = (long long)(((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)((unsigned long long)item >> 32))
+                        << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)item));
+    if (item >= n_items) return;
+    unsigned long long next = 0;
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1ull);  // the following claim, read after this tile
+    while (lo + 1 < n_beams && scalar_load(&beams[lo + 1].item_begin, 0) <= item) ++lo;
+    const BeamDesc &b = beams[lo];
+    const long long k = item - b.item_begin;
+    const int tblk = (int)(k / b.tiles_d), dblk = (int)(k - (long long)tblk * b.tiles_d);
+    DirectArgs a;
+    a.x = b.x;
+    a.shift = (const int32_t *)b.offs;
+    a.out = b.out;
+    a.pitch = b.pitch;
+    a.n_out = b.n_out;
+    a.out_pitch = b.out_pitch;
+    a.n_chan = b.n_chan;
+    a.n_dm = b.n_dm;
+    a.out_mode = kOutFloat;
+    direct_tile<BITS, R, NW>(a, dblk, tblk);
+    if (threadIdx.x == 0) claimed = (long long)next;
+    claim_barrier();  // publishes the claim
+    item = claimed;
+    claim_barrier();  // every wave has read it before thread 0 writes the next one
   }
 }
 
@@ -359,6 +431,35 @@ int launch_forward_direct(const dd_plan &p, const void *tables, const void *d_in
   DD_DIRECT_SHAPES(DD_TRY)
 #undef DD_TRY
   return (int)hipErrorInvalidValue;
+}
+
+int direct_tile_samples(int dtype) {
+  return kOutLanes * (dtype == DD_U4 ? lane_samples<4>() : dtype == DD_U16 ? lane_samples<16>() : lane_samples<8>());
+}
+
+int batch_direct_kernels(int dm_per_wave, int waves, int dtype, BatchLaunch *out) {
+  const void *fn = nullptr;
+#define DD_TRY(R, NW)                                                                                    \
+  if (dm_per_wave == R && waves == NW)                                                                   \
+    fn = dtype == DD_U4    ? (const void *)fwd_direct_batched_kernel<4, R, NW>                           \
+         : dtype == DD_U16 ? (const void *)fwd_direct_batched_kernel<16, R, NW>                          \
+                           : (const void *)fwd_direct_batched_kernel<8, R, NW>;
+  DD_DIRECT_SHAPES(DD_TRY)
+#undef DD_TRY
+  if (!fn) return (int)hipErrorInvalidValue;
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, waves * 64, 0);
+  if (e != hipSuccess) return (int)e;
+  int dev = 0, n_cu = 0;
+  e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e != hipSuccess) return (int)e;
+  out->reset_fn = (const void *)reset_direct_counter_kernel;
+  out->main_fn = fn;
+  out->grid = n_cu * (per_cu > 0 ? per_cu : 1);
+  out->block = waves * 64;
+  out->lds_bytes = 0;
+  return 0;
 }
 
 }  // namespace dd

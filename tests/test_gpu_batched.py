@@ -5,7 +5,7 @@ import torch
 
 import oracle
 import synth
-from helpers import oracle_table, plan_for, sample_rows
+from helpers import host_input, oracle_table, plan_for, sample_rows
 
 pytestmark = pytest.mark.gpu
 
@@ -122,8 +122,9 @@ def test_batched_u16_beams(dd):
 
 
 def test_batched_every_shape_and_autotune(dd):
-    """Every staged shape that holds the beams gives the same bits (equal to plain calls), and the
-    batch autotuner leaves the batch bound with one of them, results unchanged."""
+    """Every staged shape that holds the beams and both direct-read shapes give the same bits (equal
+    to plain calls), and the batch autotuner leaves the batch bound with one of them, results
+    unchanged."""
     beams = _beams(5, 78, 60000)
     plans, xs = [], []
     for cfg in beams:
@@ -133,7 +134,7 @@ def test_batched_every_shape_and_autotune(dd):
     plain = [p.forward(x).clone() for p, x in zip(plans, xs)]
     batch = dd.Batch(plans, xs)
     n_ok = 0
-    for shape in range(plans[0].n_shapes - 2):  # every staged shape (the two direct-read shapes come last)
+    for shape in range(plans[0].n_shapes):  # every staged shape, then the two direct-read shapes
         try:
             batch.set_tiles(shape)
         except dd.DDError as e:
@@ -146,7 +147,7 @@ def test_batched_every_shape_and_autotune(dd):
         for b in range(len(beams)):
             assert torch.equal(outs[b], plain[b]), (shape, b)
         n_ok += 1
-    assert n_ok >= 5
+    assert n_ok >= 7
     rep = batch.autotune()
     assert rep["n_tried"] >= 2 and rep["best"]["shape"] == batch.tiles()["shape"]
     outs = batch.run()
@@ -181,3 +182,38 @@ def test_batched_beam_with_one_output_sample(dd, dtype):
     torch.cuda.synchronize()
     for o, w in zip(outs, wants):
         assert np.array_equal(o.cpu().numpy(), w)
+
+
+@pytest.mark.parametrize("dtype", ["u8", "u4", "u16"])
+def test_batched_wide_beams_read_directly(dtype):
+    """Beams whose delay spread is too wide to stage (120-190 MHz, ~4000 samples of spread per
+    16 DM rows) run their plans' direct-read shape inside a batch, next to a narrow staged beam:
+    two direct beams (100 and a ragged 37 DM rows) and the staged one, over two replays,
+    bit-exact against plain calls and the oracle."""
+    import paper_2311_05341_amd as dd
+    wide = dict(dtype=dtype, n_chan=256, n_samp=1 << 17, f_high=190.0, chan_bw=70.0 / 256, t_samp=327.68e-6,
+                dm_start=0.0, dm_step=0.5, n_dm=100, seed=71)
+    beams = [wide, dict(wide, n_chan=200, chan_bw=70.0 / 200, n_samp=100000, n_dm=37, dm_start=3.0, seed=72),
+             dict(dtype=dtype, n_chan=96, n_samp=50016, f_high=1500.0, chan_bw=3.0, t_samp=64e-6,
+                  dm_start=0.0, dm_step=0.5, n_dm=64, seed=73)]
+    plans, xs, hosts, tables = [], [], [], []
+    for cfg in beams:
+        tables.append(oracle_table(cfg))
+        x, _ = host_input(cfg)
+        plans.append(plan_for(dd, cfg))
+        xs.append(torch.from_numpy(x).cuda())
+        hosts.append(x)
+    assert [p.tiles(0)["row_block"] == 0 for p in plans] == [True, True, False]
+    batch = dd.Batch(plans, xs)
+    for b, p in enumerate(plans):
+        assert batch.beam_tiles(b)["shape"] == p.tiles(0)["shape"]
+    print("batch with direct-read beams: %s" % dtype, flush=True)
+    outs = [o.clone() for o in batch.run()]
+    outs2 = batch.run()
+    torch.cuda.synchronize()
+    for b, cfg in enumerate(beams):
+        assert torch.equal(outs[b], outs2[b]), b
+        assert torch.equal(outs[b], plans[b].forward(xs[b])), b
+        rows = sample_rows(cfg["n_dm"], every=13)
+        want = oracle.forward(hosts[b], dtype, cfg["n_samp"], tables[b], rows=rows)
+        assert np.array_equal(outs[b][rows].cpu().numpy(), want), b

@@ -266,8 +266,9 @@ def test_large_spread_plan_uses_direct_kernel(dd):
 
 
 def test_batch_tile_choice_host(dd):
-    """Batch shape selection on the host: the default stages every beam, set_tiles switches or
-    refuses (DD_ERR_RANGE, batch unchanged), and the workspace size does not depend on the shape."""
+    """Batch shape selection on the host: by default each beam runs its plan's own shape (staged,
+    or direct-read for a wide delay spread), set_tiles switches or refuses (DD_ERR_RANGE, batch
+    unchanged), and the workspace size does not depend on the shape."""
     lib = ctypes.CDLL(dd.LIB_PATH)
     lib.dd_batch_create.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.POINTER(ctypes.c_void_p)]
     lib.dd_batch_workspace_bytes.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_size_t)]
@@ -276,10 +277,14 @@ def test_batch_tile_choice_host(dd):
     lib.dd_batch_destroy.argtypes = [ctypes.c_void_p]
     small = synth.CONFIGS["small"]
     wide = dict(small, n_chan=64, chan_bw=0.3, dm_step=40.0, n_dm=40, n_samp=1 << 17)  # a wide delay spread
-    plans = [_plan(dd, small), _plan(dd, wide)]
-    arr = (ctypes.c_void_p * 2)(*[p._h for p in plans])
+    # a spread of ~4000 samples per 16 DM rows at 120-190 MHz: the plan reads directly
+    widest = dict(small, n_chan=256, f_high=190.0, chan_bw=70.0 / 256, t_samp=327.68e-6, dm_step=0.5, n_dm=100,
+                  n_samp=1 << 17)
+    plans = [_plan(dd, small), _plan(dd, wide), _plan(dd, widest)]
+    assert plans[2].tiles(0)["row_block"] == 0
+    arr = (ctypes.c_void_p * 3)(*[p._h for p in plans])
     h = ctypes.c_void_p()
-    assert lib.dd_batch_create(arr, 2, ctypes.byref(h)) == 0
+    assert lib.dd_batch_create(arr, 3, ctypes.byref(h)) == 0
     try:
         t = dd.binding.Tiles()
         assert lib.dd_batch_get_tiles(h, ctypes.byref(t)) == 0
@@ -287,9 +292,9 @@ def test_batch_tile_choice_host(dd):
         lib.dd_batch_workspace_bytes(h, ctypes.byref(ws0))
         first = t.shape
         n_staged = plans[0].n_shapes - 2  # the staged shapes; the two direct-read shapes follow them
-        assert lib.dd_batch_set_tiles(h, n_staged) == -1 and lib.dd_batch_set_tiles(h, -1) == -1
+        assert lib.dd_batch_set_tiles(h, n_staged + 2) == -1 and lib.dd_batch_set_tiles(h, -1) == -1
         ok, segs = [], {}
-        for s in range(n_staged):
+        for s in range(n_staged + 2):
             rc = lib.dd_batch_set_tiles(h, s)
             assert rc in (0, -3), rc
             lib.dd_batch_get_tiles(h, ctypes.byref(t))
@@ -300,29 +305,36 @@ def test_batch_tile_choice_host(dd):
             ws = ctypes.c_size_t()
             lib.dd_batch_workspace_bytes(h, ctypes.byref(ws))
             assert ws.value == ws0.value
-        assert ok and len(ok) < n_staged  # the wide beam rules some shapes out
-        # the default: every beam on its plan's own shape when that is staged, else on the first
-        # staged shape that holds it (phase-load shapes first); here the two beams differ
+        assert ok and len(ok) < n_staged + 2  # the wide beam rules some staged shapes out
+        assert n_staged in ok and n_staged + 1 in ok  # the direct-read shapes take any spread
+        lib.dd_batch_set_tiles(h, n_staged + 1)
+        lib.dd_batch_get_tiles(h, ctypes.byref(t))
+        assert t.row_block == 0 and t.per_wave == 2 and t.waves == 8
+        # the default: every beam on its plan's own shape, staged or direct-read, else (a staged
+        # shape whose LDS need falls in the persistent kernel's own 64 bytes) on the first staged
+        # shape that holds it (phase-load shapes first); here the two beams differ
         assert first == -1
     finally:
         lib.dd_batch_destroy(h)
     # a fresh batch reports each beam's default
     lib.dd_batch_get_beam_tiles.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(dd.binding.Tiles)]
     h = ctypes.c_void_p()
-    assert lib.dd_batch_create(arr, 2, ctypes.byref(h)) == 0
+    assert lib.dd_batch_create(arr, 3, ctypes.byref(h)) == 0
     try:
         for b, p in enumerate(plans):
             t = dd.binding.Tiles()
             assert lib.dd_batch_get_beam_tiles(h, b, ctypes.byref(t)) == 0
             own = p.tiles(0)
-            assert t.row_block > 0
-            if own["row_block"] > 0:
+            assert (t.row_block > 0) == (own["row_block"] > 0)
+            if own["row_block"] == 0:
+                assert t.shape == own["shape"]  # the plan's direct-read shape
+            else:
                 # the plan's own shape, unless its LDS need falls in the 64 bytes the persistent
                 # kernel keeps for itself: then a later staged shape
                 assert t.shape >= own["shape"]
                 if b == 0:
                     assert t.shape == own["shape"]
-        assert lib.dd_batch_get_beam_tiles(h, 2, ctypes.byref(t)) == -1
+        assert lib.dd_batch_get_beam_tiles(h, 3, ctypes.byref(t)) == -1
     finally:
         lib.dd_batch_destroy(h)
 
