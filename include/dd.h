@@ -212,10 +212,11 @@ dd_status dd_execute_adjoint(const dd_plan *plan, const float *d_y, int64_t y_pi
  * shape that holds the plan's delay spread, 8- and 4-bit plans trying the
  * phase-load shapes first (integer plans that only fit 1- or 2-channel stages,
  * and 4-bit plans left with 4-channel raw-ring stages, take a direct-read
- * shape: 2 rows x 8 waves for 4-bit input, 4 rows x 4 waves otherwise; 16-bit
- * plans take the 8-wave, 4-rows-per-wave, 4-channel shape, phase-load form
- * first, when two of its workgroups fit in one CU's LDS), or the choice
- * recorded for an identical plan in the tuning cache (below).
+ * shape: 2 rows x 8 waves in order 1 for 4-bit input, 4 rows x 4 waves
+ * otherwise; 16-bit plans take the 8-wave, 4-rows-per-wave, 4-channel shape,
+ * phase-load form first, when two of its workgroups fit in one CU's LDS), in
+ * order 2 unless stated, or the choice recorded for an identical plan in the
+ * tuning cache (below).
  *
  * direction: 0 = forward; 1 = adjoint (DD_F32 plans only).
  *

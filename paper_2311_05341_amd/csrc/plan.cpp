@@ -357,10 +357,13 @@ dd_status choose_forward_tiles(dd_plan &p) {
   // Tadds/s for the 4-channel raw ring)
   // Direct shape: 2 rows x 8 waves for 4-bit input (4096 ch x 2^19 at 120-190 MHz: 46.2
   // against 38.3 Tadds/s for 4 x 4), 4 rows x 4 waves otherwise (4096 ch x 2^20 at 120-190
-  // MHz, DM step 0.5: 30.0 against 25.9 for 8-bit samples, 11.7 against 8.2 for 16-bit)
+  // MHz, DM step 0.5: 30.0 against 25.9 for 8-bit samples, 11.7 against 8.2 for 16-bit).
+  // Order: whole time tiles per XCD for 4-bit input (there 50.0 against 46.2 Tadds/s for the
+  // grouped order), the grouped order otherwise (8-bit 30.1 against 29.7; 16-bit equal)
   const int direct_below = p.desc.dtype == DD_U4 && !is_direct(p.fwd) && p.fwd.segs == 0 ? 4 : 2;
   if (p.desc.dtype != DD_F32 && !is_direct(p.fwd) && p.fwd.chan_block <= direct_below)
-    return set_tiles(p, 0, kNumIntShapes + (p.desc.dtype == DD_U4 ? 1 : 0), kOrderDmGroups);
+    return p.desc.dtype == DD_U4 ? set_tiles(p, 0, kNumIntShapes + 1, kOrderXcdTiles)
+                                 : set_tiles(p, 0, kNumIntShapes, kOrderDmGroups);
   // 16-bit plans: the 8-wave shape with 4 rows per wave and 4 channels per stage,
   // where two of its workgroups fit in a CU's LDS, so that one's barrier waits
   // overlap the other's adds: first in its phase-load form (the two copies loaded
