@@ -217,3 +217,29 @@ def test_batched_wide_beams_read_directly(dtype):
         rows = sample_rows(cfg["n_dm"], every=13)
         want = oracle.forward(hosts[b], dtype, cfg["n_samp"], tables[b], rows=rows)
         assert np.array_equal(outs[b][rows].cpu().numpy(), want), b
+
+
+def test_batched_two_direct_shapes_in_one_graph():
+    """Two 4-bit wide-spread beams, one set to each direct-read shape (4 x 4 and 2 x 8), run as
+    two direct-read groups of one graph: bit-exact against plain calls on the same shapes."""
+    import paper_2311_05341_amd as dd
+    base = dict(dtype="u4", n_chan=256, n_samp=1 << 17, f_high=190.0, chan_bw=70.0 / 256, t_samp=327.68e-6,
+                dm_start=0.0, dm_step=0.5, n_dm=90, seed=81)
+    beams = [base, dict(base, n_dm=51, dm_start=7.0, seed=82)]
+    plans, xs = [], []
+    for cfg in beams:
+        x, _ = host_input(cfg)
+        plans.append(plan_for(dd, cfg))
+        xs.append(torch.from_numpy(x).cuda())
+    n = plans[0].n_shapes
+    plans[0].set_tiles(0, n - 2, 2)  # 4 rows x 4 waves
+    plans[1].set_tiles(0, n - 1, 1)  # 2 rows x 8 waves
+    plain = [p.forward(x).clone() for p, x in zip(plans, xs)]
+    batch = dd.Batch(plans, xs)
+    assert [batch.beam_tiles(b)["shape"] for b in range(2)] == [n - 2, n - 1]
+    assert batch.tiles()["shape"] == -1
+    print("batch with both direct-read shapes", flush=True)
+    outs = batch.run()
+    torch.cuda.synchronize()
+    for b in range(2):
+        assert torch.equal(outs[b], plain[b]), b
