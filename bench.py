@@ -16,7 +16,7 @@ against the same work as plain calls.
 
   python bench.py [--steps K] [--warmup W]
                   [--workload headline|headline_shard8|lowfreq_u4|headline_u4|lowfreq_wide|lowfreq_wide_u16|headline_u16|grad_f32|small|
-                              batch48|tab_plans_8192|pipeline_high]
+                              batch48|batch_wide8|batch_wide8_u4|batch_wide8_u16|tab_plans_8192|pipeline_high]
                   [--adjoint] [--time-major] [--tiles SHAPE,ORDER] [--no-cpu-baseline] [--no-autotune]
                   [--autotune] [--no-extras] [--copy-calibration]
 
@@ -625,6 +625,89 @@ def bench_batch48(args, dd, torch, synth):
     print(json.dumps(rec), flush=True)
 
 
+# Batches of wide-spread beams (every plan on a direct-read shape), by input type.
+BATCH_WIDE = {"batch_wide8": "u8", "batch_wide8_u4": "u4", "batch_wide8_u16": "u16"}
+
+
+def bench_batch_wide(args, dd, torch, synth):
+    """8 wide-spread beams (120-190 MHz, synth.wide_beams), whose plans all read directly: one graph
+    replay of the batch (persistent direct-read kernel) per step against the 8 plain calls, each
+    step bracketed by HIP events on the stream both launch on."""
+    dtype = BATCH_WIDE[args.workload]
+    beams = synth.wide_beams(dtype)
+    plans, inputs, outputs = [], [], []
+    for b in beams:
+        p = dd.Plan(b["n_chan"], b["n_samp"], dtype, b["f_high"], b["chan_bw"], b["t_samp"], b["dm_start"],
+                    b["dm_step"], b["n_dm"])
+        plans.append(p)
+        inputs.append(make_input(dd, torch, synth, b, p))
+        outputs.append(torch.empty((p.n_dm, p.out_pitch), dtype=torch.float32, device="cuda"))
+    adds = float(sum(b["n_chan"] * b["n_dm"] * p.n_out for b, p in zip(beams, plans)))
+    log("batch_wide: %d %s beams, %.3e adds, plan shapes %s" % (len(beams), dtype, adds,
+                                                                 [p.tiles(0)["shape"] for p in plans]))
+    batch = dd.Batch(plans, inputs)
+    tune = None
+    if args.tiles:
+        batch.set_tiles(int(args.tiles.split(",")[0]))
+    elif not args.no_autotune:
+        tune = batch.autotune()
+        log("batch autotune: %s" % tune)
+
+    def plain():
+        for p, x, o in zip(plans, inputs, outputs):
+            p.forward(x, out=o)
+
+    b_ms, b_med = timed_events(torch, batch.run, args.steps, args.warmup)
+    p_ms, _ = timed_events(torch, plain, args.steps, args.warmup)
+    got = batch.run()
+    plain()
+    torch.cuda.synchronize()
+    same = all(torch.equal(g, o[:, : p.n_out]) for g, o, p in zip(got, outputs, plans))
+    form, per_op, _ = accumulate_form(dtype, {"row_block": 0})
+    achieved = adds / (b_ms * 1e-3) / 1e12
+    rec = {
+        "metric": "Tadds/s (8 wide-spread beams, batched)",
+        "value": achieved,
+        "unit": "Tadds/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": b_ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": args.workload, "beams": len(beams), "adds_per_step": adds,
+                   "n_chan_set": sorted(set(b["n_chan"] for b in beams)),
+                   "n_samp_range": [min(b["n_samp"] for b in beams), max(b["n_samp"] for b in beams)],
+                   "n_dm_range": [min(b["n_dm"] for b in beams), max(b["n_dm"] for b in beams)],
+                   "band_mhz": [beams[0]["f_high"] - 70.0, beams[0]["f_high"]], "t_samp": beams[0]["t_samp"],
+                   "dm_step": beams[0]["dm_step"]},
+        "plain_calls": {"value": adds / (p_ms * 1e-3) / 1e12, "unit": "Tadds/s", "ms_per_step": p_ms,
+                        "calls_per_step": len(plans)},
+        "batched_over_plain": p_ms / b_ms,
+        "batched_equals_plain": same,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tadds/s",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "fwd_direct_batched_kernel",
+                     "kernel_ms": b_ms, "kernel_ms_median": b_med, "instruction_form": form,
+                     "peak_instruction_form": per_op * VALU_PEAK_TOPS,
+                     "frac_instruction_form": achieved / (per_op * VALU_PEAK_TOPS)},
+        "lds_roofline": None,
+        "batch_tiles": batch.tiles(),
+        "beams_per_shape": batch_shapes(batch),
+        "batch_autotune": tune,
+    }
+    if not args.no_cpu_baseline:
+        big = max(beams, key=lambda b: b["n_chan"] * b["n_samp"] * b["n_dm"])
+        log("cpu baseline on the largest beam ...")
+        rec["cpu_baseline"] = cpu_baseline(dict(big, pulses=[]), seconds_target=12.0)
+        rec["cpu_baseline"]["sample"] = "largest beam: " + rec["cpu_baseline"]["sample"]
+    print(json.dumps(rec), flush=True)
+    if not same:
+        sys.exit("batched outputs differ from the plain calls")
+
+
 def bench_survey(args, dd, torch, synth):
     """Multi-range DM plan (binning + one transform per range) over one 8-bit filterbank.
 
@@ -784,6 +867,8 @@ def main():
         log("copy calibration: 1 GiB read + 1 GiB written")
     if args.workload == "batch48":
         return bench_batch48(args, dd, torch, synth)
+    if args.workload in BATCH_WIDE:
+        return bench_batch_wide(args, dd, torch, synth)
     if args.workload in synth.SURVEYS:
         return bench_survey(args, dd, torch, synth)
     cfg = synth.CONFIGS[args.workload]

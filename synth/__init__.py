@@ -276,6 +276,26 @@ SURVEYS = {
 }
 
 
+def wide_beams(dtype: str = "u8", n_beams: int = 8, seed: int = 3):
+    """Per-beam parameters of a batch of wide-spread beams (8 by default).
+
+    Channel counts from {1024, 2048}, lengths uniform in [2^18, 2^19) rounded
+    down to 64 samples, 256..1024 DM trials at step 0.5; 190 MHz top of a 70
+    MHz band, 327.68 us sampling: a spread of ~4000 samples per 16 DM trials,
+    too wide to stage, so every plan reads directly.  Beam b's data seed is
+    600 + b.
+    """
+    rng = np.random.default_rng(seed)
+    beams = []
+    for b in range(n_beams):
+        n_chan = int(rng.choice([1024, 2048]))
+        n_samp = int(rng.integers(1 << 18, 1 << 19)) // 64 * 64
+        n_dm = int(rng.integers(256, 1025))
+        beams.append(dict(dtype=dtype, n_chan=n_chan, n_samp=n_samp, f_high=190.0, chan_bw=70.0 / n_chan,
+                          t_samp=327.68e-6, dm_start=0.0, dm_step=0.5, n_dm=n_dm, seed=600 + b))
+    return beams
+
+
 def batch_beams(n_beams: int = 48, seed: int = 5):
     """Per-beam parameters of the multi-beam workload (48 beams by default).
 

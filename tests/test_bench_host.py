@@ -68,3 +68,17 @@ def test_accumulate_forms_follow_the_kernel():
     assert b.accumulate_form("f32", {"row_block": 8, "segs": 0})[1:] == (1, 4)
     for dtype, ops in b.DIRECT_OPS.items():  # the op counts and the stated rate agree
         assert ops[4] / sum(ops[:4]) == b.DIRECT_FORMS[dtype][1]
+
+
+def test_wide_beam_batches_read_directly():
+    """The wide-spread beam batches bench.py times (batch_wide8*) put every plan on a direct-read
+    shape by default, for each input type."""
+    import paper_2311_05341_amd as dd
+    import synth
+    b = _bench()
+    assert set(b.BATCH_WIDE.values()) == {"u8", "u4", "u16"}
+    for dtype in ("u8", "u4", "u16"):
+        for c in synth.wide_beams(dtype):
+            p = dd.Plan(c["n_chan"], c["n_samp"], dtype, c["f_high"], c["chan_bw"], c["t_samp"], c["dm_start"],
+                        c["dm_step"], c["n_dm"], bind=False)
+            assert p.tiles(0)["row_block"] == 0, (dtype, c)
