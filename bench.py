@@ -16,7 +16,7 @@ against the same work as plain calls.
 
   python bench.py [--steps K] [--warmup W]
                   [--workload headline|headline_shard8|lowfreq_u4|headline_u4|lowfreq_wide|lowfreq_wide_u16|headline_u16|grad_f32|small|
-                              batch48|batch_wide8|batch_wide8_u4|batch_wide8_u16|tab_plans_8192|pipeline_high]
+                              batch48|batch_wide8|batch_wide8_u4|batch_wide8_u16|batch_small64|tab_plans_8192|pipeline_high]
                   [--adjoint] [--time-major] [--tiles SHAPE,ORDER] [--no-cpu-baseline] [--no-autotune]
                   [--autotune] [--no-extras] [--copy-calibration]
 
@@ -625,16 +625,18 @@ def bench_batch48(args, dd, torch, synth):
     print(json.dumps(rec), flush=True)
 
 
-# Batches of wide-spread beams (every plan on a direct-read shape), by input type.
-BATCH_WIDE = {"batch_wide8": "u8", "batch_wide8_u4": "u4", "batch_wide8_u16": "u16"}
+# Batches of wide-spread beams (every plan on a direct-read shape), by input type, and a batch of
+# many small staged beams: (input type, beam generator in synth).
+BATCH_SETS = {"batch_wide8": ("u8", "wide_beams"), "batch_wide8_u4": ("u4", "wide_beams"),
+              "batch_wide8_u16": ("u16", "wide_beams"), "batch_small64": ("u8", "small_beams")}
 
 
-def bench_batch_wide(args, dd, torch, synth):
-    """8 wide-spread beams (120-190 MHz, synth.wide_beams), whose plans all read directly: one graph
-    replay of the batch (persistent direct-read kernel) per step against the 8 plain calls, each
-    step bracketed by HIP events on the stream both launch on."""
-    dtype = BATCH_WIDE[args.workload]
-    beams = synth.wide_beams(dtype)
+def bench_batch_set(args, dd, torch, synth):
+    """A batch of beams from synth.wide_beams (8 beams at 120-190 MHz, whose plans all read directly)
+    or synth.small_beams (64 small staged beams): one graph replay of the batch per step against the
+    plain calls, one per beam, each step bracketed by HIP events on the stream both launch on."""
+    dtype, gen = BATCH_SETS[args.workload]
+    beams = getattr(synth, gen)(dtype)
     plans, inputs, outputs = [], [], []
     for b in beams:
         p = dd.Plan(b["n_chan"], b["n_samp"], dtype, b["f_high"], b["chan_bw"], b["t_samp"], b["dm_start"],
@@ -643,8 +645,8 @@ def bench_batch_wide(args, dd, torch, synth):
         inputs.append(make_input(dd, torch, synth, b, p))
         outputs.append(torch.empty((p.n_dm, p.out_pitch), dtype=torch.float32, device="cuda"))
     adds = float(sum(b["n_chan"] * b["n_dm"] * p.n_out for b, p in zip(beams, plans)))
-    log("batch_wide: %d %s beams, %.3e adds, plan shapes %s" % (len(beams), dtype, adds,
-                                                                 [p.tiles(0)["shape"] for p in plans]))
+    log("%s: %d %s beams, %.3e adds, plan shapes %s" % (args.workload, len(beams), dtype, adds,
+                                                         sorted(set(p.tiles(0)["shape"] for p in plans))))
     batch = dd.Batch(plans, inputs)
     tune = None
     if args.tiles:
@@ -663,10 +665,11 @@ def bench_batch_wide(args, dd, torch, synth):
     plain()
     torch.cuda.synchronize()
     same = all(torch.equal(g, o[:, : p.n_out]) for g, o, p in zip(got, outputs, plans))
-    form, per_op, _ = accumulate_form(dtype, {"row_block": 0})
+    direct = all(p.tiles(0)["row_block"] == 0 for p in plans)
+    form, per_op, lds_b = accumulate_form(dtype, plans[0].tiles(0))
     achieved = adds / (b_ms * 1e-3) / 1e12
     rec = {
-        "metric": "Tadds/s (8 wide-spread beams, batched)",
+        "metric": "Tadds/s (%d %s beams, batched)" % (len(beams), "wide-spread" if direct else "small"),
         "value": achieved,
         "unit": "Tadds/s",
         "n_gpus": 1,
@@ -689,11 +692,13 @@ def bench_batch_wide(args, dd, torch, synth):
         "batched_over_plain": p_ms / b_ms,
         "batched_equals_plain": same,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tadds/s",
-                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None, "kernel": "fwd_direct_batched_kernel",
+                     "frac": achieved / VALU_PEAK_TOPS, "traffic": None,
+                     "kernel": "fwd_direct_batched_kernel" if direct else "fwd_int_batched_kernel",
                      "kernel_ms": b_ms, "kernel_ms_median": b_med, "instruction_form": form,
                      "peak_instruction_form": per_op * VALU_PEAK_TOPS,
                      "frac_instruction_form": achieved / (per_op * VALU_PEAK_TOPS)},
-        "lds_roofline": None,
+        "lds_roofline": None if not lds_b else {"achieved": achieved * lds_b, "peak": LDS_PEAK_TBS, "unit": "TB/s",
+                                                "frac": achieved * lds_b / LDS_PEAK_TBS, "bytes_per_add": lds_b},
         "batch_tiles": batch.tiles(),
         "beams_per_shape": batch_shapes(batch),
         "batch_autotune": tune,
@@ -867,8 +872,8 @@ def main():
         log("copy calibration: 1 GiB read + 1 GiB written")
     if args.workload == "batch48":
         return bench_batch48(args, dd, torch, synth)
-    if args.workload in BATCH_WIDE:
-        return bench_batch_wide(args, dd, torch, synth)
+    if args.workload in BATCH_SETS:
+        return bench_batch_set(args, dd, torch, synth)
     if args.workload in synth.SURVEYS:
         return bench_survey(args, dd, torch, synth)
     cfg = synth.CONFIGS[args.workload]

@@ -296,6 +296,26 @@ def wide_beams(dtype: str = "u8", n_beams: int = 8, seed: int = 3):
     return beams
 
 
+def small_beams(dtype: str = "u8", n_beams: int = 64, seed: int = 4):
+    """Per-beam parameters of a batch of many small beams (64 by default).
+
+    Channel counts from {256, 512, 1024}, lengths uniform in [2^15, 2^17)
+    rounded down to 64 samples, 64..512 DM trials with a step from {0.25, 0.5,
+    1.0}; 1500 MHz top of a 300 MHz band, 64 us sampling (staged plans).  Beam
+    b's data seed is 700 + b.
+    """
+    rng = np.random.default_rng(seed)
+    beams = []
+    for b in range(n_beams):
+        n_chan = int(rng.choice([256, 512, 1024]))
+        n_samp = int(rng.integers(1 << 15, 1 << 17)) // 64 * 64
+        n_dm = int(rng.integers(64, 513))
+        step = float(rng.choice([0.25, 0.5, 1.0]))
+        beams.append(dict(dtype=dtype, n_chan=n_chan, n_samp=n_samp, f_high=1500.0, chan_bw=300.0 / n_chan,
+                          t_samp=64e-6, dm_start=0.0, dm_step=step, n_dm=n_dm, seed=700 + b))
+    return beams
+
+
 def batch_beams(n_beams: int = 48, seed: int = 5):
     """Per-beam parameters of the multi-beam workload (48 beams by default).
 

@@ -76,7 +76,7 @@ def test_wide_beam_batches_read_directly():
     import paper_2311_05341_amd as dd
     import synth
     b = _bench()
-    assert set(b.BATCH_WIDE.values()) == {"u8", "u4", "u16"}
+    assert {v[0] for k, v in b.BATCH_SETS.items() if v[1] == "wide_beams"} == {"u8", "u4", "u16"}
     for dtype in ("u8", "u4", "u16"):
         for c in synth.wide_beams(dtype):
             p = dd.Plan(c["n_chan"], c["n_samp"], dtype, c["f_high"], c["chan_bw"], c["t_samp"], c["dm_start"],
