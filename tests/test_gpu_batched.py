@@ -178,10 +178,17 @@ def test_batched_beam_with_one_output_sample(dd, dtype):
         xs.append(torch.from_numpy(x).cuda())
     assert plans[0].n_out in (1, 2)
     print("batch with a one-output beam: %s" % dtype, flush=True)
-    outs = dd.Batch(plans, xs).run()
+    batch = dd.Batch(plans, xs)
+    outs = batch.run()
     torch.cuda.synchronize()
     for o, w in zip(outs, wants):
         assert np.array_equal(o.cpu().numpy(), w)
+    for shape in (plans[0].n_shapes - 2, plans[0].n_shapes - 1):  # both beams on a direct-read shape
+        batch.set_tiles(shape)
+        outs = batch.run()
+        torch.cuda.synchronize()
+        for o, w in zip(outs, wants):
+            assert np.array_equal(o.cpu().numpy(), w), shape
 
 
 @pytest.mark.parametrize("dtype", ["u8", "u4", "u16"])
