@@ -324,25 +324,28 @@ dd_status set_tiles(dd_plan &p, int direction, int shape, int order) {
 }
 
 // Default tiles: the first compiled shape (they are listed fastest first; for
-// 8- and 4-bit plans the phase-load shapes before the others, an 8-wave one
+// 8-bit plans the phase-load shapes before the others, an 8-wave one
 // only where two of its workgroups fit in a CU's LDS) that holds the plan's
 // delay spread, in the grouped workgroup order (as fast as time tiles fastest
 // on the headline plan, with a third of its L2 fetch traffic).
 // For an integer plan whose spread leaves only LDS shapes staging 1 or 2
 // channels at a time, the direct-read kernel is faster (measured: 12.7 against
 // 8.5-10 Tadds/s at 264-395 samples of delay per DM step) and is chosen.
+// 4-bit plans read directly whatever their spread: 2 rows x 8 waves, each XCD
+// taking whole time tiles.  Its packed 16-byte windows and in-place nibble adds
+// beat staging even on narrow spreads (8192 ch x 2^20 x 4000 DMs at 1200-1500
+// MHz: 50.1 against 44.1 Tadds/s for the best staged shape, the phase-load
+// form; 4096 ch x 2^19 x 2048 DMs at 120-190 MHz: 50.0 against 25.3 for the
+// best staged shape; grid order 1 there against 46.2 for the grouped order).
 dd_status choose_forward_tiles(dd_plan &p) {
+  if (p.desc.dtype == DD_U4) return set_tiles(p, 0, kNumIntShapes + 1, kOrderXcdTiles);
   const int dirs = p.desc.dtype == DD_F32 ? 2 : 1;
   for (int dir = 0; dir < dirs; ++dir) {
     dd_status last = DD_ERR_RANGE;
     for (int pass = 0; pass < 2 && last != DD_OK && last != DD_ERR_NOMEM; ++pass)
       for (int i = 0; i < num_shapes(p); ++i) {
-        const bool phase = (p.desc.dtype == DD_U8 || p.desc.dtype == DD_U4) && int_shape_segs(i) > 0;
+        const bool phase = p.desc.dtype == DD_U8 && int_shape_segs(i) > 0;
         if (phase != (pass == 0)) continue;
-        // 4-bit phase loads build half their copies in LDS every block: with fewer than 8
-        // channels per stage that costs more than it saves (measured on 4096 ch x 2^19,
-        // 120-190 MHz: 19.6-21.7 Tadds/s against 25.3 for the raw ring)
-        if (phase && p.desc.dtype == DD_U4 && int_shape(i)[3] < 8) continue;
         last = set_tiles(p, dir, i, kOrderDmGroups);
         // an 8-wave phase-load shape pays only when two of its workgroups share a CU
         if (last == DD_OK && phase && p.fwd.waves == 8 && 2 * p.fwd.lds_bytes > kLdsLimit) last = DD_ERR_RANGE;
@@ -351,19 +354,11 @@ dd_status choose_forward_tiles(dd_plan &p) {
     if (last == DD_ERR_NOMEM) return last;
     if (last != DD_OK) return fail(DD_ERR_RANGE, "delay spread exceeds every compiled staging shape");
   }
-  // 4-bit plans whose staged default holds at most 4 channels per raw-ring stage
-  // take the direct kernel too: it reads 32 packed samples per 16-byte load and
-  // adds nibbles in place (4096 ch x 2^19 at 120-190 MHz: 29.8 against 25.2
-  // Tadds/s for the 4-channel raw ring)
-  // Direct shape: 2 rows x 8 waves for 4-bit input (4096 ch x 2^19 at 120-190 MHz: 46.2
-  // against 38.3 Tadds/s for 4 x 4), 4 rows x 4 waves otherwise (4096 ch x 2^20 at 120-190
-  // MHz, DM step 0.5: 30.0 against 25.9 for 8-bit samples, 11.7 against 8.2 for 16-bit).
-  // Order: whole time tiles per XCD for 4-bit input (there 50.0 against 46.2 Tadds/s for the
-  // grouped order), the grouped order otherwise (8-bit 30.1 against 29.7; 16-bit equal)
-  const int direct_below = p.desc.dtype == DD_U4 && !is_direct(p.fwd) && p.fwd.segs == 0 ? 4 : 2;
-  if (p.desc.dtype != DD_F32 && !is_direct(p.fwd) && p.fwd.chan_block <= direct_below)
-    return p.desc.dtype == DD_U4 ? set_tiles(p, 0, kNumIntShapes + 1, kOrderXcdTiles)
-                                 : set_tiles(p, 0, kNumIntShapes, kOrderDmGroups);
+  // Direct shape for 8- and 16-bit samples: 4 rows x 4 waves (4096 ch x 2^20 at 120-190 MHz,
+  // DM step 0.5: 30.0 against 25.9 Tadds/s for 2 x 8 with 8-bit samples, 11.7 against 8.2 with
+  // 16-bit), in the grouped order (8-bit 30.1 against 29.7 for whole tiles per XCD; 16-bit equal)
+  if (p.desc.dtype != DD_F32 && !is_direct(p.fwd) && p.fwd.chan_block <= 2)
+    return set_tiles(p, 0, kNumIntShapes, kOrderDmGroups);
   // 16-bit plans: the 8-wave shape with 4 rows per wave and 4 channels per stage,
   // where two of its workgroups fit in a CU's LDS, so that one's barrier waits
   // overlap the other's adds: first in its phase-load form (the two copies loaded

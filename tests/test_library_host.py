@@ -245,10 +245,10 @@ def test_survey_time_major_layout(dd):
 
 
 def test_large_spread_plan_uses_direct_kernel(dd):
-    """Plans whose delay spread leaves only 1- or 2-channel LDS stages (4-bit plans: raw-ring
-    stages of at most 4 channels) default to the direct-read kernel (no staging: row_block 0),
-    whose table is the plain shift table: 4 rows x 4 waves for 8- and 16-bit samples, 2 rows x
-    8 waves for 4-bit samples."""
+    """8- and 16-bit plans whose delay spread leaves only 1- or 2-channel LDS stages, and every
+    4-bit plan, default to the direct-read kernel (no staging: row_block 0), whose table is the
+    plain shift table: 4 rows x 4 waves for 8- and 16-bit samples, 2 rows x 8 waves (order 1)
+    for 4-bit samples."""
     cfg = synth.CONFIGS["lowfreq_wide"]
     p = _plan(dd, cfg)
     t = p.tiles(0)
@@ -258,11 +258,12 @@ def test_large_spread_plan_uses_direct_kernel(dd):
     assert t16["row_block"] == 0 and t16["per_wave"] == 4 and t16["waves"] == 4
     assert p.info.dev_table_bytes >= cfg["n_dm"] * cfg["n_chan"] * 4
     assert p.info.tune_ws_bytes >= p.info.dev_table_bytes
-    for name in ["small", "headline", "headline_u4", "headline_u16"]:  # narrow spreads keep LDS staging
+    for name in ["small", "headline", "headline_u16"]:  # narrow spreads keep LDS staging
         assert _plan(dd, synth.CONFIGS[name]).tiles(0)["row_block"] > 0
-    assert _plan(dd, synth.CONFIGS["lowfreq_u4"]).tiles(0)["row_block"] == 0  # 4-bit, 4-channel ring stages
-    p4 = _plan(dd, dict(cfg, dtype="u4"))
-    assert p4.tiles(0)["row_block"] == 0 and p4.tiles(0)["per_wave"] == 2
+    for c in [synth.CONFIGS["lowfreq_u4"], synth.CONFIGS["headline_u4"], dict(cfg, dtype="u4"),
+              dict(synth.CONFIGS["small"], dtype="u4")]:  # 4-bit: direct reads for any spread
+        t4 = _plan(dd, c).tiles(0)
+        assert t4["row_block"] == 0 and t4["per_wave"] == 2 and t4["waves"] == 8 and t4["order"] == 1
 
 
 def test_batch_tile_choice_host(dd):

@@ -72,13 +72,14 @@ def test_tiles_argument_errors(dd):
 
 
 def test_default_tiles_grouped_order(dd):
-    for name in ["small", "headline", "headline_u4", "lowfreq_wide", "lowfreq_wide_u16", "grad_f32"]:
+    for name in ["small", "headline", "headline_u16", "lowfreq_wide", "lowfreq_wide_u16", "grad_f32"]:
         p = _plan(dd, synth.CONFIGS[name])
         assert p.tiles(0)["order"] == 2
         assert p.info.kernel_order == 2
-    # 4-bit direct-read plans take whole time tiles per XCD
-    p = _plan(dd, synth.CONFIGS["lowfreq_u4"])
-    assert p.tiles(0)["row_block"] == 0 and p.tiles(0)["order"] == 1 and p.info.kernel_order == 1
+    # 4-bit plans read directly, each XCD taking whole time tiles
+    for name in ["lowfreq_u4", "headline_u4"]:
+        p = _plan(dd, synth.CONFIGS[name])
+        assert p.tiles(0)["row_block"] == 0 and p.tiles(0)["order"] == 1 and p.info.kernel_order == 1
 
 
 _KEY_FMT = (b"dtype=%d,nchan=%d,nsamp=%lld,fhigh=%a,bw=%a,freqs=%016llx,tsamp=%a,dm0=%a,dmstep=%a,ndm=%d,"

@@ -97,6 +97,11 @@ def test_noalloc_both_8bit_staging_forms_and_direct(dd):
     for d, seed in ((desc, 23), (small, 24)):
         want, got = _both(dd, d, seed, shape=direct[0])
         assert np.array_equal(got, want)
+    # 4-bit plans read directly by default; their staged forms use the static area too
+    d4 = _desc("u4", 200, 30016, 80, 1.0)
+    for segs in (0, 1):
+        want, got = _both(dd, d4, 25 + segs, shape=_shape_index(dd, d4, segs))
+        assert np.array_equal(got, want), ("u4 segs", segs)
 
 
 def test_noalloc_refuses_tables_beyond_the_static_area(dd):
