@@ -210,12 +210,14 @@ dd_status dd_execute_adjoint(const dd_plan *plan, const float *d_y, int64_t y_pi
  * speed only: results are bitwise identical for every choice (exact integer
  * sums; fixed-order float sums).  dd_plan_create picks the first compiled
  * shape that holds the plan's delay spread, 8-bit plans trying the phase-load
- * shapes first (8- and 16-bit plans that only fit 1- or 2-channel stages take
- * the 4 rows x 4 waves direct-read shape; 16-bit plans take the 8-wave,
- * 4-rows-per-wave, 4-channel shape, phase-load form first, when two of its
- * workgroups fit in one CU's LDS), in order 2; 4-bit plans take the 2 rows x 8
- * waves direct-read shape in order 1 whatever their spread; or the choice
- * recorded for an identical plan in the tuning cache (below).
+ * shapes first, in order 2 (16-bit plans take the 8-wave, 4-rows-per-wave,
+ * 4-channel shape, phase-load form first, when two of its workgroups fit in
+ * one CU's LDS); an 8- or 16-bit plan left with stages of at most 4 channels
+ * (16-bit: other than that shape) takes the 4 rows x 4 waves direct-read shape
+ * in order 1 (order 2 for 8-bit plans that fit only 1- or 2-channel stages);
+ * 4-bit plans take the 2 rows x 8 waves direct-read shape in order 1 whatever
+ * their spread; or the choice recorded for an identical plan in the tuning
+ * cache (below).
  *
  * direction: 0 = forward; 1 = adjoint (DD_F32 plans only).
  *

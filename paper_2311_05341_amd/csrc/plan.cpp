@@ -356,17 +356,27 @@ dd_status choose_forward_tiles(dd_plan &p) {
   }
   // Direct shape for 8- and 16-bit samples: 4 rows x 4 waves (4096 ch x 2^20 at 120-190 MHz,
   // DM step 0.5: 30.0 against 25.9 Tadds/s for 2 x 8 with 8-bit samples, 11.7 against 8.2 with
-  // 16-bit), in the grouped order (8-bit 30.1 against 29.7 for whole tiles per XCD; 16-bit equal)
-  if (p.desc.dtype != DD_F32 && !is_direct(p.fwd) && p.fwd.chan_block <= 2)
-    return set_tiles(p, 0, kNumIntShapes, kOrderDmGroups);
+  // 16-bit), each XCD taking whole time tiles (on 4096-channel plans at 120-190, 300-400 and
+  // 1200-1500 MHz: 8-bit 33.0-34.3 against 30.5-31.2 Tadds/s for the grouped order, 16-bit
+  // 17.0-17.8 against 16.1-16.7), except 8-bit plans too wide for 4-channel stages, which
+  // keep the grouped order (4096 ch x 2^20 at 120-190 MHz, DM step 0.5: 30.0 against 29.3).
+  // An 8-bit plan reads directly when its staged shape holds at most 4 channels per stage: on
+  // those four plans (staged shapes 16, 17, 18 and 5) 33.0-34.3 against 15.0-24.4 Tadds/s.
+  const int direct = kNumIntShapes;
+  if (p.desc.dtype == DD_U8 && !is_direct(p.fwd) && p.fwd.chan_block <= 4)
+    return set_tiles(p, 0, direct, p.fwd.chan_block <= 2 ? kOrderDmGroups : kOrderXcdTiles);
   // 16-bit plans: the 8-wave shape with 4 rows per wave and 4 channels per stage,
   // where two of its workgroups fit in a CU's LDS, so that one's barrier waits
   // overlap the other's adds: first in its phase-load form (the two copies loaded
   // straight into LDS: 1111.5 against 1326.9 ms on 8192 ch x 2^20 x 4000 DMs),
   // else in its raw-ring form (13-16% faster than the 16-wave default on 8192 x
   // 2^20 and on binned 4096-channel ranges; 11% slower on a plan with ~1000
-  // samples of spread per 32 DMs, where only one fits).
+  // samples of spread per 32 DMs, where only one fits).  Otherwise a plan left
+  // with at most 4 channels per stage reads directly (4096-channel plans whose
+  // staged shape was the 1-row, 16-wave raw ring: 17.0-17.8 against 14.6-15.1
+  // Tadds/s), as does one with at most 2.
   if (p.desc.dtype == DD_U16 && !is_direct(p.fwd)) {
+    if (p.fwd.chan_block <= 2) return set_tiles(p, 0, direct, kOrderXcdTiles);
     const int keep_shape = p.fwd.shape, keep_order = p.fwd.order;
     bool moved = false;
     for (int want_phase = 1; want_phase >= 0; --want_phase)
@@ -380,7 +390,11 @@ dd_status choose_forward_tiles(dd_plan &p) {
         moved = moved || st == DD_OK;
         break;
       }
-    if (moved) return set_tiles(p, 0, keep_shape, keep_order);
+    if (moved) {
+      const dd_status st = set_tiles(p, 0, keep_shape, keep_order);
+      if (st != DD_OK) return st;
+    }
+    if (p.fwd.chan_block <= 4) return set_tiles(p, 0, direct, kOrderXcdTiles);
   }
   return DD_OK;
 }

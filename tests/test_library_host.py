@@ -245,10 +245,11 @@ def test_survey_time_major_layout(dd):
 
 
 def test_large_spread_plan_uses_direct_kernel(dd):
-    """8- and 16-bit plans whose delay spread leaves only 1- or 2-channel LDS stages, and every
-    4-bit plan, default to the direct-read kernel (no staging: row_block 0), whose table is the
-    plain shift table: 4 rows x 4 waves for 8- and 16-bit samples, 2 rows x 8 waves (order 1)
-    for 4-bit samples."""
+    """8- and 16-bit plans whose delay spread leaves only LDS stages of at most 4 channels (16-bit:
+    other than its preferred 8-wave shape), and every 4-bit plan, default to the direct-read
+    kernel (no staging: row_block 0), whose table is the plain shift table: 4 rows x 4 waves for
+    8- and 16-bit samples, 2 rows x 8 waves for 4-bit samples; grid order 1, except 8-bit plans
+    too wide for 4-channel stages (order 2)."""
     cfg = synth.CONFIGS["lowfreq_wide"]
     p = _plan(dd, cfg)
     t = p.tiles(0)
@@ -260,6 +261,11 @@ def test_large_spread_plan_uses_direct_kernel(dd):
     assert p.info.tune_ws_bytes >= p.info.dev_table_bytes
     for name in ["small", "headline", "headline_u16"]:  # narrow spreads keep LDS staging
         assert _plan(dd, synth.CONFIGS[name]).tiles(0)["row_block"] > 0
+    # a moderate spread (4-channel stages at best) reads directly for 8- and 16-bit samples
+    mid = dict(cfg, n_samp=1 << 19, dm_step=0.1, n_dm=2048)
+    for dt in ("u8", "u16"):
+        tm = _plan(dd, dict(mid, dtype=dt)).tiles(0)
+        assert tm["row_block"] == 0 and tm["per_wave"] == 4 and tm["order"] == 1, (dt, tm)
     for c in [synth.CONFIGS["lowfreq_u4"], synth.CONFIGS["headline_u4"], dict(cfg, dtype="u4"),
               dict(synth.CONFIGS["small"], dtype="u4")]:  # 4-bit: direct reads for any spread
         t4 = _plan(dd, c).tiles(0)
